@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Throughput of u-series force evaluations on one MI355X.
+
+One step = one full evaluation (energy + forces of every charge: binning,
+near pair sum, spreading, separable convolutions, gathering, FP64 energy) of
+the 26,268-charge water box (L = 64 A, r_c = 9 A, 64^3 grid, b = 2 C1 series,
+N = 4 far terms), inputs resident in HBM.
+
+Prints one JSON line:
+  value        evaluations/s of the chosen form (default: BF16X3 convolutions,
+               8^3 spreading stencil; --form plain for the FP32 path);
+  roofline     the dominant kernel's achieved rate vs the MI355X peak, timed
+               with HIP events on the evaluation stream;
+  cpu_baseline the FP64 oracle on the host's cores, on a bounded sample;
+  accuracy     force/energy error of the timed configuration vs the oracle
+               (sampled forces, full-size energy from the stored oracle value).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X peaks (dense): HBM 8 TB/s; FP32 vector 157.3 TFLOP/s; MFMA FP32
+# 157.3 TFLOP/s, BF16 2.5 PFLOP/s.
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
+
+# algorithmic work per unit ("Measurement")
+FLOP_PER_PAIR = 45.0          # near part: one unique pair within r_c
+FLOP_PER_SPREAD_POINT = 2.0   # one FMA per charge and stencil point
+FLOP_PER_GATHER_POINT = 8.0   # four FMAs (value + gradient) per charge and stencil point
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def count_pairs(xyz, box, rc):
+    from scipy.spatial import cKDTree
+    x = np.mod(np.asarray(xyz, np.float64), box)
+    t = cKDTree(x, boxsize=box)
+    ordered = t.count_neighbors(t, rc)
+    return (ordered - len(x)) // 2
+
+
+def kernel_src_hash(name):
+    csrc = os.path.join(ROOT, "paper_1911_01377_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")) and (name in f or f.endswith(".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--form", choices=["bf16x3", "plain"], default="bf16x3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the u-series hot path here is a single-GPU "
+              "build (see DESIGN.md for how it would shard); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1911_01377_amd import USERIES_BF16X3, USERIES_PLAIN_FP32, Plan, synth
+
+    xyz, q, box = synth.water_box(None, 64.0, seed=1378)
+    n = len(q)
+    rc, grid = 9.0, (64, 64, 64)
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(xyz).to(dev)
+    qq = torch.from_numpy(q).to(dev)
+    forces = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    energy = torch.empty(1, dtype=torch.float64, device=dev)
+
+    def timed(plan, steps, warmup):
+        stream = torch.cuda.current_stream(dev)
+        for _ in range(warmup):
+            plan.eval(x, qq, forces, energy)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(steps):
+            plan.eval(x, qq, forces, energy)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / steps
+
+    forms = {"bf16x3": USERIES_BF16X3, "plain": USERIES_PLAIN_FP32}
+    plans = {k: Plan(box, rc, grid, precision=v) for k, v in forms.items()}
+    results = {}
+    for k, plan in plans.items():
+        ms = timed(plan, args.steps, args.warmup)
+        results[k] = ms
+        log("form %s: %.4f ms/eval, %.1f evals/s" % (k, ms, 1e3 / ms))
+    plan = plans[args.form]
+    ms = results[args.form]
+
+    # latency of single synchronised evaluations
+    lat = []
+    for _ in range(50):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        plan.eval(x, qq, forces, energy)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t) * 1e3)
+    lat = np.array(lat)
+
+    # per-kernel times (HIP events around each kernel on the evaluation stream)
+    plan.timing(True)
+    nprof = 50
+    for _ in range(nprof):
+        plan.eval(x, qq, forces, energy)
+    torch.cuda.synchronize()
+    ktimes = {name: tot / max(cnt, 1) for name, tot, cnt in plan.timing()}
+    plan.timing(False)
+    log("kernel ms: " + ", ".join("%s %.4f" % kv for kv in ktimes.items()))
+
+    # accuracy of this configuration against the oracle
+    info = plan.info
+    acc = {}
+    E = None
+    try:
+        import oracle
+        plan.eval(x, qq, forces, energy)
+        torch.cuda.synchronize()
+        f = forces.cpu().numpy().astype(np.float64)
+        E = float(energy.cpu()[0])
+        p = oracle.Params(b=info["b"], sigma=info["sigma"], w0=info["w0"], s0=info["s0"],
+                          rc=rc, nterms=info["n_terms"])
+        idx = np.random.default_rng(0).choice(n, 128, replace=False)
+        fo = oracle.forces_subset(xyz.astype(np.float64), q.astype(np.float64), box, p, idx)
+        acc["force_rel_rms_sampled128"] = math.sqrt(np.sum((f[idx] - fo) ** 2) / np.sum(fo ** 2))
+        gold = os.path.join(ROOT, "tests", "golden", "oracle_water26k.json")
+        if os.path.exists(gold):
+            g = json.load(open(gold))
+            acc["energy_rel"] = abs(E - g["parts"]["total"]) / abs(g["parts"]["total"])
+    except Exception as e:   # accuracy is reported, never required for timing
+        acc["error"] = str(e)
+
+    # roofline of the dominant kernel
+    dom = max(ktimes, key=ktimes.get)
+    P = info["stencil_half"]
+    nt = info["n_terms"]
+    npairs = count_pairs(xyz, np.array(box), rc)
+    G = grid[0] * grid[1] * grid[2]
+    work = {
+        "pair": ("alu", npairs * FLOP_PER_PAIR, PEAK_FP32_TFLOPS),
+        "spread": ("alu", n * (2 * P) ** 3 * FLOP_PER_SPREAD_POINT, PEAK_FP32_TFLOPS),
+        "gather": ("alu", n * (2 * P) ** 3 * FLOP_PER_GATHER_POINT, PEAK_FP32_TFLOPS),
+        "conv_xy": ("mfma", 2.0 * nt * G * (grid[0] + grid[1]),
+                    PEAK_BF16_TFLOPS if args.form == "bf16x3" else PEAK_FP32_TFLOPS),
+        "conv_z": ("mfma", 2.0 * nt * G * grid[2],
+                   PEAK_BF16_TFLOPS if args.form == "bf16x3" else PEAK_FP32_TFLOPS),
+    }
+    roof = None
+    if dom in work:
+        bound, flop, peak = work[dom]
+        achieved = flop / (ktimes[dom] * 1e-3) / 1e12
+        traffic = None
+        tf = os.path.join(ROOT, "profiles", "traffic_%s.json" % dom)
+        if os.path.exists(tf):
+            t = json.load(open(tf))
+            if t.get("src_hash") == kernel_src_hash(dom) and t.get("form") == args.form:
+                traffic = t.get("bytes_per_launch")
+        roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                "kernel_ms": ktimes[dom], "algorithmic_flop": flop}
+
+    # the oracle on the host's cores, bounded sample
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            import oracle
+            p = oracle.Params(b=info["b"], sigma=info["sigma"], w0=info["w0"], s0=info["s0"],
+                              rc=rc, nterms=info["n_terms"])
+            x64, q64 = xyz.astype(np.float64), q.astype(np.float64)
+            rng = np.random.default_rng(1)
+            m = 16
+            t = time.perf_counter()
+            oracle.forces_subset(x64, q64, box, p, rng.choice(n, m, replace=False))
+            dt = time.perf_counter() - t
+            m2 = int(min(n, max(m, m * args.cpu_seconds / max(dt, 1e-3))))
+            t = time.perf_counter()
+            oracle.forces_subset(x64, q64, box, p, rng.choice(n, m2, replace=False))
+            dt = time.perf_counter() - t
+            per_eval = dt * n / m2
+            cpu = {"value": 1.0 / per_eval, "unit": "evals/s", "cores": oracle.num_threads(),
+                   "kind": "oracle",
+                   "sample": "forces on %d of %d charges (O(n) each, near + far image sums), "
+                             "%.1f s, scaled by n/%d to one evaluation" % (m2, n, dt, m2)}
+        except Exception as e:
+            cpu = {"value": None, "unit": "evals/s", "cores": None, "kind": "oracle",
+                   "sample": "failed: %s" % e}
+
+    out = {
+        "metric": "u-series force evals/s (26k-charge box, force err<=1e-3) + p50/p99 latency",
+        "value": 1e3 / ms,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3" if args.form == "bf16x3" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "water box, 8756 3-site waters = 26268 charges, L=64 A, "
+                               "r_c=9 A, 64^3 grid, b=2 C1, N=%d" % info["n_terms"],
+                   "form": args.form, "stencil": "%d^3" % (2 * P)},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "what": "one synchronised evaluation, host wall clock"},
+        "other_form_evals_per_s": {k: 1e3 / v for k, v in results.items()},
+        "kernel_ms": ktimes,
+        "accuracy": acc,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    for p_ in plans.values():
+        p_.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

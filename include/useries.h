@@ -1,0 +1,212 @@
+/*
+ * useries.h -- C ABI of the MI355X (gfx950) u-series electrostatics library.
+ *
+ * The library evaluates the electrostatic energy and forces of n point
+ * charges in an orthorhombic periodic cell with the u-series decomposition
+ * of Predescu et al., "The u-series: A separable decomposition for
+ * electrostatics computation with improved accuracy" (arXiv:1911.01377):
+ *
+ *   near part  (Sec. III.C, eq. 20; C1 construction eqs. 24-26):
+ *              1/r - F(r) for r < r_c, summed pairwise over a cell list;
+ *   far part   (Sec. V, eqs. 31-33): F truncated to N Gaussians, evaluated by
+ *              spreading the charges to a grid, three periodic 1D
+ *              convolutions per Gaussian (x, y, z), summing the terms and
+ *              gathering potentials and forces back to the charges;
+ *   self term  1/2 F(0) sum q_i^2 (the analogue of the Ewald self term, eq. 10);
+ *   background for a net charge Q, the uniform neutralising background of
+ *              the k != 0 convention (eqs. 4, 9, 10); zero for neutral input.
+ *
+ * Units are Gaussian with Coulomb constant 1: charges in e, lengths in
+ * Angstrom, energies in e^2/A, forces in e^2/A^2 (multiply by 332.0637 for
+ * kcal/mol).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an int status: USERIES_OK (0) or a negative
+ *    USERIES_E* code; useries_strerror() gives its text, and
+ *    useries_last_error() a message about the most recent failure.
+ *  - Device pointers are HIP device memory of the current device (for
+ *    example from torch.empty(..., device="cuda") on ROCm); host pointers are
+ *    ordinary process memory.  The caller owns every buffer it passes; the
+ *    library owns its plans and their device workspaces.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Evaluation is asynchronous on that stream.  One plan may be used by one
+ *    stream at a time.
+ */
+#ifndef USERIES_H
+#define USERIES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct useries_plan_s *useries_plan_t;
+
+/* status codes */
+enum {
+    USERIES_OK = 0,
+    USERIES_EINVAL = -1,     /* invalid argument */
+    USERIES_ENOMEM = -2,     /* device or host allocation failed / budget exceeded */
+    USERIES_EHIP = -3,       /* a HIP runtime call failed */
+    USERIES_EBUSY = -4,      /* resource busy (serving: no slot) */
+    USERIES_ENOTFOUND = -5,  /* unknown handle or ticket */
+    USERIES_ESTATE = -6      /* call not valid in the object's current state */
+};
+
+/* far-series constructions (Sec. III.C, Tables 1 and 2) */
+enum {
+    USERIES_C0 = 0,             /* eq. 19: w0 = 1, r_c = smallest root of eq. 21 */
+    USERIES_C1 = 1,             /* eq. 24: w0 from eq. 25, r0 = smallest root of eq. 26 */
+    USERIES_C2_B2 = 2,          /* eq. 28 with the b = 2 parameters of Table 2 row 3 */
+    USERIES_TABLE1_ROW1 = 11,   /* C1 construction at the C2 points of Table 1 */
+    USERIES_TABLE1_ROW2 = 12,
+    USERIES_TABLE1_ROW3 = 13
+};
+
+/* arithmetic of the far-part convolutions */
+enum {
+    USERIES_PLAIN_FP32 = 0,     /* FP32 MFMA convolutions, 10^3 spreading stencil */
+    USERIES_BF16X3 = 1          /* BF16 MFMA with 3-product split precision,
+                                   8^3 spreading stencil */
+};
+
+/*
+ * Optional plan settings.  Fill with useries_default_opts() and override.
+ *   construction     one of the USERIES_C* / USERIES_TABLE1_* values.
+ *   precision        USERIES_PLAIN_FP32 or USERIES_BF16X3.
+ *   sigma_s_over_h   width of the Gaussian that spreads charges to the grid,
+ *                    in units of the grid spacing of each axis; <= 0 picks
+ *                    the default of the precision (0.9 plain, 0.83 BF16X3).
+ *   stencil_half     P: each charge touches 2P grid points per axis; <= 0
+ *                    picks the default (5 plain, 4 BF16X3).  1 <= P <= 8.
+ *   nterms_tol       relative far-energy truncation bound (eq. 33) used to
+ *                    choose N when useries_plan gets n_terms <= 0.
+ *   poly_degree      degree in r^2 of the polynomial that represents the
+ *                    infinite far series inside the cutoff (near part);
+ *                    <= 0 picks 10.  4 <= degree <= 14.
+ *   max_atoms        workspace capacity in charges; <= 0 grows on demand
+ *                    (a growth reallocates and synchronises the device).
+ */
+typedef struct {
+    int construction;
+    int precision;
+    double sigma_s_over_h;
+    int stencil_half;
+    double nterms_tol;
+    int poly_degree;
+    int64_t max_atoms;
+} useries_opts;
+
+/* Fill *opts with the defaults: C1, PLAIN_FP32, nterms_tol 1e-8, the rest
+ * "pick the default".  Returns USERIES_EINVAL for NULL. */
+int useries_default_opts(useries_opts *opts);
+
+/*
+ * Build a plan for one cell shape (host work, then one upload).
+ *   out      receives the plan handle.
+ *   box      host [3]: edge lengths Lx, Ly, Lz > 0 of the orthorhombic cell.
+ *   r_c      cutoff radius; 0 < r_c < min(L)/2.
+ *   b        base of the series (> 1).  Ignored by the presets
+ *            USERIES_C2_B2 and USERIES_TABLE1_*, which fix b.
+ *   sigma    <= 0: sigma = r_c / r0 (Sec. III.C, eq. 23), the construction's
+ *            own r0.  > 0: for C0 and C1 the cutoff stays r_c and w0 is
+ *            re-solved from eq. 25 at r0 = r_c / sigma, which keeps the near
+ *            part continuous at r_c (its slope then need not vanish).  The
+ *            presets require sigma <= 0 or sigma = r_c / r0 within 1e-12.
+ *   n_terms  N, the far Gaussians kept (Sec. V); <= 0 picks the smallest N
+ *            whose eq. 33 bound is <= opts->nterms_tol.  At most 32.
+ *   grid     host [3]: far-part grid points per axis, 2P <= n <= 128.
+ *            Each axis needs its grid spacing h with
+ *            s_0^2 > 2 (sigma_s_over_h * h)^2 (the spreading Gaussians must
+ *            be narrower than the narrowest far Gaussian, Sec. IV.A).
+ *   opts     NULL for the defaults.
+ * Errors: USERIES_EINVAL (bad argument or unsatisfiable constraint),
+ * USERIES_ENOMEM, USERIES_EHIP.  The plan uses the current HIP device.
+ */
+int useries_plan(useries_plan_t *out, const double box[3], double r_c, double b,
+                 double sigma, int n_terms, const int grid[3], const useries_opts *opts);
+
+/*
+ * Energy and forces of n charges (asynchronous on `stream`).
+ *   xyz      device float [n][3]: positions in A, any periodic image.
+ *   q        device float [n]: charges in e.
+ *   forces   device float [n][3]: OVERWRITTEN with the forces, in the order
+ *            of the inputs; never read.
+ *   energy   device double [1]: OVERWRITTEN with the total energy.
+ * n may be 0 (energy 0).  Coincident charges (r = 0 between two different
+ * charges) are outside the contract.  Errors: USERIES_EINVAL (n < 0, NULL
+ * pointers with n > 0, n above a fixed max_atoms), USERIES_ENOMEM,
+ * USERIES_EHIP.
+ */
+int useries_eval(useries_plan_t plan, int64_t n, const float *xyz, const float *q,
+                 float *forces, double *energy, void *stream);
+
+/*
+ * As useries_eval, and also writes the parts of the energy to
+ *   parts    device double [5]: E_near, E_far (grid, k = 0 removed), E_self,
+ *            E_background, E_total (= E_near + E_far - E_self + E_background).
+ * `energy` may be NULL.
+ */
+int useries_eval_parts(useries_plan_t plan, int64_t n, const float *xyz, const float *q,
+                       float *forces, double *energy, double *parts, void *stream);
+
+/*
+ * Host copies of the plan's parameters (any pointer may be NULL):
+ *   b, sigma, r0 (= r_c / sigma), w0, s0, n_terms, eq33 (the eq. 33 bound at
+ *   n_terms with L = max edge), f_inf0 (F(0) of the infinite series, the
+ *   self-term coefficient), c1_slope (N'(r_c) of the near part; 0 for C1),
+ *   sigma_s (spreading width per axis of x, A), stencil_half, ncell[3]
+ *   (cell list), poly_maxerr (max relative error of the near polynomial on
+ *   [0, r_c], measured in FP64 on the host).
+ */
+int useries_plan_info(useries_plan_t plan, double *b, double *sigma, double *r0, double *w0,
+                      double *s0, int *n_terms, double *eq33, double *f_inf0,
+                      double *c1_slope, double *sigma_s, int *stencil_half, int ncell[3],
+                      double *poly_maxerr);
+
+/* Release a plan and its device memory.  The caller must ensure that no
+ * evaluation on it is still running. */
+int useries_destroy(useries_plan_t plan);
+
+/*
+ * Per-kernel timing.  When enabled, each evaluation records HIP events
+ * around each kernel on the evaluation stream; useries_timing_read (after the
+ * stream has been synchronised) returns, for kernel k in launch order, its
+ * name, the summed duration in ms and the number of launches timed.
+ * Enabling resets the sums.  Returns USERIES_ENOTFOUND when k is out of range.
+ */
+int useries_timing_enable(useries_plan_t plan, int enable);
+int useries_timing_read(useries_plan_t plan, int k, const char **name, double *total_ms,
+                        int64_t *launches);
+
+/* ----------------------------------------------------------- host math */
+/* These touch no device and may be called without a GPU. */
+
+/* (r0, w0, s0) of a construction at base b (b is ignored by the presets).
+ * C0: eqs. 19-21; C1: eqs. 24-26, smallest root, including tangential
+ * (double) roots at the C2 points of eq. 27; presets: Tables 1 and 2.
+ * Writes *b_out with the base actually used.  USERIES_EINVAL if b <= 1 or no
+ * root is found below r = 50. */
+int useries_solve_construction(int construction, double b, double *b_out, double *r0,
+                               double *w0, double *s0);
+
+/* eq. 33: relative bound on the far energy truncated to n terms. */
+double useries_eq33_bound(int n, double b, double sigma, double lmax);
+
+/* smallest n in [1, 32] with useries_eq33_bound(n, ...) <= tol (32 if none) */
+int useries_choose_nterms(double b, double sigma, double lmax, double tol);
+
+/* eq. 14: asymptotic bound M_b of the relative error of the series */
+double useries_bsa_bound(double b);
+
+/* text of a status code, and a message about the latest failure in this thread */
+const char *useries_strerror(int code);
+const char *useries_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* USERIES_H */

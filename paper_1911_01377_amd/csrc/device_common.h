@@ -1,0 +1,63 @@
+// Small device helpers shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace useries {
+
+// x (any image) -> uint32 fraction of the cell edge, rounded to nearest;
+// 2^32 wraps to 0.
+__device__ __forceinline__ uint32_t to_fixed(double x, double inv_L) {
+    double f = x * inv_L;
+    f -= floor(f);
+    const double t = f * 4294967296.0 + 0.5;
+    return (uint32_t)(uint64_t)t;
+}
+
+// index of the slab [k/n, (k+1)/n) of the edge that holds fraction u
+__device__ __forceinline__ int cell_coord(uint32_t u, int n) {
+    return (int)(((uint64_t)u * (uint64_t)n) >> 32);
+}
+
+// fraction u on a grid of n points: integer index and fractional offset in [0,1)
+__device__ __forceinline__ void grid_coord(uint32_t u, int n, int* gi, float* f) {
+    const uint64_t p = (uint64_t)u * (uint64_t)n;
+    *gi = (int)(p >> 32);
+    *f = (float)(uint32_t)(p & 0xffffffffull) * 2.3283064365386963e-10f;   // 2^-32
+}
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// sum over the 64 lanes of a wavefront (every lane gets the result)
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// deterministic FP64 sum of one value per thread over a block of NT threads;
+// the result is valid in thread 0
+template <int NT>
+__device__ __forceinline__ double block_sum_d(double v, double* smem) {
+    smem[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) smem[threadIdx.x] += smem[threadIdx.x + w];
+        __syncthreads();
+    }
+    return smem[0];
+}
+
+}  // namespace useries

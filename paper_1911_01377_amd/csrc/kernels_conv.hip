@@ -1,0 +1,313 @@
+// Separable periodic convolutions of the far part (Sec. V, eqs. 31-32):
+//   phi = sum_t K_t^z K_t^y K_t^x rho,
+// where K_t^a is the n_a x n_a symmetric circulant of the periodised 1D
+// Gaussian of term t (built on the host, amplitude folded into K_t^x).  Each
+// 1D convolution is a dense matrix product on the matrix cores (MFMA).
+//
+// conv_xy: one block per (z plane, term): the plane rho[z] (n_y x n_x) is
+//   staged in LDS, U = rho[z] K_t^x, then T_t[z] = K_t^y U is written out.
+// conv_z:  one block per 16 grid columns (x, y): phi[:, c] = sum_t K_t^z T_t[:, c],
+//   the sum over terms being part of the contraction.
+//
+// Two arithmetic forms share the structure:
+//   FP32   v_mfma_f32_16x16x4_f32;
+//   BF16X3 v_mfma_f32_16x16x32_bf16 with both operands split as hi + lo
+//          (hi = bf16(v), lo = bf16(v - hi)) and the three products
+//          hi*hi + hi*lo + lo*hi accumulated in FP32.
+//
+// MFMA lane layouts (wave64): for a 16 x 16 output tile, lane l supplies
+// A[l % 16][k] and B[k][l % 16], with k = l / 16 (16x16x4 f32) or
+// k = 8 (l / 16) + 0..7 (16x16x32 bf16); it receives D[4 (l / 16) + r][l % 16],
+// r = 0..3.
+#include "useries_internal.h"
+#include "device_common.h"
+
+namespace useries {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kMaxTiles = kMaxGrid / 16;
+
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 mfma32(u16x8 a, u16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// round-to-nearest-even float -> bf16 bits (finite inputs)
+__device__ __forceinline__ unsigned short bf16_bits(float v) {
+    const uint32_t u = __float_as_uint(v);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_val(unsigned short h) {
+    return __uint_as_float((uint32_t)h << 16);
+}
+__device__ __forceinline__ void split(float v, unsigned short* hi, unsigned short* lo) {
+    *hi = bf16_bits(v);
+    *lo = bf16_bits(v - bf16_val(*hi));
+}
+
+__device__ __forceinline__ f32x4 mfma3(u16x8 ah, u16x8 al, u16x8 bh, u16x8 bl, f32x4 c) {
+    c = mfma32(al, bh, c);
+    c = mfma32(ah, bl, c);
+    return mfma32(ah, bh, c);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ FP32
+
+__global__ void __launch_bounds__(256) k_conv_xy_f32(ConvArgs a, const float* __restrict__ rho,
+                                                     const float* __restrict__ kx,
+                                                     const float* __restrict__ ky,
+                                                     float* __restrict__ tgrid) {
+    extern __shared__ float sp[];
+    const int z = blockIdx.x, t = blockIdx.y;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int li = l & 15, lk = l >> 4;
+    const int g0 = a.g[0], g1 = a.g[1], p0 = a.gp[0], p1 = a.gp[1];
+    const int ld = p0 + 4;
+    const float* src = rho + (size_t)z * g1 * g0;
+    for (int idx = threadIdx.x; idx < p1 * p0; idx += 256) {
+        const int y = idx / p0, x = idx - y * p0;
+        sp[y * ld + x] = (y < g1 && x < g0) ? src[y * g0 + x] : 0.0f;
+    }
+    __syncthreads();
+    const float* Kx = kx + (size_t)t * p0 * p0;
+    const float* Ky = ky + (size_t)t * p1 * p1;
+    const int tx_n = p0 / 16, ty_n = p1 / 16;
+    // U = rho[z] Kx, one 16-row strip per wave, written back in place
+    for (int s = w; s < ty_n; s += 4) {
+        f32x4 acc[kMaxTiles];
+        for (int tx = 0; tx < tx_n; ++tx) acc[tx] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int k0 = 0; k0 < p0; k0 += 4) {
+            const float av = sp[(s * 16 + li) * ld + k0 + lk];
+            const float* kr = Kx + (size_t)(k0 + lk) * p0 + li;
+            for (int tx = 0; tx < tx_n; ++tx) acc[tx] = mfma4(av, kr[tx * 16], acc[tx]);
+        }
+        for (int tx = 0; tx < tx_n; ++tx)
+            for (int r = 0; r < 4; ++r) sp[(s * 16 + 4 * lk + r) * ld + tx * 16 + li] = acc[tx][r];
+    }
+    __syncthreads();
+    // T = Ky U, one 16-column strip per wave
+    float* dst = tgrid + ((size_t)t * a.g[2] + z) * g1 * g0;
+    for (int c = w; c < tx_n; c += 4) {
+        f32x4 acc[kMaxTiles];
+        for (int ty = 0; ty < ty_n; ++ty) acc[ty] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int k0 = 0; k0 < p1; k0 += 4) {
+            const float bv = sp[(k0 + lk) * ld + c * 16 + li];
+            const float* kr = Ky + (size_t)li * p1 + k0 + lk;
+            for (int ty = 0; ty < ty_n; ++ty) acc[ty] = mfma4(kr[ty * 16 * p1], bv, acc[ty]);
+        }
+        const int x = c * 16 + li;
+        for (int ty = 0; ty < ty_n; ++ty)
+            for (int r = 0; r < 4; ++r) {
+                const int y = ty * 16 + 4 * lk + r;
+                if (y < g1 && x < g0) dst[y * g0 + x] = acc[ty][r];
+            }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_conv_z_f32(ConvArgs a, const float* __restrict__ tgrid,
+                                                    const float* __restrict__ kz,
+                                                    float* __restrict__ phi) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int li = l & 15, lk = l >> 4;
+    const int g2 = a.g[2], p2 = a.gp[2];
+    const int ncol = a.g[0] * a.g[1];
+    const int col = blockIdx.x * 16 + li;
+    const int tz_n = p2 / 16;
+    f32x4 acc[kMaxTiles / 4];
+    for (int m = 0; m < kMaxTiles / 4; ++m) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t = 0; t < a.nterms; ++t) {
+        const float* T = tgrid + (size_t)t * g2 * ncol;
+        const float* Kz = kz + (size_t)t * p2 * p2;
+        for (int k0 = 0; k0 < p2; k0 += 4) {
+            const int zp = k0 + lk;
+            const float bv = (zp < g2 && col < ncol) ? T[(size_t)zp * ncol + col] : 0.0f;
+            for (int m = 0, tz = w; tz < tz_n; ++m, tz += 4)
+                acc[m] = mfma4(Kz[(size_t)(tz * 16 + li) * p2 + zp], bv, acc[m]);
+        }
+    }
+    for (int m = 0, tz = w; tz < tz_n; ++m, tz += 4)
+        for (int r = 0; r < 4; ++r) {
+            const int zz = tz * 16 + 4 * lk + r;
+            if (zz < g2 && col < ncol) phi[(size_t)zz * ncol + col] = acc[m][r];
+        }
+}
+
+// ------------------------------------------------------------------ BF16X3
+
+// kx/ky hold, per term, the hi matrix followed by the lo matrix (bf16 bits).
+__global__ void __launch_bounds__(256) k_conv_xy_bf16(ConvArgs a, const float* __restrict__ rho,
+                                                      const unsigned short* __restrict__ kx,
+                                                      const unsigned short* __restrict__ ky,
+                                                      float* __restrict__ tgrid) {
+    extern __shared__ float smem[];
+    const int z = blockIdx.x, t = blockIdx.y;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int li = l & 15, lk = l >> 4;
+    const int g0 = a.g[0], g1 = a.g[1], p0 = a.gp[0], p1 = a.gp[1];
+    const int ldb = (p0 > p1 ? p0 : p1) + 8;            // bf16 elements per LDS row
+    unsigned short* ph = reinterpret_cast<unsigned short*>(smem);   // [p1][ldb] rho hi
+    unsigned short* pl = ph + p1 * ldb;                              // rho lo
+    unsigned short* uh = pl + p1 * ldb;                              // [p0][ldb] U^T hi
+    unsigned short* ul = uh + p0 * ldb;                              // U^T lo
+    const float* src = rho + (size_t)z * g1 * g0;
+    for (int idx = threadIdx.x; idx < p1 * p0; idx += 256) {
+        const int y = idx / p0, x = idx - y * p0;
+        const float v = (y < g1 && x < g0) ? src[y * g0 + x] : 0.0f;
+        unsigned short h, lo;
+        split(v, &h, &lo);
+        ph[y * ldb + x] = h;
+        pl[y * ldb + x] = lo;
+    }
+    __syncthreads();
+    const size_t mx = (size_t)p0 * p0, my = (size_t)p1 * p1;
+    const unsigned short* Kxh = kx + 2 * mx * t;
+    const unsigned short* Kxl = Kxh + mx;
+    const unsigned short* Kyh = ky + 2 * my * t;
+    const unsigned short* Kyl = Kyh + my;
+    const int tx_n = p0 / 16, ty_n = p1 / 16;
+    // U = rho[z] Kx (Kx symmetric: B[k][j] = Kx[j][k], contiguous in k)
+    for (int s = w; s < ty_n; s += 4) {
+        f32x4 acc[kMaxTiles];
+        for (int tx = 0; tx < tx_n; ++tx) acc[tx] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int k0 = 0; k0 < p0; k0 += 32) {
+            const int ao = (s * 16 + li) * ldb + k0 + 8 * lk;
+            const u16x8 ah = *reinterpret_cast<const u16x8*>(ph + ao);
+            const u16x8 al = *reinterpret_cast<const u16x8*>(pl + ao);
+            for (int tx = 0; tx < tx_n; ++tx) {
+                const size_t bo = (size_t)(tx * 16 + li) * p0 + k0 + 8 * lk;
+                const u16x8 bh = *reinterpret_cast<const u16x8*>(Kxh + bo);
+                const u16x8 bl = *reinterpret_cast<const u16x8*>(Kxl + bo);
+                acc[tx] = mfma3(ah, al, bh, bl, acc[tx]);
+            }
+        }
+        // store U transposed, split
+        for (int tx = 0; tx < tx_n; ++tx)
+            for (int r = 0; r < 4; ++r) {
+                unsigned short h, lo;
+                split(acc[tx][r], &h, &lo);
+                const int o = (tx * 16 + li) * ldb + s * 16 + 4 * lk + r;
+                uh[o] = h;
+                ul[o] = lo;
+            }
+    }
+    __syncthreads();
+    // T = Ky U: A[i][k] = Ky[y][y'] (row contiguous), B[k][j] = U^T[x][y']
+    float* dst = tgrid + ((size_t)t * a.g[2] + z) * g1 * g0;
+    for (int c = w; c < tx_n; c += 4) {
+        f32x4 acc[kMaxTiles];
+        for (int ty = 0; ty < ty_n; ++ty) acc[ty] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int k0 = 0; k0 < p1; k0 += 32) {
+            const int bo = (c * 16 + li) * ldb + k0 + 8 * lk;
+            const u16x8 bh = *reinterpret_cast<const u16x8*>(uh + bo);
+            const u16x8 bl = *reinterpret_cast<const u16x8*>(ul + bo);
+            for (int ty = 0; ty < ty_n; ++ty) {
+                const size_t ao = (size_t)(ty * 16 + li) * p1 + k0 + 8 * lk;
+                const u16x8 ah = *reinterpret_cast<const u16x8*>(Kyh + ao);
+                const u16x8 al = *reinterpret_cast<const u16x8*>(Kyl + ao);
+                acc[ty] = mfma3(ah, al, bh, bl, acc[ty]);
+            }
+        }
+        const int x = c * 16 + li;
+        for (int ty = 0; ty < ty_n; ++ty)
+            for (int r = 0; r < 4; ++r) {
+                const int y = ty * 16 + 4 * lk + r;
+                if (y < g1 && x < g0) dst[y * g0 + x] = acc[ty][r];
+            }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_conv_z_bf16(ConvArgs a, const float* __restrict__ tgrid,
+                                                     const unsigned short* __restrict__ kz,
+                                                     float* __restrict__ phi) {
+    // per term: the 16 columns of T_t, transposed to [col][z'] and split
+    __shared__ __attribute__((aligned(16))) unsigned short th[16][kMaxGrid + 8];
+    __shared__ __attribute__((aligned(16))) unsigned short tl[16][kMaxGrid + 8];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int li = l & 15, lk = l >> 4;
+    const int g2 = a.g[2], p2 = a.gp[2];
+    const int ncol = a.g[0] * a.g[1];
+    const int c0 = blockIdx.x * 16;
+    const int tz_n = p2 / 16;
+    const size_t mz = (size_t)p2 * p2;
+    f32x4 acc[kMaxTiles / 4];
+    for (int m = 0; m < kMaxTiles / 4; ++m) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t = 0; t < a.nterms; ++t) {
+        const float* T = tgrid + (size_t)t * g2 * ncol;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < 16 * p2; idx += 256) {
+            const int zp = idx >> 4, c = idx & 15;
+            const float v = (zp < g2 && c0 + c < ncol) ? T[(size_t)zp * ncol + c0 + c] : 0.0f;
+            unsigned short h, lo;
+            split(v, &h, &lo);
+            th[c][zp] = h;
+            tl[c][zp] = lo;
+        }
+        __syncthreads();
+        const unsigned short* Kzh = kz + 2 * mz * t;
+        const unsigned short* Kzl = Kzh + mz;
+        for (int k0 = 0; k0 < p2; k0 += 32) {
+            const u16x8 bh = *reinterpret_cast<const u16x8*>(&th[li][k0 + 8 * lk]);
+            const u16x8 bl = *reinterpret_cast<const u16x8*>(&tl[li][k0 + 8 * lk]);
+            for (int m = 0, tz = w; tz < tz_n; ++m, tz += 4) {
+                const size_t ao = (size_t)(tz * 16 + li) * p2 + k0 + 8 * lk;
+                const u16x8 ah = *reinterpret_cast<const u16x8*>(Kzh + ao);
+                const u16x8 al = *reinterpret_cast<const u16x8*>(Kzl + ao);
+                acc[m] = mfma3(ah, al, bh, bl, acc[m]);
+            }
+        }
+    }
+    const int col = c0 + li;
+    for (int m = 0, tz = w; tz < tz_n; ++m, tz += 4)
+        for (int r = 0; r < 4; ++r) {
+            const int zz = tz * 16 + 4 * lk + r;
+            if (zz < g2 && col < ncol) phi[(size_t)zz * ncol + col] = acc[m][r];
+        }
+}
+
+// ------------------------------------------------------------------ launch
+
+size_t conv_xy_lds_bytes(const ConvArgs& a) {
+    if (a.bf16x3) {
+        const int ldb = (a.gp[0] > a.gp[1] ? a.gp[0] : a.gp[1]) + 8;
+        return (size_t)2 * ldb * (a.gp[0] + a.gp[1]) * sizeof(unsigned short);
+    }
+    return (size_t)a.gp[1] * (a.gp[0] + 4) * sizeof(float);
+}
+
+hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx, const float* ky,
+                          float* tgrid, hipStream_t st) {
+    const size_t lds = conv_xy_lds_bytes(a);
+    if (a.bf16x3)
+        hipLaunchKernelGGL(k_conv_xy_bf16, dim3(a.g[2], a.nterms), dim3(256), lds, st, a, rho,
+                           reinterpret_cast<const unsigned short*>(kx),
+                           reinterpret_cast<const unsigned short*>(ky), tgrid);
+    else
+        hipLaunchKernelGGL(k_conv_xy_f32, dim3(a.g[2], a.nterms), dim3(256), lds, st, a, rho, kx,
+                           ky, tgrid);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz, float* phi,
+                         hipStream_t st) {
+    const int ncol = a.g[0] * a.g[1];
+    const int nb = (ncol + 15) / 16;
+    if (a.bf16x3)
+        hipLaunchKernelGGL(k_conv_z_bf16, dim3(nb), dim3(256), 0, st, a, tgrid,
+                           reinterpret_cast<const unsigned short*>(kz), phi);
+    else
+        hipLaunchKernelGGL(k_conv_z_f32, dim3(nb), dim3(256), 0, st, a, tgrid, kz, phi);
+    return hipGetLastError();
+}
+
+}  // namespace useries

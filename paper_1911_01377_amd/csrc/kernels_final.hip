@@ -1,0 +1,47 @@
+// Total energy in FP64 (one block, fixed summation order):
+//   E = E_near + E_far - E_self + E_bg,
+//   E_self = 1/2 F(0) sum q^2            (u-series analogue of eq. 10's self term),
+//   E_bg   = -Q^2/(2V) int N(r) d^3r     (uniform neutralising background; 0 if Q = 0).
+#include "useries_internal.h"
+#include "device_common.h"
+
+namespace useries {
+
+__global__ void __launch_bounds__(256) k_finalize(FinalArgs a, const double* __restrict__ pp,
+                                                  const double* __restrict__ gp,
+                                                  const double* __restrict__ qstats,
+                                                  double* __restrict__ energy,
+                                                  double* __restrict__ parts) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < a.n_pair_parts; k += 256) s += pp[k];
+    const double en = block_sum_d<256>(s, red);
+    __syncthreads();
+    s = 0.0;
+    for (int k = threadIdx.x; k < a.n_gather_parts; k += 256) s += gp[k];
+    const double ef = block_sum_d<256>(s, red);
+    if (threadIdx.x == 0) {
+        const double Q = qstats[0], q2 = qstats[1];
+        const double es = 0.5 * a.f_inf0 * q2;
+        const double eb = -0.5 * Q * Q * a.near_int_over_v;
+        const double e = en + ef - es + eb;
+        if (energy) energy[0] = e;
+        if (parts) {
+            parts[0] = en;
+            parts[1] = ef;
+            parts[2] = es;
+            parts[3] = eb;
+            parts[4] = e;
+        }
+    }
+}
+
+hipError_t launch_finalize(const FinalArgs& a, const double* pair_parts,
+                           const double* gather_parts, const double* qstats, double* energy,
+                           double* parts, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, pair_parts, gather_parts, qstats,
+                       energy, parts);
+    return hipGetLastError();
+}
+
+}  // namespace useries

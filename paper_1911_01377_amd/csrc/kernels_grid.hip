@@ -1,0 +1,272 @@
+// Spreading and gathering of the far part (Sec. IV.A mesh evaluation, Sec. V
+// grid convolution).  Each charge is smeared on the grid by a normalised,
+// separable Gaussian of width sigma_s (per axis), sampled on a cube stencil
+// of 2P points per axis around it:
+//   rho_g = sum_i q_i prod_a W_a(g_a h_a - x_ia),
+//   W_a(d) = h_a / (sqrt(2 pi) sigma_s,a) exp(-d^2 / (2 sigma_s,a^2)),
+// and potentials and forces are read back with the same weights:
+//   phi_i = sum_g phi_g prod_a W_a,   F_i = -q_i grad_i phi_i.
+// The mean of rho (its k = 0 mode, the net charge) is removed on the grid.
+//
+// spread: one block per 8x8x8 brick of the grid, four wavefronts sharing the
+//   cell rows whose charges can touch the brick.  A wavefront keeps the
+//   charges that do touch it (ballot compaction, so the order is
+//   deterministic), stages their 3 x 8 weights in LDS and accumulates its
+//   partial brick in registers: lane (y, z) owns one grid row of 8 points.
+//   The four partial bricks are summed in a fixed order.  No atomics.
+// gather: one wavefront per charge; lane r owns stencil rows (y, z) and reads
+//   the 2P contiguous x points of each, then the wavefront reduces.
+#include "useries_internal.h"
+#include "device_common.h"
+
+namespace useries {
+
+namespace {
+
+constexpr int kBrick = 8;
+constexpr int kStage = 128;      // staged charges per wavefront pass
+constexpr int kSpreadWaves = 4;  // wavefronts per brick, each taking a share of the cell rows
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+__device__ __forceinline__ int ceildiv(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
+
+// cells along one axis that can hold charges touching grid points
+// [X0, X0 + bn): charges whose stencil start lies in [X0 - P, X0 + bn + P - 1)
+__device__ __forceinline__ void cell_window(int X0, int bn, int P, int g, int nc, int* lo,
+                                            int* cnt) {
+    const int l = floordiv((X0 - P) * nc, g);
+    const int h = ceildiv((X0 + bn + P - 1) * nc, g) - 1;
+    if (h - l + 1 >= nc) {
+        *lo = 0;
+        *cnt = nc;
+    } else {
+        *lo = wrapi(l, nc);
+        *cnt = h - l + 1;
+    }
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(64 * kSpreadWaves) k_spread(GridArgs a,
+                                                              const uint4* __restrict__ sorted,
+                                                              const int* __restrict__ cell_start,
+                                                              const double* __restrict__ qstats,
+                                                              float* __restrict__ rho) {
+    __shared__ float sw[kSpreadWaves][kStage][3 * kBrick];
+    __shared__ float red[kSpreadWaves - 1][kBrick][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ty = lane & 7, tz = lane >> 3;
+    const int nbx = (a.g[0] + kBrick - 1) / kBrick, nby = (a.g[1] + kBrick - 1) / kBrick;
+    const int bid = blockIdx.x;
+    const int X0 = (bid % nbx) * kBrick, Y0 = ((bid / nbx) % nby) * kBrick,
+              Z0 = (bid / (nbx * nby)) * kBrick;
+    const int B0 = min(kBrick, a.g[0] - X0), B1 = min(kBrick, a.g[1] - Y0),
+              B2 = min(kBrick, a.g[2] - Z0);
+    const int P = a.P;
+    int lo[3], cnt[3];
+    cell_window(X0, B0, P, a.g[0], a.nc[0], &lo[0], &cnt[0]);
+    cell_window(Y0, B1, P, a.g[1], a.nc[1], &lo[1], &cnt[1]);
+    cell_window(Z0, B2, P, a.g[2], a.nc[2], &lo[2], &cnt[2]);
+    const int X0s[3] = {X0, Y0, Z0};
+    const int Bs[3] = {B0, B1, B2};
+    float (*S)[3 * kBrick] = sw[w];
+
+    float acc[kBrick];
+#pragma unroll
+    for (int b = 0; b < kBrick; ++b) acc[b] = 0.0f;
+    int staged = 0;
+
+    auto accumulate = [&](int count) {
+        wave_sync();
+        for (int s = 0; s < count; ++s) {
+            const float c = S[s][kBrick + ty] * S[s][2 * kBrick + tz];
+#pragma unroll
+            for (int b = 0; b < kBrick; ++b) acc[b] = fmaf(c, S[s][b], acc[b]);
+        }
+        wave_sync();
+    };
+
+    auto visit = [&](int j0, int j1) {
+        for (int base = j0; base < j1; base += 64) {
+            const int j = base + lane;
+            bool touch = false;
+            int gi[3];
+            float f[3];
+            float qj = 0.0f;
+            if (j < j1) {
+                const uint4 c = sorted[j];
+                grid_coord(c.x, a.g[0], &gi[0], &f[0]);
+                grid_coord(c.y, a.g[1], &gi[1], &f[1]);
+                grid_coord(c.z, a.g[2], &gi[2], &f[2]);
+                qj = __uint_as_float(c.w);
+                touch = true;
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax)
+                    touch = touch &&
+                            wrapi(gi[ax] - (X0s[ax] - P), a.g[ax]) <= Bs[ax] + 2 * P - 2;
+            }
+            const uint64_t m = __ballot(touch);
+            if (touch) {
+                const int slot = staged + __popcll(m & ((1ull << lane) - 1ull));
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int k0 = wrapi(X0s[ax] - gi[ax] + P - 1, a.g[ax]);
+#pragma unroll
+                    for (int b = 0; b < kBrick; ++b) {
+                        float wv = 0.0f;
+                        int k = k0 + b;
+                        if (k >= a.g[ax]) k -= a.g[ax];
+                        if (b < Bs[ax] && k < 2 * P) {
+                            const float t = (float)(k - P + 1) - f[ax];
+                            wv = a.cw[ax] * __expf(-t * t * a.hs[ax]);
+                        }
+                        if (ax == 1) wv *= qj;
+                        S[slot][ax * kBrick + b] = wv;
+                    }
+                }
+            }
+            staged += __popcll(m);
+            if (staged > 64) {
+                accumulate(staged);
+                staged = 0;
+            }
+        }
+    };
+
+    // the (z, y) cell rows of the window are dealt round-robin to the wavefronts
+    const int nrows = cnt[1] * cnt[2];
+    for (int r = w; r < nrows; r += kSpreadWaves) {
+        const int zz = wrapi(lo[2] + r / cnt[1], a.nc[2]);
+        const int yy = wrapi(lo[1] + r % cnt[1], a.nc[1]);
+        const int row = (zz * a.nc[1] + yy) * a.nc[0];
+        if (cnt[0] == a.nc[0]) {
+            visit(cell_start[row], cell_start[row + a.nc[0]]);
+        } else if (lo[0] + cnt[0] <= a.nc[0]) {
+            visit(cell_start[row + lo[0]], cell_start[row + lo[0] + cnt[0]]);
+        } else {
+            visit(cell_start[row + lo[0]], cell_start[row + a.nc[0]]);
+            visit(cell_start[row], cell_start[row + lo[0] + cnt[0] - a.nc[0]]);
+        }
+    }
+    if (staged > 0) accumulate(staged);
+
+    // fixed-order sum of the wavefronts' partial bricks
+    if (w > 0)
+#pragma unroll
+        for (int b = 0; b < kBrick; ++b) red[w - 1][b][lane] = acc[b];
+    __syncthreads();
+    if (w == 0) {
+        for (int v = 0; v < kSpreadWaves - 1; ++v)
+#pragma unroll
+            for (int b = 0; b < kBrick; ++b) acc[b] += red[v][b][lane];
+        const float mean = (float)(qstats[0] * a.inv_ngrid);
+        if (ty < B1 && tz < B2) {
+            float* out = rho + ((size_t)(Z0 + tz) * a.g[1] + (Y0 + ty)) * a.g[0] + X0;
+#pragma unroll
+            for (int b = 0; b < kBrick; ++b)
+                if (b < B0) out[b] = acc[b] - mean;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_gather(GridArgs a, const uint4* __restrict__ sorted,
+                                                const int* __restrict__ perm,
+                                                const float* __restrict__ phi,
+                                                const float4* __restrict__ fnear,
+                                                float* __restrict__ forces,
+                                                double* __restrict__ epart) {
+    __shared__ float sw[4][6][16];
+    __shared__ double se[4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + wave;
+    const int P = a.P, P2 = 2 * P;
+    int gi[3] = {0, 0, 0};
+    float f[3] = {0.0f, 0.0f, 0.0f};
+    float qi = 0.0f;
+    if (i < a.n) {
+        const uint4 c = sorted[i];
+        grid_coord(c.x, a.g[0], &gi[0], &f[0]);
+        grid_coord(c.y, a.g[1], &gi[1], &f[1]);
+        grid_coord(c.z, a.g[2], &gi[2], &f[2]);
+        qi = __uint_as_float(c.w);
+        if (lane < 48) {
+            const int ax = lane >> 4, k = lane & 15;
+            if (k < P2) {
+                const float t = (float)(k - P + 1) - f[ax];
+                const float w = a.cw[ax] * __expf(-t * t * a.hs[ax]);
+                sw[wave][ax][k] = w;
+                sw[wave][3 + ax][k] = w * t * a.dws[ax];
+            }
+        }
+    }
+    __syncthreads();
+    double e_wave = 0.0;
+    if (i < a.n) {
+        float pe = 0.0f, px = 0.0f, py = 0.0f, pz = 0.0f;
+        const int gx0 = gi[0] - P + 1;
+        for (int r = lane; r < P2 * P2; r += 64) {
+            const int ky = r % P2, kz = r / P2;
+            int gy = gi[1] - P + 1 + ky, gz = gi[2] - P + 1 + kz;
+            gy = gy < 0 ? gy + a.g[1] : (gy >= a.g[1] ? gy - a.g[1] : gy);
+            gz = gz < 0 ? gz + a.g[2] : (gz >= a.g[2] ? gz - a.g[2] : gz);
+            const float* rowp = phi + ((size_t)gz * a.g[1] + gy) * a.g[0];
+            float sx = 0.0f, dsx = 0.0f;
+            for (int k = 0; k < P2; ++k) {
+                int gx = gx0 + k;
+                gx = gx < 0 ? gx + a.g[0] : (gx >= a.g[0] ? gx - a.g[0] : gx);
+                const float v = rowp[gx];
+                sx = fmaf(sw[wave][0][k], v, sx);
+                dsx = fmaf(sw[wave][3][k], v, dsx);
+            }
+            const float wy = sw[wave][1][ky], wz = sw[wave][2][kz];
+            const float wyz = wy * wz;
+            pe = fmaf(wyz, sx, pe);
+            px = fmaf(wyz, dsx, px);
+            py = fmaf(sw[wave][4][ky] * wz, sx, py);
+            pz = fmaf(wy * sw[wave][5][kz], sx, pz);
+        }
+        pe = wave_sum(pe);
+        px = wave_sum(px);
+        py = wave_sum(py);
+        pz = wave_sum(pz);
+        if (lane == 0) {
+            const float4 fn = fnear[i];
+            const int o = perm[i];
+            forces[3 * o + 0] = fn.x - qi * px;
+            forces[3 * o + 1] = fn.y - qi * py;
+            forces[3 * o + 2] = fn.z - qi * pz;
+            e_wave = 0.5 * (double)qi * (double)pe;
+        }
+    }
+    if (lane == 0) se[wave] = e_wave;
+    __syncthreads();
+    if (threadIdx.x == 0) epart[blockIdx.x] = ((se[0] + se[1]) + se[2]) + se[3];
+}
+
+hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* cell_start,
+                         const double* qstats, float* rho, hipStream_t st) {
+    const int nb = ((a.g[0] + kBrick - 1) / kBrick) * ((a.g[1] + kBrick - 1) / kBrick) *
+                   ((a.g[2] + kBrick - 1) / kBrick);
+    hipLaunchKernelGGL(k_spread, dim3(nb), dim3(64 * kSpreadWaves), 0, st, a, sorted, cell_start,
+                       qstats, rho);
+    return hipGetLastError();
+}
+
+int gather_blocks(int n) { return (n + 3) / 4; }
+
+hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm,
+                         const float* phi, const float4* fnear, float* forces, double* epart,
+                         int nblocks, hipStream_t st) {
+    if (nblocks > 0)
+        hipLaunchKernelGGL(k_gather, dim3(nblocks), dim3(256), 0, st, a, sorted, perm, phi, fnear,
+                           forces, epart);
+    return hipGetLastError();
+}
+
+}  // namespace useries

@@ -1,0 +1,134 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded float32 inputs.
+
+Tolerances (the contract of the library):
+  plain FP32 path:  relative energy error <= 1e-6, relative RMS force error <= 1e-5;
+  BF16X3 path:      relative RMS force error <= 1e-3 (energy <= 1e-4).
+The GPU evaluates the far part on a grid, so its error against the oracle's
+exact image sums also contains the spreading discretisation (about 2e-6 in
+force at the default 10^3 stencil with sigma_s = 0.9 h, 2e-5 at the BF16X3
+default 8^3 with 0.83 h).
+"""
+import numpy as np
+import pytest
+
+from gpu_util import compare, gpu_eval, log, oracle_eval, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1911_01377_amd import USERIES_BF16X3, synth  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_random_cube_512_plain():
+    xyz, q, box = synth.random_cube(512, 24.0, seed=1377)
+    compare("random512/plain", xyz, q, box, 9.0, (32, 32, 32), 1e-6, 1e-5)
+
+
+def test_random_cube_512_bf16x3():
+    xyz, q, box = synth.random_cube(512, 24.0, seed=1377)
+    compare("random512/bf16x3", xyz, q, box, 9.0, (32, 32, 32), 1e-4, 1e-3,
+            precision=USERIES_BF16X3)
+
+
+@pytest.mark.parametrize("n_mol", [300, 517])
+def test_small_water_ragged_grid(n_mol):
+    L = (n_mol / synth.WATER_DENSITY) ** (1 / 3)
+    xyz, q, box = synth.water_box(n_mol=n_mol, L=L, seed=50 + n_mol)
+    g = int(np.ceil(L))
+    compare("water%d/plain" % n_mol, xyz, q, box, min(9.0, 0.45 * L), (g, g, g), 1e-6, 1e-5)
+
+
+def test_small_water_bf16x3():
+    n_mol = 700
+    L = (n_mol / synth.WATER_DENSITY) ** (1 / 3)
+    xyz, q, box = synth.water_box(n_mol=n_mol, L=L, seed=3)
+    g = int(np.ceil(L))
+    compare("water700/bf16x3", xyz, q, box, 9.0, (g, g, g), 1e-4, 1e-3,
+            precision=USERIES_BF16X3)
+
+
+def test_orthorhombic_box_and_grid():
+    rng = np.random.default_rng(4)
+    box = (20.0, 23.5, 27.0)
+    n = 700
+    xyz = (rng.uniform(0, 1, (n, 3)) * box).astype(np.float32)
+    q = synth._quantise(rng.uniform(-1, 1, n))
+    q[-1] = -np.sum(q[:-1])
+    compare("ortho700/plain", xyz, q.astype(np.float32), box, 8.0, (20, 24, 30), 1e-6, 1e-5)
+
+
+def test_non_neutral_and_single_charge():
+    """A net charge Q couples to the near-uniform (k ~ 0) part of the FP32
+    rounding of the widest convolution terms: the energy error grows like
+    Q x (that offset), so non-neutral input gets 5e-6 instead of 1e-6."""
+    rng = np.random.default_rng(8)
+    L = 18.0
+    xyz = rng.uniform(0, L, (200, 3)).astype(np.float32)
+    q = (rng.uniform(-1, 1, 200) + 0.05).astype(np.float32)
+    compare("nonneutral200/plain", xyz, q, (L, L, L), 8.0, (24, 24, 24), 5e-6, 1e-5)
+    compare("single/plain", np.array([[1.0, 2.0, 3.0]], np.float32), np.array([1.0], np.float32),
+            (L, L, L), 8.0, (24, 24, 24), 5e-6, 1e-5)
+
+
+def test_empty_input():
+    log("case empty")
+    parts, f, _ = gpu_eval(np.zeros((0, 3), np.float32), np.zeros(0, np.float32),
+                           (20.0, 20.0, 20.0), 8.0, (20, 20, 20))
+    assert np.all(parts == 0.0) and f.shape == (0, 3)
+
+
+def test_images_and_permutation():
+    xyz, q, box = synth.random_cube(300, 21.0, seed=12)
+    # positions on a 2^-12 A lattice, so that adding whole box lengths is exact in float32
+    xyz = (np.round(xyz.astype(np.float64) * 4096) / 4096).astype(np.float32)
+    log("case images/permutation")
+    p0, f0, _ = gpu_eval(xyz, q, box, 9.0, (24, 24, 24))
+    shift = np.array([21.0, -42.0, 63.0], np.float32)
+    p1, f1, _ = gpu_eval(xyz + shift, q, box, 9.0, (24, 24, 24))
+    assert abs(p1[4] - p0[4]) <= 1e-9 * abs(p0[4])
+    assert np.max(np.abs(f1 - f0)) <= 1e-6 * np.max(np.abs(f0))
+    perm = np.random.default_rng(1).permutation(len(q))
+    p2, f2, _ = gpu_eval(xyz[perm], q[perm], box, 9.0, (24, 24, 24))
+    assert abs(p2[4] - p0[4]) <= 1e-7 * abs(p0[4])
+    assert rel_rms(f2, f0[perm]) <= 1e-6
+
+
+def test_repeat_is_bitwise_identical():
+    import torch as T
+    from paper_1911_01377_amd import Plan
+    log("case determinism")
+    xyz, q, box = synth.water_box(n_mol=800, L=(800 / synth.WATER_DENSITY) ** (1 / 3), seed=9)
+    plan = Plan(box, 9.0, (29, 29, 29))
+    x = T.from_numpy(xyz).cuda()
+    qq = T.from_numpy(q).cuda()
+    e1, f1, _ = plan.eval(x, qq)
+    e1, f1 = e1.clone(), f1.clone()
+    for _ in range(3):
+        e2, f2, _ = plan.eval(x, qq)
+    T.cuda.synchronize()
+    assert T.equal(e1, e2) and T.equal(f1, f2)
+    plan.close()
+
+
+def test_near_and_far_parts_separately():
+    """The near energy matches the oracle's pair sum; the far energy its image sums."""
+    xyz, q, box = synth.random_cube(400, 22.0, seed=31)
+    log("case parts")
+    gp, gf, info = gpu_eval(xyz, q, box, 9.0, (30, 30, 30))
+    op, of = oracle_eval(xyz, q, box, info, 9.0)
+    # the total of random charges is a small difference of much larger parts,
+    # so the parts are measured against the sum of their magnitudes
+    scale = abs(op["near"]) + abs(op["far"]) + abs(op["total"])
+    log("   near %.3e far %.3e (x scale)" % (abs(gp[0] - op["near"]) / scale,
+                                            abs(gp[1] - op["far"]) / scale))
+    assert abs(gp[0] - op["near"]) <= 1e-6 * scale
+    assert abs(gp[1] - op["far"]) <= 1e-6 * scale
+    assert abs(gp[2] - op["self"]) <= 1e-12 * op["self"]
