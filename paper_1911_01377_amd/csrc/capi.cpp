@@ -121,7 +121,8 @@ struct useries_plan_s {
         const int64_t c = std::max<int64_t>(n, 256);
         hipError_t e;
         if ((e = dalloc(&coord, c)) || (e = dalloc(&sorted, c)) || (e = dalloc(&cell_of, c)) ||
-            (e = dalloc(&perm, c)) || (e = dalloc(&slots, c)) || (e = dalloc(&fnear, c)) ||
+            (e = dalloc(&perm, c)) || (e = dalloc(&slots, c)) ||
+            (e = dalloc(&fnear, (size_t)kPairSlices * c)) ||
             (e = dalloc(&qpart, 2 * (size_t)((c + 255) / 256))) ||
             (e = dalloc(&gather_parts, (size_t)gather_blocks((int)c)))) {
             free_atoms();
@@ -338,6 +339,7 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
         p->bin.nc[a] = pa.nc[a] = p->gridargs.nc[a] = nc[a];
         p->bin.inv_box[a] = 1.0 / box[a];
         pa.scale[a] = (float)(box[a] / 4294967296.0);
+        pa.cw[a] = (float)(box[a] / nc[a]);
     }
 
     // far part
@@ -404,7 +406,7 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
     hipError_t e;
     if ((e = dalloc(&p->cell_count, p->ncell)) || (e = dalloc(&p->cell_fill, p->ncell)) ||
         (e = dalloc(&p->cell_start, p->ncell + 1)) || (e = dalloc(&p->qstats, 2)) ||
-        (e = dalloc(&p->pair_parts, p->ncell)) ||
+        (e = dalloc(&p->pair_parts, (size_t)kPairSlices * p->ncell)) ||
         (e = dalloc(&p->parts_tmp, 5)) || (e = dalloc(&p->rho, ng)) ||
         (e = dalloc(&p->tgrid, ng * p->nterms)) || (e = dalloc(&p->phi, ng))) {
         delete p;
@@ -488,7 +490,7 @@ static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float*
     USERIES_STEP(launch_spread(p->gridargs, p->sorted, p->cell_start, p->qstats, p->rho, st));
     USERIES_STEP(launch_conv_xy(p->conv, p->rho, p->kx, p->ky, p->tgrid, st));
     USERIES_STEP(launch_conv_z(p->conv, p->tgrid, p->kz, p->phi, st));
-    USERIES_STEP(launch_gather(p->gridargs, p->sorted, p->perm, p->phi, p->fnear, forces,
+    USERIES_STEP(launch_gather(p->gridargs, p->sorted, p->perm, p->phi, p->fnear, ni, forces,
                                p->gather_parts, ngb, st));
     USERIES_STEP(launch_finalize(p->fin, p->pair_parts, p->gather_parts, p->qstats, energy, parts, st));
 #undef USERIES_STEP

@@ -33,6 +33,14 @@ __device__ __forceinline__ int wrapi(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
+// Order LDS traffic between the lanes of one wavefront (the LDS of a
+// wavefront-private region needs no block barrier).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // sum over the 64 lanes of a wavefront (every lane gets the result)
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll

@@ -49,42 +49,57 @@ __global__ void __launch_bounds__(256) k_encode(BinArgs a, const float* __restri
 }
 
 // One block of 1024 threads: exclusive scan of the cell counts (each thread
-// owns a contiguous chunk), zero the fill counters, and reduce the charge
-// partials in a fixed order (sum q, sum q^2).
+// owns a contiguous chunk; wavefront scans by shuffles, then a scan of the 16
+// wavefront totals), zero the fill counters, and reduce the charge partials
+// in a fixed order (sum q, sum q^2).
 __global__ void __launch_bounds__(1024) k_scan(int ncell, const int* __restrict__ count,
                                                int* __restrict__ start, int* __restrict__ fill,
                                                const double* __restrict__ qpart, int nqpart,
                                                double* __restrict__ qstats) {
-    __shared__ int part[1024];
-    const int t = threadIdx.x;
+    __shared__ int wsum[16];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int chunk = (ncell + 1023) / 1024;
     const int lo = min(t * chunk, ncell), hi = min(lo + chunk, ncell);
     int s = 0;
     for (int c = lo; c < hi; ++c) s += count[c];
-    part[t] = s;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over the 1024 chunk sums
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    int v = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
     }
-    int run = part[t] - s;   // exclusive prefix of this chunk
+    if (lane == 63) wsum[wv] = v;
+    __syncthreads();
+    if (wv == 0) {
+        int x = lane < 16 ? wsum[lane] : 0;
+        const int own = x;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const int u = __shfl_up(x, off, 64);
+            if (lane >= off) x += u;
+        }
+        if (lane < 16) wsum[lane] = x - own;
+    }
+    __syncthreads();
+    int run = wsum[wv] + v - s;   // exclusive prefix of this chunk
     for (int c = lo; c < hi; ++c) {
         start[c] = run;
         run += count[c];
         fill[c] = 0;
     }
-    if (t == 1023) start[ncell] = part[1023];
-    if (t == 0) {
+    if (t == 1023) start[ncell] = run;
+    if (wv == 1) {
         double a = 0.0, b = 0.0;
-        for (int k = 0; k < nqpart; ++k) {
+        for (int k = lane; k < nqpart; k += 64) {
             a += qpart[2 * k];
             b += qpart[2 * k + 1];
         }
-        qstats[0] = a;
-        qstats[1] = b;
+        a = wave_sum_d(a);
+        b = wave_sum_d(b);
+        if (lane == 0) {
+            qstats[0] = a;
+            qstats[1] = b;
+        }
     }
 }
 

@@ -7,19 +7,19 @@
 
 namespace useries {
 
-__global__ void __launch_bounds__(256) k_finalize(FinalArgs a, const double* __restrict__ pp,
+__global__ void __launch_bounds__(1024) k_finalize(FinalArgs a, const double* __restrict__ pp,
                                                   const double* __restrict__ gp,
                                                   const double* __restrict__ qstats,
                                                   double* __restrict__ energy,
                                                   double* __restrict__ parts) {
-    __shared__ double red[256];
+    __shared__ double red[1024];
     double s = 0.0;
-    for (int k = threadIdx.x; k < a.n_pair_parts; k += 256) s += pp[k];
-    const double en = block_sum_d<256>(s, red);
+    for (int k = threadIdx.x; k < a.n_pair_parts; k += 1024) s += pp[k];
+    const double en = block_sum_d<1024>(s, red);
     __syncthreads();
     s = 0.0;
-    for (int k = threadIdx.x; k < a.n_gather_parts; k += 256) s += gp[k];
-    const double ef = block_sum_d<256>(s, red);
+    for (int k = threadIdx.x; k < a.n_gather_parts; k += 1024) s += gp[k];
+    const double ef = block_sum_d<1024>(s, red);
     if (threadIdx.x == 0) {
         const double Q = qstats[0], q2 = qstats[1];
         const double es = 0.5 * a.f_inf0 * q2;
@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(256) k_finalize(FinalArgs a, const double* __r
 hipError_t launch_finalize(const FinalArgs& a, const double* pair_parts,
                            const double* gather_parts, const double* qstats, double* energy,
                            double* parts, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a, pair_parts, gather_parts, qstats,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, a, pair_parts, gather_parts, qstats,
                        energy, parts);
     return hipGetLastError();
 }

@@ -14,8 +14,11 @@
 //   deterministic), stages their 3 x 8 weights in LDS and accumulates its
 //   partial brick in registers: lane (y, z) owns one grid row of 8 points.
 //   The four partial bricks are summed in a fixed order.  No atomics.
-// gather: one wavefront per charge; lane r owns stencil rows (y, z) and reads
-//   the 2P contiguous x points of each, then the wavefront reduces.
+// gather: one wavefront per charge at a time (charges dealt round-robin to a
+//   fixed set of wavefronts); lane r owns stencil rows (y, z) and reads the 2P
+//   contiguous x points of each, then the wavefront reduces.
+#include <algorithm>
+
 #include "useries_internal.h"
 #include "device_common.h"
 
@@ -26,12 +29,6 @@ namespace {
 constexpr int kBrick = 8;
 constexpr int kStage = 128;      // staged charges per wavefront pass
 constexpr int kSpreadWaves = 4;  // wavefronts per brick, each taking a share of the cell rows
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 __device__ __forceinline__ int ceildiv(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
@@ -179,22 +176,24 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs a, const uint4* __restr
                                                 const int* __restrict__ perm,
                                                 const float* __restrict__ phi,
                                                 const float4* __restrict__ fnear,
+                                                int slice_stride,
                                                 float* __restrict__ forces,
                                                 double* __restrict__ epart) {
     __shared__ float sw[4][6][16];
     __shared__ double se[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + wave;
     const int P = a.P, P2 = 2 * P;
-    int gi[3] = {0, 0, 0};
-    float f[3] = {0.0f, 0.0f, 0.0f};
-    float qi = 0.0f;
-    if (i < a.n) {
+    const int nw = gridDim.x * 4;
+    double e_wave = 0.0;
+    // charges are dealt to the wavefronts round-robin (fixed for a given n)
+    for (int i = blockIdx.x * 4 + wave; i < a.n; i += nw) {
+        int gi[3];
+        float f[3];
         const uint4 c = sorted[i];
         grid_coord(c.x, a.g[0], &gi[0], &f[0]);
         grid_coord(c.y, a.g[1], &gi[1], &f[1]);
         grid_coord(c.z, a.g[2], &gi[2], &f[2]);
-        qi = __uint_as_float(c.w);
+        const float qi = __uint_as_float(c.w);
         if (lane < 48) {
             const int ax = lane >> 4, k = lane & 15;
             if (k < P2) {
@@ -204,10 +203,7 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs a, const uint4* __restr
                 sw[wave][3 + ax][k] = w * t * a.dws[ax];
             }
         }
-    }
-    __syncthreads();
-    double e_wave = 0.0;
-    if (i < a.n) {
+        wave_sync();
         float pe = 0.0f, px = 0.0f, py = 0.0f, pz = 0.0f;
         const int gx0 = gi[0] - P + 1;
         for (int r = lane; r < P2 * P2; r += 64) {
@@ -236,13 +232,21 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs a, const uint4* __restr
         py = wave_sum(py);
         pz = wave_sum(pz);
         if (lane == 0) {
-            const float4 fn = fnear[i];
+            // near force: the pair kernel's partial slices, summed in a fixed order
+            float4 fn = fnear[i];
+            for (int sl = 1; sl < kPairSlices; ++sl) {
+                const float4 v = fnear[(size_t)sl * slice_stride + i];
+                fn.x += v.x;
+                fn.y += v.y;
+                fn.z += v.z;
+            }
             const int o = perm[i];
             forces[3 * o + 0] = fn.x - qi * px;
             forces[3 * o + 1] = fn.y - qi * py;
             forces[3 * o + 2] = fn.z - qi * pz;
-            e_wave = 0.5 * (double)qi * (double)pe;
+            e_wave += 0.5 * (double)qi * (double)pe;
         }
+        wave_sync();
     }
     if (lane == 0) se[wave] = e_wave;
     __syncthreads();
@@ -258,14 +262,14 @@ hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* cell
     return hipGetLastError();
 }
 
-int gather_blocks(int n) { return (n + 3) / 4; }
+int gather_blocks(int n) { return std::min((n + 3) / 4, 8192); }
 
 hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm,
-                         const float* phi, const float4* fnear, float* forces, double* epart,
-                         int nblocks, hipStream_t st) {
+                         const float* phi, const float4* fnear, int slice_stride, float* forces,
+                         double* epart, int nblocks, hipStream_t st) {
     if (nblocks > 0)
         hipLaunchKernelGGL(k_gather, dim3(nblocks), dim3(256), 0, st, a, sorted, perm, phi, fnear,
-                           forces, epart);
+                           slice_stride, forces, epart);
     return hipGetLastError();
 }
 

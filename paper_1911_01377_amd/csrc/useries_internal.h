@@ -16,6 +16,7 @@ constexpr int kMaxGrid = 128;      // grid points per axis
 constexpr int kMaxPolyDeg = 14;    // near polynomial degree
 constexpr int kMaxStencilHalf = 8; // P
 constexpr int kMaxPairGroup = 12;  // cells per pair-kernel block
+constexpr int kPairSlices = 5;     // partial near-force slices per charge
 
 // ------------------------------------------------------------ host math
 // FP64 parameter math of the u-series (plan_math.cpp).
@@ -55,6 +56,7 @@ struct PairArgs {
     int n;
     int nc[3];
     float scale[3];       // L / 2^32: fixed-point units to A
+    float cw[3];          // cell widths L / nc
     float rc2;            // r_c^2
     float inv_rc2;        // 1 / r_c^2
     int deg;              // polynomial degree
@@ -110,8 +112,8 @@ hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx,
 hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz, float* phi,
                          hipStream_t st);
 hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm,
-                         const float* phi, const float4* fnear, float* forces, double* epart,
-                         int nblocks, hipStream_t st);
+                         const float* phi, const float4* fnear, int slice_stride, float* forces,
+                         double* epart, int nblocks, hipStream_t st);
 int gather_blocks(int n);
 hipError_t launch_finalize(const FinalArgs& a, const double* pair_parts,
                            const double* gather_parts, const double* qstats, double* energy,
