@@ -157,8 +157,10 @@ int useries_eval_parts(useries_plan_t plan, int64_t n, const float *xyz, const f
  *   b, sigma, r0 (= r_c / sigma), w0, s0, n_terms, eq33 (the eq. 33 bound at
  *   n_terms with L = max edge), f_inf0 (F(0) of the infinite series, the
  *   self-term coefficient), c1_slope (N'(r_c) of the near part; 0 for C1),
- *   sigma_s (spreading width per axis of x, A), stencil_half, ncell[3]
- *   (cell list), poly_maxerr (max relative error of the near polynomial on
+ *   sigma_s (spreading width along x, A), stencil_half, ncell[3] (the x-y
+ *   column grid used by the latest evaluation, chosen per evaluation from
+ *   the number of charges; third entry 1; zeros before the first
+ *   evaluation), poly_maxerr (max relative error of the near polynomial on
  *   [0, r_c], measured in FP64 on the host).
  */
 int useries_plan_info(useries_plan_t plan, double *b, double *sigma, double *r0, double *w0,

@@ -1,6 +1,6 @@
 // C ABI of the library: plan construction (host FP64 math + one upload),
 // device workspace, and the evaluation sequence
-//   encode -> scan -> scatter -> rank -> pair (near part)
+//   encode -> scan -> scatter -> colsort -> pair (near part)
 //   -> spread -> conv_xy -> conv_z -> gather (far part, + near forces)
 //   -> finalize (FP64 energy).
 #include <hip/hip_runtime.h>
@@ -34,8 +34,8 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(USERIES_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-constexpr const char* kKernelNames[] = {"encode", "scan",   "scatter", "rank",   "pair",
-                                        "spread", "conv_xy", "conv_z", "gather", "finalize"};
+constexpr const char* kKernelNames[] = {"encode", "scan",   "scatter", "colsort", "pair",
+                                        "spread", "conv_xy", "conv_z", "gather",  "finalize"};
 constexpr int kNumKernels = sizeof(kKernelNames) / sizeof(kKernelNames[0]);
 
 uint16_t host_bf16(float v) {
@@ -69,7 +69,9 @@ struct useries_plan_s {
     double eq33 = 0, f_inf0 = 0, c1_slope = 0, poly_maxerr = 0, sigma_s[3] = {0, 0, 0};
     int P = 5;
     int grid[3] = {0, 0, 0};
-    int ncell = 0;
+    int ncmax[2] = {1, 1};   // x-y column grid bounds (the grid itself is chosen per evaluation)
+    int ncol_max = 1;
+    int nc_used[2] = {0, 0};
     // kernel arguments
     BinArgs bin{};
     PairArgs pair{};
@@ -79,14 +81,18 @@ struct useries_plan_s {
     // device constants
     float *kx = nullptr, *ky = nullptr, *kz = nullptr;
     // fixed workspace
-    int *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr;
+    int *col_count = nullptr, *col_start = nullptr, *col_fill = nullptr, *clus_start = nullptr;
     double *qstats = nullptr, *parts_tmp = nullptr;
     float *rho = nullptr, *tgrid = nullptr, *phi = nullptr;
     // per-atom workspace
     int64_t cap = 0;
     bool fixed_cap = false;
     uint4 *coord = nullptr, *sorted = nullptr;
-    int *cell_of = nullptr, *perm = nullptr, *slots = nullptr;
+    int *col_of = nullptr, *perm = nullptr, *slots = nullptr;
+    int2* cl_info = nullptr;
+    int* cl_col = nullptr;
+    uint2* cl_z = nullptr;
+    int64_t clmax = 0;
     float4* fnear = nullptr;
     double *qpart = nullptr, *pair_parts = nullptr, *gather_parts = nullptr;
     // timing
@@ -103,14 +109,21 @@ struct useries_plan_s {
     void free_atoms() {
         hipFree(coord);
         hipFree(sorted);
-        hipFree(cell_of);
+        hipFree(col_of);
+        hipFree(cl_info);
+        hipFree(cl_col);
+        hipFree(cl_z);
+        hipFree(pair_parts);
         hipFree(perm);
         hipFree(slots);
         hipFree(fnear);
         hipFree(qpart);
         hipFree(gather_parts);
         coord = sorted = nullptr;
-        cell_of = perm = slots = nullptr;
+        col_of = perm = slots = cl_col = nullptr;
+        cl_info = nullptr;
+        cl_z = nullptr;
+        pair_parts = nullptr;
         fnear = nullptr;
         qpart = gather_parts = nullptr;
         cap = 0;
@@ -120,8 +133,11 @@ struct useries_plan_s {
         free_atoms();
         const int64_t c = std::max<int64_t>(n, 256);
         hipError_t e;
-        if ((e = dalloc(&coord, c)) || (e = dalloc(&sorted, c)) || (e = dalloc(&cell_of, c)) ||
-            (e = dalloc(&perm, c)) || (e = dalloc(&slots, c)) ||
+        clmax = c / 8 + 1 + ncol_max;   // clusters: sum over columns of ceil(count / 8)
+        if ((e = dalloc(&coord, c)) || (e = dalloc(&sorted, c)) || (e = dalloc(&col_of, c)) ||
+            (e = dalloc(&perm, c)) || (e = dalloc(&slots, c)) || (e = dalloc(&cl_info, clmax)) ||
+            (e = dalloc(&cl_col, clmax)) || (e = dalloc(&cl_z, clmax)) ||
+            (e = dalloc(&pair_parts, clmax)) ||
             (e = dalloc(&fnear, (size_t)kPairSlices * c)) ||
             (e = dalloc(&qpart, 2 * (size_t)((c + 255) / 256))) ||
             (e = dalloc(&gather_parts, (size_t)gather_blocks((int)c)))) {
@@ -163,12 +179,12 @@ struct useries_plan_s {
         hipFree(kx);
         hipFree(ky);
         hipFree(kz);
-        hipFree(cell_count);
-        hipFree(cell_start);
-        hipFree(cell_fill);
+        hipFree(col_count);
+        hipFree(col_start);
+        hipFree(col_fill);
+        hipFree(clus_start);
         hipFree(qstats);
         hipFree(parts_tmp);
-        hipFree(pair_parts);
         hipFree(rho);
         hipFree(tgrid);
         hipFree(phi);
@@ -325,22 +341,24 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
     pa.rc2 = (float)(r_c * r_c);
     pa.inv_rc2 = (float)(1.0 / (r_c * r_c));
 
-    // cell list: cells at least r_c/2 wide, at most 4M cells
-    int nc[3];
-    for (int a = 0; a < 3; ++a) nc[a] = std::max(1, (int)std::floor(box[a] / (0.5 * r_c)));
-    while ((int64_t)nc[0] * nc[1] * nc[2] > (1 << 22)) {
-        int am = 0;
-        for (int a = 1; a < 3; ++a)
-            if (nc[a] > nc[am]) am = a;
-        nc[am] = std::max(4, nc[am] * 3 / 4);
+    // x-y columns: at least r_c / 4 wide (so the pair stencil stays within
+    // 9 x 9 columns), and wide enough that a spreading brick touches at most
+    // 16 columns per axis; the grid used is chosen per evaluation from n
+    for (int a = 0; a < 2; ++a) {
+        const double h = box[a] / grid[a];
+        const double wmin = std::max(0.25 * r_c, (8 + 2 * P - 1) * h / 14.0);
+        p->ncmax[a] = std::max(1, (int)std::floor(box[a] / wmin));
     }
-    p->ncell = nc[0] * nc[1] * nc[2];
+    while ((int64_t)p->ncmax[0] * p->ncmax[1] > (1 << 20)) {
+        const int am = p->ncmax[1] > p->ncmax[0] ? 1 : 0;
+        p->ncmax[am] = std::max(1, p->ncmax[am] * 3 / 4);
+    }
+    p->ncol_max = p->ncmax[0] * p->ncmax[1];
     for (int a = 0; a < 3; ++a) {
-        p->bin.nc[a] = pa.nc[a] = p->gridargs.nc[a] = nc[a];
         p->bin.inv_box[a] = 1.0 / box[a];
         pa.scale[a] = (float)(box[a] / 4294967296.0);
-        pa.cw[a] = (float)(box[a] / nc[a]);
     }
+    pa.zinv = (float)(4294967296.0 / box[2]);
 
     // far part
     GridArgs& ga = p->gridargs;
@@ -404,9 +422,9 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
     }
     const size_t ng = (size_t)grid[0] * grid[1] * grid[2];
     hipError_t e;
-    if ((e = dalloc(&p->cell_count, p->ncell)) || (e = dalloc(&p->cell_fill, p->ncell)) ||
-        (e = dalloc(&p->cell_start, p->ncell + 1)) || (e = dalloc(&p->qstats, 2)) ||
-        (e = dalloc(&p->pair_parts, (size_t)kPairSlices * p->ncell)) ||
+    if ((e = dalloc(&p->col_count, p->ncol_max)) || (e = dalloc(&p->col_fill, p->ncol_max)) ||
+        (e = dalloc(&p->col_start, p->ncol_max + 1)) ||
+        (e = dalloc(&p->clus_start, p->ncol_max + 1)) || (e = dalloc(&p->qstats, 2)) ||
         (e = dalloc(&p->parts_tmp, 5)) || (e = dalloc(&p->rho, ng)) ||
         (e = dalloc(&p->tgrid, ng * p->nterms)) || (e = dalloc(&p->phi, ng))) {
         delete p;
@@ -435,7 +453,7 @@ static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float*
     if (n > 0 && (!xyz || !q || !forces)) return fail(USERIES_EINVAL, "NULL buffer");
     DeviceGuard guard(p->device);
     hipStream_t st = (hipStream_t)stream;
-    if (n > p->cap) {
+    if (n > p->cap || !p->coord) {
         if (p->fixed_cap) return fail(USERIES_EINVAL, "n exceeds max_atoms");
         hipStreamSynchronize(st);
         int r = p->alloc_atoms(n);
@@ -443,19 +461,26 @@ static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float*
     }
     const int ni = (int)n;
     const int nq = (ni + 255) / 256;
-    // cells per pair block: about 48 charges per block
+    // x-y columns for this n: about 8 charges per cluster of one column
+    // cross-section and similar z extent, within the plan's bounds
     {
-        const double occ = (double)ni / p->ncell;
-        int G = (int)std::lround(48.0 / std::max(occ, 1.0));
-        p->pair.group = std::max(1, std::min(kMaxPairGroup, G));
+        const double V = p->box[0] * p->box[1] * p->box[2];
+        const double w = ni > 0 ? std::cbrt(8.0 * V / ni) : 1e300;
+        for (int a = 0; a < 2; ++a) {
+            const int nc = std::max(1, std::min(p->ncmax[a], (int)std::floor(p->box[a] / w)));
+            p->bin.nc[a] = p->pair.nc[a] = p->gridargs.nc[a] = p->nc_used[a] = nc;
+            p->pair.cw[a] = (float)(p->box[a] / nc);
+            p->pair.R[a] = (int)std::ceil(p->rc * nc / p->box[a]);
+        }
     }
-    const int npb = pair_blocks(p->pair), ngb = gather_blocks(ni);
+    const int ncol = p->bin.nc[0] * p->bin.nc[1];
+    const int npb = ni / 8 + 1 + ncol, ngb = gather_blocks(ni);
     p->bin.n = p->pair.n = p->gridargs.n = ni;
     p->fin.n_pair_parts = npb;
     p->fin.n_gather_parts = ngb;
     if (!parts && !energy) parts = p->parts_tmp;
 
-    hipError_t e = hipMemsetAsync(p->cell_count, 0, sizeof(int) * p->ncell, st);
+    hipError_t e = hipMemsetAsync(p->col_count, 0, sizeof(int) * ncol, st);
     if (e) return hip_fail(e, "memset");
     int k = 0;
     hipEvent_t ev0 = nullptr;
@@ -480,14 +505,16 @@ static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float*
         hipError_t err_ = post(call);                                  \
         if (err_ != hipSuccess) return hip_fail(err_, kKernelNames[k - 1]); \
     } while (0)
-    USERIES_STEP(launch_encode(p->bin, xyz, q, p->coord, p->cell_of, p->cell_count, p->qpart, nq, st));
-    USERIES_STEP(launch_scan(p->ncell, p->cell_count, p->cell_start, p->cell_fill, p->qpart, nq,
-                             p->qstats, st));
-    USERIES_STEP(launch_scatter(ni, p->cell_of, p->cell_start, p->cell_fill, p->slots, st));
-    USERIES_STEP(launch_rank(ni, p->cell_of, p->cell_start, p->slots, p->coord, p->perm, p->sorted,
-                             st));
-    USERIES_STEP(launch_pair(p->pair, p->sorted, p->cell_start, p->fnear, p->pair_parts, st));
-    USERIES_STEP(launch_spread(p->gridargs, p->sorted, p->cell_start, p->qstats, p->rho, st));
+    USERIES_STEP(launch_encode(p->bin, xyz, q, p->coord, p->col_of, p->col_count, p->qpart, nq, st));
+    USERIES_STEP(launch_scan(ncol, p->col_count, p->col_start, p->clus_start, p->col_fill, p->qpart,
+                             nq, p->qstats, st));
+    USERIES_STEP(launch_scatter(ni, ncol, p->col_of, p->col_start, p->col_fill, p->slots, st));
+    USERIES_STEP(launch_colsort(ncol, p->col_start, p->clus_start, p->slots, p->coord, p->perm,
+                                p->sorted, p->cl_info, p->cl_col, p->cl_z, st));
+    USERIES_STEP(launch_pair(p->pair, npb, p->sorted, p->clus_start, p->cl_info, p->cl_col, p->cl_z,
+                             p->fnear, p->pair_parts, st));
+    USERIES_STEP(launch_spread(p->gridargs, p->sorted, p->clus_start, p->cl_info, p->cl_z,
+                               p->qstats, p->rho, st));
     USERIES_STEP(launch_conv_xy(p->conv, p->rho, p->kx, p->ky, p->tgrid, st));
     USERIES_STEP(launch_conv_z(p->conv, p->tgrid, p->kz, p->phi, st));
     USERIES_STEP(launch_gather(p->gridargs, p->sorted, p->perm, p->phi, p->fnear, ni, forces,
@@ -524,8 +551,11 @@ int useries_plan_info(useries_plan_t p, double* b, double* sigma, double* r0, do
     if (c1_slope) *c1_slope = p->c1_slope;
     if (sigma_s) *sigma_s = p->sigma_s[0];
     if (stencil_half) *stencil_half = p->P;
-    if (ncell)
-        for (int a = 0; a < 3; ++a) ncell[a] = p->bin.nc[a];
+    if (ncell) {
+        ncell[0] = p->nc_used[0];
+        ncell[1] = p->nc_used[1];
+        ncell[2] = 1;
+    }
     if (poly_maxerr) *poly_maxerr = p->poly_maxerr;
     return USERIES_OK;
 }

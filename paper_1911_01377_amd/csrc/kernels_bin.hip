@@ -1,21 +1,37 @@
-// Binning of the charges into the cell list used by the near part and by the
-// spreading step: fixed-point encoding of the positions, cell histogram,
-// scan, scatter and a per-cell ranking that makes the order deterministic.
+// Binning of the charges into x-y columns, sorted by z inside each column,
+// and cut into clusters of up to 8 consecutive charges (spatially compact:
+// one column cross-section by about the same extent in z).  Used by the near
+// part (cluster-pair tiles) and by the spreading step (z-ranges per column).
 //
 // Positions are stored as uint32 fractions of the cell edge (u = x/L * 2^32),
 // so a periodic wrap is an integer overflow and the int32 difference of two
 // encodings is the exact minimum-image separation.
+//
+// encode -> scan (column and cluster offsets) -> scatter (atomic slots) ->
+// colsort (per column, sort by (z, input index): deterministic order; write
+// the permutation, the sorted positions and the cluster table).
 #include "useries_internal.h"
 #include "device_common.h"
 
 namespace useries {
 
+// Column histograms are first taken in LDS per block (many charges share a
+// column), then added to the global counters once per (block, column).
+constexpr int kHistCols = 4096;
+
 __global__ void __launch_bounds__(256) k_encode(BinArgs a, const float* __restrict__ xyz,
                                                 const float* __restrict__ q,
                                                 uint4* __restrict__ coord,
-                                                int* __restrict__ cell_of,
-                                                int* __restrict__ cell_count,
+                                                int* __restrict__ col_of,
+                                                int* __restrict__ col_count,
                                                 double* __restrict__ qpart) {
+    __shared__ double red[256];
+    __shared__ int hist[kHistCols];
+    const int ncol = a.nc[0] * a.nc[1];
+    const bool local = ncol <= kHistCols;
+    if (local)
+        for (int k = threadIdx.x; k < ncol; k += 256) hist[k] = 0;
+    __syncthreads();
     const int i = blockIdx.x * 256 + threadIdx.x;
     double qs = 0.0, q2 = 0.0;
     if (i < a.n) {
@@ -23,145 +39,238 @@ __global__ void __launch_bounds__(256) k_encode(BinArgs a, const float* __restri
 #pragma unroll
         for (int k = 0; k < 3; ++k) u[k] = to_fixed((double)xyz[3 * i + k], a.inv_box[k]);
         const float qi = q[i];
-        const int c = (cell_coord(u[2], a.nc[2]) * a.nc[1] + cell_coord(u[1], a.nc[1])) * a.nc[0] +
-                      cell_coord(u[0], a.nc[0]);
+        const int c = cell_coord(u[1], a.nc[1]) * a.nc[0] + cell_coord(u[0], a.nc[0]);
         coord[i] = make_uint4(u[0], u[1], u[2], __float_as_uint(qi));
-        cell_of[i] = c;
-        atomicAdd(&cell_count[c], 1);
+        col_of[i] = c;
+        if (local) atomicAdd(&hist[c], 1);
+        else atomicAdd(&col_count[c], 1);
         qs = qi;
         q2 = (double)qi * (double)qi;
     }
-    __shared__ double s1[256], s2[256];
-    s1[threadIdx.x] = qs;
-    s2[threadIdx.x] = q2;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            s1[threadIdx.x] += s1[threadIdx.x + w];
-            s2[threadIdx.x] += s2[threadIdx.x + w];
-        }
-        __syncthreads();
-    }
+    if (local)
+        for (int k = threadIdx.x; k < ncol; k += 256)
+            if (hist[k] > 0) atomicAdd(&col_count[k], hist[k]);
+    const double s1 = block_sum_d<256>(qs, red);
+    __syncthreads();
+    const double s2 = block_sum_d<256>(q2, red);
     if (threadIdx.x == 0) {
-        qpart[2 * blockIdx.x] = s1[0];
-        qpart[2 * blockIdx.x + 1] = s2[0];
+        qpart[2 * blockIdx.x] = s1;
+        qpart[2 * blockIdx.x + 1] = s2;
     }
 }
 
-// One block of 1024 threads: exclusive scan of the cell counts (each thread
-// owns a contiguous chunk; wavefront scans by shuffles, then a scan of the 16
-// wavefront totals), zero the fill counters, and reduce the charge partials
-// in a fixed order (sum q, sum q^2).
-__global__ void __launch_bounds__(1024) k_scan(int ncell, const int* __restrict__ count,
-                                               int* __restrict__ start, int* __restrict__ fill,
+// One block of 1024 threads: exclusive scans of the column counts and of the
+// cluster counts ceil(count / 8) (each thread owns a contiguous chunk;
+// wavefront scans by shuffles, then a scan of the 16 wavefront totals), zero
+// the fill counters, and reduce the charge partials in a fixed order.
+__global__ void __launch_bounds__(1024) k_scan(int ncol, const int* __restrict__ count,
+                                               int* __restrict__ start, int* __restrict__ cstart,
+                                               int* __restrict__ fill,
                                                const double* __restrict__ qpart, int nqpart,
                                                double* __restrict__ qstats) {
-    __shared__ int wsum[16];
+    __shared__ int wsum[2][16];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int chunk = (ncell + 1023) / 1024;
-    const int lo = min(t * chunk, ncell), hi = min(lo + chunk, ncell);
-    int s = 0;
-    for (int c = lo; c < hi; ++c) s += count[c];
-    int v = s;
+    const int chunk = (ncol + 1023) / 1024;
+    const int lo = min(t * chunk, ncol), hi = min(lo + chunk, ncol);
+    int s = 0, sc = 0;
+    for (int c = lo; c < hi; ++c) {
+        const int k = count[c];
+        s += k;
+        sc += (k + 7) >> 3;
+    }
+    int v = s, vc = sc;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        const int u = __shfl_up(v, off, 64);
-        if (lane >= off) v += u;
+        const int u = __shfl_up(v, off, 64), uc = __shfl_up(vc, off, 64);
+        if (lane >= off) {
+            v += u;
+            vc += uc;
+        }
     }
-    if (lane == 63) wsum[wv] = v;
+    if (lane == 63) {
+        wsum[0][wv] = v;
+        wsum[1][wv] = vc;
+    }
     __syncthreads();
     if (wv == 0) {
-        int x = lane < 16 ? wsum[lane] : 0;
-        const int own = x;
+        int x = lane < 16 ? wsum[0][lane] : 0, xc = lane < 16 ? wsum[1][lane] : 0;
+        const int own = x, ownc = xc;
 #pragma unroll
         for (int off = 1; off < 16; off <<= 1) {
-            const int u = __shfl_up(x, off, 64);
-            if (lane >= off) x += u;
+            const int u = __shfl_up(x, off, 64), uc = __shfl_up(xc, off, 64);
+            if (lane >= off) {
+                x += u;
+                xc += uc;
+            }
         }
-        if (lane < 16) wsum[lane] = x - own;
+        if (lane < 16) {
+            wsum[0][lane] = x - own;
+            wsum[1][lane] = xc - ownc;
+        }
     }
     __syncthreads();
-    int run = wsum[wv] + v - s;   // exclusive prefix of this chunk
+    int run = wsum[0][wv] + v - s, runc = wsum[1][wv] + vc - sc;   // exclusive prefixes
     for (int c = lo; c < hi; ++c) {
+        const int k = count[c];
         start[c] = run;
-        run += count[c];
+        cstart[c] = runc;
+        run += k;
+        runc += (k + 7) >> 3;
         fill[c] = 0;
     }
-    if (t == 1023) start[ncell] = run;
+    if (t == 1023) {
+        start[ncol] = run;
+        cstart[ncol] = runc;
+    }
     if (wv == 1) {
-        double a = 0.0, b = 0.0;
+        double qa = 0.0, qb = 0.0;
         for (int k = lane; k < nqpart; k += 64) {
-            a += qpart[2 * k];
-            b += qpart[2 * k + 1];
+            qa += qpart[2 * k];
+            qb += qpart[2 * k + 1];
         }
-        a = wave_sum_d(a);
-        b = wave_sum_d(b);
+        qa = wave_sum_d(qa);
+        qb = wave_sum_d(qb);
         if (lane == 0) {
-            qstats[0] = a;
-            qstats[1] = b;
+            qstats[0] = qa;
+            qstats[1] = qb;
         }
     }
 }
 
-__global__ void __launch_bounds__(256) k_scatter(int n, const int* __restrict__ cell_of,
+// Slots inside a column: the rank among the block's charges of that column
+// (LDS atomic) plus a base reserved once per (block, column).  The order they
+// produce is arbitrary; colsort makes it deterministic.
+__global__ void __launch_bounds__(256) k_scatter(int n, int ncol, const int* __restrict__ col_of,
                                                  const int* __restrict__ start,
-                                                 int* __restrict__ fill, int* __restrict__ perm) {
+                                                 int* __restrict__ fill, int* __restrict__ slots) {
+    __shared__ int hist[kHistCols];
+    __shared__ int base[kHistCols];
+    const bool local = ncol <= kHistCols;
+    if (local)
+        for (int k = threadIdx.x; k < ncol; k += 256) hist[k] = 0;
+    __syncthreads();
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const int c = cell_of[i];
-    const int slot = atomicAdd(&fill[c], 1);
-    perm[start[c] + slot] = i;
+    int c = 0, r = 0;
+    if (i < n) {
+        c = col_of[i];
+        r = local ? atomicAdd(&hist[c], 1) : atomicAdd(&fill[c], 1);
+    }
+    __syncthreads();
+    if (local)
+        for (int k = threadIdx.x; k < ncol; k += 256)
+            if (hist[k] > 0) base[k] = atomicAdd(&fill[k], hist[k]);
+    __syncthreads();
+    if (i < n) slots[start[c] + (local ? base[c] : 0) + r] = i;
 }
 
-// One thread per charge: its rank inside its cell is the number of charges of
-// the same cell with a smaller input index, so the order inside a cell does
-// not depend on the timing of the scatter atomics.  Writes the permutation
-// (sorted slot -> input index) and the sorted encoded positions.
-__global__ void __launch_bounds__(256) k_rank(int n, const int* __restrict__ cell_of,
-                                              const int* __restrict__ start,
-                                              const int* __restrict__ slots,
-                                              const uint4* __restrict__ coord,
-                                              int* __restrict__ perm,
-                                              uint4* __restrict__ sorted) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const int c = cell_of[i];
-    const int lo = start[c], hi = start[c + 1];
-    int rank = 0;
-    for (int k = lo; k < hi; ++k) rank += slots[k] < i;
-    perm[lo + rank] = i;
-    sorted[lo + rank] = coord[i];
+// One block per column: sort the column's charges by the key (z, input
+// index) -- unique, so the order is deterministic -- with a bitonic sort in
+// LDS (columns above kSortCap charges fall back to ranking by counting), then
+// write the permutation, the sorted positions and the column's clusters.
+constexpr int kSortCap = 1024;
+
+__global__ void __launch_bounds__(256) k_colsort(const int* __restrict__ start,
+                                                 const int* __restrict__ cstart,
+                                                 const int* __restrict__ slots,
+                                                 const uint4* __restrict__ coord,
+                                                 int* __restrict__ perm,
+                                                 uint4* __restrict__ sorted,
+                                                 int2* __restrict__ cl_info,
+                                                 int* __restrict__ cl_col,
+                                                 uint2* __restrict__ cl_z) {
+    __shared__ unsigned long long key[kSortCap];
+    const int col = blockIdx.x, t = threadIdx.x;
+    const int lo = start[col], cnt = start[col + 1] - lo;
+    if (cnt == 0) return;
+    if (cnt <= kSortCap) {
+        int m = 1;
+        while (m < cnt) m <<= 1;
+        for (int k = t; k < m; k += 256) {
+            if (k < cnt) {
+                const int i = slots[lo + k];
+                key[k] = ((unsigned long long)coord[i].z << 32) | (unsigned)i;
+            } else {
+                key[k] = ~0ull;
+            }
+        }
+        __syncthreads();
+        for (int size = 2; size <= m; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int k = t; k < m; k += 256) {
+                    const int o = k ^ stride;
+                    if (o > k) {
+                        const bool up = (k & size) == 0;
+                        const unsigned long long x = key[k], y = key[o];
+                        if ((x > y) == up) {
+                            key[k] = y;
+                            key[o] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int k = t; k < cnt; k += 256) {
+            const int i = (int)(unsigned)(key[k] & 0xffffffffull);
+            perm[lo + k] = i;
+            sorted[lo + k] = coord[i];
+        }
+    } else {
+        // rank by counting (O(cnt^2) work spread over the block)
+        for (int k = t; k < cnt; k += 256) {
+            const int i = slots[lo + k];
+            const unsigned long long ki = ((unsigned long long)coord[i].z << 32) | (unsigned)i;
+            int rank = 0;
+            for (int m = 0; m < cnt; ++m) {
+                const int j = slots[lo + m];
+                rank += (((unsigned long long)coord[j].z << 32) | (unsigned)j) < ki;
+            }
+            perm[lo + rank] = i;
+            sorted[lo + rank] = coord[i];
+        }
+    }
+    __syncthreads();
+    // clusters: 8 consecutive charges of the column (the last may be short)
+    const int c0 = cstart[col], nclus = (cnt + 7) >> 3;
+    for (int k = t; k < nclus; k += 256) {
+        const int b = lo + 8 * k;
+        const int nk = min(8, cnt - 8 * k);
+        cl_info[c0 + k] = make_int2(b, nk);
+        cl_col[c0 + k] = col;
+        cl_z[c0 + k] = make_uint2(sorted[b].z, sorted[b + nk - 1].z);
+    }
 }
 
 hipError_t launch_encode(const BinArgs& a, const float* xyz, const float* q, uint4* coord,
-                         int* cell_of, int* cell_count, double* qpart, int nqpart,
-                         hipStream_t st) {
+                         int* col_of, int* col_count, double* qpart, int nqpart, hipStream_t st) {
     if (a.n > 0)
-        hipLaunchKernelGGL(k_encode, dim3(nqpart), dim3(256), 0, st, a, xyz, q, coord, cell_of,
-                           cell_count, qpart);
+        hipLaunchKernelGGL(k_encode, dim3(nqpart), dim3(256), 0, st, a, xyz, q, coord, col_of,
+                           col_count, qpart);
     return hipGetLastError();
 }
 
-hipError_t launch_scan(int ncell, const int* cell_count, int* cell_start, int* cell_fill,
-                       const double* qpart, int nqpart, double* qstats, hipStream_t st) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, ncell, cell_count, cell_start,
-                       cell_fill, qpart, nqpart, qstats);
+hipError_t launch_scan(int ncol, const int* col_count, int* col_start, int* clus_start,
+                       int* col_fill, const double* qpart, int nqpart, double* qstats,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, ncol, col_count, col_start, clus_start,
+                       col_fill, qpart, nqpart, qstats);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(int n, const int* cell_of, const int* cell_start, int* cell_fill,
-                          int* perm, hipStream_t st) {
+hipError_t launch_scatter(int n, int ncol, const int* col_of, const int* col_start, int* col_fill,
+                          int* slots, hipStream_t st) {
     if (n > 0)
-        hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, st, n, cell_of,
-                           cell_start, cell_fill, perm);
+        hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, st, n, ncol, col_of,
+                           col_start, col_fill, slots);
     return hipGetLastError();
 }
 
-hipError_t launch_rank(int n, const int* cell_of, const int* cell_start, const int* slots,
-                       const uint4* coord, int* perm, uint4* sorted, hipStream_t st) {
-    if (n > 0)
-        hipLaunchKernelGGL(k_rank, dim3((n + 255) / 256), dim3(256), 0, st, n, cell_of,
-                           cell_start, slots, coord, perm, sorted);
+hipError_t launch_colsort(int ncol, const int* col_start, const int* clus_start, const int* slots,
+                          const uint4* coord, int* perm, uint4* sorted, int2* cl_info,
+                          int* cl_col, uint2* cl_z, hipStream_t st) {
+    hipLaunchKernelGGL(k_colsort, dim3(ncol), dim3(256), 0, st, col_start, clus_start, slots,
+                       coord, perm, sorted, cl_info, cl_col, cl_z);
     return hipGetLastError();
 }
 

@@ -9,7 +9,8 @@
 // The mean of rho (its k = 0 mode, the net charge) is removed on the grid.
 //
 // spread: one block per 8x8x8 brick of the grid, four wavefronts sharing the
-//   cell rows whose charges can touch the brick.  A wavefront keeps the
+//   x-y columns whose charges can touch the brick (for each column, the
+//   z-range of clusters that can, found by binary search).  A wavefront keeps the
 //   charges that do touch it (ballot compaction, so the order is
 //   deterministic), stages their 3 x 8 weights in LDS and accumulates its
 //   partial brick in registers: lane (y, z) owns one grid row of 8 points.
@@ -32,8 +33,14 @@ constexpr int kSpreadWaves = 4;  // wavefronts per brick, each taking a share of
 
 __device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 __device__ __forceinline__ int ceildiv(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
+__device__ __forceinline__ long long floordiv_ll(long long a, long long b) {
+    return a >= 0 ? a / b : -((-a + b - 1) / b);
+}
+__device__ __forceinline__ long long ceildiv_ll(long long a, long long b) {
+    return a >= 0 ? (a + b - 1) / b : -((-a) / b);
+}
 
-// cells along one axis that can hold charges touching grid points
+// columns along one axis that can hold charges touching grid points
 // [X0, X0 + bn): charges whose stencil start lies in [X0 - P, X0 + bn + P - 1)
 __device__ __forceinline__ void cell_window(int X0, int bn, int P, int g, int nc, int* lo,
                                             int* cnt) {
@@ -52,11 +59,14 @@ __device__ __forceinline__ void cell_window(int X0, int bn, int P, int g, int nc
 
 __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread(GridArgs a,
                                                               const uint4* __restrict__ sorted,
-                                                              const int* __restrict__ cell_start,
+                                                              const int* __restrict__ clus_start,
+                                                              const int2* __restrict__ cl_info,
+                                                              const uint2* __restrict__ cl_z,
                                                               const double* __restrict__ qstats,
                                                               float* __restrict__ rho) {
     __shared__ float sw[kSpreadWaves][kStage][3 * kBrick];
     __shared__ float red[kSpreadWaves - 1][kBrick][64];
+    __shared__ int2 win[2 * kMaxWindowCols];   // charge ranges [begin, end) per column piece
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ty = lane & 7, tz = lane >> 3;
     const int nbx = (a.g[0] + kBrick - 1) / kBrick, nby = (a.g[1] + kBrick - 1) / kBrick;
@@ -66,10 +76,31 @@ __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread(GridArgs a,
     const int B0 = min(kBrick, a.g[0] - X0), B1 = min(kBrick, a.g[1] - Y0),
               B2 = min(kBrick, a.g[2] - Z0);
     const int P = a.P;
-    int lo[3], cnt[3];
+    int lo[2], cnt[2];
     cell_window(X0, B0, P, a.g[0], a.nc[0], &lo[0], &cnt[0]);
     cell_window(Y0, B1, P, a.g[1], a.nc[1], &lo[1], &cnt[1]);
-    cell_window(Z0, B2, P, a.g[2], a.nc[2], &lo[2], &cnt[2]);
+    const int ncw = cnt[0] * cnt[1];
+    // z window in fixed point (widened to whole units): charges whose
+    // stencil start lies in [Z0 - P, Z0 + B2 + P - 1)
+    const long long zlo = floordiv_ll((long long)(Z0 - P) << 32, a.g[2]);
+    const long long zhi = ceildiv_ll((long long)(Z0 + B2 + P - 1) << 32, a.g[2]);
+    for (int k = threadIdx.x; k < ncw; k += 64 * kSpreadWaves) {
+        const int col = wrapi(lo[1] + k / cnt[0], a.nc[1]) * a.nc[0] + wrapi(lo[0] + k % cnt[0], a.nc[0]);
+        int b0, l0, b1, l1;
+        column_zrange(cl_z, clus_start[col], clus_start[col + 1], zlo, zhi, &b0, &l0, &b1, &l1);
+        int2 r0 = make_int2(0, 0), r1 = make_int2(0, 0);
+        if (l0 > 0) {
+            const int2 e = cl_info[b0 + l0 - 1];
+            r0 = make_int2(cl_info[b0].x, e.x + e.y);
+        }
+        if (l1 > 0) {
+            const int2 e = cl_info[b1 + l1 - 1];
+            r1 = make_int2(cl_info[b1].x, e.x + e.y);
+        }
+        win[2 * k] = r0;
+        win[2 * k + 1] = r1;
+    }
+    __syncthreads();
     const int X0s[3] = {X0, Y0, Z0};
     const int Bs[3] = {B0, B1, B2};
     float (*S)[3 * kBrick] = sw[w];
@@ -136,20 +167,10 @@ __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread(GridArgs a,
         }
     };
 
-    // the (z, y) cell rows of the window are dealt round-robin to the wavefronts
-    const int nrows = cnt[1] * cnt[2];
-    for (int r = w; r < nrows; r += kSpreadWaves) {
-        const int zz = wrapi(lo[2] + r / cnt[1], a.nc[2]);
-        const int yy = wrapi(lo[1] + r % cnt[1], a.nc[1]);
-        const int row = (zz * a.nc[1] + yy) * a.nc[0];
-        if (cnt[0] == a.nc[0]) {
-            visit(cell_start[row], cell_start[row + a.nc[0]]);
-        } else if (lo[0] + cnt[0] <= a.nc[0]) {
-            visit(cell_start[row + lo[0]], cell_start[row + lo[0] + cnt[0]]);
-        } else {
-            visit(cell_start[row + lo[0]], cell_start[row + a.nc[0]]);
-            visit(cell_start[row], cell_start[row + lo[0] + cnt[0] - a.nc[0]]);
-        }
+    // the column pieces of the window are dealt round-robin to the wavefronts
+    for (int k = w; k < 2 * ncw; k += kSpreadWaves) {
+        const int2 r = win[k];
+        if (r.y > r.x) visit(r.x, r.y);
     }
     if (staged > 0) accumulate(staged);
 
@@ -253,12 +274,13 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs a, const uint4* __restr
     if (threadIdx.x == 0) epart[blockIdx.x] = ((se[0] + se[1]) + se[2]) + se[3];
 }
 
-hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* cell_start,
-                         const double* qstats, float* rho, hipStream_t st) {
+hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* clus_start,
+                         const int2* cl_info, const uint2* cl_z, const double* qstats, float* rho,
+                         hipStream_t st) {
     const int nb = ((a.g[0] + kBrick - 1) / kBrick) * ((a.g[1] + kBrick - 1) / kBrick) *
                    ((a.g[2] + kBrick - 1) / kBrick);
-    hipLaunchKernelGGL(k_spread, dim3(nb), dim3(64 * kSpreadWaves), 0, st, a, sorted, cell_start,
-                       qstats, rho);
+    hipLaunchKernelGGL(k_spread, dim3(nb), dim3(64 * kSpreadWaves), 0, st, a, sorted, clus_start,
+                       cl_info, cl_z, qstats, rho);
     return hipGetLastError();
 }
 

@@ -15,8 +15,9 @@ constexpr int kMaxTerms = 32;      // far Gaussians N
 constexpr int kMaxGrid = 128;      // grid points per axis
 constexpr int kMaxPolyDeg = 14;    // near polynomial degree
 constexpr int kMaxStencilHalf = 8; // P
-constexpr int kMaxPairGroup = 12;  // cells per pair-kernel block
-constexpr int kPairSlices = 5;     // partial near-force slices per charge
+constexpr int kMaxStencilCols = 128;  // x-y columns within r_c of a column (pair kernel)
+constexpr int kMaxWindowCols = 256;   // x-y columns touching a spreading brick
+constexpr int kPairSlices = 1;        // near-force slices per charge
 
 // ------------------------------------------------------------ host math
 // FP64 parameter math of the u-series (plan_math.cpp).
@@ -48,19 +49,20 @@ void circulant_column(int n, double h, double sk, double scale, double* k);
 // ------------------------------------------------------------ device args
 struct BinArgs {
     int n;
-    int nc[3];            // cells per axis
+    int nc[2];            // x-y columns per axis
     double inv_box[3];    // 1/L
 };
 
 struct PairArgs {
     int n;
-    int nc[3];
+    int nc[2];            // x-y columns per axis
+    int R[2];             // columns within reach of r_c per axis: ceil(r_c / cw)
     float scale[3];       // L / 2^32: fixed-point units to A
-    float cw[3];          // cell widths L / nc
+    float cw[2];          // column widths L / nc
+    float zinv;           // 2^32 / L_z: A to fixed-point units along z
     float rc2;            // r_c^2
     float inv_rc2;        // 1 / r_c^2
     int deg;              // polynomial degree
-    int group;            // cells of one x-row per block (1..kMaxPairGroup)
     float c[kMaxPolyDeg + 1];   // F_inf(r) = sum c_k x^k, x = r^2/rc^2
     float c0lo, c1lo;           // c_0 - (float)c_0 and c_1 - (float)c_1
     float d[kMaxPolyDeg];       // F_inf'(r)/r = sum d_k x^k
@@ -69,7 +71,7 @@ struct PairArgs {
 struct GridArgs {
     int n;
     int g[3];             // grid points per axis
-    int nc[3];            // cells per axis (candidate search for spreading)
+    int nc[2];            // x-y columns per axis (candidate search for spreading)
     int P;                // stencil half width: 2P points per axis
     float hs[3];          // h^2 / (2 sigma_s^2) per axis
     float cw[3];          // h / (sqrt(2 pi) sigma_s): weight prefactor per axis
@@ -94,19 +96,21 @@ struct FinalArgs {
 // ------------------------------------------------------------ kernel launchers
 // All launchers enqueue on `st` and return hipGetLastError().
 hipError_t launch_encode(const BinArgs& a, const float* xyz, const float* q, uint4* coord,
-                         int* cell_of, int* cell_count, double* qpart, int nqpart,
+                         int* col_of, int* col_count, double* qpart, int nqpart, hipStream_t st);
+hipError_t launch_scan(int ncol, const int* col_count, int* col_start, int* clus_start,
+                       int* col_fill, const double* qpart, int nqpart, double* qstats,
+                       hipStream_t st);
+hipError_t launch_scatter(int n, int ncol, const int* col_of, const int* col_start, int* col_fill,
+                          int* slots, hipStream_t st);
+hipError_t launch_colsort(int ncol, const int* col_start, const int* clus_start, const int* slots,
+                          const uint4* coord, int* perm, uint4* sorted, int2* cl_info,
+                          int* cl_col, uint2* cl_z, hipStream_t st);
+hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, const int* clus_start,
+                       const int2* cl_info, const int* cl_col, const uint2* cl_z, float4* fnear,
+                       double* epart, hipStream_t st);
+hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* clus_start,
+                         const int2* cl_info, const uint2* cl_z, const double* qstats, float* rho,
                          hipStream_t st);
-hipError_t launch_scan(int ncell, const int* cell_count, int* cell_start, int* cell_fill,
-                       const double* qpart, int nqpart, double* qstats, hipStream_t st);
-hipError_t launch_scatter(int n, const int* cell_of, const int* cell_start, int* cell_fill,
-                          int* perm, hipStream_t st);
-hipError_t launch_rank(int n, const int* cell_of, const int* cell_start, const int* slots,
-                       const uint4* coord, int* perm, uint4* sorted, hipStream_t st);
-hipError_t launch_pair(const PairArgs& a, const uint4* sorted, const int* cell_start,
-                       float4* fnear, double* epart, hipStream_t st);
-int pair_blocks(const PairArgs& a);
-hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* cell_start,
-                         const double* qstats, float* rho, hipStream_t st);
 hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx,
                           const float* ky, float* tgrid, hipStream_t st);
 hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz, float* phi,
