@@ -83,9 +83,9 @@ enum {
  *                    picks the default (5 plain, 4 BF16X3).  1 <= P <= 8.
  *   nterms_tol       relative far-energy truncation bound (eq. 33) used to
  *                    choose N when useries_plan gets n_terms <= 0.
- *   poly_degree      degree in r^2 of the polynomial that represents the
- *                    infinite far series inside the cutoff (near part);
- *                    <= 0 picks 10.  4 <= degree <= 14.
+ *   poly_degree      degree in r^2 of the polynomials that represent the
+ *                    infinite far series F and F'(r)/r inside the cutoff
+ *                    (near part); <= 0 picks 8.  4 <= degree <= 14.
  *   max_atoms        workspace capacity in charges; <= 0 grows on demand
  *                    (a growth reallocates and synchronises the device).
  */

@@ -267,7 +267,7 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
     const bool bf = o.precision == USERIES_BF16X3;
     const double ratio = o.sigma_s_over_h > 0 ? o.sigma_s_over_h : (bf ? 0.83 : 0.9);
     const int P = o.stencil_half > 0 ? o.stencil_half : (bf ? 4 : 5);
-    const int deg = o.poly_degree > 0 ? o.poly_degree : 10;
+    const int deg = o.poly_degree > 0 ? o.poly_degree : 8;
     if (P < 1 || P > kMaxStencilHalf) return fail(USERIES_EINVAL, "stencil_half out of [1, 8]");
     if (deg < 4 || deg > kMaxPolyDeg) return fail(USERIES_EINVAL, "poly_degree out of [4, 14]");
     if (!(o.nterms_tol > 0)) return fail(USERIES_EINVAL, "nterms_tol must be > 0");
@@ -330,14 +330,13 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
     p->c1_slope = -1.0 / (r_c * r_c) - dF;
 
     // near part
-    double coef[kMaxPolyDeg + 1];
-    p->poly_maxerr = fit_near_poly(s, r_c, deg, coef);
+    double coef[kMaxPolyDeg + 1], gcoef[kMaxPolyDeg + 1];
+    p->poly_maxerr = fit_near_poly(s, r_c, deg, coef, gcoef);
     PairArgs& pa = p->pair;
     pa.deg = deg;
     for (int k = 0; k <= deg; ++k) pa.c[k] = (float)coef[k];
     pa.c0lo = (float)(coef[0] - (double)pa.c[0]);
-    pa.c1lo = (float)(coef[1] - (double)pa.c[1]);
-    for (int k = 0; k < deg; ++k) pa.d[k] = (float)(2.0 * (k + 1) * coef[k + 1] / (r_c * r_c));
+    for (int k = 0; k <= deg; ++k) pa.d[k] = (float)gcoef[k];
     pa.rc2 = (float)(r_c * r_c);
     pa.inv_rc2 = (float)(1.0 / (r_c * r_c));
 

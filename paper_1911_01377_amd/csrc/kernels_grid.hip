@@ -15,9 +15,10 @@
 //   deterministic), stages their 3 x 8 weights in LDS and accumulates its
 //   partial brick in registers: lane (y, z) owns one grid row of 8 points.
 //   The four partial bricks are summed in a fixed order.  No atomics.
-// gather: one wavefront per charge at a time (charges dealt round-robin to a
-//   fixed set of wavefronts); lane r owns stencil rows (y, z) and reads the 2P
-//   contiguous x points of each, then the wavefront reduces.
+// gather: a wavefront takes four charges at a time, 16 lanes each (groups of
+//   charges dealt round-robin to a fixed set of wavefronts); a lane owns
+//   stencil rows (y, z) of its charge and reads the 2P contiguous x points of
+//   each, then each 16-lane group reduces.
 #include <algorithm>
 
 #include "useries_internal.h"
@@ -193,6 +194,8 @@ __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread(GridArgs a,
     }
 }
 
+constexpr int kGatherPerWave = 4;   // charges per wavefront at a time, 16 lanes each
+
 __global__ void __launch_bounds__(256) k_gather(GridArgs a, const uint4* __restrict__ sorted,
                                                 const int* __restrict__ perm,
                                                 const float* __restrict__ phi,
@@ -200,59 +203,72 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs a, const uint4* __restr
                                                 int slice_stride,
                                                 float* __restrict__ forces,
                                                 double* __restrict__ epart) {
-    __shared__ float sw[4][6][16];
+    __shared__ float sw[4][kGatherPerWave][6][16];
     __shared__ double se[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, l16 = lane & 15;
     const int P = a.P, P2 = 2 * P;
     const int nw = gridDim.x * 4;
     double e_wave = 0.0;
-    // charges are dealt to the wavefronts round-robin (fixed for a given n)
-    for (int i = blockIdx.x * 4 + wave; i < a.n; i += nw) {
-        int gi[3];
-        float f[3];
-        const uint4 c = sorted[i];
-        grid_coord(c.x, a.g[0], &gi[0], &f[0]);
-        grid_coord(c.y, a.g[1], &gi[1], &f[1]);
-        grid_coord(c.z, a.g[2], &gi[2], &f[2]);
-        const float qi = __uint_as_float(c.w);
-        if (lane < 48) {
-            const int ax = lane >> 4, k = lane & 15;
-            if (k < P2) {
-                const float t = (float)(k - P + 1) - f[ax];
-                const float w = a.cw[ax] * __expf(-t * t * a.hs[ax]);
-                sw[wave][ax][k] = w;
-                sw[wave][3 + ax][k] = w * t * a.dws[ax];
+    // groups of kGatherPerWave charges are dealt to the wavefronts round-robin
+    for (int i0 = (blockIdx.x * 4 + wave) * kGatherPerWave; i0 < a.n; i0 += nw * kGatherPerWave) {
+        const int i = i0 + g;
+        const bool valid = i < a.n;
+        int gi[3] = {0, 0, 0};
+        float f[3] = {0.0f, 0.0f, 0.0f};
+        float qi = 0.0f;
+        if (valid) {
+            const uint4 c = sorted[i];
+            grid_coord(c.x, a.g[0], &gi[0], &f[0]);
+            grid_coord(c.y, a.g[1], &gi[1], &f[1]);
+            grid_coord(c.z, a.g[2], &gi[2], &f[2]);
+            qi = __uint_as_float(c.w);
+            // lane l16 < 2P computes the weights and derivatives of point l16, all axes
+            if (l16 < P2) {
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    const float t = (float)(l16 - P + 1) - f[ax];
+                    const float w = a.cw[ax] * __expf(-t * t * a.hs[ax]);
+                    sw[wave][g][ax][l16] = w;
+                    sw[wave][g][3 + ax][l16] = w * t * a.dws[ax];
+                }
             }
         }
         wave_sync();
         float pe = 0.0f, px = 0.0f, py = 0.0f, pz = 0.0f;
-        const int gx0 = gi[0] - P + 1;
-        for (int r = lane; r < P2 * P2; r += 64) {
-            const int ky = r % P2, kz = r / P2;
-            int gy = gi[1] - P + 1 + ky, gz = gi[2] - P + 1 + kz;
-            gy = gy < 0 ? gy + a.g[1] : (gy >= a.g[1] ? gy - a.g[1] : gy);
-            gz = gz < 0 ? gz + a.g[2] : (gz >= a.g[2] ? gz - a.g[2] : gz);
-            const float* rowp = phi + ((size_t)gz * a.g[1] + gy) * a.g[0];
-            float sx = 0.0f, dsx = 0.0f;
-            for (int k = 0; k < P2; ++k) {
-                int gx = gx0 + k;
-                gx = gx < 0 ? gx + a.g[0] : (gx >= a.g[0] ? gx - a.g[0] : gx);
-                const float v = rowp[gx];
-                sx = fmaf(sw[wave][0][k], v, sx);
-                dsx = fmaf(sw[wave][3][k], v, dsx);
+        if (valid) {
+            const float* W = &sw[wave][g][0][0];
+            const int gx0 = gi[0] - P + 1;
+            for (int r = l16; r < P2 * P2; r += 16) {
+                const int ky = r % P2, kz = r / P2;
+                int gy = gi[1] - P + 1 + ky, gz = gi[2] - P + 1 + kz;
+                gy = gy < 0 ? gy + a.g[1] : (gy >= a.g[1] ? gy - a.g[1] : gy);
+                gz = gz < 0 ? gz + a.g[2] : (gz >= a.g[2] ? gz - a.g[2] : gz);
+                const float* rowp = phi + ((size_t)gz * a.g[1] + gy) * a.g[0];
+                float sx = 0.0f, dsx = 0.0f;
+                for (int k = 0; k < P2; ++k) {
+                    int gx = gx0 + k;
+                    gx = gx < 0 ? gx + a.g[0] : (gx >= a.g[0] ? gx - a.g[0] : gx);
+                    const float v = rowp[gx];
+                    sx = fmaf(W[k], v, sx);
+                    dsx = fmaf(W[3 * 16 + k], v, dsx);
+                }
+                const float wy = W[16 + ky], wz = W[32 + kz];
+                const float wyz = wy * wz;
+                pe = fmaf(wyz, sx, pe);
+                px = fmaf(wyz, dsx, px);
+                py = fmaf(W[64 + ky] * wz, sx, py);
+                pz = fmaf(wy * W[80 + kz], sx, pz);
             }
-            const float wy = sw[wave][1][ky], wz = sw[wave][2][kz];
-            const float wyz = wy * wz;
-            pe = fmaf(wyz, sx, pe);
-            px = fmaf(wyz, dsx, px);
-            py = fmaf(sw[wave][4][ky] * wz, sx, py);
-            pz = fmaf(wy * sw[wave][5][kz], sx, pz);
         }
-        pe = wave_sum(pe);
-        px = wave_sum(px);
-        py = wave_sum(py);
-        pz = wave_sum(pz);
-        if (lane == 0) {
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {
+            pe += __shfl_xor(pe, off, 64);
+            px += __shfl_xor(px, off, 64);
+            py += __shfl_xor(py, off, 64);
+            pz += __shfl_xor(pz, off, 64);
+        }
+        if (valid && l16 == 0) {
             // near force: the pair kernel's partial slices, summed in a fixed order
             float4 fn = fnear[i];
             for (int sl = 1; sl < kPairSlices; ++sl) {
@@ -265,8 +281,12 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs a, const uint4* __restr
             forces[3 * o + 0] = fn.x - qi * px;
             forces[3 * o + 1] = fn.y - qi * py;
             forces[3 * o + 2] = fn.z - qi * pz;
-            e_wave += 0.5 * (double)qi * (double)pe;
         }
+        // the four charges' energies, in a fixed order
+        double ei = (valid && l16 == 0) ? 0.5 * (double)qi * (double)pe : 0.0;
+        ei += __shfl_xor(ei, 16, 64);
+        ei += __shfl_xor(ei, 32, 64);
+        e_wave += ei;
         wave_sync();
     }
     if (lane == 0) se[wave] = e_wave;
@@ -284,7 +304,7 @@ hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* clus
     return hipGetLastError();
 }
 
-int gather_blocks(int n) { return std::min((n + 3) / 4, 8192); }
+int gather_blocks(int n) { return std::min((n + 4 * kGatherPerWave - 1) / (4 * kGatherPerWave), 8192); }
 
 hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm,
                          const float* phi, const float4* fnear, int slice_stride, float* forces,

@@ -29,20 +29,20 @@ namespace {
 constexpr int kChunk = 32;            // staged j-clusters per pass (4 KB of LDS)
 
 // Polynomial coefficients held in registers (compile-time degree, fully
-// unrolled): F = c0 + x (c1 + x P(x)) with c0 and c1 as hi + lo pairs, and
-// G = F'(r)/r.
+// unrolled): F = c0 + x P(x) with c0 carried as hi + lo, and G = F'(r)/r,
+// each fitted separately in FP64 on the host.
 template <int DEG>
 struct Poly {
     float c[DEG + 1];
-    float c0lo, c1lo;
-    float d[DEG];
+    float c0lo;
+    float d[DEG + 1];
     __device__ __forceinline__ explicit Poly(const PairArgs& a) {
 #pragma unroll
-        for (int m = 0; m <= DEG; ++m) c[m] = a.c[m];
-#pragma unroll
-        for (int m = 0; m < DEG; ++m) d[m] = a.d[m];
+        for (int m = 0; m <= DEG; ++m) {
+            c[m] = a.c[m];
+            d[m] = a.d[m];
+        }
         c0lo = a.c0lo;
-        c1lo = a.c1lo;
     }
 };
 
@@ -146,8 +146,9 @@ __global__ void __launch_bounds__(64) k_pair(PairArgs a, const uint4* __restrict
     const float qi = __uint_as_float(ci.w);
     const float sx = a.scale[0], sy = a.scale[1], sz = a.scale[2], rc2 = a.rc2, irc2 = a.inv_rc2;
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-    double e = 0.0;
+    double e = 0.0;                      // FP32 pair energies, flushed to FP64 per chunk
     for (int base = 0; base < total; base += kChunk) {
+        float ec = 0.0f;
         const int nch = min(kChunk, total - base);
         for (int t = lane; t < nch * 8; t += 64) {
             const int p = base + (t >> 3), k = t & 7;
@@ -173,19 +174,19 @@ __global__ void __launch_bounds__(64) k_pair(PairArgs a, const uint4* __restrict
                 const float x = r2 * irc2;
                 float Pp = P.c[DEG];
 #pragma unroll
-                for (int m = DEG - 1; m >= 2; --m) Pp = fmaf(Pp, x, P.c[m]);
-                const float t1 = fmaf(Pp, x, P.c1lo) + P.c[1];
-                const float Flo = fmaf(t1, x, P.c0lo);
-                float G = P.d[DEG - 1];
+                for (int m = DEG - 1; m >= 1; --m) Pp = fmaf(Pp, x, P.c[m]);
+                const float Flo = fmaf(Pp, x, P.c0lo);
+                float G = P.d[DEG];
 #pragma unroll
-                for (int m = DEG - 2; m >= 0; --m) G = fmaf(G, x, P.d[m]);
-                e += (double)(qq * ((rinv - P.c[0]) - Flo));
+                for (int m = DEG - 1; m >= 0; --m) G = fmaf(G, x, P.d[m]);
+                ec = fmaf(qq, (rinv - P.c[0]) - Flo, ec);
                 const float fs = qq * fmaf(rinv * rinv, rinv, G);
                 fx = fmaf(fs, dx, fx);
                 fy = fmaf(fs, dy, fy);
                 fz = fmaf(fs, dz, fz);
             }
         }
+        e += (double)ec;
         wave_sync();
     }
     // force on i-charge a: sum over its 8 lanes

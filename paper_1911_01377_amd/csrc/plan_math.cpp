@@ -287,16 +287,31 @@ int solve_construction(int construction, double b, double* b_out, double* r0, do
 
 // ---------------------------------------------------------------- near polynomial
 
-double fit_near_poly(const Series& s, double rc, int degree, double* coef) {
-    // Chebyshev interpolation of f(x) = F_inf(rc sqrt(x)) on x in [0, 1] at
-    // degree+1 Chebyshev nodes, then conversion to monomials in x.
+double Series::g_inf(double r) const {
+    // F'(r) / r = -sum_j a_j / s_j^2 exp(-r^2 / (2 s_j^2)), regular at r = 0
+    double v = 0.0;
+    for (int j = length() - 1; j >= 0; --j) {
+        double a, s;
+        term(j, &a, &s);
+        v -= a / (s * s) * std::exp(-r * r / (2.0 * s * s));
+    }
+    return v;
+}
+
+namespace {
+
+// Chebyshev interpolation of f on x in [0, 1] at degree+1 Chebyshev nodes,
+// converted to monomial coefficients in x; returns the max error relative to
+// max |f| on a fine sample.
+template <class Fn>
+double fit_poly01(Fn f, int degree, double* coef) {
     const int m = degree + 1;
     double cheb[kMaxPolyDeg + 1] = {0};
     double fv[kMaxPolyDeg + 1];
     double tn[kMaxPolyDeg + 1];
     for (int k = 0; k < m; ++k) {
         const double t = std::cos(kPi * (k + 0.5) / m);
-        fv[k] = s.f_inf(rc * std::sqrt((t + 1.0) / 2.0));
+        fv[k] = f((t + 1.0) / 2.0);
         tn[k] = t;
     }
     for (int j = 0; j < m; ++j) {
@@ -327,16 +342,25 @@ double fit_near_poly(const Series& s, double rc, int degree, double* coef) {
             coef[k] += cheb[j] * tc[k];
         }
     }
-    // measured relative error of the monomial form
-    double maxerr = 0.0;
+    double maxerr = 0.0, maxf = 0.0;
     for (int i = 0; i <= 4000; ++i) {
         const double x = i / 4000.0;
         double p = 0.0;
         for (int k = degree; k >= 0; --k) p = p * x + coef[k];
-        const double f = s.f_inf(rc * std::sqrt(x));
-        maxerr = std::fmax(maxerr, std::fabs(p - f) / std::fabs(f));
+        const double v = f(x);
+        maxerr = std::fmax(maxerr, std::fabs(p - v));
+        maxf = std::fmax(maxf, std::fabs(v));
     }
-    return maxerr;
+    return maxerr / maxf;
+}
+
+}  // namespace
+
+double fit_near_poly(const Series& s, double rc, int degree, double* fcoef, double* gcoef) {
+    // F_inf(r) and F_inf'(r)/r as polynomials in x = r^2 / rc^2, fitted separately
+    const double ef = fit_poly01([&](double x) { return s.f_inf(rc * std::sqrt(x)); }, degree, fcoef);
+    const double eg = fit_poly01([&](double x) { return s.g_inf(rc * std::sqrt(x)); }, degree, gcoef);
+    return std::fmax(ef, eg);
 }
 
 // ---------------------------------------------------------------- far kernels

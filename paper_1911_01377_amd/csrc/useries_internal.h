@@ -27,6 +27,7 @@ struct Series {
     void term(int j, double* a, double* s) const;
     int length() const;                         // terms with b^-j > 1e-18
     double f_inf(double r, double* df = nullptr) const;   // all terms
+    double g_inf(double r) const;               // F_inf'(r) / r, all terms
     double f_inf0() const;                      // closed form (w0 + 1/(b-1)) 2ln b/(sqrt(2pi) sigma)
     double near_integral(double rc) const;      // int_{|r|<rc} (1/r - F_inf) d^3r
 };
@@ -38,9 +39,10 @@ double eq33_bound(int n, double b, double sigma, double lmax);
 int choose_nterms(double b, double sigma, double lmax, double tol);
 double bsa_bound(double b);
 
-// monomial coefficients c[k] of F_inf(r) ~ sum_k c_k x^k, x = r^2/rc^2 on [0,1];
-// returns the max relative error on a fine sample.
-double fit_near_poly(const Series& s, double rc, int degree, double* coef);
+// monomial coefficients in x = r^2/rc^2 on [0,1] of F_inf(r) (fcoef) and of
+// F_inf'(r)/r (gcoef), each fitted separately; returns the larger of the two
+// max errors relative to the function's max magnitude, on a fine sample.
+double fit_near_poly(const Series& s, double rc, int degree, double* fcoef, double* gcoef);
 
 // first column k[m], m = 0..n-1, of the periodic circulant that convolves the
 // grid with a Gaussian of width sk (grid spacing h), scaled by `scale`.
@@ -64,8 +66,8 @@ struct PairArgs {
     float inv_rc2;        // 1 / r_c^2
     int deg;              // polynomial degree
     float c[kMaxPolyDeg + 1];   // F_inf(r) = sum c_k x^k, x = r^2/rc^2
-    float c0lo, c1lo;           // c_0 - (float)c_0 and c_1 - (float)c_1
-    float d[kMaxPolyDeg];       // F_inf'(r)/r = sum d_k x^k
+    float c0lo;                 // c_0 - (float)c_0
+    float d[kMaxPolyDeg + 1];   // F_inf'(r)/r = sum d_k x^k
 };
 
 struct GridArgs {
