@@ -69,6 +69,9 @@ def main():
     ap.add_argument("--form", choices=["bf16x3", "plain"], default="bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a known-size "
+                         "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the u-series hot path here is a single-GPU "
@@ -101,6 +104,16 @@ def main():
         t1.record(stream)
         torch.cuda.synchronize()
         return t0.elapsed_time(t1) / steps
+
+    if args.copy_probe_mib > 0:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: %d bytes read, %d bytes written" % (nb, nb))
+        del src, dst
 
     forms = {"bf16x3": USERIES_BF16X3, "plain": USERIES_PLAIN_FP32}
     plans = {k: Plan(box, rc, grid, precision=v) for k, v in forms.items()}
