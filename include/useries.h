@@ -183,6 +183,140 @@ int useries_timing_enable(useries_plan_t plan, int enable);
 int useries_timing_read(useries_plan_t plan, int k, const char **name, double *total_ms,
                         int64_t *launches);
 
+/* ----------------------------------------------------------- serving */
+/*
+ * A server evaluates a stream of independent requests.  Each request is one
+ * periodic cell (its own box, cutoff, grid and charges) evaluated n_evals
+ * times; between two evaluations every coordinate moves by a normal deviate
+ * of standard deviation disp_sigma drawn on the device from Philox4x32-10
+ * (counter: charge index, evaluation index; key: the request's seed), so a
+ * request's trajectory depends on nothing but the request.
+ *
+ * Continuous batching: a worker thread owns one HIP stream.  All running
+ * requests advance together, one evaluation per step, in one sequence of
+ * batched kernels (one captured HIP graph replay per step): every kernel
+ * takes a table of the boxes in the batch and the per-box work-item offsets.
+ * Between steps finished requests leave and waiting ones are admitted, as
+ * batch slots and device memory allow.  Each request's positions, cell
+ * lists, grids and convolution matrices stay resident in a device arena of
+ * hbm_budget bytes, allocated once; a request is admitted when a slot is
+ * free and its workspace fits in the arena (first fit, in arrival order,
+ * with later requests allowed ahead of a waiting one for a bounded number of
+ * rounds).  The arithmetic of a box does not depend on the rest of the batch:
+ * each result is bitwise the same alone and in any mix.
+ *
+ * Parameters of every request: the construction and b of the server options,
+ * sigma = r_c / r0, the eq. 33 term count at the options' tolerance, and the
+ * precision form of the server.
+ */
+typedef struct useries_server_s *useries_server_t;
+
+/* request states */
+enum {
+    USERIES_PENDING = 0,   /* queued, not yet admitted */
+    USERIES_RUNNING = 1,   /* admitted: resident on the device, evaluations in progress */
+    USERIES_DONE = 2,      /* outputs written to the request's host buffers */
+    USERIES_ERROR = 3      /* failed; useries_poll sets the message of useries_last_error() */
+};
+
+/*
+ * One request.  Every pointer is host memory owned by the caller and must
+ * stay valid until useries_poll reports DONE or ERROR.
+ *   n          charges, >= 1.
+ *   xyz, q     [n][3] positions (A, any image) and [n] charges (e).
+ *   box        cell edges; r_c cutoff (0 < r_c < min(L)/2); grid points per
+ *              axis (2P <= n_a <= 128).
+ *   n_evals    evaluations, >= 1.
+ *   disp_sigma displacement per coordinate between evaluations (A), >= 0.
+ *   seed       Philox key of the request's displacements.
+ *   energies   [n_evals] out: total energy of each evaluation.
+ *   forces     [n][3] out: forces of the last evaluation, input order.
+ *   xyz_final  [n][3] out, or NULL: positions of the last evaluation.
+ */
+typedef struct {
+    int64_t n;
+    const float *xyz;
+    const float *q;
+    double box[3];
+    double r_c;
+    int grid[3];
+    int n_evals;
+    double disp_sigma;
+    uint64_t seed;
+    double *energies;
+    float *forces;
+    float *xyz_final;
+} useries_request;
+
+/*
+ * Server options (useries_server_default_opts fills the defaults).
+ *   construction, b, nterms_tol, poly_degree: as in useries_opts / useries_plan
+ *              (defaults C1, b = 2, 1e-8, 8).
+ *   use_graph  1: one captured HIP graph per step (default); 0: the same
+ *              kernels launched one by one.
+ *   inflight   steps enqueued ahead of the device (1..4, default 2).
+ */
+typedef struct {
+    int construction;
+    double b;
+    double nterms_tol;
+    int poly_degree;
+    int use_graph;
+    int inflight;
+} useries_server_opts;
+
+int useries_server_default_opts(useries_server_opts *opts);
+
+/*
+ * Create a server on the current HIP device.
+ *   hbm_budget_bytes  device memory for the resident request workspaces
+ *                     (allocated at once; >= 1 MiB).
+ *   max_slots         requests in flight together, 1..64.
+ *   precision         USERIES_PLAIN_FP32 or USERIES_BF16X3.
+ *   opts              NULL for the defaults.
+ * Errors: USERIES_EINVAL, USERIES_ENOMEM (budget not available), USERIES_EHIP.
+ */
+int useries_server_create(useries_server_t *out, size_t hbm_budget_bytes, int max_slots,
+                          int precision, const useries_server_opts *opts);
+
+/*
+ * Queue a request (non-blocking apart from the host FP64 plan math of the
+ * request's cell).  *ticket receives its handle.  A request that can never
+ * fit (workspace above the budget, grid beyond the device's LDS) fails here
+ * with USERIES_ENOMEM / USERIES_EINVAL and gets no ticket.
+ */
+int useries_submit(useries_server_t server, const useries_request *req, uint64_t *ticket);
+
+/* hold != 0: admit no further requests (running ones go on); hold = 0:
+ * resume.  Lets a caller queue a group that is then admitted together. */
+int useries_server_hold(useries_server_t server, int hold);
+
+/* Current state of a ticket (USERIES_PENDING .. USERIES_ERROR).
+ * USERIES_ENOTFOUND for an unknown ticket. */
+int useries_poll(useries_server_t server, uint64_t ticket, int *state);
+
+/* Block until the ticket is DONE or ERROR; *state receives the final state. */
+int useries_wait(useries_server_t server, uint64_t ticket, int *state);
+
+/* Host wall-clock times (s, since the server's creation) of a ticket's
+ * submission, admission to the device and completion (negative if not yet). */
+int useries_request_times(useries_server_t server, uint64_t ticket, double *t_submit,
+                          double *t_admit, double *t_done);
+
+/*
+ * Counters: out[0] steps launched, out[1] evaluations completed,
+ * out[2] requests completed, out[3] largest batch, out[4] summed batch size
+ * over steps, out[5] graphs instantiated.
+ */
+int useries_server_stats(useries_server_t server, int64_t out[6]);
+
+/* Finish every queued request, stop the worker and free the server. */
+int useries_server_destroy(useries_server_t server);
+
+/* Host copy of the Philox4x32-10 bijection the displacements use
+ * (counter[4], key[2] -> out[4]); for known-answer tests. */
+void useries_philox4x32_10(const uint32_t counter[4], const uint32_t key[2], uint32_t out[4]);
+
 /* ----------------------------------------------------------- host math */
 /* These touch no device and may be called without a GPU. */
 

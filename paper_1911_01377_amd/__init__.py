@@ -8,11 +8,13 @@ tensors (PyTorch provides device memory and streams only).
 from . import _native
 from ._native import (USERIES_C0, USERIES_C1, USERIES_C2_B2, USERIES_TABLE1_ROW1,
                       USERIES_TABLE1_ROW2, USERIES_TABLE1_ROW3, USERIES_PLAIN_FP32,
-                      USERIES_BF16X3, UseriesError)
+                      USERIES_BF16X3, USERIES_PENDING, USERIES_RUNNING, USERIES_DONE,
+                      USERIES_ERROR, UseriesError)
 
-__all__ = ["Plan", "UseriesError", "USERIES_C0", "USERIES_C1", "USERIES_C2_B2",
+__all__ = ["Plan", "Server", "UseriesError", "USERIES_C0", "USERIES_C1", "USERIES_C2_B2",
            "USERIES_TABLE1_ROW1", "USERIES_TABLE1_ROW2", "USERIES_TABLE1_ROW3",
-           "USERIES_PLAIN_FP32", "USERIES_BF16X3"]
+           "USERIES_PLAIN_FP32", "USERIES_BF16X3", "USERIES_PENDING", "USERIES_RUNNING",
+           "USERIES_DONE", "USERIES_ERROR"]
 
 
 class Plan:
@@ -76,6 +78,93 @@ class Plan:
         if self.handle:
             _native.useries_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server of independent cells (useries_server_* of the C ABI).
+
+    Server(hbm_budget_bytes, max_slots=32, precision=USERIES_BF16X3, **opts)
+    ``opts`` may set construction, b, nterms_tol, poly_degree, use_graph, inflight.
+    The host arrays of a request are kept alive here until it is collected.
+    """
+
+    def __init__(self, hbm_budget_bytes, max_slots=32, precision=USERIES_BF16X3, **opts):
+        o = _native.useries_server_default_opts()
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise TypeError("unknown option %s" % k)
+            setattr(o, k, v)
+        self.handle = _native.useries_server_create(hbm_budget_bytes, max_slots, precision, o)
+        self._live = {}
+
+    def submit(self, xyz, q, box, r_c, grid, n_evals=1, disp_sigma=0.0, seed=0,
+               want_positions=False):
+        """Queue one request; returns its ticket.  xyz float32 [n, 3], q float32 [n]
+        (host arrays)."""
+        import numpy as np
+        xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+        q = np.ascontiguousarray(q, dtype=np.float32)
+        n = int(q.shape[0])
+        if xyz.shape != (n, 3):
+            raise ValueError("xyz must be [n, 3]")
+        energies = np.zeros(int(n_evals), dtype=np.float64)
+        forces = np.zeros((n, 3), dtype=np.float32)
+        xyz_final = np.zeros((n, 3), dtype=np.float32) if want_positions else None
+        r = _native.useries_request()
+        r.n = n
+        r.xyz = xyz.ctypes.data
+        r.q = q.ctypes.data
+        for a in range(3):
+            r.box[a] = float(box[a])
+            r.grid[a] = int(grid[a])
+        r.r_c = float(r_c)
+        r.n_evals = int(n_evals)
+        r.disp_sigma = float(disp_sigma)
+        r.seed = int(seed) & 0xffffffffffffffff
+        r.energies = energies.ctypes.data
+        r.forces = forces.ctypes.data
+        r.xyz_final = xyz_final.ctypes.data if xyz_final is not None else None
+        t = _native.useries_submit(self.handle, r)
+        self._live[t] = (xyz, q, energies, forces, xyz_final)
+        return t
+
+    def poll(self, ticket):
+        return _native.useries_poll(self.handle, ticket)
+
+    def wait(self, ticket):
+        return _native.useries_wait(self.handle, ticket)
+
+    def result(self, ticket):
+        """Wait for the ticket; returns dict(energies, forces, xyz_final, times) and
+        releases the host arrays held for it.  Raises UseriesError if it failed."""
+        st = _native.useries_wait(self.handle, ticket)
+        _, _, energies, forces, xyz_final = self._live.pop(ticket)
+        if st != USERIES_DONE:
+            raise UseriesError(_native.USERIES_EHIP, _native.useries_last_error())
+        return dict(energies=energies, forces=forces, xyz_final=xyz_final,
+                    times=_native.useries_request_times(self.handle, ticket))
+
+    def times(self, ticket):
+        return _native.useries_request_times(self.handle, ticket)
+
+    def stats(self):
+        return _native.useries_server_stats(self.handle)
+
+    def hold(self, hold=True):
+        """Pause (True) or resume (False) admissions."""
+        _native.useries_server_hold(self.handle, hold)
+
+    def close(self):
+        if self.handle:
+            _native.useries_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
 
     def __del__(self):
         try:

@@ -31,12 +31,21 @@ USERIES_TABLE1_ROW3 = 13
 USERIES_PLAIN_FP32 = 0
 USERIES_BF16X3 = 1
 
+USERIES_PENDING = 0
+USERIES_RUNNING = 1
+USERIES_DONE = 2
+USERIES_ERROR = 3
+
 # every symbol include/useries.h declares
 EXPORTED = [
     "useries_default_opts", "useries_plan", "useries_eval", "useries_eval_parts",
     "useries_plan_info", "useries_destroy", "useries_timing_enable", "useries_timing_read",
     "useries_solve_construction", "useries_eq33_bound", "useries_choose_nterms",
     "useries_bsa_bound", "useries_strerror", "useries_last_error",
+    "useries_server_default_opts", "useries_server_create", "useries_submit", "useries_poll",
+    "useries_wait", "useries_request_times", "useries_server_stats", "useries_server_destroy",
+    "useries_server_hold",
+    "useries_philox4x32_10",
 ]
 
 
@@ -51,6 +60,21 @@ class useries_opts(ctypes.Structure):
                 ("sigma_s_over_h", ctypes.c_double), ("stencil_half", ctypes.c_int),
                 ("nterms_tol", ctypes.c_double), ("poly_degree", ctypes.c_int),
                 ("max_atoms", ctypes.c_int64)]
+
+
+class useries_request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("xyz", ctypes.c_void_p), ("q", ctypes.c_void_p),
+                ("box", ctypes.c_double * 3), ("r_c", ctypes.c_double),
+                ("grid", ctypes.c_int * 3), ("n_evals", ctypes.c_int),
+                ("disp_sigma", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("energies", ctypes.c_void_p), ("forces", ctypes.c_void_p),
+                ("xyz_final", ctypes.c_void_p)]
+
+
+class useries_server_opts(ctypes.Structure):
+    _fields_ = [("construction", ctypes.c_int), ("b", ctypes.c_double),
+                ("nterms_tol", ctypes.c_double), ("poly_degree", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("inflight", ctypes.c_int)]
 
 
 _lib = None
@@ -81,6 +105,16 @@ def lib():
         "useries_bsa_bound": (D, [D]),
         "useries_strerror": (ctypes.c_char_p, [I]),
         "useries_last_error": (ctypes.c_char_p, []),
+        "useries_server_default_opts": (I, [P]),
+        "useries_server_create": (I, [P, ctypes.c_size_t, I, I, P]),
+        "useries_submit": (I, [P, P, P]),
+        "useries_poll": (I, [P, ctypes.c_uint64, P]),
+        "useries_wait": (I, [P, ctypes.c_uint64, P]),
+        "useries_request_times": (I, [P, ctypes.c_uint64, P, P, P]),
+        "useries_server_stats": (I, [P, P]),
+        "useries_server_destroy": (I, [P]),
+        "useries_server_hold": (I, [P, I]),
+        "useries_philox4x32_10": (None, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -194,6 +228,69 @@ def useries_choose_nterms(b, sigma, lmax, tol):
 
 def useries_bsa_bound(b):
     return lib().useries_bsa_bound(float(b))
+
+
+def useries_server_default_opts():
+    o = useries_server_opts()
+    _check(lib().useries_server_default_opts(ctypes.byref(o)))
+    return o
+
+
+def useries_server_create(hbm_budget_bytes, max_slots, precision, opts=None):
+    h = ctypes.c_void_p()
+    _check(lib().useries_server_create(ctypes.byref(h), int(hbm_budget_bytes), int(max_slots),
+                                       int(precision),
+                                       ctypes.byref(opts) if opts is not None else None))
+    return h.value
+
+
+def useries_submit(server, req):
+    """req: a useries_request; returns the ticket."""
+    t = ctypes.c_uint64()
+    _check(lib().useries_submit(server, ctypes.byref(req), ctypes.byref(t)))
+    return t.value
+
+
+def useries_poll(server, ticket):
+    s = ctypes.c_int()
+    _check(lib().useries_poll(server, ctypes.c_uint64(ticket), ctypes.byref(s)))
+    return s.value
+
+
+def useries_wait(server, ticket):
+    s = ctypes.c_int()
+    _check(lib().useries_wait(server, ctypes.c_uint64(ticket), ctypes.byref(s)))
+    return s.value
+
+
+def useries_request_times(server, ticket):
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().useries_request_times(server, ctypes.c_uint64(ticket), ctypes.byref(a),
+                                       ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def useries_server_stats(server):
+    out = (ctypes.c_int64 * 6)()
+    _check(lib().useries_server_stats(server, out))
+    keys = ("steps", "evals", "requests", "max_batch", "sum_batch", "graphs")
+    return dict(zip(keys, (int(v) for v in out)))
+
+
+def useries_server_hold(server, hold):
+    _check(lib().useries_server_hold(server, int(bool(hold))))
+
+
+def useries_server_destroy(server):
+    _check(lib().useries_server_destroy(server))
+
+
+def useries_philox4x32_10(counter, key):
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xffffffff for v in counter])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xffffffff for v in key])
+    out = (ctypes.c_uint32 * 4)()
+    lib().useries_philox4x32_10(c, k, out)
+    return [int(v) for v in out]
 
 
 def useries_strerror(code):

@@ -17,10 +17,6 @@
 
 using namespace useries;
 
-namespace useries {
-size_t conv_xy_lds_bytes(const ConvArgs& a);
-}
-
 namespace {
 
 thread_local std::string g_last_error;
@@ -38,18 +34,6 @@ constexpr const char* kKernelNames[] = {"encode", "scan",   "scatter", "colsort"
                                         "spread", "conv_xy", "conv_z", "gather",  "finalize"};
 constexpr int kNumKernels = sizeof(kKernelNames) / sizeof(kKernelNames[0]);
 
-uint16_t host_bf16(float v) {
-    uint32_t u;
-    std::memcpy(&u, &v, 4);
-    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
-float host_bf16_val(uint16_t h) {
-    uint32_t u = (uint32_t)h << 16;
-    float v;
-    std::memcpy(&v, &u, 4);
-    return v;
-}
-
 template <class T>
 hipError_t dalloc(T** p, size_t count) {
     *p = nullptr;
@@ -59,27 +43,17 @@ hipError_t dalloc(T** p, size_t count) {
 
 }  // namespace
 
+namespace useries {
+int set_last_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace useries
+
 struct useries_plan_s {
     int device = 0;
-    // parameters
-    double box[3] = {0, 0, 0};
-    double rc = 0, b = 2, sigma = 1, r0 = 1, w0 = 1, s0 = 1;
-    int construction = USERIES_C1, precision = USERIES_PLAIN_FP32;
-    int nterms = 0;
-    double eq33 = 0, f_inf0 = 0, c1_slope = 0, poly_maxerr = 0, sigma_s[3] = {0, 0, 0};
-    int P = 5;
-    int grid[3] = {0, 0, 0};
-    int ncmax[2] = {1, 1};   // x-y column grid bounds (the grid itself is chosen per evaluation)
-    int ncol_max = 1;
+    HostPlan hp;
     int nc_used[2] = {0, 0};
-    // kernel arguments
-    BinArgs bin{};
-    PairArgs pair{};
-    GridArgs gridargs{};
-    ConvArgs conv{};
-    FinalArgs fin{};
+    bool counts_dirty = false;   // column counters may be non-zero (an evaluation failed midway)
     // device constants
-    float *kx = nullptr, *ky = nullptr, *kz = nullptr;
+    void *kx = nullptr, *ky = nullptr, *kz = nullptr;
     // fixed workspace
     int *col_count = nullptr, *col_start = nullptr, *col_fill = nullptr, *clus_start = nullptr;
     double *qstats = nullptr, *parts_tmp = nullptr;
@@ -92,7 +66,6 @@ struct useries_plan_s {
     int2* cl_info = nullptr;
     int* cl_col = nullptr;
     uint2* cl_z = nullptr;
-    int64_t clmax = 0;
     float4* fnear = nullptr;
     double *qpart = nullptr, *pair_parts = nullptr, *gather_parts = nullptr;
     // timing
@@ -132,13 +105,13 @@ struct useries_plan_s {
     int alloc_atoms(int64_t n) {
         free_atoms();
         const int64_t c = std::max<int64_t>(n, 256);
+        // clusters: at most sum over columns of ceil(count / 8)
+        const int64_t clmax = pair_blocks((int)c, hp.ncol_max);
         hipError_t e;
-        clmax = c / 8 + 1 + ncol_max;   // clusters: sum over columns of ceil(count / 8)
         if ((e = dalloc(&coord, c)) || (e = dalloc(&sorted, c)) || (e = dalloc(&col_of, c)) ||
             (e = dalloc(&perm, c)) || (e = dalloc(&slots, c)) || (e = dalloc(&cl_info, clmax)) ||
             (e = dalloc(&cl_col, clmax)) || (e = dalloc(&cl_z, clmax)) ||
-            (e = dalloc(&pair_parts, clmax)) ||
-            (e = dalloc(&fnear, (size_t)kPairSlices * c)) ||
+            (e = dalloc(&pair_parts, clmax)) || (e = dalloc(&fnear, c)) ||
             (e = dalloc(&qpart, 2 * (size_t)((c + 255) / 256))) ||
             (e = dalloc(&gather_parts, (size_t)gather_blocks((int)c)))) {
             free_atoms();
@@ -205,40 +178,6 @@ struct DeviceGuard {
     }
 };
 
-int upload_matrices(useries_plan_s* p, const std::vector<double> (&mats)[3]) {
-    // mats[a] holds nterms padded gp x gp matrices (row-major) per axis
-    float** dst[3] = {&p->kx, &p->ky, &p->kz};
-    for (int a = 0; a < 3; ++a) {
-        const size_t m = (size_t)p->conv.gp[a] * p->conv.gp[a];
-        hipError_t e;
-        if (p->precision == USERIES_BF16X3) {
-            std::vector<uint16_t> h(2 * m * p->nterms);
-            for (int t = 0; t < p->nterms; ++t)
-                for (size_t k = 0; k < m; ++k) {
-                    const float v = (float)mats[a][t * m + k];
-                    const uint16_t hi = host_bf16(v);
-                    const uint16_t lo = host_bf16(v - host_bf16_val(hi));
-                    h[2 * m * t + k] = hi;
-                    h[2 * m * t + m + k] = lo;
-                }
-            if ((e = hipMalloc((void**)dst[a], h.size() * sizeof(uint16_t))))
-                return fail(USERIES_ENOMEM, "convolution matrices");
-            if ((e = hipMemcpy(*dst[a], h.data(), h.size() * sizeof(uint16_t),
-                               hipMemcpyHostToDevice)))
-                return hip_fail(e, "upload");
-        } else {
-            std::vector<float> h(m * p->nterms);
-            for (size_t k = 0; k < h.size(); ++k) h[k] = (float)mats[a][k];
-            if ((e = hipMalloc((void**)dst[a], h.size() * sizeof(float))))
-                return fail(USERIES_ENOMEM, "convolution matrices");
-            if ((e = hipMemcpy(*dst[a], h.data(), h.size() * sizeof(float),
-                               hipMemcpyHostToDevice)))
-                return hip_fail(e, "upload");
-        }
-    }
-    return USERIES_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -259,182 +198,57 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
                  int n_terms, const int grid[3], const useries_opts* opts) {
     if (!out || !box || !grid) return fail(USERIES_EINVAL, "NULL argument");
     *out = nullptr;
-    useries_opts o;
-    useries_default_opts(&o);
-    if (opts) o = *opts;
-    if (o.precision != USERIES_PLAIN_FP32 && o.precision != USERIES_BF16X3)
-        return fail(USERIES_EINVAL, "unknown precision");
-    const bool bf = o.precision == USERIES_BF16X3;
-    const double ratio = o.sigma_s_over_h > 0 ? o.sigma_s_over_h : (bf ? 0.83 : 0.9);
-    const int P = o.stencil_half > 0 ? o.stencil_half : (bf ? 4 : 5);
-    const int deg = o.poly_degree > 0 ? o.poly_degree : 8;
-    if (P < 1 || P > kMaxStencilHalf) return fail(USERIES_EINVAL, "stencil_half out of [1, 8]");
-    if (deg < 4 || deg > kMaxPolyDeg) return fail(USERIES_EINVAL, "poly_degree out of [4, 14]");
-    if (!(o.nterms_tol > 0)) return fail(USERIES_EINVAL, "nterms_tol must be > 0");
-    double lmin = 1e300, lmax = 0;
-    for (int a = 0; a < 3; ++a) {
-        if (!(box[a] > 0) || !std::isfinite(box[a])) return fail(USERIES_EINVAL, "box edges must be > 0");
-        lmin = std::min(lmin, box[a]);
-        lmax = std::max(lmax, box[a]);
-        if (grid[a] < 2 * P || grid[a] > kMaxGrid)
-            return fail(USERIES_EINVAL, "grid points per axis must lie in [2P, 128]");
-    }
-    if (!(r_c > 0) || !(r_c < 0.5 * lmin)) return fail(USERIES_EINVAL, "need 0 < r_c < min(L)/2");
-    if (n_terms > kMaxTerms) return fail(USERIES_EINVAL, "n_terms > 32");
-
-    double bb, r0c, w0c, s0c;
-    std::string err;
-    int rc = solve_construction(o.construction, b, &bb, &r0c, &w0c, &s0c, &err);
-    if (rc) return fail(rc, err);
-
+    if (opts && opts->max_atoms > INT_MAX / 4) return fail(USERIES_EINVAL, "max_atoms too large");
     auto* p = new useries_plan_s();
+    std::string err;
+    int r = build_host_plan(&p->hp, box, r_c, b, sigma, n_terms, grid, opts, &err);
+    if (r) {
+        delete p;
+        return fail(r, err);
+    }
     hipGetDevice(&p->device);
-    std::memcpy(p->box, box, sizeof(p->box));
-    std::memcpy(p->grid, grid, sizeof(p->grid));
-    p->rc = r_c;
-    p->b = bb;
-    p->s0 = s0c;
-    p->construction = o.construction;
-    p->precision = o.precision;
-    p->P = P;
-    const bool preset = o.construction != USERIES_C0 && o.construction != USERIES_C1;
-    if (sigma <= 0) {
-        p->r0 = r0c;
-        p->w0 = w0c;
-        p->sigma = r_c / r0c;
-    } else if (preset) {
-        if (std::fabs(sigma * r0c / r_c - 1.0) > 1e-12) {
-            delete p;
-            return fail(USERIES_EINVAL, "preset constructions fix sigma = r_c / r0");
-        }
-        p->r0 = r0c;
-        p->w0 = w0c;
-        p->sigma = sigma;
-    } else {
-        // continuity correction: keep r_c, re-solve w0 of eq. 25 at r0 = r_c / sigma
-        p->sigma = sigma;
-        p->r0 = r_c / sigma;
-        p->w0 = c1_w0_of_r0(bb, p->r0);
-    }
-    p->nterms = n_terms > 0 ? n_terms : choose_nterms(bb, p->sigma, lmax, o.nterms_tol);
-    p->eq33 = eq33_bound(p->nterms, bb, p->sigma, lmax);
-
-    Series s;
-    s.b = bb;
-    s.sigma = p->sigma;
-    s.w0 = p->w0;
-    s.s0 = p->s0;
-    p->f_inf0 = s.f_inf0();
-    double dF;
-    s.f_inf(r_c, &dF);
-    p->c1_slope = -1.0 / (r_c * r_c) - dF;
-
-    // near part
-    double coef[kMaxPolyDeg + 1], gcoef[kMaxPolyDeg + 1];
-    p->poly_maxerr = fit_near_poly(s, r_c, deg, coef, gcoef);
-    PairArgs& pa = p->pair;
-    pa.deg = deg;
-    for (int k = 0; k <= deg; ++k) pa.c[k] = (float)coef[k];
-    pa.c0lo = (float)(coef[0] - (double)pa.c[0]);
-    for (int k = 0; k <= deg; ++k) pa.d[k] = (float)gcoef[k];
-    pa.rc2 = (float)(r_c * r_c);
-    pa.inv_rc2 = (float)(1.0 / (r_c * r_c));
-
-    // x-y columns: at least r_c / 4 wide (so the pair stencil stays within
-    // 9 x 9 columns), and wide enough that a spreading brick touches at most
-    // 16 columns per axis; the grid used is chosen per evaluation from n
-    for (int a = 0; a < 2; ++a) {
-        const double h = box[a] / grid[a];
-        const double wmin = std::max(0.25 * r_c, (8 + 2 * P - 1) * h / 14.0);
-        p->ncmax[a] = std::max(1, (int)std::floor(box[a] / wmin));
-    }
-    while ((int64_t)p->ncmax[0] * p->ncmax[1] > (1 << 20)) {
-        const int am = p->ncmax[1] > p->ncmax[0] ? 1 : 0;
-        p->ncmax[am] = std::max(1, p->ncmax[am] * 3 / 4);
-    }
-    p->ncol_max = p->ncmax[0] * p->ncmax[1];
-    for (int a = 0; a < 3; ++a) {
-        p->bin.inv_box[a] = 1.0 / box[a];
-        pa.scale[a] = (float)(box[a] / 4294967296.0);
-    }
-    pa.zinv = (float)(4294967296.0 / box[2]);
-
-    // far part
-    GridArgs& ga = p->gridargs;
-    ga.P = P;
-    ga.inv_ngrid = 1.0 / ((double)grid[0] * grid[1] * grid[2]);
-    ConvArgs& ca = p->conv;
-    ca.nterms = p->nterms;
-    ca.bf16x3 = bf ? 1 : 0;
-    const double pi = 3.14159265358979323846;
-    std::vector<double> mats[3];
-    for (int a = 0; a < 3; ++a) {
-        const double h = box[a] / grid[a];
-        const double ss = ratio * h;
-        p->sigma_s[a] = ss;
-        ga.g[a] = ca.g[a] = grid[a];
-        // padded to the MFMA K step: 4 (FP32, tiles of 16) or 32 (BF16)
-        ca.gp[a] = bf ? (grid[a] + 31) / 32 * 32 : (grid[a] + 15) / 16 * 16;
-        ga.hs[a] = (float)(h * h / (2.0 * ss * ss));
-        ga.cw[a] = (float)(h / (std::sqrt(2.0 * pi) * ss));
-        ga.dws[a] = (float)(h / (ss * ss));
-        const int g = grid[a], gp = ca.gp[a];
-        mats[a].assign((size_t)p->nterms * gp * gp, 0.0);
-        std::vector<double> col(g);
-        for (int t = 0; t < p->nterms; ++t) {
-            double at, st;
-            s.term(t, &at, &st);
-            const double sk2 = st * st - 2.0 * ss * ss;
-            if (!(sk2 > 0)) {
-                delete p;
-                return fail(USERIES_EINVAL,
-                            "grid too coarse: the spreading Gaussian must be narrower than "
-                            "s_0 / sqrt(2)");
-            }
-            const double sk = std::sqrt(sk2);
-            circulant_column(g, h, sk, (st / sk) * (a == 0 ? at : 1.0), col.data());
-            double* M = mats[a].data() + (size_t)t * gp * gp;
-            for (int i = 0; i < g; ++i)
-                for (int j = 0; j < g; ++j) M[(size_t)i * gp + j] = col[((i - j) % g + g) % g];
-        }
-    }
-    const double V = box[0] * box[1] * box[2];
-    p->fin.f_inf0 = p->f_inf0;
-    p->fin.near_int_over_v = s.near_integral(r_c) / V;
+    const HostPlan& hp = p->hp;
 
     // device limits
     int lds_max = 0;
     hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
-    if (lds_max > 0 && conv_xy_lds_bytes(ca) > (size_t)lds_max) {
+    if (lds_max > 0 && conv_xy_lds_bytes(hp.conv) > (size_t)lds_max) {
         char buf[160];
         std::snprintf(buf, sizeof buf, "grid plane needs %zu bytes of LDS, device allows %d",
-                      conv_xy_lds_bytes(ca), lds_max);
+                      conv_xy_lds_bytes(hp.conv), lds_max);
         delete p;
         return fail(USERIES_EINVAL, buf);
     }
 
     // device memory
-    int r = upload_matrices(p, mats);
-    if (r) {
-        delete p;
-        return r;
-    }
-    const size_t ng = (size_t)grid[0] * grid[1] * grid[2];
+    void** dst[3] = {&p->kx, &p->ky, &p->kz};
     hipError_t e;
-    if ((e = dalloc(&p->col_count, p->ncol_max)) || (e = dalloc(&p->col_fill, p->ncol_max)) ||
-        (e = dalloc(&p->col_start, p->ncol_max + 1)) ||
-        (e = dalloc(&p->clus_start, p->ncol_max + 1)) || (e = dalloc(&p->qstats, 2)) ||
+    for (int a = 0; a < 3; ++a) {
+        if ((e = hipMalloc(dst[a], hp.mats[a].size()))) {
+            delete p;
+            return fail(USERIES_ENOMEM, "convolution matrices");
+        }
+        if ((e = hipMemcpy(*dst[a], hp.mats[a].data(), hp.mats[a].size(), hipMemcpyHostToDevice))) {
+            delete p;
+            return hip_fail(e, "upload");
+        }
+    }
+    const size_t ng = (size_t)hp.grid[0] * hp.grid[1] * hp.grid[2];
+    if ((e = dalloc(&p->col_count, hp.ncol_max)) || (e = dalloc(&p->col_fill, hp.ncol_max)) ||
+        (e = dalloc(&p->col_start, hp.ncol_max + 1)) ||
+        (e = dalloc(&p->clus_start, hp.ncol_max + 1)) || (e = dalloc(&p->qstats, 2)) ||
         (e = dalloc(&p->parts_tmp, 5)) || (e = dalloc(&p->rho, ng)) ||
-        (e = dalloc(&p->tgrid, ng * p->nterms)) || (e = dalloc(&p->phi, ng))) {
+        (e = dalloc(&p->tgrid, ng * hp.nterms)) || (e = dalloc(&p->phi, ng))) {
         delete p;
         return fail(USERIES_ENOMEM, std::string("plan allocation: ") + hipGetErrorString(e));
     }
-    if (o.max_atoms > 0) {
-        if (o.max_atoms > INT_MAX / 4) {
-            delete p;
-            return fail(USERIES_EINVAL, "max_atoms too large");
-        }
-        r = p->alloc_atoms(o.max_atoms);
+    // the column counters start at zero; each evaluation's scan clears them again
+    if ((e = hipMemset(p->col_count, 0, sizeof(int) * hp.ncol_max))) {
+        delete p;
+        return hip_fail(e, "memset");
+    }
+    if (opts && opts->max_atoms > 0) {
+        r = p->alloc_atoms(opts->max_atoms);
         if (r) {
             delete p;
             return r;
@@ -458,29 +272,21 @@ static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float*
         int r = p->alloc_atoms(n);
         if (r) return r;
     }
+    HostPlan& hp = p->hp;
     const int ni = (int)n;
     const int nq = (ni + 255) / 256;
-    // x-y columns for this n: about 8 charges per cluster of one column
-    // cross-section and similar z extent, within the plan's bounds
-    {
-        const double V = p->box[0] * p->box[1] * p->box[2];
-        const double w = ni > 0 ? std::cbrt(8.0 * V / ni) : 1e300;
-        for (int a = 0; a < 2; ++a) {
-            const int nc = std::max(1, std::min(p->ncmax[a], (int)std::floor(p->box[a] / w)));
-            p->bin.nc[a] = p->pair.nc[a] = p->gridargs.nc[a] = p->nc_used[a] = nc;
-            p->pair.cw[a] = (float)(p->box[a] / nc);
-            p->pair.R[a] = (int)std::ceil(p->rc * nc / p->box[a]);
-        }
-    }
-    const int ncol = p->bin.nc[0] * p->bin.nc[1];
-    const int npb = ni / 8 + 1 + ncol, ngb = gather_blocks(ni);
-    p->bin.n = p->pair.n = p->gridargs.n = ni;
-    p->fin.n_pair_parts = npb;
-    p->fin.n_gather_parts = ngb;
+    choose_columns(&hp, ni);
+    p->nc_used[0] = hp.bin.nc[0];
+    p->nc_used[1] = hp.bin.nc[1];
+    const int ncol = hp.bin.nc[0] * hp.bin.nc[1];
+    const int npb = hp.fin.n_pair_parts, ngb = hp.fin.n_gather_parts;
     if (!parts && !energy) parts = p->parts_tmp;
 
-    hipError_t e = hipMemsetAsync(p->col_count, 0, sizeof(int) * ncol, st);
-    if (e) return hip_fail(e, "memset");
+    if (p->counts_dirty) {
+        hipError_t e = hipMemsetAsync(p->col_count, 0, sizeof(int) * hp.ncol_max, st);
+        if (e) return hip_fail(e, "memset");
+        p->counts_dirty = false;
+    }
     int k = 0;
     hipEvent_t ev0 = nullptr;
     auto pre = [&]() {
@@ -496,29 +302,34 @@ static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float*
             p->pending.push_back({k, ev0, ev1});
         }
         ++k;
+        if (err != hipSuccess) p->counts_dirty = true;
         return err;
     };
-#define USERIES_STEP(call)                                             \
-    do {                                                               \
-        pre();                                                         \
-        hipError_t err_ = post(call);                                  \
+#define USERIES_STEP(call)                                                  \
+    do {                                                                    \
+        pre();                                                              \
+        hipError_t err_ = post(call);                                       \
         if (err_ != hipSuccess) return hip_fail(err_, kKernelNames[k - 1]); \
     } while (0)
-    USERIES_STEP(launch_encode(p->bin, xyz, q, p->coord, p->col_of, p->col_count, p->qpart, nq, st));
+    const float* kx = (const float*)p->kx;
+    const float* ky = (const float*)p->ky;
+    const float* kz = (const float*)p->kz;
+    USERIES_STEP(launch_encode(hp.bin, xyz, q, p->coord, p->col_of, p->col_count, p->qpart, nq, st));
     USERIES_STEP(launch_scan(ncol, p->col_count, p->col_start, p->clus_start, p->col_fill, p->qpart,
                              nq, p->qstats, st));
     USERIES_STEP(launch_scatter(ni, ncol, p->col_of, p->col_start, p->col_fill, p->slots, st));
     USERIES_STEP(launch_colsort(ncol, p->col_start, p->clus_start, p->slots, p->coord, p->perm,
                                 p->sorted, p->cl_info, p->cl_col, p->cl_z, st));
-    USERIES_STEP(launch_pair(p->pair, npb, p->sorted, p->clus_start, p->cl_info, p->cl_col, p->cl_z,
+    USERIES_STEP(launch_pair(hp.pair, npb, p->sorted, p->clus_start, p->cl_info, p->cl_col, p->cl_z,
                              p->fnear, p->pair_parts, st));
-    USERIES_STEP(launch_spread(p->gridargs, p->sorted, p->clus_start, p->cl_info, p->cl_z,
+    USERIES_STEP(launch_spread(hp.gridargs, p->sorted, p->clus_start, p->cl_info, p->cl_z,
                                p->qstats, p->rho, st));
-    USERIES_STEP(launch_conv_xy(p->conv, p->rho, p->kx, p->ky, p->tgrid, st));
-    USERIES_STEP(launch_conv_z(p->conv, p->tgrid, p->kz, p->phi, st));
-    USERIES_STEP(launch_gather(p->gridargs, p->sorted, p->perm, p->phi, p->fnear, ni, forces,
+    USERIES_STEP(launch_conv_xy(hp.conv, p->rho, kx, ky, p->tgrid, st));
+    USERIES_STEP(launch_conv_z(hp.conv, p->tgrid, kz, p->phi, st));
+    USERIES_STEP(launch_gather(hp.gridargs, p->sorted, p->perm, p->phi, p->fnear, forces,
                                p->gather_parts, ngb, st));
-    USERIES_STEP(launch_finalize(p->fin, p->pair_parts, p->gather_parts, p->qstats, energy, parts, st));
+    USERIES_STEP(launch_finalize(hp.fin, p->pair_parts, p->gather_parts, p->qstats, energy, parts,
+                                 st));
 #undef USERIES_STEP
     return USERIES_OK;
 }
@@ -539,23 +350,24 @@ int useries_plan_info(useries_plan_t p, double* b, double* sigma, double* r0, do
                       double* s0, int* n_terms, double* eq33, double* f_inf0, double* c1_slope,
                       double* sigma_s, int* stencil_half, int ncell[3], double* poly_maxerr) {
     if (!p) return fail(USERIES_EINVAL, "NULL plan");
-    if (b) *b = p->b;
-    if (sigma) *sigma = p->sigma;
-    if (r0) *r0 = p->r0;
-    if (w0) *w0 = p->w0;
-    if (s0) *s0 = p->s0;
-    if (n_terms) *n_terms = p->nterms;
-    if (eq33) *eq33 = p->eq33;
-    if (f_inf0) *f_inf0 = p->f_inf0;
-    if (c1_slope) *c1_slope = p->c1_slope;
-    if (sigma_s) *sigma_s = p->sigma_s[0];
-    if (stencil_half) *stencil_half = p->P;
+    const HostPlan& hp = p->hp;
+    if (b) *b = hp.b;
+    if (sigma) *sigma = hp.sigma;
+    if (r0) *r0 = hp.r0;
+    if (w0) *w0 = hp.w0;
+    if (s0) *s0 = hp.s0;
+    if (n_terms) *n_terms = hp.nterms;
+    if (eq33) *eq33 = hp.eq33;
+    if (f_inf0) *f_inf0 = hp.f_inf0;
+    if (c1_slope) *c1_slope = hp.c1_slope;
+    if (sigma_s) *sigma_s = hp.sigma_s[0];
+    if (stencil_half) *stencil_half = hp.P;
     if (ncell) {
         ncell[0] = p->nc_used[0];
         ncell[1] = p->nc_used[1];
         ncell[2] = 1;
     }
-    if (poly_maxerr) *poly_maxerr = p->poly_maxerr;
+    if (poly_maxerr) *poly_maxerr = hp.poly_maxerr;
     return USERIES_OK;
 }
 

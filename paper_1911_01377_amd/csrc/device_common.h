@@ -127,3 +127,37 @@ __device__ __forceinline__ void column_zrange(const uint2* __restrict__ cl_z, in
 }
 
 }  // namespace useries
+
+namespace useries {
+
+// Batched launches: index i of the batch entry whose work-item range
+// [off[i], off[i + 1]) holds item w (off is non-decreasing, off[0] = 0).
+__device__ __forceinline__ int batch_find(const int* __restrict__ off, int nbox, int w) {
+    int lo = 0, hi = nbox;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= w) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace useries
+
+namespace useries {
+
+// Grid-stride loop of a batched launch over the work items of kernel k:
+// f(i, item) runs the one-box body for batch entry i and its local item.
+// The block barrier between items lets a body reuse its LDS.
+template <class Table, class F>
+__device__ __forceinline__ void batch_for(const Table* __restrict__ tab, int k, F&& f) {
+    const int nbox = tab->nbox;
+    const int* off = tab->off[k];
+    const int total = off[nbox];
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const int i = batch_find(off, nbox, w);
+        f(i, w - off[i]);
+        __syncthreads();
+    }
+}
+
+}  // namespace useries

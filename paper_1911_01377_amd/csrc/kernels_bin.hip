@@ -19,12 +19,11 @@ namespace useries {
 // column), then added to the global counters once per (block, column).
 constexpr int kHistCols = 4096;
 
-__global__ void __launch_bounds__(256) k_encode(BinArgs a, const float* __restrict__ xyz,
-                                                const float* __restrict__ q,
-                                                uint4* __restrict__ coord,
-                                                int* __restrict__ col_of,
-                                                int* __restrict__ col_count,
-                                                double* __restrict__ qpart) {
+__device__ __forceinline__ void encode_body(const BinArgs& a, int bid, const float* __restrict__ xyz,
+                                            const float* __restrict__ q,
+                                            uint4* __restrict__ coord, int* __restrict__ col_of,
+                                            int* __restrict__ col_count,
+                                            double* __restrict__ qpart) {
     __shared__ double red[256];
     __shared__ int hist[kHistCols];
     const int ncol = a.nc[0] * a.nc[1];
@@ -32,7 +31,7 @@ __global__ void __launch_bounds__(256) k_encode(BinArgs a, const float* __restri
     if (local)
         for (int k = threadIdx.x; k < ncol; k += 256) hist[k] = 0;
     __syncthreads();
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = bid * 256 + threadIdx.x;
     double qs = 0.0, q2 = 0.0;
     if (i < a.n) {
         uint32_t u[3];
@@ -55,20 +54,39 @@ __global__ void __launch_bounds__(256) k_encode(BinArgs a, const float* __restri
     __syncthreads();
     const double s2 = block_sum_d<256>(q2, red);
     if (threadIdx.x == 0) {
-        qpart[2 * blockIdx.x] = s1;
-        qpart[2 * blockIdx.x + 1] = s2;
+        qpart[2 * bid] = s1;
+        qpart[2 * bid + 1] = s2;
     }
+}
+
+__global__ void __launch_bounds__(256) k_encode(BinArgs a, const float* __restrict__ xyz,
+                                                const float* __restrict__ q,
+                                                uint4* __restrict__ coord,
+                                                int* __restrict__ col_of,
+                                                int* __restrict__ col_count,
+                                                double* __restrict__ qpart) {
+    encode_body(a, blockIdx.x, xyz, q, coord, col_of, col_count, qpart);
+}
+
+__global__ void __launch_bounds__(256) k_encode_batch(const BatchTable* __restrict__ tab,
+                                                      const BoxDesc* __restrict__ desc) {
+    batch_for(tab, BK_ENCODE, [&](int i, int item) {
+        const BoxDesc& d = desc[tab->slot[i]];
+        encode_body(d.bin, item, d.xyz, d.q, d.coord, d.col_of, d.col_count, d.qpart);
+    });
 }
 
 // One block of 1024 threads: exclusive scans of the column counts and of the
 // cluster counts ceil(count / 8) (each thread owns a contiguous chunk;
 // wavefront scans by shuffles, then a scan of the 16 wavefront totals), zero
-// the fill counters, and reduce the charge partials in a fixed order.
-__global__ void __launch_bounds__(1024) k_scan(int ncol, const int* __restrict__ count,
-                                               int* __restrict__ start, int* __restrict__ cstart,
-                                               int* __restrict__ fill,
-                                               const double* __restrict__ qpart, int nqpart,
-                                               double* __restrict__ qstats) {
+// the fill counters, and reduce the charge partials in a fixed order.  The
+// column counts are cleared once read, ready for the next evaluation (they
+// start at zero when the workspace is allocated).
+__device__ __forceinline__ void scan_body(int ncol, int* __restrict__ count,
+                                          int* __restrict__ start, int* __restrict__ cstart,
+                                          int* __restrict__ fill,
+                                          const double* __restrict__ qpart, int nqpart,
+                                          double* __restrict__ qstats) {
     __shared__ int wsum[2][16];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int chunk = (ncol + 1023) / 1024;
@@ -118,6 +136,7 @@ __global__ void __launch_bounds__(1024) k_scan(int ncol, const int* __restrict__
         run += k;
         runc += (k + 7) >> 3;
         fill[c] = 0;
+        count[c] = 0;
     }
     if (t == 1023) {
         start[ncol] = run;
@@ -138,19 +157,37 @@ __global__ void __launch_bounds__(1024) k_scan(int ncol, const int* __restrict__
     }
 }
 
+__global__ void __launch_bounds__(1024) k_scan(int ncol, int* __restrict__ count,
+                                               int* __restrict__ start, int* __restrict__ cstart,
+                                               int* __restrict__ fill,
+                                               const double* __restrict__ qpart, int nqpart,
+                                               double* __restrict__ qstats) {
+    scan_body(ncol, count, start, cstart, fill, qpart, nqpart, qstats);
+}
+
+__global__ void __launch_bounds__(1024) k_scan_batch(const BatchTable* __restrict__ tab,
+                                                     const BoxDesc* __restrict__ desc) {
+    batch_for(tab, BK_SCAN, [&](int i, int) {
+        const BoxDesc& d = desc[tab->slot[i]];
+        scan_body(d.ncol, d.col_count, d.col_start, d.clus_start, d.col_fill, d.qpart, d.nq,
+                  d.qstats);
+    });
+}
+
 // Slots inside a column: the rank among the block's charges of that column
 // (LDS atomic) plus a base reserved once per (block, column).  The order they
 // produce is arbitrary; colsort makes it deterministic.
-__global__ void __launch_bounds__(256) k_scatter(int n, int ncol, const int* __restrict__ col_of,
-                                                 const int* __restrict__ start,
-                                                 int* __restrict__ fill, int* __restrict__ slots) {
+__device__ __forceinline__ void scatter_body(int n, int ncol, int bid,
+                                             const int* __restrict__ col_of,
+                                             const int* __restrict__ start,
+                                             int* __restrict__ fill, int* __restrict__ slots) {
     __shared__ int hist[kHistCols];
     __shared__ int base[kHistCols];
     const bool local = ncol <= kHistCols;
     if (local)
         for (int k = threadIdx.x; k < ncol; k += 256) hist[k] = 0;
     __syncthreads();
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = bid * 256 + threadIdx.x;
     int c = 0, r = 0;
     if (i < n) {
         c = col_of[i];
@@ -164,23 +201,35 @@ __global__ void __launch_bounds__(256) k_scatter(int n, int ncol, const int* __r
     if (i < n) slots[start[c] + (local ? base[c] : 0) + r] = i;
 }
 
+__global__ void __launch_bounds__(256) k_scatter(int n, int ncol, const int* __restrict__ col_of,
+                                                 const int* __restrict__ start,
+                                                 int* __restrict__ fill, int* __restrict__ slots) {
+    scatter_body(n, ncol, blockIdx.x, col_of, start, fill, slots);
+}
+
+__global__ void __launch_bounds__(256) k_scatter_batch(const BatchTable* __restrict__ tab,
+                                                       const BoxDesc* __restrict__ desc) {
+    batch_for(tab, BK_SCATTER, [&](int i, int item) {
+        const BoxDesc& d = desc[tab->slot[i]];
+        scatter_body(d.bin.n, d.ncol, item, d.col_of, d.col_start, d.col_fill, d.slots);
+    });
+}
+
 // One block per column: sort the column's charges by the key (z, input
 // index) -- unique, so the order is deterministic -- with a bitonic sort in
 // LDS (columns above kSortCap charges fall back to ranking by counting), then
 // write the permutation, the sorted positions and the column's clusters.
 constexpr int kSortCap = 1024;
 
-__global__ void __launch_bounds__(256) k_colsort(const int* __restrict__ start,
-                                                 const int* __restrict__ cstart,
-                                                 const int* __restrict__ slots,
-                                                 const uint4* __restrict__ coord,
-                                                 int* __restrict__ perm,
-                                                 uint4* __restrict__ sorted,
-                                                 int2* __restrict__ cl_info,
-                                                 int* __restrict__ cl_col,
-                                                 uint2* __restrict__ cl_z) {
+__device__ __forceinline__ void colsort_body(int col, const int* __restrict__ start,
+                                             const int* __restrict__ cstart,
+                                             const int* __restrict__ slots,
+                                             const uint4* __restrict__ coord,
+                                             int* __restrict__ perm, uint4* __restrict__ sorted,
+                                             int2* __restrict__ cl_info, int* __restrict__ cl_col,
+                                             uint2* __restrict__ cl_z) {
     __shared__ unsigned long long key[kSortCap];
-    const int col = blockIdx.x, t = threadIdx.x;
+    const int t = threadIdx.x;
     const int lo = start[col], cnt = start[col + 1] - lo;
     if (cnt == 0) return;
     if (cnt <= kSortCap) {
@@ -242,6 +291,27 @@ __global__ void __launch_bounds__(256) k_colsort(const int* __restrict__ start,
     }
 }
 
+__global__ void __launch_bounds__(256) k_colsort(const int* __restrict__ start,
+                                                 const int* __restrict__ cstart,
+                                                 const int* __restrict__ slots,
+                                                 const uint4* __restrict__ coord,
+                                                 int* __restrict__ perm,
+                                                 uint4* __restrict__ sorted,
+                                                 int2* __restrict__ cl_info,
+                                                 int* __restrict__ cl_col,
+                                                 uint2* __restrict__ cl_z) {
+    colsort_body(blockIdx.x, start, cstart, slots, coord, perm, sorted, cl_info, cl_col, cl_z);
+}
+
+__global__ void __launch_bounds__(256) k_colsort_batch(const BatchTable* __restrict__ tab,
+                                                       const BoxDesc* __restrict__ desc) {
+    batch_for(tab, BK_COLSORT, [&](int i, int item) {
+        const BoxDesc& d = desc[tab->slot[i]];
+        colsort_body(item, d.col_start, d.clus_start, d.slots, d.coord, d.perm, d.sorted,
+                     d.cl_info, d.cl_col, d.cl_z);
+    });
+}
+
 hipError_t launch_encode(const BinArgs& a, const float* xyz, const float* q, uint4* coord,
                          int* col_of, int* col_count, double* qpart, int nqpart, hipStream_t st) {
     if (a.n > 0)
@@ -250,7 +320,7 @@ hipError_t launch_encode(const BinArgs& a, const float* xyz, const float* q, uin
     return hipGetLastError();
 }
 
-hipError_t launch_scan(int ncol, const int* col_count, int* col_start, int* clus_start,
+hipError_t launch_scan(int ncol, int* col_count, int* col_start, int* clus_start,
                        int* col_fill, const double* qpart, int nqpart, double* qstats,
                        hipStream_t st) {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, ncol, col_count, col_start, clus_start,
@@ -271,6 +341,28 @@ hipError_t launch_colsort(int ncol, const int* col_start, const int* clus_start,
                           int* cl_col, uint2* cl_z, hipStream_t st) {
     hipLaunchKernelGGL(k_colsort, dim3(ncol), dim3(256), 0, st, col_start, clus_start, slots,
                        coord, perm, sorted, cl_info, cl_col, cl_z);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_encode_batch, dim3(grid), dim3(256), 0, st, tab, desc);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_scan_batch, dim3(grid), dim3(1024), 0, st, tab, desc);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter_batch, dim3(grid), dim3(256), 0, st, tab, desc);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsort_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_colsort_batch, dim3(grid), dim3(256), 0, st, tab, desc);
     return hipGetLastError();
 }
 

@@ -64,12 +64,12 @@ __device__ __forceinline__ f32x4 mfma3(u16x8 ah, u16x8 al, u16x8 bh, u16x8 bl, f
 
 // ------------------------------------------------------------------ FP32
 
-__global__ void __launch_bounds__(256) k_conv_xy_f32(ConvArgs a, const float* __restrict__ rho,
-                                                     const float* __restrict__ kx,
-                                                     const float* __restrict__ ky,
-                                                     float* __restrict__ tgrid) {
-    extern __shared__ float sp[];
-    const int z = blockIdx.x, t = blockIdx.y;
+// plane z, term t; sp: the dynamic LDS (conv_xy_lds_bytes)
+__device__ __forceinline__ void conv_xy_f32_body(const ConvArgs& a, int z, int t, float* sp,
+                                                 const float* __restrict__ rho,
+                                                 const float* __restrict__ kx,
+                                                 const float* __restrict__ ky,
+                                                 float* __restrict__ tgrid) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int li = l & 15, lk = l >> 4;
     const int g0 = a.g[0], g1 = a.g[1], p0 = a.gp[0], p1 = a.gp[1];
@@ -115,14 +115,15 @@ __global__ void __launch_bounds__(256) k_conv_xy_f32(ConvArgs a, const float* __
     }
 }
 
-__global__ void __launch_bounds__(256) k_conv_z_f32(ConvArgs a, const float* __restrict__ tgrid,
-                                                    const float* __restrict__ kz,
-                                                    float* __restrict__ phi) {
+__device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid,
+                                                const float* __restrict__ tgrid,
+                                                const float* __restrict__ kz,
+                                                float* __restrict__ phi) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int li = l & 15, lk = l >> 4;
     const int g2 = a.g[2], p2 = a.gp[2];
     const int ncol = a.g[0] * a.g[1];
-    const int col = blockIdx.x * 16 + li;
+    const int col = bid * 16 + li;
     const int tz_n = p2 / 16;
     f32x4 acc[kMaxTiles / 4];
     for (int m = 0; m < kMaxTiles / 4; ++m) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -146,12 +147,11 @@ __global__ void __launch_bounds__(256) k_conv_z_f32(ConvArgs a, const float* __r
 // ------------------------------------------------------------------ BF16X3
 
 // kx/ky hold, per term, the hi matrix followed by the lo matrix (bf16 bits).
-__global__ void __launch_bounds__(256) k_conv_xy_bf16(ConvArgs a, const float* __restrict__ rho,
-                                                      const unsigned short* __restrict__ kx,
-                                                      const unsigned short* __restrict__ ky,
-                                                      float* __restrict__ tgrid) {
-    extern __shared__ float smem[];
-    const int z = blockIdx.x, t = blockIdx.y;
+__device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int t, float* smem,
+                                                  const float* __restrict__ rho,
+                                                  const unsigned short* __restrict__ kx,
+                                                  const unsigned short* __restrict__ ky,
+                                                  float* __restrict__ tgrid) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int li = l & 15, lk = l >> 4;
     const int g0 = a.g[0], g1 = a.g[1], p0 = a.gp[0], p1 = a.gp[1];
@@ -227,9 +227,10 @@ __global__ void __launch_bounds__(256) k_conv_xy_bf16(ConvArgs a, const float* _
     }
 }
 
-__global__ void __launch_bounds__(256) k_conv_z_bf16(ConvArgs a, const float* __restrict__ tgrid,
-                                                     const unsigned short* __restrict__ kz,
-                                                     float* __restrict__ phi) {
+__device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid,
+                                                 const float* __restrict__ tgrid,
+                                                 const unsigned short* __restrict__ kz,
+                                                 float* __restrict__ phi) {
     // per term: the 16 columns of T_t, transposed to [col][z'] and split
     __shared__ __attribute__((aligned(16))) unsigned short th[16][kMaxGrid + 8];
     __shared__ __attribute__((aligned(16))) unsigned short tl[16][kMaxGrid + 8];
@@ -237,7 +238,7 @@ __global__ void __launch_bounds__(256) k_conv_z_bf16(ConvArgs a, const float* __
     const int li = l & 15, lk = l >> 4;
     const int g2 = a.g[2], p2 = a.gp[2];
     const int ncol = a.g[0] * a.g[1];
-    const int c0 = blockIdx.x * 16;
+    const int c0 = bid * 16;
     const int tz_n = p2 / 16;
     const size_t mz = (size_t)p2 * p2;
     f32x4 acc[kMaxTiles / 4];
@@ -275,6 +276,67 @@ __global__ void __launch_bounds__(256) k_conv_z_bf16(ConvArgs a, const float* __
         }
 }
 
+// ------------------------------------------------------------------ kernels
+
+__global__ void __launch_bounds__(256) k_conv_xy_f32(ConvArgs a, const float* __restrict__ rho,
+                                                     const float* __restrict__ kx,
+                                                     const float* __restrict__ ky,
+                                                     float* __restrict__ tgrid) {
+    extern __shared__ float dyn_lds[];
+    conv_xy_f32_body(a, blockIdx.x, blockIdx.y, dyn_lds, rho, kx, ky, tgrid);
+}
+
+__global__ void __launch_bounds__(256) k_conv_z_f32(ConvArgs a, const float* __restrict__ tgrid,
+                                                    const float* __restrict__ kz,
+                                                    float* __restrict__ phi) {
+    conv_z_f32_body(a, blockIdx.x, tgrid, kz, phi);
+}
+
+__global__ void __launch_bounds__(256) k_conv_xy_bf16(ConvArgs a, const float* __restrict__ rho,
+                                                      const unsigned short* __restrict__ kx,
+                                                      const unsigned short* __restrict__ ky,
+                                                      float* __restrict__ tgrid) {
+    extern __shared__ float dyn_lds[];
+    conv_xy_bf16_body(a, blockIdx.x, blockIdx.y, dyn_lds, rho, kx, ky, tgrid);
+}
+
+__global__ void __launch_bounds__(256) k_conv_z_bf16(ConvArgs a, const float* __restrict__ tgrid,
+                                                     const unsigned short* __restrict__ kz,
+                                                     float* __restrict__ phi) {
+    conv_z_bf16_body(a, blockIdx.x, tgrid, kz, phi);
+}
+
+// batched: item = t * g_z + z (conv_xy), 16-column group (conv_z)
+template <int BF16>
+__global__ void __launch_bounds__(256) k_conv_xy_batch(const BatchTable* __restrict__ tab,
+                                                       const BoxDesc* __restrict__ desc) {
+    extern __shared__ float dyn_lds[];
+    batch_for(tab, BK_CONV_XY, [&](int i, int item) {
+        const BoxDesc& d = desc[tab->slot[i]];
+        const int gz = d.conv.g[2];
+        const int t = item / gz, z = item - t * gz;
+        if constexpr (BF16 != 0)
+            conv_xy_bf16_body(d.conv, z, t, dyn_lds, d.rho,
+                              reinterpret_cast<const unsigned short*>(d.kx),
+                              reinterpret_cast<const unsigned short*>(d.ky), d.tgrid);
+        else
+            conv_xy_f32_body(d.conv, z, t, dyn_lds, d.rho, d.kx, d.ky, d.tgrid);
+    });
+}
+
+template <int BF16>
+__global__ void __launch_bounds__(256) k_conv_z_batch(const BatchTable* __restrict__ tab,
+                                                      const BoxDesc* __restrict__ desc) {
+    batch_for(tab, BK_CONV_Z, [&](int i, int item) {
+        const BoxDesc& d = desc[tab->slot[i]];
+        if constexpr (BF16 != 0)
+            conv_z_bf16_body(d.conv, item, d.tgrid, reinterpret_cast<const unsigned short*>(d.kz),
+                             d.phi);
+        else
+            conv_z_f32_body(d.conv, item, d.tgrid, d.kz, d.phi);
+    });
+}
+
 // ------------------------------------------------------------------ launch
 
 size_t conv_xy_lds_bytes(const ConvArgs& a) {
@@ -307,6 +369,24 @@ hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz,
                            reinterpret_cast<const unsigned short*>(kz), phi);
     else
         hipLaunchKernelGGL(k_conv_z_f32, dim3(nb), dim3(256), 0, st, a, tgrid, kz, phi);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_xy_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3,
+                                size_t lds, int grid, hipStream_t st) {
+    if (bf16x3)
+        hipLaunchKernelGGL(k_conv_xy_batch<1>, dim3(grid), dim3(256), lds, st, tab, desc);
+    else
+        hipLaunchKernelGGL(k_conv_xy_batch<0>, dim3(grid), dim3(256), lds, st, tab, desc);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_z_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3, int grid,
+                               hipStream_t st) {
+    if (bf16x3)
+        hipLaunchKernelGGL(k_conv_z_batch<1>, dim3(grid), dim3(256), 0, st, tab, desc);
+    else
+        hipLaunchKernelGGL(k_conv_z_batch<0>, dim3(grid), dim3(256), 0, st, tab, desc);
     return hipGetLastError();
 }
 

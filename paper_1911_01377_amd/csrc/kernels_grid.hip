@@ -58,20 +58,19 @@ __device__ __forceinline__ void cell_window(int X0, int bn, int P, int g, int nc
 
 }  // namespace
 
-__global__ void __launch_bounds__(64 * kSpreadWaves) k_spread(GridArgs a,
-                                                              const uint4* __restrict__ sorted,
-                                                              const int* __restrict__ clus_start,
-                                                              const int2* __restrict__ cl_info,
-                                                              const uint2* __restrict__ cl_z,
-                                                              const double* __restrict__ qstats,
-                                                              float* __restrict__ rho) {
+__device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
+                                            const uint4* __restrict__ sorted,
+                                            const int* __restrict__ clus_start,
+                                            const int2* __restrict__ cl_info,
+                                            const uint2* __restrict__ cl_z,
+                                            const double* __restrict__ qstats,
+                                            float* __restrict__ rho) {
     __shared__ float sw[kSpreadWaves][kStage][3 * kBrick];
     __shared__ float red[kSpreadWaves - 1][kBrick][64];
     __shared__ int2 win[2 * kMaxWindowCols];   // charge ranges [begin, end) per column piece
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ty = lane & 7, tz = lane >> 3;
     const int nbx = (a.g[0] + kBrick - 1) / kBrick, nby = (a.g[1] + kBrick - 1) / kBrick;
-    const int bid = blockIdx.x;
     const int X0 = (bid % nbx) * kBrick, Y0 = ((bid / nbx) % nby) * kBrick,
               Z0 = (bid / (nbx * nby)) * kBrick;
     const int B0 = min(kBrick, a.g[0] - X0), B1 = min(kBrick, a.g[1] - Y0),
@@ -194,24 +193,43 @@ __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread(GridArgs a,
     }
 }
 
+__global__ void __launch_bounds__(64 * kSpreadWaves) k_spread(GridArgs a,
+                                                              const uint4* __restrict__ sorted,
+                                                              const int* __restrict__ clus_start,
+                                                              const int2* __restrict__ cl_info,
+                                                              const uint2* __restrict__ cl_z,
+                                                              const double* __restrict__ qstats,
+                                                              float* __restrict__ rho) {
+    spread_body(a, blockIdx.x, sorted, clus_start, cl_info, cl_z, qstats, rho);
+}
+
+__global__ void __launch_bounds__(64 * kSpreadWaves) k_spread_batch(
+        const BatchTable* __restrict__ tab, const BoxDesc* __restrict__ desc) {
+    batch_for(tab, BK_SPREAD, [&](int i, int item) {
+        const BoxDesc& d = desc[tab->slot[i]];
+        spread_body(d.grid, item, d.sorted, d.clus_start, d.cl_info, d.cl_z, d.qstats, d.rho);
+    });
+}
+
 constexpr int kGatherPerWave = 4;   // charges per wavefront at a time, 16 lanes each
 
-__global__ void __launch_bounds__(256) k_gather(GridArgs a, const uint4* __restrict__ sorted,
-                                                const int* __restrict__ perm,
-                                                const float* __restrict__ phi,
-                                                const float4* __restrict__ fnear,
-                                                int slice_stride,
-                                                float* __restrict__ forces,
-                                                double* __restrict__ epart) {
+// block bid of nblocks (the blocks of one box)
+__device__ __forceinline__ void gather_body(const GridArgs& a, int bid, int nblocks,
+                                            const uint4* __restrict__ sorted,
+                                            const int* __restrict__ perm,
+                                            const float* __restrict__ phi,
+                                            const float4* __restrict__ fnear,
+                                            float* __restrict__ forces,
+                                            double* __restrict__ epart) {
     __shared__ float sw[4][kGatherPerWave][6][16];
     __shared__ double se[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, l16 = lane & 15;
     const int P = a.P, P2 = 2 * P;
-    const int nw = gridDim.x * 4;
+    const int nw = nblocks * 4;
     double e_wave = 0.0;
     // groups of kGatherPerWave charges are dealt to the wavefronts round-robin
-    for (int i0 = (blockIdx.x * 4 + wave) * kGatherPerWave; i0 < a.n; i0 += nw * kGatherPerWave) {
+    for (int i0 = (bid * 4 + wave) * kGatherPerWave; i0 < a.n; i0 += nw * kGatherPerWave) {
         const int i = i0 + g;
         const bool valid = i < a.n;
         int gi[3] = {0, 0, 0};
@@ -269,14 +287,7 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs a, const uint4* __restr
             pz += __shfl_xor(pz, off, 64);
         }
         if (valid && l16 == 0) {
-            // near force: the pair kernel's partial slices, summed in a fixed order
-            float4 fn = fnear[i];
-            for (int sl = 1; sl < kPairSlices; ++sl) {
-                const float4 v = fnear[(size_t)sl * slice_stride + i];
-                fn.x += v.x;
-                fn.y += v.y;
-                fn.z += v.z;
-            }
+            const float4 fn = fnear[i];   // near force from the pair kernel
             const int o = perm[i];
             forces[3 * o + 0] = fn.x - qi * px;
             forces[3 * o + 1] = fn.y - qi * py;
@@ -291,7 +302,25 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs a, const uint4* __restr
     }
     if (lane == 0) se[wave] = e_wave;
     __syncthreads();
-    if (threadIdx.x == 0) epart[blockIdx.x] = ((se[0] + se[1]) + se[2]) + se[3];
+    if (threadIdx.x == 0) epart[bid] = ((se[0] + se[1]) + se[2]) + se[3];
+}
+
+__global__ void __launch_bounds__(256) k_gather(GridArgs a, const uint4* __restrict__ sorted,
+                                                const int* __restrict__ perm,
+                                                const float* __restrict__ phi,
+                                                const float4* __restrict__ fnear,
+                                                float* __restrict__ forces,
+                                                double* __restrict__ epart) {
+    gather_body(a, blockIdx.x, gridDim.x, sorted, perm, phi, fnear, forces, epart);
+}
+
+__global__ void __launch_bounds__(256) k_gather_batch(const BatchTable* __restrict__ tab,
+                                                      const BoxDesc* __restrict__ desc) {
+    batch_for(tab, BK_GATHER, [&](int i, int item) {
+        const BoxDesc& d = desc[tab->slot[i]];
+        gather_body(d.grid, item, d.ngb, d.sorted, d.perm, d.phi, d.fnear, d.forces,
+                    d.gather_parts);
+    });
 }
 
 hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* clus_start,
@@ -307,11 +336,23 @@ hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* clus
 int gather_blocks(int n) { return std::min((n + 4 * kGatherPerWave - 1) / (4 * kGatherPerWave), 8192); }
 
 hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm,
-                         const float* phi, const float4* fnear, int slice_stride, float* forces,
+                         const float* phi, const float4* fnear, float* forces,
                          double* epart, int nblocks, hipStream_t st) {
     if (nblocks > 0)
         hipLaunchKernelGGL(k_gather, dim3(nblocks), dim3(256), 0, st, a, sorted, perm, phi, fnear,
-                           slice_stride, forces, epart);
+                           forces, epart);
+    return hipGetLastError();
+}
+
+hipError_t launch_spread_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_spread_batch, dim3(grid), dim3(64 * kSpreadWaves), 0, st, tab, desc);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_batch, dim3(grid), dim3(256), 0, st, tab, desc);
     return hipGetLastError();
 }
 

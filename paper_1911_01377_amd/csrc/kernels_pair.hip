@@ -65,19 +65,18 @@ __device__ __forceinline__ void stencil_col(int k, int ci, int R, int nc, bool f
 }  // namespace
 
 template <int DEG>
-__global__ void __launch_bounds__(64) k_pair(PairArgs a, const uint4* __restrict__ sorted,
-                                             const int* __restrict__ clus_start,
-                                             const int2* __restrict__ cl_info,
-                                             const int* __restrict__ cl_col,
-                                             const uint2* __restrict__ cl_z,
-                                             float4* __restrict__ fnear,
-                                             double* __restrict__ epart) {
+__device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4* __restrict__ sorted,
+                                          const int* __restrict__ clus_start,
+                                          const int2* __restrict__ cl_info,
+                                          const int* __restrict__ cl_col,
+                                          const uint2* __restrict__ cl_z,
+                                          float4* __restrict__ fnear,
+                                          double* __restrict__ epart) {
     __shared__ uint4 stage[kChunk * 8];
     __shared__ int rbeg[2 * kMaxStencilCols];
     __shared__ int roff[2 * kMaxStencilCols + 1];
     const int lane = threadIdx.x, ia = lane >> 3, ja = lane & 7;
     const int ncx = a.nc[0], ncy = a.nc[1];
-    const int I = blockIdx.x;
     if (I >= clus_start[ncx * ncy]) {
         if (lane == 0) epart[I] = 0.0;
         return;
@@ -202,6 +201,27 @@ __global__ void __launch_bounds__(64) k_pair(PairArgs a, const uint4* __restrict
     if (lane == 0) epart[I] = 0.5 * es;
 }
 
+template <int DEG>
+__global__ void __launch_bounds__(64) k_pair(PairArgs a, const uint4* __restrict__ sorted,
+                                             const int* __restrict__ clus_start,
+                                             const int2* __restrict__ cl_info,
+                                             const int* __restrict__ cl_col,
+                                             const uint2* __restrict__ cl_z,
+                                             float4* __restrict__ fnear,
+                                             double* __restrict__ epart) {
+    pair_body<DEG>(a, blockIdx.x, sorted, clus_start, cl_info, cl_col, cl_z, fnear, epart);
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(64) k_pair_batch(const BatchTable* __restrict__ tab,
+                                                   const BoxDesc* __restrict__ desc) {
+    batch_for(tab, BK_PAIR, [&](int i, int item) {
+        const BoxDesc& d = desc[tab->slot[i]];
+        pair_body<DEG>(d.pair, item, d.sorted, d.clus_start, d.cl_info, d.cl_col, d.cl_z,
+                       d.fnear, d.pair_parts);
+    });
+}
+
 hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, const int* clus_start,
                        const int2* cl_info, const int* cl_col, const uint2* cl_z, float4* fnear,
                        double* epart, hipStream_t st) {
@@ -212,6 +232,23 @@ hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, cons
     case D:                                                                                   \
         hipLaunchKernelGGL(k_pair<D>, grid, block, 0, st, a, sorted, clus_start, cl_info,     \
                            cl_col, cl_z, fnear, epart);                                       \
+        break;
+        USERIES_PAIR_DEG(4) USERIES_PAIR_DEG(5) USERIES_PAIR_DEG(6) USERIES_PAIR_DEG(7)
+        USERIES_PAIR_DEG(8) USERIES_PAIR_DEG(9) USERIES_PAIR_DEG(10) USERIES_PAIR_DEG(11)
+        USERIES_PAIR_DEG(12) USERIES_PAIR_DEG(13) USERIES_PAIR_DEG(14)
+#undef USERIES_PAIR_DEG
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_batch(const BatchTable* tab, const BoxDesc* desc, int deg, int grid,
+                             hipStream_t st) {
+    switch (deg) {
+#define USERIES_PAIR_DEG(D)                                                                   \
+    case D:                                                                                   \
+        hipLaunchKernelGGL(k_pair_batch<D>, dim3(grid), dim3(64), 0, st, tab, desc);          \
         break;
         USERIES_PAIR_DEG(4) USERIES_PAIR_DEG(5) USERIES_PAIR_DEG(6) USERIES_PAIR_DEG(7)
         USERIES_PAIR_DEG(8) USERIES_PAIR_DEG(9) USERIES_PAIR_DEG(10) USERIES_PAIR_DEG(11)

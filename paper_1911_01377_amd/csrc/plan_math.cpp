@@ -5,7 +5,11 @@
 // Paper: Predescu et al., "The u-series" (arXiv:1911.01377).
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "useries_internal.h"
 
@@ -234,6 +238,11 @@ double c1_w0_of_r0(double b, double r0) {
     return (1.0 / (2.0 * std::log(b) * r0) - t) / g0;
 }
 
+namespace {
+int solve_construction_uncached(int construction, double b, double* r0, double* w0,
+                                std::string* err);
+}  // namespace
+
 int solve_construction(int construction, double b, double* b_out, double* r0, double* w0,
                        double* s0, std::string* err) {
     switch (construction) {
@@ -266,6 +275,29 @@ int solve_construction(int construction, double b, double* b_out, double* r0, do
     }
     *b_out = b;
     *s0 = 1.0;
+    // the roots depend on (construction, b) only: solved once per process
+    static std::mutex cache_mu;
+    static std::map<std::pair<int, double>, std::pair<double, double>> cache;
+    {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        auto it = cache.find({construction, b});
+        if (it != cache.end()) {
+            *r0 = it->second.first;
+            *w0 = it->second.second;
+            return USERIES_OK;
+        }
+    }
+    const int rc = solve_construction_uncached(construction, b, r0, w0, err);
+    if (rc == USERIES_OK) {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        cache[{construction, b}] = {*r0, *w0};
+    }
+    return rc;
+}
+
+namespace {
+int solve_construction_uncached(int construction, double b, double* r0, double* w0,
+                                std::string* err) {
     double root;
     if (construction == USERIES_C0) {
         if (!smallest_root([b](double r) { return c0_resid(b, r); }, 1e-12, &root)) {
@@ -284,6 +316,7 @@ int solve_construction(int construction, double b, double* b_out, double* r0, do
     *w0 = c1_w0_of_r0(b, root);
     return USERIES_OK;
 }
+}  // namespace
 
 // ---------------------------------------------------------------- near polynomial
 
@@ -356,11 +389,81 @@ double fit_poly01(Fn f, int degree, double* coef) {
 
 }  // namespace
 
-double fit_near_poly(const Series& s, double rc, int degree, double* fcoef, double* gcoef) {
-    // F_inf(r) and F_inf'(r)/r as polynomials in x = r^2 / rc^2, fitted separately
-    const double ef = fit_poly01([&](double x) { return s.f_inf(rc * std::sqrt(x)); }, degree, fcoef);
-    const double eg = fit_poly01([&](double x) { return s.g_inf(rc * std::sqrt(x)); }, degree, gcoef);
+namespace {
+
+// the fit of the series with sigma = 1 on [0, u] (u = r_c / sigma)
+double fit_near_poly_unit(const Series& s, double rc, int degree, double* fcoef, double* gcoef) {
+    // F_inf(r) and F_inf'(r)/r as polynomials in x = r^2 / rc^2, fitted
+    // separately.  The terms are tabulated once; the sums run in the same
+    // order and with the same expressions as Series::f_inf and Series::g_inf.
+    const int len = s.length();
+    std::vector<double> ta(len), ts(len);
+    for (int j = 0; j < len; ++j) s.term(j, &ta[j], &ts[j]);
+    auto f = [&](double x) {
+        const double r = rc * std::sqrt(x);
+        double v = 0.0;
+        for (int j = len - 1; j >= 0; --j) v += ta[j] * std::exp(-r * r / (2.0 * ts[j] * ts[j]));
+        return v;
+    };
+    auto g = [&](double x) {
+        const double r = rc * std::sqrt(x);
+        double v = 0.0;
+        for (int j = len - 1; j >= 0; --j)
+            v -= ta[j] / (ts[j] * ts[j]) * std::exp(-r * r / (2.0 * ts[j] * ts[j]));
+        return v;
+    };
+    const double ef = fit_poly01(f, degree, fcoef);
+    const double eg = fit_poly01(g, degree, gcoef);
     return std::fmax(ef, eg);
+}
+
+}  // namespace
+
+double fit_near_poly(const Series& s, double rc, int degree, double* fcoef, double* gcoef) {
+    // Every term scales with sigma: F(r; sigma) = F(r / sigma; 1) / sigma and
+    // F'(r; sigma)/r = (F'/r)(r / sigma; 1) / sigma^3.  The fit is made once
+    // per (b, w0, s0, r_c / sigma, degree) at sigma = 1 and scaled.
+    struct Key {
+        double b, w0, s0, u;
+        int degree;
+        bool operator<(const Key& o) const {
+            if (b != o.b) return b < o.b;
+            if (w0 != o.w0) return w0 < o.w0;
+            if (s0 != o.s0) return s0 < o.s0;
+            if (u != o.u) return u < o.u;
+            return degree < o.degree;
+        }
+    };
+    struct Fit {
+        double f[kMaxPolyDeg + 1], g[kMaxPolyDeg + 1], err;
+    };
+    static std::mutex mu;
+    static std::map<Key, Fit> cache;
+    const Key key{s.b, s.w0, s.s0, rc / s.sigma, degree};
+    Fit fit;
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            fit = it->second;
+            have = true;
+        }
+    }
+    if (!have) {
+        Series unit = s;
+        unit.sigma = 1.0;
+        fit.err = fit_near_poly_unit(unit, key.u, degree, fit.f, fit.g);
+        std::lock_guard<std::mutex> lk(mu);
+        if (cache.size() > 4096) cache.clear();
+        cache[key] = fit;
+    }
+    const double s1 = 1.0 / s.sigma, s3 = s1 * s1 * s1;
+    for (int k = 0; k <= degree; ++k) {
+        fcoef[k] = fit.f[k] * s1;
+        gcoef[k] = fit.g[k] * s3;
+    }
+    return fit.err;
 }
 
 // ---------------------------------------------------------------- far kernels

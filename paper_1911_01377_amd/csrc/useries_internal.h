@@ -17,7 +17,6 @@ constexpr int kMaxPolyDeg = 14;    // near polynomial degree
 constexpr int kMaxStencilHalf = 8; // P
 constexpr int kMaxStencilCols = 128;  // x-y columns within r_c of a column (pair kernel)
 constexpr int kMaxWindowCols = 256;   // x-y columns touching a spreading brick
-constexpr int kPairSlices = 1;        // near-force slices per charge
 
 // ------------------------------------------------------------ host math
 // FP64 parameter math of the u-series (plan_math.cpp).
@@ -95,11 +94,118 @@ struct FinalArgs {
     double near_int_over_v;   // int N d^3r / V (background)
 };
 
+// ------------------------------------------------------------ host plan
+// Everything a plan computes on the host for one cell shape: parameters,
+// kernel arguments and the convolution matrices in the device format
+// (FP32, or per term the BF16 hi matrix followed by the lo matrix).
+struct HostPlan {
+    double box[3] = {0, 0, 0};
+    double rc = 0, b = 2, sigma = 1, r0 = 1, w0 = 1, s0 = 1;
+    int construction = USERIES_C1, precision = USERIES_PLAIN_FP32;
+    int nterms = 0, P = 5, deg = 8;
+    int grid[3] = {0, 0, 0};
+    double eq33 = 0, f_inf0 = 0, c1_slope = 0, poly_maxerr = 0, sigma_s[3] = {0, 0, 0};
+    int ncmax[2] = {1, 1};   // bounds of the x-y column grid (chosen per evaluation)
+    int ncol_max = 1;
+    BinArgs bin{};
+    PairArgs pair{};
+    GridArgs gridargs{};
+    ConvArgs conv{};
+    FinalArgs fin{};
+    std::vector<uint8_t> mats[3];   // device-format matrices per axis
+};
+
+// Record the message returned by useries_last_error() in this thread; returns code.
+int set_last_error(int code, const std::string& msg);
+
+// Host part of useries_plan (no device calls).  Returns USERIES_OK or an
+// error code with *err set.
+int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, double sigma,
+                    int n_terms, const int grid[3], const useries_opts* opts, std::string* err);
+
+// The x-y column grid for n charges (about 8 charges per cluster of one
+// column cross-section and similar z extent, within the plan's bounds):
+// sets nc, R, cw and n in the kernel arguments.
+void choose_columns(HostPlan* hp, int n);
+
+// LDS bytes of the conv_xy kernel for a grid shape
+size_t conv_xy_lds_bytes(const ConvArgs& a);
+
+// Upper bounds of the blocks of the pair and gather kernels for n charges
+inline int pair_blocks(int n, int ncol) { return n / 8 + 1 + ncol; }
+int gather_blocks(int n);
+
+// ------------------------------------------------------------ batched evaluation
+// Several independent cells evaluated by the same launches: every kernel of
+// the sequence takes a table of the boxes in the batch and, per kernel, the
+// prefix sums of the work items (blocks) of each box; a block finds its box
+// by binary search and runs the same body as the one-box launch.  Grids are
+// fixed (persistent, grid-stride over the items) so that one captured graph
+// serves every batch composition.
+constexpr int kMaxBatch = 64;
+enum BatchKernel {
+    BK_ENCODE, BK_SCAN, BK_SCATTER, BK_COLSORT, BK_PAIR, BK_SPREAD, BK_CONV_XY, BK_CONV_Z,
+    BK_GATHER, BK_FINAL, BK_DISPLACE, BK_COUNT
+};
+
+// One cell's arguments and device buffers (resident while its request runs)
+struct BoxDesc {
+    BinArgs bin;
+    PairArgs pair;
+    GridArgs grid;
+    ConvArgs conv;
+    FinalArgs fin;
+    int ncol, nq, npb, ngb;
+    int n_evals;
+    float disp_sigma;          // displacement per coordinate between evaluations (A)
+    uint32_t key[2];           // Philox key of the request
+    // state and outputs
+    float* xyz;                // [n][3]
+    const float* q;            // [n]
+    float* forces;             // [n][3], input order
+    double* energies;          // [n_evals]
+    // workspace
+    uint4 *coord, *sorted;
+    int *col_of, *perm, *slots, *cl_col;
+    int2* cl_info;
+    uint2* cl_z;
+    float4* fnear;
+    double *qpart, *pair_parts, *gather_parts, *qstats;
+    int *col_count, *col_start, *col_fill, *clus_start;
+    float *rho, *tgrid, *phi;
+    const float *kx, *ky, *kz;
+};
+
+struct BatchTable {
+    int nbox;
+    int slot[kMaxBatch];               // descriptor index of batch entry i
+    int step[kMaxBatch];               // evaluation index of batch entry i
+    int off[BK_COUNT][kMaxBatch + 1];  // work-item prefix per kernel
+};
+
+// Batched launchers: `grid` blocks, grid-stride over the table's items.
+hipError_t launch_encode_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
+hipError_t launch_scan_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
+hipError_t launch_scatter_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
+hipError_t launch_colsort_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
+hipError_t launch_pair_batch(const BatchTable* tab, const BoxDesc* desc, int deg, int grid,
+                             hipStream_t st);
+hipError_t launch_spread_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
+hipError_t launch_conv_xy_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3,
+                                size_t lds, int grid, hipStream_t st);
+hipError_t launch_conv_z_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3, int grid,
+                               hipStream_t st);
+hipError_t launch_gather_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
+hipError_t launch_finalize_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
+                                 hipStream_t st);
+hipError_t launch_displace_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
+                                 hipStream_t st);
+
 // ------------------------------------------------------------ kernel launchers
 // All launchers enqueue on `st` and return hipGetLastError().
 hipError_t launch_encode(const BinArgs& a, const float* xyz, const float* q, uint4* coord,
                          int* col_of, int* col_count, double* qpart, int nqpart, hipStream_t st);
-hipError_t launch_scan(int ncol, const int* col_count, int* col_start, int* clus_start,
+hipError_t launch_scan(int ncol, int* col_count, int* col_start, int* clus_start,
                        int* col_fill, const double* qpart, int nqpart, double* qstats,
                        hipStream_t st);
 hipError_t launch_scatter(int n, int ncol, const int* col_of, const int* col_start, int* col_fill,
@@ -118,9 +224,8 @@ hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx,
 hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz, float* phi,
                          hipStream_t st);
 hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm,
-                         const float* phi, const float4* fnear, int slice_stride, float* forces,
+                         const float* phi, const float4* fnear, float* forces,
                          double* epart, int nblocks, hipStream_t st);
-int gather_blocks(int n);
 hipError_t launch_finalize(const FinalArgs& a, const double* pair_parts,
                            const double* gather_parts, const double* qstats, double* energy,
                            double* parts, hipStream_t st);

@@ -100,3 +100,34 @@ def test_default_opts():
     o = N.useries_default_opts()
     assert o.construction == N.USERIES_C1 and o.precision == N.USERIES_PLAIN_FP32
     assert math.isclose(o.nterms_tol, 1e-8)
+
+
+# Known-answer vectors of Philox4x32-10 published with the generator
+# (Salmon et al., SC 2011, Random123 distribution): counter, key -> output.
+PHILOX_KAT = [
+    ([0, 0, 0, 0], [0, 0], [0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8]),
+    ([0xffffffff] * 4, [0xffffffff] * 2, [0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd]),
+    ([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344], [0xa4093822, 0x299f31d0],
+     [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1]),
+]
+
+
+@pytest.mark.parametrize("ctr,key,want", PHILOX_KAT)
+def test_philox_known_answers(ctr, key, want):
+    assert N.useries_philox4x32_10(ctr, key) == want
+
+
+def test_server_arguments_are_rejected_before_any_device_call():
+    for slots, prec, budget in ((0, N.USERIES_BF16X3, 1 << 30), (65, N.USERIES_BF16X3, 1 << 30),
+                                (4, 7, 1 << 30), (4, N.USERIES_BF16X3, 1000)):
+        with pytest.raises(N.UseriesError) as e:
+            N.useries_server_create(budget, slots, prec)
+        assert e.value.code == N.USERIES_EINVAL
+    o = N.useries_server_default_opts()
+    assert o.use_graph == 1 and o.inflight == 2 and o.poly_degree == 8 and o.b == 2.0
+    o.inflight = 9
+    with pytest.raises(N.UseriesError):
+        N.useries_server_create(1 << 30, 4, N.USERIES_BF16X3, o)
+    with pytest.raises(N.UseriesError) as e:
+        N.useries_submit(None, N.useries_request())
+    assert e.value.code == N.USERIES_EINVAL
