@@ -61,6 +61,83 @@ def kernel_src_hash(name):
     return h.hexdigest()[:16]
 
 
+def _make_request(k):
+    from paper_1911_01377_amd import synth
+    xyz, q, box = synth.serving_request(k)
+    return xyz, q, box
+
+
+def serving_requests(count, workers):
+    """The serving stream: request k is synth.serving_request(k) (a water box with a
+    log-uniform molecule count in [216, 16000]); r_c = min(9, 0.45 L), grid spacing
+    <= 1 A.  Generated on the host before any device work."""
+    import multiprocessing as mp
+    if workers > 1:
+        with mp.get_context("fork").Pool(workers) as pool:
+            cells = pool.map(_make_request, range(count), chunksize=16)
+    else:
+        cells = [_make_request(k) for k in range(count)]
+    out = []
+    for xyz, q, box in cells:
+        L = min(box)
+        out.append((xyz, q, box, min(9.0, 0.45 * L), tuple(int(math.ceil(b)) for b in box)))
+    return out
+
+
+def run_serving(cells, args, precision):
+    """Closed loop (all requests queued at once) for the capacity, then Poisson
+    arrivals at a fraction of it; latency = arrival -> last evaluation's outputs on
+    the host."""
+    import torch
+    from paper_1911_01377_amd import Server
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(0.8 * free, 8 << 30))
+    n_evals, disp = 10, 0.02
+    charges = sum(len(c[1]) for c in cells)
+
+    def one_pass(rate):
+        srv = Server(budget, max_slots=args.serve_slots, precision=precision)
+        rng = np.random.default_rng(4242)
+        gaps = rng.exponential(1.0 / rate, len(cells)) if rate else np.zeros(len(cells))
+        arrivals = np.cumsum(gaps)
+        tickets, lags = [], []
+        t0 = time.perf_counter()
+        for k, (xyz, q, box, rc, grid) in enumerate(cells):
+            if rate:
+                wait = arrivals[k] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+            lags.append(max(0.0, (time.perf_counter() - t0) - arrivals[k]) if rate else 0.0)
+            tickets.append(srv.submit(xyz, q, box, rc, grid, n_evals=n_evals, disp_sigma=disp,
+                                      seed=k))
+        for t in tickets:
+            srv.result(t)
+        times = np.array([srv.times(t) for t in tickets])
+        st = srv.stats()
+        srv.close()
+        wall = times[:, 2].max() - times[:, 0].min()
+        lat = (times[:, 2] - times[:, 0] + np.array(lags)) * 1e3
+        return dict(wall_s=float(wall), requests_per_s=len(cells) / wall,
+                    evals_per_s=len(cells) * n_evals / wall,
+                    charge_evals_per_s=charges * n_evals / wall,
+                    p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                    mean_batch=st["sum_batch"] / max(st["steps"], 1), steps=st["steps"],
+                    graphs=st["graphs"])
+
+    closed = one_pass(0.0)
+    log("serving closed loop: %s" % closed)
+    out = {"requests": len(cells), "evals_per_request": n_evals, "displacement_A": disp,
+           "charges_total": charges, "max_slots": args.serve_slots, "hbm_budget_bytes": budget,
+           "closed_loop": closed}
+    rate = args.serve_load * closed["requests_per_s"]
+    opened = one_pass(rate)
+    opened["arrival_rate_per_s"] = rate
+    opened["load_fraction"] = args.serve_load
+    log("serving open loop: %s" % opened)
+    out["poisson"] = opened
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +146,11 @@ def main():
     ap.add_argument("--form", choices=["bf16x3", "plain"], default="bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-requests", type=int, default=4096,
+                    help="requests in the serving stream (0: skip serving)")
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="Poisson arrival rate as a fraction of the closed-loop capacity")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -78,6 +160,13 @@ def main():
               "build (see DESIGN.md for how it would shard); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+
+    # serving inputs are generated before the process touches the device
+    cells = None
+    if args.serve_requests > 0:
+        t = time.perf_counter()
+        cells = serving_requests(args.serve_requests, min(16, os.cpu_count() or 1))
+        log("generated %d serving requests in %.1f s" % (len(cells), time.perf_counter() - t))
 
     import torch
     from paper_1911_01377_amd import USERIES_BF16X3, USERIES_PLAIN_FP32, Plan, synth
@@ -222,6 +311,13 @@ def main():
             cpu = {"value": None, "unit": "evals/s", "cores": None, "kind": "oracle",
                    "sample": "failed: %s" % e}
 
+    serving = None
+    if cells:
+        try:
+            serving = run_serving(cells, args, forms[args.form])
+        except Exception as e:
+            serving = {"error": str(e)}
+
     out = {
         "metric": "u-series force evals/s (26k-charge box, force err<=1e-3) + p50/p99 latency",
         "value": 1e3 / ms,
@@ -245,6 +341,7 @@ def main():
         "accuracy": acc,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     for p_ in plans.values():
         p_.close()
