@@ -159,8 +159,14 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
         ga.dws[a] = (float)(h / (ss * ss));
         const int g = grid[a], gp = ca.gp[a];
         const size_t m = (size_t)gp * gp;
-        std::vector<double> M(m * p.nterms, 0.0);
+        // per term the circulant M[i][j] = col[(i - j) mod g], zero-padded to gp x gp
+        if (bf)
+            p.mats[a].assign(2 * m * p.nterms * sizeof(uint16_t), 0);
+        else
+            p.mats[a].assign(m * p.nterms * sizeof(float), 0);
         std::vector<double> col(g);
+        std::vector<float> colf(g);
+        std::vector<uint16_t> chi(g), clo(g);
         for (int t = 0; t < p.nterms; ++t) {
             double at, st;
             s.term(t, &at, &st);
@@ -171,28 +177,25 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
                             "s_0 / sqrt(2)");
             const double sk = std::sqrt(sk2);
             circulant_column(g, h, sk, (st / sk) * (a == 0 ? at : 1.0), col.data());
-            double* Mt = M.data() + (size_t)t * m;
-            for (int i = 0; i < g; ++i)
-                for (int j = 0; j < g; ++j) Mt[(size_t)i * gp + j] = col[((i - j) % g + g) % g];
-        }
-        // device format
-        if (bf) {
-            std::vector<uint16_t> h16(2 * m * p.nterms);
-            for (int t = 0; t < p.nterms; ++t)
-                for (size_t k = 0; k < m; ++k) {
-                    const float v = (float)M[t * m + k];
-                    const uint16_t hi = host_bf16(v);
-                    const uint16_t lo = host_bf16(v - host_bf16_val(hi));
-                    h16[2 * m * t + k] = hi;
-                    h16[2 * m * t + m + k] = lo;
-                }
-            p.mats[a].resize(h16.size() * sizeof(uint16_t));
-            std::memcpy(p.mats[a].data(), h16.data(), p.mats[a].size());
-        } else {
-            std::vector<float> h32(M.size());
-            for (size_t k = 0; k < M.size(); ++k) h32[k] = (float)M[k];
-            p.mats[a].resize(h32.size() * sizeof(float));
-            std::memcpy(p.mats[a].data(), h32.data(), p.mats[a].size());
+            for (int k = 0; k < g; ++k) {
+                colf[k] = (float)col[k];
+                chi[k] = host_bf16(colf[k]);
+                clo[k] = host_bf16(colf[k] - host_bf16_val(chi[k]));
+            }
+            if (bf) {
+                uint16_t* hi = reinterpret_cast<uint16_t*>(p.mats[a].data()) + 2 * m * t;
+                uint16_t* lo = hi + m;
+                for (int i = 0; i < g; ++i)
+                    for (int j = 0; j < g; ++j) {
+                        const int k = i >= j ? i - j : i - j + g;
+                        hi[(size_t)i * gp + j] = chi[k];
+                        lo[(size_t)i * gp + j] = clo[k];
+                    }
+            } else {
+                float* M = reinterpret_cast<float*>(p.mats[a].data()) + m * t;
+                for (int i = 0; i < g; ++i)
+                    for (int j = 0; j < g; ++j) M[(size_t)i * gp + j] = colf[i >= j ? i - j : i - j + g];
+            }
         }
     }
     const double V = box[0] * box[1] * box[2];
