@@ -56,6 +56,7 @@ struct useries_plan_s {
     void *kx = nullptr, *ky = nullptr, *kz = nullptr;
     // fixed workspace
     int *col_count = nullptr, *col_start = nullptr, *col_fill = nullptr, *clus_start = nullptr;
+    int* zbin = nullptr;
     double *qstats = nullptr, *parts_tmp = nullptr;
     float *rho = nullptr, *tgrid = nullptr, *phi = nullptr;
     // per-atom workspace
@@ -156,6 +157,7 @@ struct useries_plan_s {
         hipFree(col_start);
         hipFree(col_fill);
         hipFree(clus_start);
+        hipFree(zbin);
         hipFree(qstats);
         hipFree(parts_tmp);
         hipFree(rho);
@@ -236,7 +238,9 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
     const size_t ng = (size_t)hp.grid[0] * hp.grid[1] * hp.grid[2];
     if ((e = dalloc(&p->col_count, hp.ncol_max)) || (e = dalloc(&p->col_fill, hp.ncol_max)) ||
         (e = dalloc(&p->col_start, hp.ncol_max + 1)) ||
-        (e = dalloc(&p->clus_start, hp.ncol_max + 1)) || (e = dalloc(&p->qstats, 2)) ||
+        (e = dalloc(&p->clus_start, hp.ncol_max + 1)) ||
+        (e = dalloc(&p->zbin, (size_t)hp.ncol_max * (hp.grid[2] + 1))) ||
+        (e = dalloc(&p->qstats, 2)) ||
         (e = dalloc(&p->parts_tmp, 5)) || (e = dalloc(&p->rho, ng)) ||
         (e = dalloc(&p->tgrid, ng * hp.nterms)) || (e = dalloc(&p->phi, ng))) {
         delete p;
@@ -287,49 +291,47 @@ static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float*
         if (e) return hip_fail(e, "memset");
         p->counts_dirty = false;
     }
-    int k = 0;
-    hipEvent_t ev0 = nullptr;
-    auto pre = [&]() {
+    // timing: HIP events around each kernel on the stream it runs on
+    auto run = [&](int k, hipStream_t s, auto&& launch) -> hipError_t {
+        hipEvent_t ev0 = nullptr;
         if (p->timing) {
             ev0 = p->get_event();
-            hipEventRecord(ev0, st);
+            hipEventRecord(ev0, s);
         }
-    };
-    auto post = [&](hipError_t err) -> hipError_t {
+        const hipError_t err = launch();
         if (p->timing) {
             hipEvent_t ev1 = p->get_event();
-            hipEventRecord(ev1, st);
+            hipEventRecord(ev1, s);
             p->pending.push_back({k, ev0, ev1});
         }
-        ++k;
         if (err != hipSuccess) p->counts_dirty = true;
         return err;
     };
-#define USERIES_STEP(call)                                                  \
-    do {                                                                    \
-        pre();                                                              \
-        hipError_t err_ = post(call);                                       \
-        if (err_ != hipSuccess) return hip_fail(err_, kKernelNames[k - 1]); \
+#define USERIES_STEP(k, s, call)                                               \
+    do {                                                                       \
+        const hipError_t err_ = run(k, s, [&]() { return (call); });          \
+        if (err_ != hipSuccess) return hip_fail(err_, kKernelNames[k]);        \
     } while (0)
     const float* kx = (const float*)p->kx;
     const float* ky = (const float*)p->ky;
     const float* kz = (const float*)p->kz;
-    USERIES_STEP(launch_encode(hp.bin, xyz, q, p->coord, p->col_of, p->col_count, p->qpart, nq, st));
-    USERIES_STEP(launch_scan(ncol, p->col_count, p->col_start, p->clus_start, p->col_fill, p->qpart,
-                             nq, p->qstats, st));
-    USERIES_STEP(launch_scatter(ni, ncol, p->col_of, p->col_start, p->col_fill, p->slots, st));
-    USERIES_STEP(launch_colsort(ncol, p->col_start, p->clus_start, p->slots, p->coord, p->perm,
-                                p->sorted, p->cl_info, p->cl_col, p->cl_z, st));
-    USERIES_STEP(launch_pair(hp.pair, npb, p->sorted, p->clus_start, p->cl_info, p->cl_col, p->cl_z,
-                             p->fnear, p->pair_parts, st));
-    USERIES_STEP(launch_spread(hp.gridargs, p->sorted, p->clus_start, p->cl_info, p->cl_z,
-                               p->qstats, p->rho, st));
-    USERIES_STEP(launch_conv_xy(hp.conv, p->rho, kx, ky, p->tgrid, st));
-    USERIES_STEP(launch_conv_z(hp.conv, p->tgrid, kz, p->phi, st));
-    USERIES_STEP(launch_gather(hp.gridargs, p->sorted, p->perm, p->phi, p->fnear, forces,
-                               p->gather_parts, ngb, st));
-    USERIES_STEP(launch_finalize(hp.fin, p->pair_parts, p->gather_parts, p->qstats, energy, parts,
-                                 st));
+    USERIES_STEP(0, st, launch_encode(hp.bin, xyz, q, p->coord, p->col_of, p->col_count, p->qpart,
+                                      nq, st));
+    USERIES_STEP(1, st, launch_scan(ncol, p->col_count, p->col_start, p->clus_start, p->col_fill,
+                                    p->qpart, nq, p->qstats, st));
+    USERIES_STEP(2, st, launch_scatter(ni, ncol, p->col_of, p->col_start, p->col_fill, p->slots, st));
+    USERIES_STEP(3, st, launch_colsort(ncol, p->col_start, p->clus_start, p->slots, p->coord,
+                                       p->perm, p->sorted, p->cl_info, p->cl_col, p->cl_z,
+                                       hp.grid[2], p->zbin, st));
+    USERIES_STEP(4, st, launch_pair(hp.pair, npb, p->sorted, p->clus_start, p->cl_info, p->cl_col,
+                                    p->cl_z, p->fnear, p->pair_parts, st));
+    USERIES_STEP(5, st, launch_spread(hp.gridargs, p->sorted, p->zbin, p->qstats, p->rho, st));
+    USERIES_STEP(6, st, launch_conv_xy(hp.conv, p->rho, kx, ky, p->tgrid, st));
+    USERIES_STEP(7, st, launch_conv_z(hp.conv, p->tgrid, kz, p->phi, st));
+    USERIES_STEP(8, st, launch_gather(hp.gridargs, p->sorted, p->perm, p->phi, p->fnear, forces,
+                                      p->gather_parts, ngb, st));
+    USERIES_STEP(9, st, launch_finalize(hp.fin, p->pair_parts, p->gather_parts, p->qstats, energy,
+                                        parts, st));
 #undef USERIES_STEP
     return USERIES_OK;
 }

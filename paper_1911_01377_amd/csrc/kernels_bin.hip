@@ -227,11 +227,16 @@ __device__ __forceinline__ void colsort_body(int col, const int* __restrict__ st
                                              const uint4* __restrict__ coord,
                                              int* __restrict__ perm, uint4* __restrict__ sorted,
                                              int2* __restrict__ cl_info, int* __restrict__ cl_col,
-                                             uint2* __restrict__ cl_z) {
+                                             uint2* __restrict__ cl_z, int gz,
+                                             int* __restrict__ zbin) {
     __shared__ unsigned long long key[kSortCap];
     const int t = threadIdx.x;
     const int lo = start[col], cnt = start[col + 1] - lo;
-    if (cnt == 0) return;
+    int* zrow = zbin + (size_t)col * (gz + 1);
+    if (cnt == 0) {
+        for (int b = t; b <= gz; b += 256) zrow[b] = lo;
+        return;
+    }
     if (cnt <= kSortCap) {
         int m = 1;
         while (m < cnt) m <<= 1;
@@ -280,6 +285,17 @@ __device__ __forceinline__ void colsort_body(int col, const int* __restrict__ st
         }
     }
     __syncthreads();
+    // z-plane index of the column: zrow[b] = first charge whose grid z index
+    // is >= b (b = 0 .. gz), for the spreading and gathering windows
+    for (int b = t; b <= gz; b += 256) {
+        int l = 0, h = cnt;
+        while (l < h) {
+            const int mid = (l + h) >> 1;
+            const uint32_t z = cnt <= kSortCap ? (uint32_t)(key[mid] >> 32) : sorted[lo + mid].z;
+            if (cell_coord(z, gz) < b) l = mid + 1; else h = mid;
+        }
+        zrow[b] = lo + l;
+    }
     // clusters: 8 consecutive charges of the column (the last may be short)
     const int c0 = cstart[col], nclus = (cnt + 7) >> 3;
     for (int k = t; k < nclus; k += 256) {
@@ -299,8 +315,10 @@ __global__ void __launch_bounds__(256) k_colsort(const int* __restrict__ start,
                                                  uint4* __restrict__ sorted,
                                                  int2* __restrict__ cl_info,
                                                  int* __restrict__ cl_col,
-                                                 uint2* __restrict__ cl_z) {
-    colsort_body(blockIdx.x, start, cstart, slots, coord, perm, sorted, cl_info, cl_col, cl_z);
+                                                 uint2* __restrict__ cl_z, int gz,
+                                                 int* __restrict__ zbin) {
+    colsort_body(blockIdx.x, start, cstart, slots, coord, perm, sorted, cl_info, cl_col, cl_z, gz,
+                 zbin);
 }
 
 __global__ void __launch_bounds__(256) k_colsort_batch(const BatchTable* __restrict__ tab,
@@ -308,7 +326,7 @@ __global__ void __launch_bounds__(256) k_colsort_batch(const BatchTable* __restr
     batch_for(tab, BK_COLSORT, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
         colsort_body(item, d.col_start, d.clus_start, d.slots, d.coord, d.perm, d.sorted,
-                     d.cl_info, d.cl_col, d.cl_z);
+                     d.cl_info, d.cl_col, d.cl_z, d.grid.g[2], d.zbin);
     });
 }
 
@@ -338,9 +356,9 @@ hipError_t launch_scatter(int n, int ncol, const int* col_of, const int* col_sta
 
 hipError_t launch_colsort(int ncol, const int* col_start, const int* clus_start, const int* slots,
                           const uint4* coord, int* perm, uint4* sorted, int2* cl_info,
-                          int* cl_col, uint2* cl_z, hipStream_t st) {
+                          int* cl_col, uint2* cl_z, int gz, int* zbin, hipStream_t st) {
     hipLaunchKernelGGL(k_colsort, dim3(ncol), dim3(256), 0, st, col_start, clus_start, slots,
-                       coord, perm, sorted, cl_info, cl_col, cl_z);
+                       coord, perm, sorted, cl_info, cl_col, cl_z, gz, zbin);
     return hipGetLastError();
 }
 

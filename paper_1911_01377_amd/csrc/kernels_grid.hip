@@ -29,8 +29,8 @@ namespace useries {
 namespace {
 
 constexpr int kBrick = 8;
-constexpr int kStage = 128;      // staged charges per wavefront pass
-constexpr int kSpreadWaves = 4;  // wavefronts per brick, each taking a share of the cell rows
+constexpr int kSpreadWaves = 4;                  // wavefronts per brick
+constexpr int kSpreadChunk = 64 * kSpreadWaves;  // candidates loaded per pass, one per thread
 
 __device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 __device__ __forceinline__ int ceildiv(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
@@ -58,121 +58,150 @@ __device__ __forceinline__ void cell_window(int X0, int bn, int P, int g, int nc
 
 }  // namespace
 
+// One block per 8x8x8 brick.  The window of a brick: in x and y the columns
+// that can hold a charge whose stencil touches it, in z the grid planes
+// [Z0 - P, Z0 + B2 + P - 2] (periodic), read from each column's z-plane index
+// as at most two contiguous charge ranges.  The block loads the candidates in
+// chunks of 256 (one per thread), keeps those whose stencil touches the brick
+// (compacted in thread order, so the order is deterministic), stages their
+// 3 x 8 weights in LDS, and each wavefront accumulates every fourth staged
+// charge into its partial brick; the four partial bricks are summed in a
+// fixed order at the end.
 __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
                                             const uint4* __restrict__ sorted,
-                                            const int* __restrict__ clus_start,
-                                            const int2* __restrict__ cl_info,
-                                            const uint2* __restrict__ cl_z,
+                                            const int* __restrict__ zbin,
                                             const double* __restrict__ qstats,
                                             float* __restrict__ rho) {
-    __shared__ float sw[kSpreadWaves][kStage][3 * kBrick];
+    __shared__ float sw[kSpreadChunk][3 * kBrick];
     __shared__ float red[kSpreadWaves - 1][kBrick][64];
-    __shared__ int2 win[2 * kMaxWindowCols];   // charge ranges [begin, end) per column piece
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ int pbeg[2 * kMaxWindowCols];       // first charge of each column piece
+    __shared__ int poff[2 * kMaxWindowCols + 1];   // prefix sums of the piece lengths
+    __shared__ int wtot[kSpreadWaves];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int ty = lane & 7, tz = lane >> 3;
     const int nbx = (a.g[0] + kBrick - 1) / kBrick, nby = (a.g[1] + kBrick - 1) / kBrick;
     const int X0 = (bid % nbx) * kBrick, Y0 = ((bid / nbx) % nby) * kBrick,
               Z0 = (bid / (nbx * nby)) * kBrick;
     const int B0 = min(kBrick, a.g[0] - X0), B1 = min(kBrick, a.g[1] - Y0),
               B2 = min(kBrick, a.g[2] - Z0);
-    const int P = a.P;
+    const int P = a.P, gz = a.g[2];
     int lo[2], cnt[2];
     cell_window(X0, B0, P, a.g[0], a.nc[0], &lo[0], &cnt[0]);
     cell_window(Y0, B1, P, a.g[1], a.nc[1], &lo[1], &cnt[1]);
     const int ncw = cnt[0] * cnt[1];
-    // z window in fixed point (widened to whole units): charges whose
-    // stencil start lies in [Z0 - P, Z0 + B2 + P - 1)
-    const long long zlo = floordiv_ll((long long)(Z0 - P) << 32, a.g[2]);
-    const long long zhi = ceildiv_ll((long long)(Z0 + B2 + P - 1) << 32, a.g[2]);
-    for (int k = threadIdx.x; k < ncw; k += 64 * kSpreadWaves) {
+    const int np = 2 * ncw;
+    // z planes of the window: [zs, zs + zl) modulo gz
+    const int zl = B2 + 2 * P - 1;
+    const int zs = wrapi(Z0 - P, gz);
+    for (int k = tid; k < ncw; k += 64 * kSpreadWaves) {
         const int col = wrapi(lo[1] + k / cnt[0], a.nc[1]) * a.nc[0] + wrapi(lo[0] + k % cnt[0], a.nc[0]);
-        int b0, l0, b1, l1;
-        column_zrange(cl_z, clus_start[col], clus_start[col + 1], zlo, zhi, &b0, &l0, &b1, &l1);
-        int2 r0 = make_int2(0, 0), r1 = make_int2(0, 0);
-        if (l0 > 0) {
-            const int2 e = cl_info[b0 + l0 - 1];
-            r0 = make_int2(cl_info[b0].x, e.x + e.y);
+        const int* zr = zbin + (size_t)col * (gz + 1);
+        int b0, e0, b1 = 0, e1 = 0;
+        if (zl >= gz) {
+            b0 = zr[0];
+            e0 = zr[gz];
+        } else if (zs + zl <= gz) {
+            b0 = zr[zs];
+            e0 = zr[zs + zl];
+        } else {
+            b0 = zr[zs];
+            e0 = zr[gz];
+            b1 = zr[0];
+            e1 = zr[zs + zl - gz];
         }
-        if (l1 > 0) {
-            const int2 e = cl_info[b1 + l1 - 1];
-            r1 = make_int2(cl_info[b1].x, e.x + e.y);
-        }
-        win[2 * k] = r0;
-        win[2 * k + 1] = r1;
+        pbeg[2 * k] = b0;
+        pbeg[2 * k + 1] = b1;
+        poff[2 * k + 1] = e0 - b0;
+        poff[2 * k + 2] = e1 - b1;
     }
     __syncthreads();
+    // inclusive prefix of the np <= 512 piece lengths: two per thread
+    {
+        const int r0 = 2 * tid, r1 = 2 * tid + 1;
+        const int v0 = r0 < np ? poff[r0 + 1] : 0, v1 = r1 < np ? poff[r1 + 1] : 0;
+        int incl = v0 + v1;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int u = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += u;
+        }
+        if (lane == 63) wtot[w] = incl;
+        __syncthreads();
+        int wbase = 0;
+        for (int v = 0; v < w; ++v) wbase += wtot[v];
+        const int excl = wbase + incl - v0 - v1;
+        if (r0 < np) poff[r0 + 1] = excl + v0;
+        if (r1 < np) poff[r1 + 1] = excl + v0 + v1;
+        if (tid == 0) poff[0] = 0;
+        __syncthreads();
+    }
+    const int total = poff[np];
     const int X0s[3] = {X0, Y0, Z0};
     const int Bs[3] = {B0, B1, B2};
-    float (*S)[3 * kBrick] = sw[w];
 
     float acc[kBrick];
 #pragma unroll
     for (int b = 0; b < kBrick; ++b) acc[b] = 0.0f;
-    int staged = 0;
 
-    auto accumulate = [&](int count) {
-        wave_sync();
-        for (int s = 0; s < count; ++s) {
-            const float c = S[s][kBrick + ty] * S[s][2 * kBrick + tz];
-#pragma unroll
-            for (int b = 0; b < kBrick; ++b) acc[b] = fmaf(c, S[s][b], acc[b]);
-        }
-        wave_sync();
-    };
-
-    auto visit = [&](int j0, int j1) {
-        for (int base = j0; base < j1; base += 64) {
-            const int j = base + lane;
-            bool touch = false;
-            int gi[3];
-            float f[3];
-            float qj = 0.0f;
-            if (j < j1) {
-                const uint4 c = sorted[j];
-                grid_coord(c.x, a.g[0], &gi[0], &f[0]);
-                grid_coord(c.y, a.g[1], &gi[1], &f[1]);
-                grid_coord(c.z, a.g[2], &gi[2], &f[2]);
-                qj = __uint_as_float(c.w);
-                touch = true;
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax)
-                    touch = touch &&
-                            wrapi(gi[ax] - (X0s[ax] - P), a.g[ax]) <= Bs[ax] + 2 * P - 2;
+    for (int base = 0; base < total; base += kSpreadChunk) {
+        const int t = base + tid;
+        bool touch = false;
+        int gi[3];
+        float f[3];
+        float qj = 0.0f;
+        if (t < total) {
+            int l = 0, h = np;                 // piece r with poff[r] <= t < poff[r + 1]
+            while (h - l > 1) {
+                const int mid = (l + h) >> 1;
+                if (poff[mid] <= t) l = mid; else h = mid;
             }
-            const uint64_t m = __ballot(touch);
-            if (touch) {
-                const int slot = staged + __popcll(m & ((1ull << lane) - 1ull));
+            const uint4 c = sorted[pbeg[l] + (t - poff[l])];
+            grid_coord(c.x, a.g[0], &gi[0], &f[0]);
+            grid_coord(c.y, a.g[1], &gi[1], &f[1]);
+            grid_coord(c.z, a.g[2], &gi[2], &f[2]);
+            qj = __uint_as_float(c.w);
+            touch = true;
 #pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    const int k0 = wrapi(X0s[ax] - gi[ax] + P - 1, a.g[ax]);
+            for (int ax = 0; ax < 3; ++ax)
+                touch = touch && wrapi(gi[ax] - (X0s[ax] - P), a.g[ax]) <= Bs[ax] + 2 * P - 2;
+        }
+        // compaction in thread order
+        const uint64_t m = __ballot(touch);
+        if (lane == 0) wtot[w] = __popcll(m);
+        __syncthreads();
+        int before = 0, nst = 0;
 #pragma unroll
-                    for (int b = 0; b < kBrick; ++b) {
-                        float wv = 0.0f;
-                        int k = k0 + b;
-                        if (k >= a.g[ax]) k -= a.g[ax];
-                        if (b < Bs[ax] && k < 2 * P) {
-                            const float t = (float)(k - P + 1) - f[ax];
-                            wv = a.cw[ax] * __expf(-t * t * a.hs[ax]);
-                        }
-                        if (ax == 1) wv *= qj;
-                        S[slot][ax * kBrick + b] = wv;
+        for (int v = 0; v < kSpreadWaves; ++v) {
+            before += v < w ? wtot[v] : 0;
+            nst += wtot[v];
+        }
+        if (touch) {
+            const int slot = before + __popcll(m & ((1ull << lane) - 1ull));
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const int k0 = wrapi(X0s[ax] - gi[ax] + P - 1, a.g[ax]);
+#pragma unroll
+                for (int b = 0; b < kBrick; ++b) {
+                    float wv = 0.0f;
+                    int k = k0 + b;
+                    if (k >= a.g[ax]) k -= a.g[ax];
+                    if (b < Bs[ax] && k < 2 * P) {
+                        const float tt = (float)(k - P + 1) - f[ax];
+                        wv = a.cw[ax] * __expf(-tt * tt * a.hs[ax]);
                     }
+                    if (ax == 1) wv *= qj;
+                    sw[slot][ax * kBrick + b] = wv;
                 }
             }
-            staged += __popcll(m);
-            if (staged > 64) {
-                accumulate(staged);
-                staged = 0;
-            }
         }
-    };
-
-    // the column pieces of the window are dealt round-robin to the wavefronts
-    for (int k = w; k < 2 * ncw; k += kSpreadWaves) {
-        const int2 r = win[k];
-        if (r.y > r.x) visit(r.x, r.y);
+        __syncthreads();
+        for (int sidx = w; sidx < nst; sidx += kSpreadWaves) {
+            const float c = sw[sidx][kBrick + ty] * sw[sidx][2 * kBrick + tz];
+#pragma unroll
+            for (int b = 0; b < kBrick; ++b) acc[b] = fmaf(c, sw[sidx][b], acc[b]);
+        }
+        __syncthreads();
     }
-    if (staged > 0) accumulate(staged);
 
     // fixed-order sum of the wavefronts' partial bricks
     if (w > 0)
@@ -195,19 +224,17 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
 
 __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread(GridArgs a,
                                                               const uint4* __restrict__ sorted,
-                                                              const int* __restrict__ clus_start,
-                                                              const int2* __restrict__ cl_info,
-                                                              const uint2* __restrict__ cl_z,
+                                                              const int* __restrict__ zbin,
                                                               const double* __restrict__ qstats,
                                                               float* __restrict__ rho) {
-    spread_body(a, blockIdx.x, sorted, clus_start, cl_info, cl_z, qstats, rho);
+    spread_body(a, blockIdx.x, sorted, zbin, qstats, rho);
 }
 
 __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread_batch(
         const BatchTable* __restrict__ tab, const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_SPREAD, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        spread_body(d.grid, item, d.sorted, d.clus_start, d.cl_info, d.cl_z, d.qstats, d.rho);
+        spread_body(d.grid, item, d.sorted, d.zbin, d.qstats, d.rho);
     });
 }
 
@@ -323,13 +350,12 @@ __global__ void __launch_bounds__(256) k_gather_batch(const BatchTable* __restri
     });
 }
 
-hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* clus_start,
-                         const int2* cl_info, const uint2* cl_z, const double* qstats, float* rho,
-                         hipStream_t st) {
+hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* zbin,
+                         const double* qstats, float* rho, hipStream_t st) {
     const int nb = ((a.g[0] + kBrick - 1) / kBrick) * ((a.g[1] + kBrick - 1) / kBrick) *
                    ((a.g[2] + kBrick - 1) / kBrick);
-    hipLaunchKernelGGL(k_spread, dim3(nb), dim3(64 * kSpreadWaves), 0, st, a, sorted, clus_start,
-                       cl_info, cl_z, qstats, rho);
+    hipLaunchKernelGGL(k_spread, dim3(nb), dim3(64 * kSpreadWaves), 0, st, a, sorted, zbin,
+                       qstats, rho);
     return hipGetLastError();
 }
 

@@ -85,7 +85,7 @@ private:
 struct Layout {
     size_t xyz, q, forces, energies, coord, sorted, col_of, perm, slots, cl_info, cl_col, cl_z,
         fnear, qpart, pair_parts, gather_parts, qstats, col_count, col_start, col_fill,
-        clus_start, rho, tgrid, phi, mat[3], total;
+        clus_start, zbin, rho, tgrid, phi, mat[3], total;
 };
 
 Layout make_layout(const HostPlan& hp, int n, int n_evals) {
@@ -121,6 +121,7 @@ Layout make_layout(const HostPlan& hp, int n, int n_evals) {
     L.col_start = take(4 * (ncm + 1));
     L.col_fill = take(4 * ncm);
     L.clus_start = take(4 * (ncm + 1));
+    L.zbin = take(4 * ncm * (size_t)(hp.grid[2] + 1));
     L.rho = take(4 * ng);
     L.tgrid = take(4 * ng * (size_t)hp.nterms);
     L.phi = take(4 * ng);
@@ -182,6 +183,8 @@ double seconds_since(std::chrono::steady_clock::time_point t0) {
 struct useries_server_s {
     int device = 0;
     hipStream_t st = nullptr;
+    hipStream_t side = nullptr;                 // far part of a step
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     int precision = USERIES_PLAIN_FP32;
     int max_slots = 1;
     useries_server_opts o{};
@@ -259,10 +262,15 @@ struct useries_server_s {
         if ((e = launch_scan_batch(d_table, d_desc, grid[BK_SCAN], st))) return e;
         if ((e = launch_scatter_batch(d_table, d_desc, grid[BK_SCATTER], st))) return e;
         if ((e = launch_colsort_batch(d_table, d_desc, grid[BK_COLSORT], st))) return e;
+        // far part on the side stream, beside the pair kernel; gather joins them
+        if ((e = hipEventRecord(fork_ev, st))) return e;
+        if ((e = hipStreamWaitEvent(side, fork_ev, 0))) return e;
+        if ((e = launch_spread_batch(d_table, d_desc, grid[BK_SPREAD], side))) return e;
+        if ((e = launch_conv_xy_batch(d_table, d_desc, bf, lds, grid[BK_CONV_XY], side))) return e;
+        if ((e = launch_conv_z_batch(d_table, d_desc, bf, grid[BK_CONV_Z], side))) return e;
+        if ((e = hipEventRecord(join_ev, side))) return e;
         if ((e = launch_pair_batch(d_table, d_desc, popts.poly_degree, grid[BK_PAIR], st))) return e;
-        if ((e = launch_spread_batch(d_table, d_desc, grid[BK_SPREAD], st))) return e;
-        if ((e = launch_conv_xy_batch(d_table, d_desc, bf, lds, grid[BK_CONV_XY], st))) return e;
-        if ((e = launch_conv_z_batch(d_table, d_desc, bf, grid[BK_CONV_Z], st))) return e;
+        if ((e = hipStreamWaitEvent(st, join_ev, 0))) return e;
         if ((e = launch_gather_batch(d_table, d_desc, grid[BK_GATHER], st))) return e;
         if ((e = launch_finalize_batch(d_table, d_desc, grid[BK_FINAL], st))) return e;
         return launch_displace_batch(d_table, d_desc, grid[BK_DISPLACE], st);
@@ -352,6 +360,7 @@ struct useries_server_s {
         d.col_start = (int*)(base + L.col_start);
         d.col_fill = (int*)(base + L.col_fill);
         d.clus_start = (int*)(base + L.clus_start);
+        d.zbin = (int*)(base + L.zbin);
         d.rho = (float*)(base + L.rho);
         d.tgrid = (float*)(base + L.tgrid);
         d.phi = (float*)(base + L.phi);
@@ -608,6 +617,7 @@ struct useries_server_s {
             worker.join();
         }
         if (st) hipStreamSynchronize(st);
+        if (side) hipStreamSynchronize(side);
         for (auto& g : graphs) hipGraphExecDestroy(g.second);
         for (auto g : graph_objs) hipGraphDestroy(g);
         for (auto e : ev_pool) hipEventDestroy(e);
@@ -620,6 +630,9 @@ struct useries_server_s {
         hipFree(d_desc);
         hipFree(d_table);
         hipFree(arena_base);
+        if (fork_ev) hipEventDestroy(fork_ev);
+        if (join_ev) hipEventDestroy(join_ev);
+        if (side) hipStreamDestroy(side);
         if (st) hipStreamDestroy(st);
     }
 };
@@ -683,6 +696,9 @@ int useries_server_create(useries_server_t* out, size_t hbm_budget_bytes, int ma
     S->grid[BK_FINAL] = max_slots;
     S->grid[BK_DISPLACE] = 2 * cu;
     if ((e = hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking)) ||
+        (e = hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking)) ||
+        (e = hipEventCreateWithFlags(&S->fork_ev, hipEventDisableTiming)) ||
+        (e = hipEventCreateWithFlags(&S->join_ev, hipEventDisableTiming)) ||
         (e = hipMalloc((void**)&S->d_desc, sizeof(BoxDesc) * max_slots)) ||
         (e = hipMalloc((void**)&S->d_table, sizeof(BatchTable))) ||
         (e = hipHostMalloc((void**)&S->h_desc, sizeof(BoxDesc) * max_slots, hipHostMallocDefault)) ||

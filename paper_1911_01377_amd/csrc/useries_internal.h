@@ -172,6 +172,7 @@ struct BoxDesc {
     float4* fnear;
     double *qpart, *pair_parts, *gather_parts, *qstats;
     int *col_count, *col_start, *col_fill, *clus_start;
+    int* zbin;                 // [ncol][g_z + 1]: first charge of each grid z-plane per column
     float *rho, *tgrid, *phi;
     const float *kx, *ky, *kz;
 };
@@ -212,13 +213,12 @@ hipError_t launch_scatter(int n, int ncol, const int* col_of, const int* col_sta
                           int* slots, hipStream_t st);
 hipError_t launch_colsort(int ncol, const int* col_start, const int* clus_start, const int* slots,
                           const uint4* coord, int* perm, uint4* sorted, int2* cl_info,
-                          int* cl_col, uint2* cl_z, hipStream_t st);
+                          int* cl_col, uint2* cl_z, int gz, int* zbin, hipStream_t st);
 hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, const int* clus_start,
                        const int2* cl_info, const int* cl_col, const uint2* cl_z, float4* fnear,
                        double* epart, hipStream_t st);
-hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* clus_start,
-                         const int2* cl_info, const uint2* cl_z, const double* qstats, float* rho,
-                         hipStream_t st);
+hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* zbin,
+                         const double* qstats, float* rho, hipStream_t st);
 hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx,
                           const float* ky, float* tgrid, hipStream_t st);
 hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz, float* phi,
