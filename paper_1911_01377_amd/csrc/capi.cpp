@@ -92,14 +92,13 @@ struct useries_plan_s {
         hipFree(slots);
         hipFree(fnear);
         hipFree(qpart);
-        hipFree(gather_parts);
         coord = sorted = nullptr;
         col_of = perm = slots = cl_col = nullptr;
         cl_info = nullptr;
         cl_z = nullptr;
         pair_parts = nullptr;
         fnear = nullptr;
-        qpart = gather_parts = nullptr;
+        qpart = nullptr;
         cap = 0;
     }
 
@@ -113,8 +112,7 @@ struct useries_plan_s {
             (e = dalloc(&perm, c)) || (e = dalloc(&slots, c)) || (e = dalloc(&cl_info, clmax)) ||
             (e = dalloc(&cl_col, clmax)) || (e = dalloc(&cl_z, clmax)) ||
             (e = dalloc(&pair_parts, clmax)) || (e = dalloc(&fnear, c)) ||
-            (e = dalloc(&qpart, 2 * (size_t)((c + 255) / 256))) ||
-            (e = dalloc(&gather_parts, (size_t)gather_blocks((int)c)))) {
+            (e = dalloc(&qpart, 2 * (size_t)((c + 255) / 256)))) {
             free_atoms();
             return fail(USERIES_ENOMEM, std::string("workspace allocation: ") + hipGetErrorString(e));
         }
@@ -159,6 +157,7 @@ struct useries_plan_s {
         hipFree(clus_start);
         hipFree(zbin);
         hipFree(qstats);
+        hipFree(gather_parts);
         hipFree(parts_tmp);
         hipFree(rho);
         hipFree(tgrid);
@@ -241,6 +240,7 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
         (e = dalloc(&p->clus_start, hp.ncol_max + 1)) ||
         (e = dalloc(&p->zbin, (size_t)hp.ncol_max * (hp.grid[2] + 1))) ||
         (e = dalloc(&p->qstats, 2)) ||
+        (e = dalloc(&p->gather_parts, (size_t)gather_blocks(hp.gridargs))) ||
         (e = dalloc(&p->parts_tmp, 5)) || (e = dalloc(&p->rho, ng)) ||
         (e = dalloc(&p->tgrid, ng * hp.nterms)) || (e = dalloc(&p->phi, ng))) {
         delete p;
@@ -283,7 +283,7 @@ static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float*
     p->nc_used[0] = hp.bin.nc[0];
     p->nc_used[1] = hp.bin.nc[1];
     const int ncol = hp.bin.nc[0] * hp.bin.nc[1];
-    const int npb = hp.fin.n_pair_parts, ngb = hp.fin.n_gather_parts;
+    const int npb = hp.fin.n_pair_parts;
     if (!parts && !energy) parts = p->parts_tmp;
 
     if (p->counts_dirty) {
@@ -328,8 +328,8 @@ static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float*
     USERIES_STEP(5, st, launch_spread(hp.gridargs, p->sorted, p->zbin, p->qstats, p->rho, st));
     USERIES_STEP(6, st, launch_conv_xy(hp.conv, p->rho, kx, ky, p->tgrid, st));
     USERIES_STEP(7, st, launch_conv_z(hp.conv, p->tgrid, kz, p->phi, st));
-    USERIES_STEP(8, st, launch_gather(hp.gridargs, p->sorted, p->perm, p->phi, p->fnear, forces,
-                                      p->gather_parts, ngb, st));
+    USERIES_STEP(8, st, launch_gather(hp.gridargs, p->sorted, p->perm, p->zbin, p->phi, p->fnear,
+                                      forces, p->gather_parts, st));
     USERIES_STEP(9, st, launch_finalize(hp.fin, p->pair_parts, p->gather_parts, p->qstats, energy,
                                         parts, st));
 #undef USERIES_STEP

@@ -238,114 +238,202 @@ __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread_batch(
     });
 }
 
-constexpr int kGatherPerWave = 4;   // charges per wavefront at a time, 16 lanes each
+// gather: one block per brick of the grid (8^3 for P <= 5, 4^3 beyond).  The
+// block stages the potential on the brick and its stencil halo (edge
+// brick + 2P - 1) in LDS with coalesced row loads, then takes the charges
+// whose stencil anchor (grid cell) lies in the brick: per overlapping column
+// the z-plane index gives one contiguous range; candidates are loaded one per
+// thread and the owners compacted in thread order.  A wavefront evaluates
+// four owners at a time, 16 lanes each: a lane owns stencil rows (y, z) and
+// reads the 2P x points of each from LDS; the 16-lane groups then reduce.
+constexpr int kGatherMaxEdge = 19;        // halo edge: 8 + 2*5 - 1 = 17, 4 + 2*8 - 1 = 19
+constexpr int kGatherMaxPieces = 256;     // columns overlapping a brick
 
-// block bid of nblocks (the blocks of one box)
-__device__ __forceinline__ void gather_body(const GridArgs& a, int bid, int nblocks,
+__host__ __device__ inline int gather_brick(int P) { return P <= 5 ? 8 : 4; }
+
+__device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                                             const uint4* __restrict__ sorted,
                                             const int* __restrict__ perm,
+                                            const int* __restrict__ zbin,
                                             const float* __restrict__ phi,
                                             const float4* __restrict__ fnear,
                                             float* __restrict__ forces,
                                             double* __restrict__ epart) {
-    __shared__ float sw[4][kGatherPerWave][6][16];
+    __shared__ float sphi[kGatherMaxEdge * kGatherMaxEdge * kGatherMaxEdge];
+    __shared__ uint4 own[256];
+    __shared__ int ownj[256];
+    __shared__ int pbeg[kGatherMaxPieces];
+    __shared__ int poff[kGatherMaxPieces + 1];
+    __shared__ float sw[4][4][6][16];
+    __shared__ int wtot[4];
     __shared__ double se[4];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, l16 = lane & 15;
-    const int P = a.P, P2 = 2 * P;
-    const int nw = nblocks * 4;
+    const int P = a.P, P2 = 2 * P, GB = gather_brick(P);
+    const int nbx = (a.g[0] + GB - 1) / GB, nby = (a.g[1] + GB - 1) / GB;
+    const int X0 = (bid % nbx) * GB, Y0 = ((bid / nbx) % nby) * GB, Z0 = (bid / (nbx * nby)) * GB;
+    const int B0 = min(GB, a.g[0] - X0), B1 = min(GB, a.g[1] - Y0), B2 = min(GB, a.g[2] - Z0);
+    const int E0 = B0 + P2 - 1, E1 = B1 + P2 - 1, E2 = B2 + P2 - 1;
+    // potential on the brick and halo: local (hx, hy, hz) = global (X0 - P + 1 + hx, ...)
+    for (int idx = tid; idx < E0 * E1 * E2; idx += 256) {
+        const int hx = idx % E0, r = idx / E0, hy = r % E1, hz = r / E1;
+        const int gx = wrapi(X0 - P + 1 + hx, a.g[0]);
+        const int gy = wrapi(Y0 - P + 1 + hy, a.g[1]);
+        const int gz = wrapi(Z0 - P + 1 + hz, a.g[2]);
+        sphi[idx] = phi[((size_t)gz * a.g[1] + gy) * a.g[0] + gx];
+    }
+    // columns overlapping the brick's cells in x and y
+    const int cxl = X0 * a.nc[0] / a.g[0], cxh = ((X0 + B0) * a.nc[0] + a.g[0] - 1) / a.g[0] - 1;
+    const int cyl = Y0 * a.nc[1] / a.g[1], cyh = ((Y0 + B1) * a.nc[1] + a.g[1] - 1) / a.g[1] - 1;
+    const int cxn = cxh - cxl + 1, np = cxn * (cyh - cyl + 1);
+    for (int k = tid; k < np; k += 256) {
+        const int col = (cyl + k / cxn) * a.nc[0] + cxl + k % cxn;
+        const int* zr = zbin + (size_t)col * (a.g[2] + 1);
+        const int b = zr[Z0];
+        pbeg[k] = b;
+        poff[k + 1] = zr[Z0 + B2] - b;
+    }
+    __syncthreads();
+    {
+        const int v = tid < np ? poff[tid + 1] : 0;
+        int incl = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int u = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += u;
+        }
+        if (lane == 63) wtot[wave] = incl;
+        __syncthreads();
+        int wbase = 0;
+        for (int w = 0; w < wave; ++w) wbase += wtot[w];
+        if (tid < np) poff[tid + 1] = wbase + incl;
+        if (tid == 0) poff[0] = 0;
+        __syncthreads();
+    }
+    const int total = poff[np];
     double e_wave = 0.0;
-    // groups of kGatherPerWave charges are dealt to the wavefronts round-robin
-    for (int i0 = (bid * 4 + wave) * kGatherPerWave; i0 < a.n; i0 += nw * kGatherPerWave) {
-        const int i = i0 + g;
-        const bool valid = i < a.n;
-        int gi[3] = {0, 0, 0};
-        float f[3] = {0.0f, 0.0f, 0.0f};
-        float qi = 0.0f;
-        if (valid) {
-            const uint4 c = sorted[i];
-            grid_coord(c.x, a.g[0], &gi[0], &f[0]);
-            grid_coord(c.y, a.g[1], &gi[1], &f[1]);
-            grid_coord(c.z, a.g[2], &gi[2], &f[2]);
-            qi = __uint_as_float(c.w);
-            // lane l16 < 2P computes the weights and derivatives of point l16, all axes
-            if (l16 < P2) {
+    for (int base = 0; base < total; base += 256) {
+        const int t = base + tid;
+        bool mine = false;
+        uint4 c = make_uint4(0, 0, 0, 0);
+        int j = 0;
+        if (t < total) {
+            int l = 0, h = np;
+            while (h - l > 1) {
+                const int mid = (l + h) >> 1;
+                if (poff[mid] <= t) l = mid; else h = mid;
+            }
+            j = pbeg[l] + (t - poff[l]);
+            c = sorted[j];
+            const int gx = cell_coord(c.x, a.g[0]), gy = cell_coord(c.y, a.g[1]);
+            mine = gx >= X0 && gx < X0 + B0 && gy >= Y0 && gy < Y0 + B1;
+        }
+        const uint64_t m = __ballot(mine);
+        if (lane == 0) wtot[wave] = __popcll(m);
+        __syncthreads();
+        int before = 0, nown = 0;
 #pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    const float t = (float)(l16 - P + 1) - f[ax];
-                    const float w = a.cw[ax] * __expf(-t * t * a.hs[ax]);
-                    sw[wave][g][ax][l16] = w;
-                    sw[wave][g][3 + ax][l16] = w * t * a.dws[ax];
+        for (int w = 0; w < 4; ++w) {
+            before += w < wave ? wtot[w] : 0;
+            nown += wtot[w];
+        }
+        if (mine) {
+            const int slot = before + __popcll(m & ((1ull << lane) - 1ull));
+            own[slot] = c;
+            ownj[slot] = j;
+        }
+        __syncthreads();
+        // four owners per wavefront pass, groups dealt round-robin to the wavefronts
+        for (int o0 = wave * 4; o0 < nown; o0 += 16) {
+            const int o = o0 + g;
+            const bool valid = o < nown;
+            int gi[3] = {0, 0, 0};
+            float f[3] = {0.0f, 0.0f, 0.0f};
+            float qi = 0.0f;
+            if (valid) {
+                const uint4 cc = own[o];
+                grid_coord(cc.x, a.g[0], &gi[0], &f[0]);
+                grid_coord(cc.y, a.g[1], &gi[1], &f[1]);
+                grid_coord(cc.z, a.g[2], &gi[2], &f[2]);
+                qi = __uint_as_float(cc.w);
+                // lane l16 < 2P: weights and derivatives of stencil point l16, all axes
+                if (l16 < P2) {
+#pragma unroll
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const float tt = (float)(l16 - P + 1) - f[ax];
+                        const float w = a.cw[ax] * __expf(-tt * tt * a.hs[ax]);
+                        sw[wave][g][ax][l16] = w;
+                        sw[wave][g][3 + ax][l16] = w * tt * a.dws[ax];
+                    }
                 }
             }
-        }
-        wave_sync();
-        float pe = 0.0f, px = 0.0f, py = 0.0f, pz = 0.0f;
-        if (valid) {
-            const float* W = &sw[wave][g][0][0];
-            const int gx0 = gi[0] - P + 1;
-            for (int r = l16; r < P2 * P2; r += 16) {
-                const int ky = r % P2, kz = r / P2;
-                int gy = gi[1] - P + 1 + ky, gz = gi[2] - P + 1 + kz;
-                gy = gy < 0 ? gy + a.g[1] : (gy >= a.g[1] ? gy - a.g[1] : gy);
-                gz = gz < 0 ? gz + a.g[2] : (gz >= a.g[2] ? gz - a.g[2] : gz);
-                const float* rowp = phi + ((size_t)gz * a.g[1] + gy) * a.g[0];
-                float sx = 0.0f, dsx = 0.0f;
-                for (int k = 0; k < P2; ++k) {
-                    int gx = gx0 + k;
-                    gx = gx < 0 ? gx + a.g[0] : (gx >= a.g[0] ? gx - a.g[0] : gx);
-                    const float v = rowp[gx];
-                    sx = fmaf(W[k], v, sx);
-                    dsx = fmaf(W[3 * 16 + k], v, dsx);
+            wave_sync();
+            float pe = 0.0f, px = 0.0f, py = 0.0f, pz = 0.0f;
+            if (valid) {
+                const float* W = &sw[wave][g][0][0];
+                // stencil point k of the charge is halo point (gi - brick origin) + k
+                const int lx = gi[0] - X0, ly = gi[1] - Y0, lz = gi[2] - Z0;
+                for (int r = l16; r < P2 * P2; r += 16) {
+                    const int ky = r % P2, kz = r / P2;
+                    const float* rowp = sphi + ((lz + kz) * E1 + (ly + ky)) * E0 + lx;
+                    float sx = 0.0f, dsx = 0.0f;
+                    for (int k = 0; k < P2; ++k) {
+                        const float v = rowp[k];
+                        sx = fmaf(W[k], v, sx);
+                        dsx = fmaf(W[3 * 16 + k], v, dsx);
+                    }
+                    const float wy = W[16 + ky], wz = W[32 + kz];
+                    const float wyz = wy * wz;
+                    pe = fmaf(wyz, sx, pe);
+                    px = fmaf(wyz, dsx, px);
+                    py = fmaf(W[64 + ky] * wz, sx, py);
+                    pz = fmaf(wy * W[80 + kz], sx, pz);
                 }
-                const float wy = W[16 + ky], wz = W[32 + kz];
-                const float wyz = wy * wz;
-                pe = fmaf(wyz, sx, pe);
-                px = fmaf(wyz, dsx, px);
-                py = fmaf(W[64 + ky] * wz, sx, py);
-                pz = fmaf(wy * W[80 + kz], sx, pz);
             }
-        }
 #pragma unroll
-        for (int off = 8; off > 0; off >>= 1) {
-            pe += __shfl_xor(pe, off, 64);
-            px += __shfl_xor(px, off, 64);
-            py += __shfl_xor(py, off, 64);
-            pz += __shfl_xor(pz, off, 64);
+            for (int off = 8; off > 0; off >>= 1) {
+                pe += __shfl_xor(pe, off, 64);
+                px += __shfl_xor(px, off, 64);
+                py += __shfl_xor(py, off, 64);
+                pz += __shfl_xor(pz, off, 64);
+            }
+            if (valid && l16 == 0) {
+                const int i = ownj[o];
+                const float4 fn = fnear[i];   // near force from the pair kernel
+                const int oi = perm[i];
+                forces[3 * oi + 0] = fn.x - qi * px;
+                forces[3 * oi + 1] = fn.y - qi * py;
+                forces[3 * oi + 2] = fn.z - qi * pz;
+            }
+            // the four charges' energies, in a fixed order
+            double ei = (valid && l16 == 0) ? 0.5 * (double)qi * (double)pe : 0.0;
+            ei += __shfl_xor(ei, 16, 64);
+            ei += __shfl_xor(ei, 32, 64);
+            e_wave += ei;
+            wave_sync();
         }
-        if (valid && l16 == 0) {
-            const float4 fn = fnear[i];   // near force from the pair kernel
-            const int o = perm[i];
-            forces[3 * o + 0] = fn.x - qi * px;
-            forces[3 * o + 1] = fn.y - qi * py;
-            forces[3 * o + 2] = fn.z - qi * pz;
-        }
-        // the four charges' energies, in a fixed order
-        double ei = (valid && l16 == 0) ? 0.5 * (double)qi * (double)pe : 0.0;
-        ei += __shfl_xor(ei, 16, 64);
-        ei += __shfl_xor(ei, 32, 64);
-        e_wave += ei;
-        wave_sync();
+        __syncthreads();
     }
     if (lane == 0) se[wave] = e_wave;
     __syncthreads();
-    if (threadIdx.x == 0) epart[bid] = ((se[0] + se[1]) + se[2]) + se[3];
+    if (tid == 0) epart[bid] = ((se[0] + se[1]) + se[2]) + se[3];
 }
 
 __global__ void __launch_bounds__(256) k_gather(GridArgs a, const uint4* __restrict__ sorted,
                                                 const int* __restrict__ perm,
+                                                const int* __restrict__ zbin,
                                                 const float* __restrict__ phi,
                                                 const float4* __restrict__ fnear,
                                                 float* __restrict__ forces,
                                                 double* __restrict__ epart) {
-    gather_body(a, blockIdx.x, gridDim.x, sorted, perm, phi, fnear, forces, epart);
+    gather_body(a, blockIdx.x, sorted, perm, zbin, phi, fnear, forces, epart);
 }
 
 __global__ void __launch_bounds__(256) k_gather_batch(const BatchTable* __restrict__ tab,
                                                       const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_GATHER, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        gather_body(d.grid, item, d.ngb, d.sorted, d.perm, d.phi, d.fnear, d.forces,
+        gather_body(d.grid, item, d.sorted, d.perm, d.zbin, d.phi, d.fnear, d.forces,
                     d.gather_parts);
     });
 }
@@ -359,14 +447,16 @@ hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* zbin
     return hipGetLastError();
 }
 
-int gather_blocks(int n) { return std::min((n + 4 * kGatherPerWave - 1) / (4 * kGatherPerWave), 8192); }
+int gather_blocks(const GridArgs& a) {
+    const int GB = gather_brick(a.P);
+    return ((a.g[0] + GB - 1) / GB) * ((a.g[1] + GB - 1) / GB) * ((a.g[2] + GB - 1) / GB);
+}
 
-hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm,
-                         const float* phi, const float4* fnear, float* forces,
-                         double* epart, int nblocks, hipStream_t st) {
-    if (nblocks > 0)
-        hipLaunchKernelGGL(k_gather, dim3(nblocks), dim3(256), 0, st, a, sorted, perm, phi, fnear,
-                           forces, epart);
+hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm, const int* zbin,
+                         const float* phi, const float4* fnear, float* forces, double* epart,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_gather, dim3(gather_blocks(a)), dim3(256), 0, st, a, sorted, perm, zbin,
+                       phi, fnear, forces, epart);
     return hipGetLastError();
 }
 

@@ -217,7 +217,7 @@ void choose_columns(HostPlan* hp, int n) {
     p.bin.n = p.pair.n = p.gridargs.n = n;
     const int ncol = p.bin.nc[0] * p.bin.nc[1];
     p.fin.n_pair_parts = pair_blocks(n, ncol);
-    p.fin.n_gather_parts = gather_blocks(n);
+    p.fin.n_gather_parts = gather_blocks(p.gridargs);
 }
 
 }  // namespace useries

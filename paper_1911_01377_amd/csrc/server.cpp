@@ -115,7 +115,7 @@ Layout make_layout(const HostPlan& hp, int n, int n_evals) {
     L.fnear = take(16 * c);
     L.qpart = take(16 * ((c + 255) / 256));
     L.pair_parts = take(8 * clmax);
-    L.gather_parts = take(8 * (size_t)gather_blocks(n));
+    L.gather_parts = take(8 * (size_t)gather_blocks(hp.gridargs));
     L.qstats = take(16);
     L.col_count = take(4 * ncm);
     L.col_start = take(4 * (ncm + 1));

@@ -131,9 +131,10 @@ void choose_columns(HostPlan* hp, int n);
 // LDS bytes of the conv_xy kernel for a grid shape
 size_t conv_xy_lds_bytes(const ConvArgs& a);
 
-// Upper bounds of the blocks of the pair and gather kernels for n charges
+// Blocks of the pair kernel for n charges (an upper bound of the clusters)
+// and of the gather kernel (its bricks)
 inline int pair_blocks(int n, int ncol) { return n / 8 + 1 + ncol; }
-int gather_blocks(int n);
+int gather_blocks(const GridArgs& a);
 
 // ------------------------------------------------------------ batched evaluation
 // Several independent cells evaluated by the same launches: every kernel of
@@ -223,9 +224,9 @@ hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx,
                           const float* ky, float* tgrid, hipStream_t st);
 hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz, float* phi,
                          hipStream_t st);
-hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm,
-                         const float* phi, const float4* fnear, float* forces,
-                         double* epart, int nblocks, hipStream_t st);
+hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm, const int* zbin,
+                         const float* phi, const float4* fnear, float* forces, double* epart,
+                         hipStream_t st);
 hipError_t launch_finalize(const FinalArgs& a, const double* pair_parts,
                            const double* gather_parts, const double* qstats, double* energy,
                            double* parts, hipStream_t st);
