@@ -5,18 +5,21 @@
 // by a polynomial in x = r^2/r_c^2 fitted on the host in FP64.
 //
 // Layout: cluster-pair tiles.  Charges are binned into x-y columns, sorted
-// by z, and cut into clusters of up to 8 (see kernels_bin.hip).  One
-// wavefront takes one i-cluster: lane (a, b) = (lane / 8, lane % 8) holds
-// i-charge a and, at each step, j-charge b of the current j-cluster, so every
+// by z, and cut into clusters of up to 8 (see kernels_bin.hip).  One block of
+// two wavefronts takes one i-cluster.  Its candidate j-charges are those of
+// the columns within r_c of the i-column (x-y gap) whose clusters' z extent
+// meets the i-cluster's z extent widened by the z reach sqrt(r_c^2 - gap^2):
+// per column a contiguous cluster range, found by binary search on the
+// z-sorted clusters, and so a contiguous range of sorted charges.  The
+// concatenated ranges are walked 8 charges per step: lane (a, b) =
+// (lane / 8, lane % 8) holds i-charge a and j-charge b of the step, so every
 // lane evaluates one pair per step and no lane waits on another's branch.
-// The j-clusters are those of the columns within r_c of the i-column (x-y
-// gap) whose z extent meets the i-cluster's z extent widened by the z reach
-// sqrt(r_c^2 - gap^2): a contiguous range per column, found by binary search
-// on the z-sorted clusters.  The candidate j-charges are staged in LDS in
-// chunks with coalesced loads.  The force on charge a is summed over its 8
-// lanes by shuffles at the end.
+// The two wavefronts take alternate chunks of 32 steps, each staging its
+// chunk in LDS with coalesced loads issued one chunk ahead.  The force on
+// charge a is summed over its 8 lanes by shuffles, then over the two
+// wavefronts in a fixed order.
 //
-// Each ordered pair (i, j) is evaluated once, by i's wavefront (no
+// Each ordered pair (i, j) is evaluated once, by i's block (no
 // Newton's-third-law sharing), so forces need no atomics and the result does
 // not depend on scheduling.
 #include "useries_internal.h"
@@ -26,7 +29,17 @@ namespace useries {
 
 namespace {
 
-constexpr int kChunk = 32;            // staged j-clusters per pass (4 KB of LDS)
+constexpr int kPairWaves = 2;         // wavefronts per i-cluster
+constexpr int kChunk = 32;            // steps of 8 j-charges staged per pass (4 KB of LDS)
+constexpr int kChunkCharges = 8 * kChunk;
+
+// a loop-invariant value held in a vector register (lets a polynomial step
+// take its two coefficients from one scalar and one vector operand)
+__device__ __forceinline__ float to_vgpr(float s) {
+    float v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
 
 // Polynomial coefficients held in registers (compile-time degree, fully
 // unrolled): F = c0 + x P(x) with c0 carried as hi + lo, and G = F'(r)/r,
@@ -72,13 +85,17 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
                                           const uint2* __restrict__ cl_z,
                                           float4* __restrict__ fnear,
                                           double* __restrict__ epart) {
-    __shared__ uint4 stage[kChunk * 8];
-    __shared__ int rbeg[2 * kMaxStencilCols];
-    __shared__ int roff[2 * kMaxStencilCols + 1];
-    const int lane = threadIdx.x, ia = lane >> 3, ja = lane & 7;
+    __shared__ uint4 stage[kPairWaves][kChunkCharges];
+    __shared__ int rbeg[2 * kMaxStencilCols];       // first sorted charge of each range
+    __shared__ int roff[2 * kMaxStencilCols + 1];   // prefix sums of the range lengths
+    __shared__ int wtot[kPairWaves];
+    __shared__ float4 fother[8];
+    __shared__ double eother;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int ia = lane >> 3, ja = lane & 7;
     const int ncx = a.nc[0], ncy = a.nc[1];
     if (I >= clus_start[ncx * ncy]) {
-        if (lane == 0) epart[I] = 0.0;
+        if (tid == 0) epart[I] = 0.0;
         return;
     }
     const Poly<DEG> P(a);
@@ -90,8 +107,8 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     const int nxs = fullx ? ncx : 2 * a.R[0] + 1, nys = fully ? ncy : 2 * a.R[1] + 1;
     const int NC = nxs * nys;
 
-    // candidate j-cluster ranges, two slots per stencil column
-    for (int k = lane; k < NC; k += 64) {
+    // candidate charge ranges, two slots per stencil column
+    for (int k = tid; k < NC; k += 64 * kPairWaves) {
         int colx, coly, dx, dy;
         stencil_col(k % nxs, cx, a.R[0], ncx, fullx, &colx, &dx);
         stencil_col(k / nxs, cy, a.R[1], ncy, fully, &coly, &dy);
@@ -105,79 +122,98 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
             column_zrange(cl_z, clus_start[col], clus_start[col + 1], (long long)zI.x - rz,
                           (long long)zI.y + rz, &b0, &l0, &b1, &l1);
         }
-        rbeg[2 * k] = b0;
-        rbeg[2 * k + 1] = b1;
-        roff[2 * k + 1] = l0;
-        roff[2 * k + 2] = l1;
+        // consecutive clusters of a column hold consecutive sorted charges
+        int c0 = 0, n0 = 0, c1 = 0, n1 = 0;
+        if (l0 > 0) {
+            const int2 f = cl_info[b0], e = cl_info[b0 + l0 - 1];
+            c0 = f.x;
+            n0 = e.x + e.y - f.x;
+        }
+        if (l1 > 0) {
+            const int2 f = cl_info[b1], e = cl_info[b1 + l1 - 1];
+            c1 = f.x;
+            n1 = e.x + e.y - f.x;
+        }
+        rbeg[2 * k] = c0;
+        rbeg[2 * k + 1] = c1;
+        roff[2 * k + 1] = n0;
+        roff[2 * k + 2] = n1;
     }
-    wave_sync();
-    // prefix offsets of the 2 NC ranges (4 per lane, wavefront scan)
+    __syncthreads();
+    // inclusive prefix of the nr <= 2 * kMaxStencilCols range lengths, two per thread
     const int nr = 2 * NC;
     {
-        int v[4], s = 0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int r = 4 * lane + u;
-            v[u] = r < nr ? roff[r + 1] : 0;
-            s += v[u];
-        }
-        int incl = s;
+        const int r0 = 2 * tid, r1 = 2 * tid + 1;
+        const int v0 = r0 < nr ? roff[r0 + 1] : 0, v1 = r1 < nr ? roff[r1 + 1] : 0;
+        int incl = v0 + v1;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const int t = __shfl_up(incl, off, 64);
             if (lane >= off) incl += t;
         }
-        int run = incl - s;
-        wave_sync();
-        if (lane == 0) roff[0] = 0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int r = 4 * lane + u;
-            run += v[u];
-            if (r < nr) roff[r + 1] = run;
-        }
+        if (lane == 63) wtot[w] = incl;
+        __syncthreads();
+        const int excl = (w > 0 ? wtot[0] : 0) + incl - v0 - v1;
+        if (r0 < nr) roff[r0 + 1] = excl + v0;
+        if (r1 < nr) roff[r1 + 1] = excl + v0 + v1;
+        if (tid == 0) roff[0] = 0;
+        __syncthreads();
     }
-    wave_sync();
     const int total = roff[nr];
+
+    // candidate u of a chunk, loaded by this lane (q = 0 and position 0 past the end)
+    auto fetch = [&](int c, uint4* out) {
+#pragma unroll
+        for (int u = 0; u < kChunkCharges / 64; ++u) {
+            const int p = c * kChunkCharges + u * 64 + lane;
+            out[u] = make_uint4(0, 0, 0, 0);
+            if (p < total) {
+                int lo = 0, hi = nr;             // range r with roff[r] <= p < roff[r + 1]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (roff[mid] <= p) lo = mid; else hi = mid;
+                }
+                out[u] = sorted[rbeg[lo] + (p - roff[lo])];
+            }
+        }
+    };
 
     const bool ivalid = ia < ii.y;
     const uint4 ci = ivalid ? sorted[ii.x + ia] : make_uint4(0, 0, 0, 0);   // q = 0 if invalid
     const float qi = __uint_as_float(ci.w);
     const float sx = a.scale[0], sy = a.scale[1], sz = a.scale[2], rc2 = a.rc2, irc2 = a.inv_rc2;
+    const float ctop = to_vgpr(P.c[DEG]), dtop = to_vgpr(P.d[DEG]);
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     double e = 0.0;                      // FP32 pair energies, flushed to FP64 per chunk
-    for (int base = 0; base < total; base += kChunk) {
-        float ec = 0.0f;
-        const int nch = min(kChunk, total - base);
-        for (int t = lane; t < nch * 8; t += 64) {
-            const int p = base + (t >> 3), k = t & 7;
-            int lo = 0, hi = nr;                 // range r with roff[r] <= p < roff[r + 1]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (roff[mid] <= p) lo = mid; else hi = mid;
-            }
-            const int J = rbeg[lo] + (p - roff[lo]);
-            const int2 jj = cl_info[J];
-            stage[t] = k < jj.y ? sorted[jj.x + k] : make_uint4(0, 0, 0, 0);
-        }
+    const int nchunks = (total + kChunkCharges - 1) / kChunkCharges;
+    uint4 pre[kChunkCharges / 64];
+    if (w < nchunks) fetch(w, pre);
+    for (int c = w; c < nchunks; c += kPairWaves) {
+#pragma unroll
+        for (int u = 0; u < kChunkCharges / 64; ++u) stage[w][u * 64 + lane] = pre[u];
         wave_sync();
-        for (int s = 0; s < nch; ++s) {
-            const uint4 cj = stage[s * 8 + ja];
+        if (c + kPairWaves < nchunks) fetch(c + kPairWaves, pre);   // in flight during the steps
+        const int nsteps = min(kChunk, (total - c * kChunkCharges + 7) >> 3);
+        float ec = 0.0f;
+        for (int s = 0; s < nsteps; ++s) {
+            const uint4 cj = stage[w][s * 8 + ja];
             const float dx = (float)(int)(ci.x - cj.x) * sx;
             const float dy = (float)(int)(ci.y - cj.y) * sy;
             const float dz = (float)(int)(ci.z - cj.z) * sz;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const float qq = qi * __uint_as_float(cj.w);
-            if (r2 < rc2 && r2 > 0.0f && qq != 0.0f) {
-                const float rinv = __builtin_amdgcn_rsqf(r2);   // r2 is a normal number here
+            // a charge of 0 (padding) contributes exactly 0; r2 is then still
+            // >= (L / 2^32)^2 or 0, never subnormal
+            if (r2 < rc2 && r2 > 0.0f) {
+                const float qq = qi * __uint_as_float(cj.w);
+                const float rinv = __builtin_amdgcn_rsqf(r2);
                 const float x = r2 * irc2;
-                float Pp = P.c[DEG];
+                float Pp = fmaf(ctop, x, P.c[DEG - 1]);
 #pragma unroll
-                for (int m = DEG - 1; m >= 1; --m) Pp = fmaf(Pp, x, P.c[m]);
+                for (int m = DEG - 2; m >= 1; --m) Pp = fmaf(Pp, x, P.c[m]);
                 const float Flo = fmaf(Pp, x, P.c0lo);
-                float G = P.d[DEG];
+                float G = fmaf(dtop, x, P.d[DEG - 1]);
 #pragma unroll
-                for (int m = DEG - 1; m >= 0; --m) G = fmaf(G, x, P.d[m]);
+                for (int m = DEG - 2; m >= 0; --m) G = fmaf(G, x, P.d[m]);
                 ec = fmaf(qq, (rinv - P.c[0]) - Flo, ec);
                 const float fs = qq * fmaf(rinv * rinv, rinv, G);
                 fx = fmaf(fs, dx, fx);
@@ -188,21 +224,31 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         e += (double)ec;
         wave_sync();
     }
-    // force on i-charge a: sum over its 8 lanes
+    // force on i-charge a: sum over its 8 lanes, then over the wavefronts
 #pragma unroll
     for (int off = 1; off < 8; off <<= 1) {
         fx += __shfl_xor(fx, off, 64);
         fy += __shfl_xor(fy, off, 64);
         fz += __shfl_xor(fz, off, 64);
     }
-    if (ja == 0 && ivalid) fnear[ii.x + ia] = make_float4(fx, fy, fz, 0.0f);
-    // each pair was seen from both ends: half of the summed pair energies
     const double es = wave_sum_d(e);
-    if (lane == 0) epart[I] = 0.5 * es;
+    if (w == 1) {
+        if (ja == 0) fother[ia] = make_float4(fx, fy, fz, 0.0f);
+        if (lane == 0) eother = es;
+    }
+    __syncthreads();
+    if (w == 0) {
+        if (ja == 0 && ivalid) {
+            const float4 o = fother[ia];
+            fnear[ii.x + ia] = make_float4(fx + o.x, fy + o.y, fz + o.z, 0.0f);
+        }
+        // each pair was seen from both ends: half of the summed pair energies
+        if (lane == 0) epart[I] = 0.5 * (es + eother);
+    }
 }
 
 template <int DEG>
-__global__ void __launch_bounds__(64) k_pair(PairArgs a, const uint4* __restrict__ sorted,
+__global__ void __launch_bounds__(64 * kPairWaves) k_pair(PairArgs a, const uint4* __restrict__ sorted,
                                              const int* __restrict__ clus_start,
                                              const int2* __restrict__ cl_info,
                                              const int* __restrict__ cl_col,
@@ -213,7 +259,7 @@ __global__ void __launch_bounds__(64) k_pair(PairArgs a, const uint4* __restrict
 }
 
 template <int DEG>
-__global__ void __launch_bounds__(64) k_pair_batch(const BatchTable* __restrict__ tab,
+__global__ void __launch_bounds__(64 * kPairWaves) k_pair_batch(const BatchTable* __restrict__ tab,
                                                    const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_PAIR, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
@@ -226,7 +272,7 @@ hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, cons
                        const int2* cl_info, const int* cl_col, const uint2* cl_z, float4* fnear,
                        double* epart, hipStream_t st) {
     if (nblocks <= 0) return hipSuccess;
-    const dim3 grid(nblocks), block(64);
+    const dim3 grid(nblocks), block(64 * kPairWaves);
     switch (a.deg) {
 #define USERIES_PAIR_DEG(D)                                                                   \
     case D:                                                                                   \
@@ -248,7 +294,7 @@ hipError_t launch_pair_batch(const BatchTable* tab, const BoxDesc* desc, int deg
     switch (deg) {
 #define USERIES_PAIR_DEG(D)                                                                   \
     case D:                                                                                   \
-        hipLaunchKernelGGL(k_pair_batch<D>, dim3(grid), dim3(64), 0, st, tab, desc);          \
+        hipLaunchKernelGGL(k_pair_batch<D>, dim3(grid), dim3(64 * kPairWaves), 0, st, tab, desc); \
         break;
         USERIES_PAIR_DEG(4) USERIES_PAIR_DEG(5) USERIES_PAIR_DEG(6) USERIES_PAIR_DEG(7)
         USERIES_PAIR_DEG(8) USERIES_PAIR_DEG(9) USERIES_PAIR_DEG(10) USERIES_PAIR_DEG(11)
