@@ -33,6 +33,19 @@ __device__ __forceinline__ int wrapi(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
+// v mod n for -n <= v < 2n (no integer division)
+__device__ __forceinline__ int wrap1(int v, int n) {
+    v = v < 0 ? v + n : v;
+    return v >= n ? v - n : v;
+}
+
+// floor(v / d) for 0 <= v < 2^13 and 1 <= d <= 32, from a float reciprocal:
+// (v + 1/2)/d lies at least 1/(2d) >= 2^-6 from an integer, and the float
+// error of the product is below v 2^-23 < 2^-10
+__device__ __forceinline__ int small_div(int v, float inv_d) {
+    return (int)(((float)v + 0.5f) * inv_d);
+}
+
 // Order LDS traffic between the lanes of one wavefront (the LDS of a
 // wavefront-private region needs no block barrier).
 __device__ __forceinline__ void wave_sync() {

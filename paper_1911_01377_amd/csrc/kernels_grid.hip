@@ -8,17 +8,16 @@
 //   phi_i = sum_g phi_g prod_a W_a,   F_i = -q_i grad_i phi_i.
 // The mean of rho (its k = 0 mode, the net charge) is removed on the grid.
 //
-// spread: one block per 8x8x8 brick of the grid, four wavefronts sharing the
-//   x-y columns whose charges can touch the brick (for each column, the
-//   z-range of clusters that can, found by binary search).  A wavefront keeps the
-//   charges that do touch it (ballot compaction, so the order is
-//   deterministic), stages their 3 x 8 weights in LDS and accumulates its
-//   partial brick in registers: lane (y, z) owns one grid row of 8 points.
-//   The four partial bricks are summed in a fixed order.  No atomics.
-// gather: a wavefront takes four charges at a time, 16 lanes each (groups of
-//   charges dealt round-robin to a fixed set of wavefronts); a lane owns
-//   stencil rows (y, z) of its charge and reads the 2P contiguous x points of
-//   each, then each 16-lane group reduces.
+// spread: one block per 8x8x8 brick of the grid.  Candidates come from the
+//   x-y columns that can hold a charge touching the brick, each contributing
+//   the charges of the brick's z-planes (per-column z-plane index); the block
+//   keeps those that touch it, stages their weights in LDS and accumulates the
+//   brick in registers, lane (y, z) owning one grid row of 8 points, each
+//   wavefront a share of the staged charges; the partial bricks are summed in
+//   a fixed order.  No atomics.
+// gather: one block per brick with the potential on the brick and its halo in
+//   LDS; each charge is evaluated by the block whose brick holds its stencil
+//   anchor, 16 lanes per charge.
 #include <algorithm>
 
 #include "useries_internal.h"
@@ -29,7 +28,7 @@ namespace useries {
 namespace {
 
 constexpr int kBrick = 8;
-constexpr int kSpreadWaves = 4;                  // wavefronts per brick
+constexpr int kSpreadWaves = 8;                  // wavefronts per brick
 constexpr int kSpreadChunk = 64 * kSpreadWaves;  // candidates loaded per pass, one per thread
 
 __device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
@@ -62,10 +61,10 @@ __device__ __forceinline__ void cell_window(int X0, int bn, int P, int g, int nc
 // that can hold a charge whose stencil touches it, in z the grid planes
 // [Z0 - P, Z0 + B2 + P - 2] (periodic), read from each column's z-plane index
 // as at most two contiguous charge ranges.  The block loads the candidates in
-// chunks of 256 (one per thread), keeps those whose stencil touches the brick
+// chunks of one per thread, keeps those whose stencil touches the brick
 // (compacted in thread order, so the order is deterministic), stages their
-// 3 x 8 weights in LDS, and each wavefront accumulates every fourth staged
-// charge into its partial brick; the four partial bricks are summed in a
+// 3 x 8 weights in LDS, and wavefront w accumulates the staged charges w, w + W, ...
+// (W wavefronts) into its partial brick; the partial bricks are summed in a
 // fixed order at the end.
 __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
                                             const uint4* __restrict__ sorted,
@@ -143,19 +142,29 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
 #pragma unroll
     for (int b = 0; b < kBrick; ++b) acc[b] = 0.0f;
 
-    for (int base = 0; base < total; base += kSpreadChunk) {
-        const int t = base + tid;
-        bool touch = false;
-        int gi[3];
-        float f[3];
-        float qj = 0.0f;
+    // candidate t of the window (loads are issued one chunk ahead)
+    auto fetch = [&](int t) {
+        uint4 c = make_uint4(0, 0, 0, 0);
         if (t < total) {
             int l = 0, h = np;                 // piece r with poff[r] <= t < poff[r + 1]
             while (h - l > 1) {
                 const int mid = (l + h) >> 1;
                 if (poff[mid] <= t) l = mid; else h = mid;
             }
-            const uint4 c = sorted[pbeg[l] + (t - poff[l])];
+            c = sorted[pbeg[l] + (t - poff[l])];
+        }
+        return c;
+    };
+    uint4 next = fetch(tid);
+    for (int base = 0; base < total; base += kSpreadChunk) {
+        const int t = base + tid;
+        bool touch = false;
+        int gi[3];
+        float f[3];
+        float qj = 0.0f;
+        const uint4 c = next;
+        if (base + kSpreadChunk < total) next = fetch(t + kSpreadChunk);
+        if (t < total) {
             grid_coord(c.x, a.g[0], &gi[0], &f[0]);
             grid_coord(c.y, a.g[1], &gi[1], &f[1]);
             grid_coord(c.z, a.g[2], &gi[2], &f[2]);
@@ -163,7 +172,7 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
             touch = true;
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax)
-                touch = touch && wrapi(gi[ax] - (X0s[ax] - P), a.g[ax]) <= Bs[ax] + 2 * P - 2;
+                touch = touch && wrap1(gi[ax] - (X0s[ax] - P), a.g[ax]) <= Bs[ax] + 2 * P - 2;
         }
         // compaction in thread order
         const uint64_t m = __ballot(touch);
@@ -179,7 +188,7 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
             const int slot = before + __popcll(m & ((1ull << lane) - 1ull));
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
-                const int k0 = wrapi(X0s[ax] - gi[ax] + P - 1, a.g[ax]);
+                const int k0 = wrap1(X0s[ax] - gi[ax] + P - 1, a.g[ax]);
 #pragma unroll
                 for (int b = 0; b < kBrick; ++b) {
                     float wv = 0.0f;
@@ -248,6 +257,8 @@ __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread_batch(
 // reads the 2P x points of each from LDS; the 16-lane groups then reduce.
 constexpr int kGatherMaxEdge = 19;        // halo edge: 8 + 2*5 - 1 = 17, 4 + 2*8 - 1 = 19
 constexpr int kGatherMaxPieces = 256;     // columns overlapping a brick
+constexpr int kGatherWaves = 8;           // wavefronts per brick
+constexpr int kGatherThreads = 64 * kGatherWaves;
 
 __host__ __device__ inline int gather_brick(int P) { return P <= 5 ? 8 : 4; }
 
@@ -260,13 +271,14 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                                             float* __restrict__ forces,
                                             double* __restrict__ epart) {
     __shared__ float sphi[kGatherMaxEdge * kGatherMaxEdge * kGatherMaxEdge];
-    __shared__ uint4 own[256];
-    __shared__ int ownj[256];
+    __shared__ uint4 own[kGatherThreads];
+    __shared__ float4 ownf[kGatherThreads];   // near force of the owner
+    __shared__ int ownp[kGatherThreads];      // input index of the owner
     __shared__ int pbeg[kGatherMaxPieces];
     __shared__ int poff[kGatherMaxPieces + 1];
-    __shared__ float sw[4][4][6][16];
-    __shared__ int wtot[4];
-    __shared__ double se[4];
+    __shared__ float sw[kGatherWaves][4][6][16];
+    __shared__ int wtot[kGatherWaves];
+    __shared__ double se[kGatherWaves];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, l16 = lane & 15;
     const int P = a.P, P2 = 2 * P, GB = gather_brick(P);
@@ -275,18 +287,20 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
     const int B0 = min(GB, a.g[0] - X0), B1 = min(GB, a.g[1] - Y0), B2 = min(GB, a.g[2] - Z0);
     const int E0 = B0 + P2 - 1, E1 = B1 + P2 - 1, E2 = B2 + P2 - 1;
     // potential on the brick and halo: local (hx, hy, hz) = global (X0 - P + 1 + hx, ...)
-    for (int idx = tid; idx < E0 * E1 * E2; idx += 256) {
-        const int hx = idx % E0, r = idx / E0, hy = r % E1, hz = r / E1;
-        const int gx = wrapi(X0 - P + 1 + hx, a.g[0]);
-        const int gy = wrapi(Y0 - P + 1 + hy, a.g[1]);
-        const int gz = wrapi(Z0 - P + 1 + hz, a.g[2]);
+    const float inv0 = 1.0f / (float)E0, inv1 = 1.0f / (float)E1;
+    for (int idx = tid; idx < E0 * E1 * E2; idx += kGatherThreads) {
+        const int r = small_div(idx, inv0), hx = idx - r * E0;
+        const int hz = small_div(r, inv1), hy = r - hz * E1;
+        const int gx = wrap1(X0 - P + 1 + hx, a.g[0]);
+        const int gy = wrap1(Y0 - P + 1 + hy, a.g[1]);
+        const int gz = wrap1(Z0 - P + 1 + hz, a.g[2]);
         sphi[idx] = phi[((size_t)gz * a.g[1] + gy) * a.g[0] + gx];
     }
     // columns overlapping the brick's cells in x and y
     const int cxl = X0 * a.nc[0] / a.g[0], cxh = ((X0 + B0) * a.nc[0] + a.g[0] - 1) / a.g[0] - 1;
     const int cyl = Y0 * a.nc[1] / a.g[1], cyh = ((Y0 + B1) * a.nc[1] + a.g[1] - 1) / a.g[1] - 1;
     const int cxn = cxh - cxl + 1, np = cxn * (cyh - cyl + 1);
-    for (int k = tid; k < np; k += 256) {
+    for (int k = tid; k < np; k += kGatherThreads) {
         const int col = (cyl + k / cxn) * a.nc[0] + cxl + k % cxn;
         const int* zr = zbin + (size_t)col * (a.g[2] + 1);
         const int b = zr[Z0];
@@ -312,7 +326,7 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
     }
     const int total = poff[np];
     double e_wave = 0.0;
-    for (int base = 0; base < total; base += 256) {
+    for (int base = 0; base < total; base += kGatherThreads) {
         const int t = base + tid;
         bool mine = false;
         uint4 c = make_uint4(0, 0, 0, 0);
@@ -333,18 +347,19 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
         __syncthreads();
         int before = 0, nown = 0;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < kGatherWaves; ++w) {
             before += w < wave ? wtot[w] : 0;
             nown += wtot[w];
         }
         if (mine) {
             const int slot = before + __popcll(m & ((1ull << lane) - 1ull));
             own[slot] = c;
-            ownj[slot] = j;
+            ownf[slot] = fnear[j];
+            ownp[slot] = perm[j];
         }
         __syncthreads();
         // four owners per wavefront pass, groups dealt round-robin to the wavefronts
-        for (int o0 = wave * 4; o0 < nown; o0 += 16) {
+        for (int o0 = wave * 4; o0 < nown; o0 += 4 * kGatherWaves) {
             const int o = o0 + g;
             const bool valid = o < nown;
             int gi[3] = {0, 0, 0};
@@ -398,9 +413,8 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                 pz += __shfl_xor(pz, off, 64);
             }
             if (valid && l16 == 0) {
-                const int i = ownj[o];
-                const float4 fn = fnear[i];   // near force from the pair kernel
-                const int oi = perm[i];
+                const float4 fn = ownf[o];    // near force from the pair kernel
+                const int oi = ownp[o];
                 forces[3 * oi + 0] = fn.x - qi * px;
                 forces[3 * oi + 1] = fn.y - qi * py;
                 forces[3 * oi + 2] = fn.z - qi * pz;
@@ -416,10 +430,14 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
     }
     if (lane == 0) se[wave] = e_wave;
     __syncthreads();
-    if (tid == 0) epart[bid] = ((se[0] + se[1]) + se[2]) + se[3];
+    if (tid == 0) {
+        double es = 0.0;
+        for (int w = 0; w < kGatherWaves; ++w) es += se[w];
+        epart[bid] = es;
+    }
 }
 
-__global__ void __launch_bounds__(256) k_gather(GridArgs a, const uint4* __restrict__ sorted,
+__global__ void __launch_bounds__(kGatherThreads) k_gather(GridArgs a, const uint4* __restrict__ sorted,
                                                 const int* __restrict__ perm,
                                                 const int* __restrict__ zbin,
                                                 const float* __restrict__ phi,
@@ -429,7 +447,7 @@ __global__ void __launch_bounds__(256) k_gather(GridArgs a, const uint4* __restr
     gather_body(a, blockIdx.x, sorted, perm, zbin, phi, fnear, forces, epart);
 }
 
-__global__ void __launch_bounds__(256) k_gather_batch(const BatchTable* __restrict__ tab,
+__global__ void __launch_bounds__(kGatherThreads) k_gather_batch(const BatchTable* __restrict__ tab,
                                                       const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_GATHER, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
@@ -455,7 +473,7 @@ int gather_blocks(const GridArgs& a) {
 hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm, const int* zbin,
                          const float* phi, const float4* fnear, float* forces, double* epart,
                          hipStream_t st) {
-    hipLaunchKernelGGL(k_gather, dim3(gather_blocks(a)), dim3(256), 0, st, a, sorted, perm, zbin,
+    hipLaunchKernelGGL(k_gather, dim3(gather_blocks(a)), dim3(kGatherThreads), 0, st, a, sorted, perm, zbin,
                        phi, fnear, forces, epart);
     return hipGetLastError();
 }
@@ -468,7 +486,7 @@ hipError_t launch_spread_batch(const BatchTable* tab, const BoxDesc* desc, int g
 
 hipError_t launch_gather_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
                                hipStream_t st) {
-    hipLaunchKernelGGL(k_gather_batch, dim3(grid), dim3(256), 0, st, tab, desc);
+    hipLaunchKernelGGL(k_gather_batch, dim3(grid), dim3(kGatherThreads), 0, st, tab, desc);
     return hipGetLastError();
 }
 

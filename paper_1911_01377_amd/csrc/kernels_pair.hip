@@ -195,8 +195,10 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         if (c + kPairWaves < nchunks) fetch(c + kPairWaves, pre);   // in flight during the steps
         const int nsteps = min(kChunk, (total - c * kChunkCharges + 7) >> 3);
         float ec = 0.0f;
+        uint4 cjn = stage[w][ja];
         for (int s = 0; s < nsteps; ++s) {
-            const uint4 cj = stage[w][s * 8 + ja];
+            const uint4 cj = cjn;                    // the next step's charge is read ahead
+            if (s + 1 < nsteps) cjn = stage[w][(s + 1) * 8 + ja];
             const float dx = (float)(int)(ci.x - cj.x) * sx;
             const float dy = (float)(int)(ci.y - cj.y) * sy;
             const float dz = (float)(int)(ci.z - cj.z) * sz;
