@@ -11,9 +11,17 @@ Prints one JSON line:
                8^3 spreading stencil; --form plain for the FP32 path);
   roofline     the dominant kernel's achieved rate vs the MI355X peak, timed
                with HIP events on the evaluation stream;
+  kernels      every kernel's HIP-event time, algorithmic flop and bytes, and the
+               fractions of the FP32 vector peak, the HBM peak and (convolutions)
+               the MFMA peak they reach;
   cpu_baseline the FP64 oracle on the host's cores, on a bounded sample;
   accuracy     force/energy error of the timed configuration vs the oracle
-               (sampled forces, full-size energy from the stored oracle value).
+               (sampled forces, full-size energy from the stored oracle value);
+  serving      a stream of independent water-box requests (molecule counts
+               log-uniform in [216, 16000], 10 evaluations each with 0.02 A
+               displacements between them) through the continuous-batching
+               server: closed-loop capacity, then Poisson arrivals at a fraction
+               of it, with p50/p99 request latency.
 """
 import argparse
 import hashlib
@@ -285,6 +293,47 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                 "kernel_ms": ktimes[dom], "algorithmic_flop": flop}
 
+    # every kernel against its roofline: algorithmic flop and bytes per launch
+    # over the HIP-event time; for the convolutions also the MFMA
+    # work actually issued (padded tiles, three BF16 products per BF16X3 product)
+    bf = args.form == "bf16x3"
+    pad = 32 if bf else 16
+    gp = [(g + pad - 1) // pad * pad for g in grid]
+    nprod = 3 if bf else 1
+    mfma_peak = PEAK_BF16_TFLOPS if bf else PEAK_FP32_TFLOPS
+    alg_bytes = {
+        "encode": n * (12 + 4) + n * (16 + 4),
+        "scan": 0,
+        "scatter": n * (4 + 4),
+        "colsort": n * (4 + 16) + n * (4 + 16),
+        "pair": n * 16 + n * 16,
+        "spread": n * 16 + 4 * G,
+        "conv_xy": 4 * G + 4 * nt * G,
+        "conv_z": 4 * nt * G + 4 * G,
+        "gather": 4 * G + n * (16 + 16 + 4) + n * 12,
+        "finalize": 0,
+    }
+    issued = {
+        "conv_xy": nprod * nt * grid[2] * 2.0 * (gp[1] * gp[0] * gp[0] + gp[1] * gp[1] * gp[0]),
+        "conv_z": nprod * nt * ((grid[0] * grid[1] + 15) // 16) * 2.0 * gp[2] * gp[2] * 16,
+    }
+    kernels = {}
+    for k, ms_k in ktimes.items():
+        sec = ms_k * 1e-3
+        row = {"ms": ms_k}
+        if k in work:
+            row["algorithmic_flop"] = work[k][1]
+            row["tflops"] = work[k][1] / sec / 1e12
+            row["flop_frac"] = row["tflops"] / work[k][2]
+        if k in alg_bytes and alg_bytes[k]:
+            row["algorithmic_bytes"] = alg_bytes[k]
+            row["gbs"] = alg_bytes[k] / sec / 1e9
+            row["hbm_frac"] = row["gbs"] / PEAK_HBM_GBS
+        if k in issued:
+            row["mfma_issued_tflops"] = issued[k] / sec / 1e12
+            row["mfma_util"] = row["mfma_issued_tflops"] / mfma_peak
+        kernels[k] = row
+
     # the oracle on the host's cores, bounded sample
     cpu = None
     if not args.no_cpu_baseline:
@@ -338,6 +387,7 @@ def main():
                        "what": "one synchronised evaluation, host wall clock"},
         "other_form_evals_per_s": {k: 1e3 / v for k, v in results.items()},
         "kernel_ms": ktimes,
+        "kernels": kernels,
         "accuracy": acc,
         "roofline": roof,
         "cpu_baseline": cpu,
