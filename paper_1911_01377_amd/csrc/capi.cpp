@@ -213,10 +213,12 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
     // device limits
     int lds_max = 0;
     hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
-    if (lds_max > 0 && conv_xy_lds_bytes(hp.conv) > (size_t)lds_max) {
+    const size_t lds_need = std::max(conv_xy_lds_bytes(hp.conv), conv_z_lds_bytes(hp.conv));
+    if (lds_max > 0 && lds_need > (size_t)lds_max) {
         char buf[160];
-        std::snprintf(buf, sizeof buf, "grid plane needs %zu bytes of LDS, device allows %d",
-                      conv_xy_lds_bytes(hp.conv), lds_max);
+        std::snprintf(buf, sizeof buf,
+                      "grid and term count need %zu bytes of LDS per block, device allows %d",
+                      lds_need, lds_max);
         delete p;
         return fail(USERIES_EINVAL, buf);
     }
@@ -324,7 +326,7 @@ static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float*
                                        p->perm, p->sorted, p->cl_info, p->cl_col, p->cl_z,
                                        hp.grid[2], p->zbin, st));
     USERIES_STEP(4, st, launch_pair(hp.pair, npb, p->sorted, p->clus_start, p->cl_info, p->cl_col,
-                                    p->cl_z, p->fnear, p->pair_parts, st));
+                                    p->cl_z, p->zbin, p->fnear, p->pair_parts, st));
     USERIES_STEP(5, st, launch_spread(hp.gridargs, p->sorted, p->zbin, p->qstats, p->rho, st));
     USERIES_STEP(6, st, launch_conv_xy(hp.conv, p->rho, kx, ky, p->tgrid, st));
     USERIES_STEP(7, st, launch_conv_z(hp.conv, p->tgrid, kz, p->phi, st));

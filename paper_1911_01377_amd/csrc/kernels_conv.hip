@@ -146,7 +146,38 @@ __device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid,
 
 // ------------------------------------------------------------------ BF16X3
 
-// kx/ky hold, per term, the hi matrix followed by the lo matrix (bf16 bits).
+// kx/ky/kz hold, per term, the hi matrix followed by the lo matrix (bf16 bits).
+//
+// Wavefront w owns the output tile columns w, w + 4 of each product (at most
+// two: padded edges up to 128 = 8 tiles) and keeps the matching fragments of
+// the constant matrix in registers for the whole item, loaded together with
+// the staging of the plane, so the MFMA loops read only LDS and registers.
+constexpr int kMaxKSteps = kMaxGrid / 32;   // K steps of 32 (BF16 MFMA)
+constexpr int kTilesPerWave = kMaxTiles / 4;
+
+struct Frags {
+    u16x8 h[kTilesPerWave][kMaxKSteps], l[kTilesPerWave][kMaxKSteps];
+};
+
+// fragments of rows tile*16 + li, k = 32 ks + 8 lk .. + 7, of the gp x gp
+// matrices mh / ml (row-major), for the tiles w, w + 4 below ntiles
+__device__ __forceinline__ void load_frags(Frags& f, const unsigned short* __restrict__ mh,
+                                           const unsigned short* __restrict__ ml, int gp,
+                                           int ntiles, int w, int li, int lk) {
+#pragma unroll
+    for (int j = 0; j < kTilesPerWave; ++j) {
+        const int tile = w + 4 * j;
+#pragma unroll
+        for (int ks = 0; ks < kMaxKSteps; ++ks) {
+            if (tile < ntiles && 32 * ks < gp) {
+                const size_t o = (size_t)(tile * 16 + li) * gp + 32 * ks + 8 * lk;
+                f.h[j][ks] = *reinterpret_cast<const u16x8*>(mh + o);
+                f.l[j][ks] = *reinterpret_cast<const u16x8*>(ml + o);
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int t, float* smem,
                                                   const float* __restrict__ rho,
                                                   const unsigned short* __restrict__ kx,
@@ -160,6 +191,12 @@ __device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int 
     unsigned short* pl = ph + p1 * ldb;                              // rho lo
     unsigned short* uh = pl + p1 * ldb;                              // [p0][ldb] U^T hi
     unsigned short* ul = uh + p0 * ldb;                              // U^T lo
+    const size_t mx = (size_t)p0 * p0, my = (size_t)p1 * p1;
+    const int tx_n = p0 / 16, ty_n = p1 / 16;
+    // B of U = rho Kx: Kx[j][k] (Kx symmetric), tiles j owned; A of T = Ky U: Ky rows owned
+    Frags bx, ay;
+    load_frags(bx, kx + 2 * mx * t, kx + 2 * mx * t + mx, p0, tx_n, w, li, lk);
+    load_frags(ay, ky + 2 * my * t, ky + 2 * my * t + my, p1, ty_n, w, li, lk);
     const float* src = rho + (size_t)z * g1 * g0;
     for (int idx = threadIdx.x; idx < p1 * p0; idx += 256) {
         const int y = idx / p0, x = idx - y * p0;
@@ -170,110 +207,121 @@ __device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int 
         pl[y * ldb + x] = lo;
     }
     __syncthreads();
-    const size_t mx = (size_t)p0 * p0, my = (size_t)p1 * p1;
-    const unsigned short* Kxh = kx + 2 * mx * t;
-    const unsigned short* Kxl = Kxh + mx;
-    const unsigned short* Kyh = ky + 2 * my * t;
-    const unsigned short* Kyl = Kyh + my;
-    const int tx_n = p0 / 16, ty_n = p1 / 16;
-    // U = rho[z] Kx (Kx symmetric: B[k][j] = Kx[j][k], contiguous in k)
-    for (int s = w; s < ty_n; s += 4) {
-        f32x4 acc[kMaxTiles];
-        for (int tx = 0; tx < tx_n; ++tx) acc[tx] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int k0 = 0; k0 < p0; k0 += 32) {
-            const int ao = (s * 16 + li) * ldb + k0 + 8 * lk;
-            const u16x8 ah = *reinterpret_cast<const u16x8*>(ph + ao);
-            const u16x8 al = *reinterpret_cast<const u16x8*>(pl + ao);
-            for (int tx = 0; tx < tx_n; ++tx) {
-                const size_t bo = (size_t)(tx * 16 + li) * p0 + k0 + 8 * lk;
-                const u16x8 bh = *reinterpret_cast<const u16x8*>(Kxh + bo);
-                const u16x8 bl = *reinterpret_cast<const u16x8*>(Kxl + bo);
-                acc[tx] = mfma3(ah, al, bh, bl, acc[tx]);
+    // U = rho Kx: tiles (strip s, column tile tx = w + 4j); U stored transposed, split
+    for (int s = 0; s < ty_n; ++s) {
+#pragma unroll
+        for (int j = 0; j < kTilesPerWave; ++j) {
+            const int tx = w + 4 * j;
+            if (tx < tx_n) {
+                f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int ks = 0; ks < kMaxKSteps; ++ks) {
+                    if (32 * ks < p0) {
+                        const int ao = (s * 16 + li) * ldb + 32 * ks + 8 * lk;
+                        const u16x8 ah = *reinterpret_cast<const u16x8*>(ph + ao);
+                        const u16x8 al = *reinterpret_cast<const u16x8*>(pl + ao);
+                        acc = mfma3(ah, al, bx.h[j][ks], bx.l[j][ks], acc);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    unsigned short h, lo;
+                    split(acc[r], &h, &lo);
+                    const int o = (tx * 16 + li) * ldb + s * 16 + 4 * lk + r;
+                    uh[o] = h;
+                    ul[o] = lo;
+                }
             }
         }
-        // store U transposed, split
-        for (int tx = 0; tx < tx_n; ++tx)
-            for (int r = 0; r < 4; ++r) {
-                unsigned short h, lo;
-                split(acc[tx][r], &h, &lo);
-                const int o = (tx * 16 + li) * ldb + s * 16 + 4 * lk + r;
-                uh[o] = h;
-                ul[o] = lo;
-            }
     }
     __syncthreads();
-    // T = Ky U: A[i][k] = Ky[y][y'] (row contiguous), B[k][j] = U^T[x][y']
+    // T = Ky U: tiles (row tile ty = w + 4j, column strip c); B[k][j] = U^T[x][y']
     float* dst = tgrid + ((size_t)t * a.g[2] + z) * g1 * g0;
-    for (int c = w; c < tx_n; c += 4) {
-        f32x4 acc[kMaxTiles];
-        for (int ty = 0; ty < ty_n; ++ty) acc[ty] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int k0 = 0; k0 < p1; k0 += 32) {
-            const int bo = (c * 16 + li) * ldb + k0 + 8 * lk;
-            const u16x8 bh = *reinterpret_cast<const u16x8*>(uh + bo);
-            const u16x8 bl = *reinterpret_cast<const u16x8*>(ul + bo);
-            for (int ty = 0; ty < ty_n; ++ty) {
-                const size_t ao = (size_t)(ty * 16 + li) * p1 + k0 + 8 * lk;
-                const u16x8 ah = *reinterpret_cast<const u16x8*>(Kyh + ao);
-                const u16x8 al = *reinterpret_cast<const u16x8*>(Kyl + ao);
-                acc[ty] = mfma3(ah, al, bh, bl, acc[ty]);
+    for (int c = 0; c < tx_n; ++c) {
+        const int x = c * 16 + li;
+#pragma unroll
+        for (int j = 0; j < kTilesPerWave; ++j) {
+            const int ty = w + 4 * j;
+            if (ty < ty_n) {
+                f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int ks = 0; ks < kMaxKSteps; ++ks) {
+                    if (32 * ks < p1) {
+                        const int bo = (c * 16 + li) * ldb + 32 * ks + 8 * lk;
+                        const u16x8 bh = *reinterpret_cast<const u16x8*>(uh + bo);
+                        const u16x8 bl = *reinterpret_cast<const u16x8*>(ul + bo);
+                        acc = mfma3(ay.h[j][ks], ay.l[j][ks], bh, bl, acc);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int y = ty * 16 + 4 * lk + r;
+                    if (y < g1 && x < g0) dst[y * g0 + x] = acc[r];
+                }
             }
         }
-        const int x = c * 16 + li;
-        for (int ty = 0; ty < ty_n; ++ty)
-            for (int r = 0; r < 4; ++r) {
-                const int y = ty * 16 + 4 * lk + r;
-                if (y < g1 && x < g0) dst[y * g0 + x] = acc[ty][r];
-            }
     }
 }
 
-__device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid,
+// phi[:, c] = sum_t Kz_t T_t[:, c] for 16 grid columns c: every term's
+// columns are staged (transposed to [col][z'], split) at once; the Kz
+// fragments of term t + 1 are loaded while term t is multiplied.
+__device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, float* smem,
                                                  const float* __restrict__ tgrid,
                                                  const unsigned short* __restrict__ kz,
                                                  float* __restrict__ phi) {
-    // per term: the 16 columns of T_t, transposed to [col][z'] and split
-    __shared__ __attribute__((aligned(16))) unsigned short th[16][kMaxGrid + 8];
-    __shared__ __attribute__((aligned(16))) unsigned short tl[16][kMaxGrid + 8];
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int li = l & 15, lk = l >> 4;
-    const int g2 = a.g[2], p2 = a.gp[2];
+    const int g2 = a.g[2], p2 = a.gp[2], ld = p2 + 8;
     const int ncol = a.g[0] * a.g[1];
     const int c0 = bid * 16;
     const int tz_n = p2 / 16;
     const size_t mz = (size_t)p2 * p2;
-    f32x4 acc[kMaxTiles / 4];
-    for (int m = 0; m < kMaxTiles / 4; ++m) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    unsigned short* th = reinterpret_cast<unsigned short*>(smem);   // [t][16][ld] hi
+    unsigned short* tl = th + (size_t)a.nterms * 16 * ld;           // lo
+    Frags cur, nxt;
+    load_frags(cur, kz, kz + mz, p2, tz_n, w, li, lk);
+    for (int idx = threadIdx.x; idx < a.nterms * 16 * p2; idx += 256) {
+        const int t = idx / (16 * p2), r = idx - t * 16 * p2;
+        const int zp = r >> 4, c = r & 15;
+        const float v = (zp < g2 && c0 + c < ncol)
+                            ? tgrid[((size_t)t * g2 + zp) * ncol + c0 + c] : 0.0f;
+        unsigned short h, lo;
+        split(v, &h, &lo);
+        th[((size_t)t * 16 + c) * ld + zp] = h;
+        tl[((size_t)t * 16 + c) * ld + zp] = lo;
+    }
+    __syncthreads();
+    f32x4 acc[kTilesPerWave];
+#pragma unroll
+    for (int j = 0; j < kTilesPerWave; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int t = 0; t < a.nterms; ++t) {
-        const float* T = tgrid + (size_t)t * g2 * ncol;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < 16 * p2; idx += 256) {
-            const int zp = idx >> 4, c = idx & 15;
-            const float v = (zp < g2 && c0 + c < ncol) ? T[(size_t)zp * ncol + c0 + c] : 0.0f;
-            unsigned short h, lo;
-            split(v, &h, &lo);
-            th[c][zp] = h;
-            tl[c][zp] = lo;
-        }
-        __syncthreads();
-        const unsigned short* Kzh = kz + 2 * mz * t;
-        const unsigned short* Kzl = Kzh + mz;
-        for (int k0 = 0; k0 < p2; k0 += 32) {
-            const u16x8 bh = *reinterpret_cast<const u16x8*>(&th[li][k0 + 8 * lk]);
-            const u16x8 bl = *reinterpret_cast<const u16x8*>(&tl[li][k0 + 8 * lk]);
-            for (int m = 0, tz = w; tz < tz_n; ++m, tz += 4) {
-                const size_t ao = (size_t)(tz * 16 + li) * p2 + k0 + 8 * lk;
-                const u16x8 ah = *reinterpret_cast<const u16x8*>(Kzh + ao);
-                const u16x8 al = *reinterpret_cast<const u16x8*>(Kzl + ao);
-                acc[m] = mfma3(ah, al, bh, bl, acc[m]);
+        if (t + 1 < a.nterms)
+            load_frags(nxt, kz + 2 * mz * (t + 1), kz + 2 * mz * (t + 1) + mz, p2, tz_n, w, li, lk);
+        const unsigned short* bhp = th + ((size_t)t * 16 + li) * ld + 8 * lk;
+        const unsigned short* blp = tl + ((size_t)t * 16 + li) * ld + 8 * lk;
+#pragma unroll
+        for (int ks = 0; ks < kMaxKSteps; ++ks) {
+            if (32 * ks < p2) {
+                const u16x8 bh = *reinterpret_cast<const u16x8*>(bhp + 32 * ks);
+                const u16x8 bl = *reinterpret_cast<const u16x8*>(blp + 32 * ks);
+#pragma unroll
+                for (int j = 0; j < kTilesPerWave; ++j)
+                    if (w + 4 * j < tz_n) acc[j] = mfma3(cur.h[j][ks], cur.l[j][ks], bh, bl, acc[j]);
             }
         }
+        cur = nxt;
     }
     const int col = c0 + li;
-    for (int m = 0, tz = w; tz < tz_n; ++m, tz += 4)
-        for (int r = 0; r < 4; ++r) {
-            const int zz = tz * 16 + 4 * lk + r;
-            if (zz < g2 && col < ncol) phi[(size_t)zz * ncol + col] = acc[m][r];
-        }
+#pragma unroll
+    for (int j = 0; j < kTilesPerWave; ++j) {
+        const int tz = w + 4 * j;
+        if (tz < tz_n)
+            for (int r = 0; r < 4; ++r) {
+                const int zz = tz * 16 + 4 * lk + r;
+                if (zz < g2 && col < ncol) phi[(size_t)zz * ncol + col] = acc[j][r];
+            }
+    }
 }
 
 // ------------------------------------------------------------------ kernels
@@ -303,7 +351,8 @@ __global__ void __launch_bounds__(256) k_conv_xy_bf16(ConvArgs a, const float* _
 __global__ void __launch_bounds__(256) k_conv_z_bf16(ConvArgs a, const float* __restrict__ tgrid,
                                                      const unsigned short* __restrict__ kz,
                                                      float* __restrict__ phi) {
-    conv_z_bf16_body(a, blockIdx.x, tgrid, kz, phi);
+    extern __shared__ float dyn_lds[];
+    conv_z_bf16_body(a, blockIdx.x, dyn_lds, tgrid, kz, phi);
 }
 
 // batched: item = t * g_z + z (conv_xy), 16-column group (conv_z)
@@ -327,11 +376,12 @@ __global__ void __launch_bounds__(256) k_conv_xy_batch(const BatchTable* __restr
 template <int BF16>
 __global__ void __launch_bounds__(256) k_conv_z_batch(const BatchTable* __restrict__ tab,
                                                       const BoxDesc* __restrict__ desc) {
+    extern __shared__ float dyn_lds[];
     batch_for(tab, BK_CONV_Z, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
         if constexpr (BF16 != 0)
-            conv_z_bf16_body(d.conv, item, d.tgrid, reinterpret_cast<const unsigned short*>(d.kz),
-                             d.phi);
+            conv_z_bf16_body(d.conv, item, dyn_lds, d.tgrid,
+                             reinterpret_cast<const unsigned short*>(d.kz), d.phi);
         else
             conv_z_f32_body(d.conv, item, d.tgrid, d.kz, d.phi);
     });
@@ -345,6 +395,11 @@ size_t conv_xy_lds_bytes(const ConvArgs& a) {
         return (size_t)2 * ldb * (a.gp[0] + a.gp[1]) * sizeof(unsigned short);
     }
     return (size_t)a.gp[1] * (a.gp[0] + 4) * sizeof(float);
+}
+
+size_t conv_z_lds_bytes(const ConvArgs& a) {
+    if (!a.bf16x3) return 0;
+    return (size_t)2 * a.nterms * 16 * (a.gp[2] + 8) * sizeof(unsigned short);
 }
 
 hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx, const float* ky,
@@ -365,7 +420,7 @@ hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz,
     const int ncol = a.g[0] * a.g[1];
     const int nb = (ncol + 15) / 16;
     if (a.bf16x3)
-        hipLaunchKernelGGL(k_conv_z_bf16, dim3(nb), dim3(256), 0, st, a, tgrid,
+        hipLaunchKernelGGL(k_conv_z_bf16, dim3(nb), dim3(256), conv_z_lds_bytes(a), st, a, tgrid,
                            reinterpret_cast<const unsigned short*>(kz), phi);
     else
         hipLaunchKernelGGL(k_conv_z_f32, dim3(nb), dim3(256), 0, st, a, tgrid, kz, phi);
@@ -381,10 +436,10 @@ hipError_t launch_conv_xy_batch(const BatchTable* tab, const BoxDesc* desc, int 
     return hipGetLastError();
 }
 
-hipError_t launch_conv_z_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3, int grid,
-                               hipStream_t st) {
+hipError_t launch_conv_z_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3, size_t lds,
+                               int grid, hipStream_t st) {
     if (bf16x3)
-        hipLaunchKernelGGL(k_conv_z_batch<1>, dim3(grid), dim3(256), 0, st, tab, desc);
+        hipLaunchKernelGGL(k_conv_z_batch<1>, dim3(grid), dim3(256), lds, st, tab, desc);
     else
         hipLaunchKernelGGL(k_conv_z_batch<0>, dim3(grid), dim3(256), 0, st, tab, desc);
     return hipGetLastError();

@@ -7,10 +7,10 @@
 // Layout: cluster-pair tiles.  Charges are binned into x-y columns, sorted
 // by z, and cut into clusters of up to 8 (see kernels_bin.hip).  One block of
 // two wavefronts takes one i-cluster.  Its candidate j-charges are those of
-// the columns within r_c of the i-column (x-y gap) whose clusters' z extent
-// meets the i-cluster's z extent widened by the z reach sqrt(r_c^2 - gap^2):
-// per column a contiguous cluster range, found by binary search on the
-// z-sorted clusters, and so a contiguous range of sorted charges.  The
+// the columns within r_c of the i-column (x-y gap) lying in the grid z-planes
+// that meet the i-cluster's z extent widened by the z reach
+// sqrt(r_c^2 - gap^2): per column at most two contiguous ranges of sorted
+// charges, read from the column's z-plane index (kernels_bin.hip).  The
 // concatenated ranges are walked 8 charges per step: lane (a, b) =
 // (lane / 8, lane % 8) holds i-charge a and j-charge b of the step, so every
 // lane evaluates one pair per step and no lane waits on another's branch.
@@ -83,6 +83,7 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
                                           const int2* __restrict__ cl_info,
                                           const int* __restrict__ cl_col,
                                           const uint2* __restrict__ cl_z,
+                                          const int* __restrict__ zbin,
                                           float4* __restrict__ fnear,
                                           double* __restrict__ epart) {
     __shared__ uint4 stage[kPairWaves][kChunkCharges];
@@ -93,7 +94,7 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     __shared__ double eother;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int ia = lane >> 3, ja = lane & 7;
-    const int ncx = a.nc[0], ncy = a.nc[1];
+    const int ncx = a.nc[0], ncy = a.nc[1], gz = a.gz;
     if (I >= clus_start[ncx * ncy]) {
         if (tid == 0) epart[I] = 0.0;
         return;
@@ -115,24 +116,30 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         const float gx = (float)max(0, abs(dx) - 1) * a.cw[0];
         const float gy = (float)max(0, abs(dy) - 1) * a.cw[1];
         const float d2 = gx * gx + gy * gy;
-        int b0 = 0, l0 = 0, b1 = 0, l1 = 0;
-        if (d2 < a.rc2) {
-            const long long rz = (long long)(sqrtf(a.rc2 - d2) * a.zinv) + 2;
-            const int col = coly * ncx + colx;
-            column_zrange(cl_z, clus_start[col], clus_start[col + 1], (long long)zI.x - rz,
-                          (long long)zI.y + rz, &b0, &l0, &b1, &l1);
-        }
-        // consecutive clusters of a column hold consecutive sorted charges
         int c0 = 0, n0 = 0, c1 = 0, n1 = 0;
-        if (l0 > 0) {
-            const int2 f = cl_info[b0], e = cl_info[b0 + l0 - 1];
-            c0 = f.x;
-            n0 = e.x + e.y - f.x;
-        }
-        if (l1 > 0) {
-            const int2 f = cl_info[b1], e = cl_info[b1 + l1 - 1];
-            c1 = f.x;
-            n1 = e.x + e.y - f.x;
+        if (d2 < a.rc2) {
+            // grid z-planes of the window [zI.x - rz, zI.y + rz] (fixed point,
+            // periodic), then the column's charges of those planes
+            const long long rz = (long long)(sqrtf(a.rc2 - d2) * a.zinv) + 2;
+            const long long plo = (((long long)zI.x - rz) * gz) >> 32;
+            const long long phi = (((long long)zI.y + rz) * gz) >> 32;
+            const int len = (int)(phi - plo) + 1;
+            const int* zr = zbin + (size_t)(coly * ncx + colx) * (gz + 1);
+            if (len >= gz) {
+                c0 = zr[0];
+                n0 = zr[gz] - c0;
+            } else {
+                const int zs = (int)(plo < 0 ? plo + gz : (plo >= gz ? plo - gz : plo));
+                const int ze = zs + len;
+                c0 = zr[zs];
+                if (ze <= gz) {
+                    n0 = zr[ze] - c0;
+                } else {
+                    n0 = zr[gz] - c0;
+                    c1 = zr[0];
+                    n1 = zr[ze - gz] - c1;
+                }
+            }
         }
         rbeg[2 * k] = c0;
         rbeg[2 * k + 1] = c1;
@@ -255,9 +262,10 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pair(PairArgs a, const uint
                                              const int2* __restrict__ cl_info,
                                              const int* __restrict__ cl_col,
                                              const uint2* __restrict__ cl_z,
+                                             const int* __restrict__ zbin,
                                              float4* __restrict__ fnear,
                                              double* __restrict__ epart) {
-    pair_body<DEG>(a, blockIdx.x, sorted, clus_start, cl_info, cl_col, cl_z, fnear, epart);
+    pair_body<DEG>(a, blockIdx.x, sorted, clus_start, cl_info, cl_col, cl_z, zbin, fnear, epart);
 }
 
 template <int DEG>
@@ -265,21 +273,21 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pair_batch(const BatchTable
                                                    const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_PAIR, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        pair_body<DEG>(d.pair, item, d.sorted, d.clus_start, d.cl_info, d.cl_col, d.cl_z,
+        pair_body<DEG>(d.pair, item, d.sorted, d.clus_start, d.cl_info, d.cl_col, d.cl_z, d.zbin,
                        d.fnear, d.pair_parts);
     });
 }
 
 hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, const int* clus_start,
-                       const int2* cl_info, const int* cl_col, const uint2* cl_z, float4* fnear,
-                       double* epart, hipStream_t st) {
+                       const int2* cl_info, const int* cl_col, const uint2* cl_z, const int* zbin,
+                       float4* fnear, double* epart, hipStream_t st) {
     if (nblocks <= 0) return hipSuccess;
     const dim3 grid(nblocks), block(64 * kPairWaves);
     switch (a.deg) {
 #define USERIES_PAIR_DEG(D)                                                                   \
     case D:                                                                                   \
         hipLaunchKernelGGL(k_pair<D>, grid, block, 0, st, a, sorted, clus_start, cl_info,     \
-                           cl_col, cl_z, fnear, epart);                                       \
+                           cl_col, cl_z, zbin, fnear, epart);                                 \
         break;
         USERIES_PAIR_DEG(4) USERIES_PAIR_DEG(5) USERIES_PAIR_DEG(6) USERIES_PAIR_DEG(7)
         USERIES_PAIR_DEG(8) USERIES_PAIR_DEG(9) USERIES_PAIR_DEG(10) USERIES_PAIR_DEG(11)

@@ -117,6 +117,7 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     for (int k = 0; k <= deg; ++k) pa.c[k] = (float)coef[k];
     pa.c0lo = (float)(coef[0] - (double)pa.c[0]);
     for (int k = 0; k <= deg; ++k) pa.d[k] = (float)gcoef[k];
+    pa.gz = grid[2];
     pa.rc2 = (float)(r_c * r_c);
     pa.inv_rc2 = (float)(1.0 / (r_c * r_c));
 

@@ -160,7 +160,7 @@ struct Req {
     Layout lay{};
     Staging stg{};
     int items[BK_COUNT] = {0};
-    size_t lds = 0;
+    size_t lds = 0, lds_z = 0;   // dynamic LDS of conv_xy and conv_z
     // shared with API threads (under the server mutex)
     int state = USERIES_PENDING;
     int err_code = USERIES_OK;
@@ -207,7 +207,7 @@ struct useries_server_s {
     std::vector<Slot> slots;
     int grid[BK_COUNT] = {0};
     int lds_limit = 0;
-    std::map<size_t, hipGraphExec_t> graphs;
+    std::map<std::pair<size_t, size_t>, hipGraphExec_t> graphs;   // by the conv LDS sizes
     std::vector<hipGraph_t> graph_objs;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
@@ -255,36 +255,32 @@ struct useries_server_s {
     }
 
     // the kernels of one step, in order, on the server stream
-    hipError_t enqueue_kernels(size_t lds) {
+    hipError_t enqueue_kernels(size_t lds, size_t lds_z) {
         const bool bf = precision == USERIES_BF16X3;
         hipError_t e;
         if ((e = launch_encode_batch(d_table, d_desc, grid[BK_ENCODE], st))) return e;
         if ((e = launch_scan_batch(d_table, d_desc, grid[BK_SCAN], st))) return e;
         if ((e = launch_scatter_batch(d_table, d_desc, grid[BK_SCATTER], st))) return e;
         if ((e = launch_colsort_batch(d_table, d_desc, grid[BK_COLSORT], st))) return e;
-        // far part on the side stream, beside the pair kernel; gather joins them
-        if ((e = hipEventRecord(fork_ev, st))) return e;
-        if ((e = hipStreamWaitEvent(side, fork_ev, 0))) return e;
-        if ((e = launch_spread_batch(d_table, d_desc, grid[BK_SPREAD], side))) return e;
-        if ((e = launch_conv_xy_batch(d_table, d_desc, bf, lds, grid[BK_CONV_XY], side))) return e;
-        if ((e = launch_conv_z_batch(d_table, d_desc, bf, grid[BK_CONV_Z], side))) return e;
-        if ((e = hipEventRecord(join_ev, side))) return e;
         if ((e = launch_pair_batch(d_table, d_desc, popts.poly_degree, grid[BK_PAIR], st))) return e;
-        if ((e = hipStreamWaitEvent(st, join_ev, 0))) return e;
+        if ((e = launch_spread_batch(d_table, d_desc, grid[BK_SPREAD], st))) return e;
+        if ((e = launch_conv_xy_batch(d_table, d_desc, bf, lds, grid[BK_CONV_XY], st))) return e;
+        if ((e = launch_conv_z_batch(d_table, d_desc, bf, lds_z, grid[BK_CONV_Z], st))) return e;
         if ((e = launch_gather_batch(d_table, d_desc, grid[BK_GATHER], st))) return e;
         if ((e = launch_finalize_batch(d_table, d_desc, grid[BK_FINAL], st))) return e;
         return launch_displace_batch(d_table, d_desc, grid[BK_DISPLACE], st);
     }
 
-    hipError_t graph_for(size_t lds, hipGraphExec_t* out) {
-        auto it = graphs.find(lds);
+    hipError_t graph_for(size_t lds, size_t lds_z, hipGraphExec_t* out) {
+        const std::pair<size_t, size_t> key(lds, lds_z);
+        auto it = graphs.find(key);
         if (it != graphs.end()) {
             *out = it->second;
             return hipSuccess;
         }
         hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e) return e;
-        const hipError_t el = enqueue_kernels(lds);
+        const hipError_t el = enqueue_kernels(lds, lds_z);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(st, &g);
         if (el) {
@@ -298,7 +294,7 @@ struct useries_server_s {
             return e;
         }
         graph_objs.push_back(g);
-        graphs[lds] = ex;
+        graphs[key] = ex;
         {
             std::lock_guard<std::mutex> lk(mu);
             stats[5] += 1;
@@ -432,7 +428,7 @@ struct useries_server_s {
         const int nb = (int)active.size();
         T.nbox = nb;
         for (int k = 0; k < BK_COUNT; ++k) T.off[k][0] = 0;
-        size_t lds = 0;
+        size_t lds = 0, lds_z = 0;
         for (int i = 0; i < nb; ++i) {
             Req* R = active[i];
             T.slot[i] = R->slot;
@@ -444,14 +440,15 @@ struct useries_server_s {
                 T.off[k][i + 1] = T.off[k][i] + items;
             }
             lds = std::max(lds, R->lds);
+            lds_z = std::max(lds_z, R->lds_z);
         }
         if ((e = hipMemcpyAsync(d_table, &T, sizeof(BatchTable), hipMemcpyHostToDevice, st)))
             return e;
         if (o.use_graph) {
             hipGraphExec_t ex = nullptr;
-            if ((e = graph_for(lds, &ex))) return e;
+            if ((e = graph_for(lds, lds_z, &ex))) return e;
             if ((e = hipGraphLaunch(ex, st))) return e;
-        } else if ((e = enqueue_kernels(lds))) {
+        } else if ((e = enqueue_kernels(lds, lds_z))) {
             return e;
         }
         if ((e = hipEventRecord(ring_ev[r], st))) return e;
@@ -734,8 +731,9 @@ int useries_submit(useries_server_t S, const useries_request* req, uint64_t* tic
     choose_columns(&R->hp, n);
     const HostPlan& hp = R->hp;
     R->lds = conv_xy_lds_bytes(hp.conv);
-    if (S->lds_limit > 0 && R->lds > (size_t)S->lds_limit)
-        return set_last_error(USERIES_EINVAL, "grid plane needs more LDS than the device has");
+    R->lds_z = conv_z_lds_bytes(hp.conv);
+    if (S->lds_limit > 0 && std::max(R->lds, R->lds_z) > (size_t)S->lds_limit)
+        return set_last_error(USERIES_EINVAL, "grid and term count need more LDS than the device has");
     R->lay = make_layout(hp, n, r.n_evals);
     R->stg = make_staging(hp, n, r.n_evals);
     if (R->lay.total > S->budget)

@@ -63,6 +63,7 @@ struct PairArgs {
     float zinv;           // 2^32 / L_z: A to fixed-point units along z
     float rc2;            // r_c^2
     float inv_rc2;        // 1 / r_c^2
+    int gz;               // grid points along z (planes of the z-plane index)
     int deg;              // polynomial degree
     float c[kMaxPolyDeg + 1];   // F_inf(r) = sum c_k x^k, x = r^2/rc^2
     float c0lo;                 // c_0 - (float)c_0
@@ -128,8 +129,9 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
 // sets nc, R, cw and n in the kernel arguments.
 void choose_columns(HostPlan* hp, int n);
 
-// LDS bytes of the conv_xy kernel for a grid shape
+// dynamic LDS bytes of the conv_xy and conv_z kernels for a grid shape
 size_t conv_xy_lds_bytes(const ConvArgs& a);
+size_t conv_z_lds_bytes(const ConvArgs& a);
 
 // Blocks of the pair kernel for n charges (an upper bound of the clusters)
 // and of the gather kernel (its bricks)
@@ -195,8 +197,8 @@ hipError_t launch_pair_batch(const BatchTable* tab, const BoxDesc* desc, int deg
 hipError_t launch_spread_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
 hipError_t launch_conv_xy_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3,
                                 size_t lds, int grid, hipStream_t st);
-hipError_t launch_conv_z_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3, int grid,
-                               hipStream_t st);
+hipError_t launch_conv_z_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3, size_t lds,
+                               int grid, hipStream_t st);
 hipError_t launch_gather_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
 hipError_t launch_finalize_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
                                  hipStream_t st);
@@ -216,8 +218,8 @@ hipError_t launch_colsort(int ncol, const int* col_start, const int* clus_start,
                           const uint4* coord, int* perm, uint4* sorted, int2* cl_info,
                           int* cl_col, uint2* cl_z, int gz, int* zbin, hipStream_t st);
 hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, const int* clus_start,
-                       const int2* cl_info, const int* cl_col, const uint2* cl_z, float4* fnear,
-                       double* epart, hipStream_t st);
+                       const int2* cl_info, const int* cl_col, const uint2* cl_z, const int* zbin,
+                       float4* fnear, double* epart, hipStream_t st);
 hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* zbin,
                          const double* qstats, float* rho, hipStream_t st);
 hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx,
