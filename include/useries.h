@@ -85,7 +85,8 @@ enum {
  *                    choose N when useries_plan gets n_terms <= 0.
  *   poly_degree      degree in r^2 of the polynomials that represent the
  *                    infinite far series F and F'(r)/r inside the cutoff
- *                    (near part); <= 0 picks 8.  4 <= degree <= 14.
+ *                    (near part); <= 0 picks 7 (fit error ~4e-8 of max |F|,
+ *                    FP32 level).  4 <= degree <= 14.
  *   max_atoms        workspace capacity in charges; <= 0 grows on demand
  *                    (a growth reallocates and synchronises the device).
  */
@@ -251,7 +252,7 @@ typedef struct {
 /*
  * Server options (useries_server_default_opts fills the defaults).
  *   construction, b, nterms_tol, poly_degree: as in useries_opts / useries_plan
- *              (defaults C1, b = 2, 1e-8, 8).
+ *              (defaults C1, b = 2, 1e-8, 7).
  *   use_graph  1: one captured HIP graph per step (default); 0: the same
  *              kernels launched one by one.
  *   inflight   steps enqueued ahead of the device (1..4, default 2).

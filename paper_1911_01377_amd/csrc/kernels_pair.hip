@@ -77,6 +77,47 @@ __device__ __forceinline__ void stencil_col(int k, int ci, int R, int nc, bool f
 
 }  // namespace
 
+// nsteps steps of 8 staged j-charges (st8[s * 8 + ja]) against i-charge ci.
+// CUBIC: distances in fixed-point units (one scale for all axes), qw = q_i u,
+// rc2/irc2 in those units and is = 1/u; otherwise distances in A, qw = q_i.
+template <int DEG, bool CUBIC>
+__device__ __forceinline__ void pair_steps(const Poly<DEG>& P, const uint4* st8, int ja, int nsteps,
+                                           uint4 ci, float qw, float sx, float sy, float sz,
+                                           float rc2, float irc2, float is, float ctop, float dtop,
+                                           float& fx, float& fy, float& fz, float& ec) {
+    for (int s = 0; s < nsteps; ++s) {
+        const uint4 cj = st8[s * 8 + ja];
+        float dx = (float)(int)(ci.x - cj.x), dy = (float)(int)(ci.y - cj.y),
+              dz = (float)(int)(ci.z - cj.z);
+        if (!CUBIC) {
+            dx *= sx;
+            dy *= sy;
+            dz *= sz;
+        }
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        // a charge of 0 (padding) contributes exactly 0; r2 is then still
+        // >= (L / 2^32)^2 (>= 1 in fixed-point units) or 0, never subnormal
+        if (r2 < rc2 && r2 > 0.0f) {
+            const float qq = qw * __uint_as_float(cj.w);
+            const float rsq = __builtin_amdgcn_rsqf(r2);
+            const float rinv = CUBIC ? rsq * is : rsq;   // 1/r in 1/A
+            const float x = r2 * irc2;
+            float Pp = fmaf(ctop, x, P.c[DEG - 1]);
+#pragma unroll
+            for (int m = DEG - 2; m >= 1; --m) Pp = fmaf(Pp, x, P.c[m]);
+            const float Flo = fmaf(Pp, x, P.c0lo);
+            float G = fmaf(dtop, x, P.d[DEG - 1]);
+#pragma unroll
+            for (int m = DEG - 2; m >= 0; --m) G = fmaf(G, x, P.d[m]);
+            ec = fmaf(qq, (rinv - P.c[0]) - Flo, ec);
+            const float fs = qq * fmaf(rinv * rinv, rinv, G);
+            fx = fmaf(fs, dx, fx);
+            fy = fmaf(fs, dy, fy);
+            fz = fmaf(fs, dz, fz);
+        }
+    }
+}
+
 template <int DEG>
 __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4* __restrict__ sorted,
                                           const int* __restrict__ clus_start,
@@ -166,7 +207,7 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         if (tid == 0) roff[0] = 0;
         __syncthreads();
     }
-    const int total = roff[nr];
+    const int total = __builtin_amdgcn_readfirstlane(roff[nr]);   // uniform: loop bounds in SGPRs
 
     // candidate u of a chunk, loaded by this lane (q = 0 and position 0 past the end)
     auto fetch = [&](int c, uint4* out) {
@@ -188,7 +229,15 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     const bool ivalid = ia < ii.y;
     const uint4 ci = ivalid ? sorted[ii.x + ia] : make_uint4(0, 0, 0, 0);   // q = 0 if invalid
     const float qi = __uint_as_float(ci.w);
-    const float sx = a.scale[0], sy = a.scale[1], sz = a.scale[2], rc2 = a.rc2, irc2 = a.inv_rc2;
+    const float sx = a.scale[0], sy = a.scale[1], sz = a.scale[2];
+    // cubic cells: distances stay in fixed-point units u = L / 2^32 (the
+    // scale folded into r_c^2, x = r^2 / r_c^2, 1/r, and the charge of the
+    // force); otherwise each component is scaled to A
+    const bool cubic = sx == sy && sx == sz;
+    const float isx = 1.0f / sx;
+    const float rc2w = cubic ? a.rc2 * isx * isx : a.rc2;
+    const float irc2w = cubic ? a.inv_rc2 * sx * sx : a.inv_rc2;
+    const float qw = cubic ? qi * sx : qi;
     const float ctop = to_vgpr(P.c[DEG]), dtop = to_vgpr(P.d[DEG]);
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     double e = 0.0;                      // FP32 pair energies, flushed to FP64 per chunk
@@ -202,34 +251,12 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         if (c + kPairWaves < nchunks) fetch(c + kPairWaves, pre);   // in flight during the steps
         const int nsteps = min(kChunk, (total - c * kChunkCharges + 7) >> 3);
         float ec = 0.0f;
-        uint4 cjn = stage[w][ja];
-        for (int s = 0; s < nsteps; ++s) {
-            const uint4 cj = cjn;                    // the next step's charge is read ahead
-            if (s + 1 < nsteps) cjn = stage[w][(s + 1) * 8 + ja];
-            const float dx = (float)(int)(ci.x - cj.x) * sx;
-            const float dy = (float)(int)(ci.y - cj.y) * sy;
-            const float dz = (float)(int)(ci.z - cj.z) * sz;
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            // a charge of 0 (padding) contributes exactly 0; r2 is then still
-            // >= (L / 2^32)^2 or 0, never subnormal
-            if (r2 < rc2 && r2 > 0.0f) {
-                const float qq = qi * __uint_as_float(cj.w);
-                const float rinv = __builtin_amdgcn_rsqf(r2);
-                const float x = r2 * irc2;
-                float Pp = fmaf(ctop, x, P.c[DEG - 1]);
-#pragma unroll
-                for (int m = DEG - 2; m >= 1; --m) Pp = fmaf(Pp, x, P.c[m]);
-                const float Flo = fmaf(Pp, x, P.c0lo);
-                float G = fmaf(dtop, x, P.d[DEG - 1]);
-#pragma unroll
-                for (int m = DEG - 2; m >= 0; --m) G = fmaf(G, x, P.d[m]);
-                ec = fmaf(qq, (rinv - P.c[0]) - Flo, ec);
-                const float fs = qq * fmaf(rinv * rinv, rinv, G);
-                fx = fmaf(fs, dx, fx);
-                fy = fmaf(fs, dy, fy);
-                fz = fmaf(fs, dz, fz);
-            }
-        }
+        if (cubic)
+            pair_steps<DEG, true>(P, stage[w], ja, nsteps, ci, qw, sx, sx, sx, rc2w, irc2w, isx,
+                                  ctop, dtop, fx, fy, fz, ec);
+        else
+            pair_steps<DEG, false>(P, stage[w], ja, nsteps, ci, qw, sx, sy, sz, rc2w, irc2w, 1.0f,
+                                   ctop, dtop, fx, fy, fz, ec);
         e += (double)ec;
         wave_sync();
     }
@@ -240,7 +267,8 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         fy += __shfl_xor(fy, off, 64);
         fz += __shfl_xor(fz, off, 64);
     }
-    const double es = wave_sum_d(e);
+    // the cubic path summed (q_i u) q_j (...): back to q_i q_j
+    const double es = wave_sum_d(e) * (cubic ? 1.0 / (double)sx : 1.0);
     if (w == 1) {
         if (ja == 0) fother[ia] = make_float4(fx, fy, fz, 0.0f);
         if (lane == 0) eother = es;

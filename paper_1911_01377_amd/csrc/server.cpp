@@ -641,7 +641,7 @@ int useries_server_default_opts(useries_server_opts* o) {
     o->construction = USERIES_C1;
     o->b = 2.0;
     o->nterms_tol = 1e-8;
-    o->poly_degree = 8;
+    o->poly_degree = 7;
     o->use_graph = 1;
     o->inflight = 2;
     return USERIES_OK;
