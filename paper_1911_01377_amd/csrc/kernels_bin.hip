@@ -216,9 +216,10 @@ __global__ void __launch_bounds__(256) k_scatter_batch(const BatchTable* __restr
 }
 
 // One block per column: sort the column's charges by the key (z, input
-// index) -- unique, so the order is deterministic -- with a bitonic sort in
-// LDS (columns above kSortCap charges fall back to ranking by counting), then
-// write the permutation, the sorted positions and the column's clusters.
+// index) -- unique, so the order is deterministic: up to 256 charges by
+// counting each key's rank in LDS, up to kSortCap by a bitonic sort in LDS,
+// beyond by ranking from global memory -- then write the permutation, the
+// sorted positions, the column's clusters and its z-plane index.
 constexpr int kSortCap = 1024;
 
 __device__ __forceinline__ void colsort_body(int col, const int* __restrict__ start,
@@ -230,6 +231,7 @@ __device__ __forceinline__ void colsort_body(int col, const int* __restrict__ st
                                              uint2* __restrict__ cl_z, int gz,
                                              int* __restrict__ zbin) {
     __shared__ unsigned long long key[kSortCap];
+    __shared__ uint32_t skz[kSortCap];         // z of the sorted charges
     const int t = threadIdx.x;
     const int lo = start[col], cnt = start[col + 1] - lo;
     int* zrow = zbin + (size_t)col * (gz + 1);
@@ -237,7 +239,26 @@ __device__ __forceinline__ void colsort_body(int col, const int* __restrict__ st
         for (int b = t; b <= gz; b += 256) zrow[b] = lo;
         return;
     }
-    if (cnt <= kSortCap) {
+    if (cnt <= 256) {
+        // one charge per thread, its rank counted against every key
+        unsigned long long mine = ~0ull;
+        uint4 c = make_uint4(0, 0, 0, 0);
+        int i = 0;
+        if (t < cnt) {
+            i = slots[lo + t];
+            c = coord[i];
+            mine = ((unsigned long long)c.z << 32) | (unsigned)i;
+            key[t] = mine;
+        }
+        __syncthreads();
+        if (t < cnt) {
+            int r = 0;
+            for (int m = 0; m < cnt; ++m) r += key[m] < mine;
+            perm[lo + r] = i;
+            sorted[lo + r] = c;
+            skz[r] = c.z;
+        }
+    } else if (cnt <= kSortCap) {
         int m = 1;
         while (m < cnt) m <<= 1;
         for (int k = t; k < m; k += 256) {
@@ -269,6 +290,7 @@ __device__ __forceinline__ void colsort_body(int col, const int* __restrict__ st
             const int i = (int)(unsigned)(key[k] & 0xffffffffull);
             perm[lo + k] = i;
             sorted[lo + k] = coord[i];
+            skz[k] = (uint32_t)(key[k] >> 32);
         }
     } else {
         // rank by counting (O(cnt^2) work spread over the block)
@@ -285,13 +307,14 @@ __device__ __forceinline__ void colsort_body(int col, const int* __restrict__ st
         }
     }
     __syncthreads();
+    const bool in_lds = cnt <= kSortCap;
     // z-plane index of the column: zrow[b] = first charge whose grid z index
     // is >= b (b = 0 .. gz), for the spreading and gathering windows
     for (int b = t; b <= gz; b += 256) {
         int l = 0, h = cnt;
         while (l < h) {
             const int mid = (l + h) >> 1;
-            const uint32_t z = cnt <= kSortCap ? (uint32_t)(key[mid] >> 32) : sorted[lo + mid].z;
+            const uint32_t z = in_lds ? skz[mid] : sorted[lo + mid].z;
             if (cell_coord(z, gz) < b) l = mid + 1; else h = mid;
         }
         zrow[b] = lo + l;
@@ -303,7 +326,8 @@ __device__ __forceinline__ void colsort_body(int col, const int* __restrict__ st
         const int nk = min(8, cnt - 8 * k);
         cl_info[c0 + k] = make_int2(b, nk);
         cl_col[c0 + k] = col;
-        cl_z[c0 + k] = make_uint2(sorted[b].z, sorted[b + nk - 1].z);
+        cl_z[c0 + k] = in_lds ? make_uint2(skz[8 * k], skz[8 * k + nk - 1])
+                              : make_uint2(sorted[b].z, sorted[b + nk - 1].z);
     }
 }
 

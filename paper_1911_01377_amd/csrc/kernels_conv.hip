@@ -31,6 +31,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kMaxTiles = kMaxGrid / 16;
+constexpr int kStageBatch = 16;   // global loads issued together per thread when staging
 
 __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -75,9 +76,22 @@ __device__ __forceinline__ void conv_xy_f32_body(const ConvArgs& a, int z, int t
     const int g0 = a.g[0], g1 = a.g[1], p0 = a.gp[0], p1 = a.gp[1];
     const int ld = p0 + 4;
     const float* src = rho + (size_t)z * g1 * g0;
-    for (int idx = threadIdx.x; idx < p1 * p0; idx += 256) {
-        const int y = idx / p0, x = idx - y * p0;
-        sp[y * ld + x] = (y < g1 && x < g0) ? src[y * g0 + x] : 0.0f;
+    const float ip0 = 1.0f / (float)p0;
+    // the loads of a pass are issued together, then stored
+    for (int base = threadIdx.x; base < p1 * p0; base += 256 * kStageBatch) {
+        float v[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int idx = base + 256 * u;
+            const int y = small_div(idx, ip0), x = idx - y * p0;
+            v[u] = (idx < p1 * p0 && y < g1 && x < g0) ? src[y * g0 + x] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int idx = base + 256 * u;
+            const int y = small_div(idx, ip0), x = idx - y * p0;
+            if (idx < p1 * p0) sp[y * ld + x] = v[u];
+        }
     }
     __syncthreads();
     const float* Kx = kx + (size_t)t * p0 * p0;
@@ -198,13 +212,27 @@ __device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int 
     load_frags(bx, kx + 2 * mx * t, kx + 2 * mx * t + mx, p0, tx_n, w, li, lk);
     load_frags(ay, ky + 2 * my * t, ky + 2 * my * t + my, p1, ty_n, w, li, lk);
     const float* src = rho + (size_t)z * g1 * g0;
-    for (int idx = threadIdx.x; idx < p1 * p0; idx += 256) {
-        const int y = idx / p0, x = idx - y * p0;
-        const float v = (y < g1 && x < g0) ? src[y * g0 + x] : 0.0f;
-        unsigned short h, lo;
-        split(v, &h, &lo);
-        ph[y * ldb + x] = h;
-        pl[y * ldb + x] = lo;
+    const float ip0 = 1.0f / (float)p0;
+    // the loads of a pass are issued together, then split and stored
+    for (int base = threadIdx.x; base < p1 * p0; base += 256 * kStageBatch) {
+        float v[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int idx = base + 256 * u;
+            const int y = small_div(idx, ip0), x = idx - y * p0;
+            v[u] = (idx < p1 * p0 && y < g1 && x < g0) ? src[y * g0 + x] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int idx = base + 256 * u;
+            const int y = small_div(idx, ip0), x = idx - y * p0;
+            if (idx < p1 * p0) {
+                unsigned short h, lo;
+                split(v[u], &h, &lo);
+                ph[y * ldb + x] = h;
+                pl[y * ldb + x] = lo;
+            }
+        }
     }
     __syncthreads();
     // U = rho Kx: tiles (strip s, column tile tx = w + 4j); U stored transposed, split
@@ -281,15 +309,30 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
     unsigned short* tl = th + (size_t)a.nterms * 16 * ld;           // lo
     Frags cur, nxt;
     load_frags(cur, kz, kz + mz, p2, tz_n, w, li, lk);
-    for (int idx = threadIdx.x; idx < a.nterms * 16 * p2; idx += 256) {
-        const int t = idx / (16 * p2), r = idx - t * 16 * p2;
-        const int zp = r >> 4, c = r & 15;
-        const float v = (zp < g2 && c0 + c < ncol)
-                            ? tgrid[((size_t)t * g2 + zp) * ncol + c0 + c] : 0.0f;
-        unsigned short h, lo;
-        split(v, &h, &lo);
-        th[((size_t)t * 16 + c) * ld + zp] = h;
-        tl[((size_t)t * 16 + c) * ld + zp] = lo;
+    // per term, the loads of a pass are issued together, then split and stored
+    for (int t = 0; t < a.nterms; ++t) {
+        const float* T = tgrid + (size_t)t * g2 * ncol;
+        for (int base = threadIdx.x; base < 16 * p2; base += 256 * kStageBatch) {
+            float v[kStageBatch];
+#pragma unroll
+            for (int u = 0; u < kStageBatch; ++u) {
+                const int r = base + 256 * u;
+                const int zp = r >> 4, c = r & 15;
+                v[u] = (r < 16 * p2 && zp < g2 && c0 + c < ncol) ? T[(size_t)zp * ncol + c0 + c]
+                                                                  : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kStageBatch; ++u) {
+                const int r = base + 256 * u;
+                const int zp = r >> 4, c = r & 15;
+                if (r < 16 * p2) {
+                    unsigned short h, lo;
+                    split(v[u], &h, &lo);
+                    th[((size_t)t * 16 + c) * ld + zp] = h;
+                    tl[((size_t)t * 16 + c) * ld + zp] = lo;
+                }
+            }
+        }
     }
     __syncthreads();
     f32x4 acc[kTilesPerWave];

@@ -259,6 +259,7 @@ constexpr int kGatherMaxEdge = 19;        // halo edge: 8 + 2*5 - 1 = 17, 4 + 2*
 constexpr int kGatherMaxPieces = 256;     // columns overlapping a brick
 constexpr int kGatherWaves = 8;           // wavefronts per brick
 constexpr int kGatherThreads = 64 * kGatherWaves;
+constexpr int kGatherBatch = 8;           // halo loads issued together per thread
 
 __host__ __device__ inline int gather_brick(int P) { return P <= 5 ? 8 : 4; }
 
@@ -288,13 +289,25 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
     const int E0 = B0 + P2 - 1, E1 = B1 + P2 - 1, E2 = B2 + P2 - 1;
     // potential on the brick and halo: local (hx, hy, hz) = global (X0 - P + 1 + hx, ...)
     const float inv0 = 1.0f / (float)E0, inv1 = 1.0f / (float)E1;
-    for (int idx = tid; idx < E0 * E1 * E2; idx += kGatherThreads) {
-        const int r = small_div(idx, inv0), hx = idx - r * E0;
-        const int hz = small_div(r, inv1), hy = r - hz * E1;
-        const int gx = wrap1(X0 - P + 1 + hx, a.g[0]);
-        const int gy = wrap1(Y0 - P + 1 + hy, a.g[1]);
-        const int gz = wrap1(Z0 - P + 1 + hz, a.g[2]);
-        sphi[idx] = phi[((size_t)gz * a.g[1] + gy) * a.g[0] + gx];
+    const int nh = E0 * E1 * E2;
+    // the loads of a pass are issued together, then stored
+    for (int base = tid; base < nh; base += kGatherThreads * kGatherBatch) {
+        float v[kGatherBatch];
+#pragma unroll
+        for (int u = 0; u < kGatherBatch; ++u) {
+            const int idx = base + kGatherThreads * u;
+            const int r = small_div(idx, inv0), hx = idx - r * E0;
+            const int hz = small_div(r, inv1), hy = r - hz * E1;
+            const int gx = wrap1(X0 - P + 1 + hx, a.g[0]);
+            const int gy = wrap1(Y0 - P + 1 + hy, a.g[1]);
+            const int gz = wrap1(Z0 - P + 1 + hz, a.g[2]);
+            v[u] = idx < nh ? phi[((size_t)gz * a.g[1] + gy) * a.g[0] + gx] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherBatch; ++u) {
+            const int idx = base + kGatherThreads * u;
+            if (idx < nh) sphi[idx] = v[u];
+        }
     }
     // columns overlapping the brick's cells in x and y
     const int cxl = X0 * a.nc[0] / a.g[0], cxh = ((X0 + B0) * a.nc[0] + a.g[0] - 1) / a.g[0] - 1;

@@ -24,7 +24,9 @@ def gpu_eval(xyz, q, box, rc, grid, **kw):
     parts = torch.zeros(5, dtype=torch.float64, device=dev)
     energy, forces, _ = plan.eval(x, qq, parts=parts)
     torch.cuda.synchronize()
-    out = parts.cpu().numpy().copy(), forces.cpu().numpy().astype(np.float64), plan.info
+    from paper_1911_01377_amd import _native
+    info = _native.useries_plan_info(plan.handle)   # after the evaluation: its column grid
+    out = parts.cpu().numpy().copy(), forces.cpu().numpy().astype(np.float64), info
     assert abs(float(energy.cpu()[0]) - out[0][4]) == 0.0
     plan.close()
     return out

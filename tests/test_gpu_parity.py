@@ -65,6 +65,20 @@ def test_orthorhombic_box_and_grid():
     compare("ortho700/plain", xyz, q.astype(np.float32), box, 8.0, (20, 24, 30), 1e-6, 1e-5)
 
 
+def test_tall_box_long_columns():
+    # a 16 x 16 x 96 A water cell (six z-replicas of a 16 A water box): 9
+    # columns of ~270 charges, so the column sort takes its bitonic path
+    # (columns of up to 256 charges are ranked by counting)
+    x1, q1, box1 = synth.water_box(n_mol=137, L=16.0, seed=29)
+    L = box1[0]
+    xyz = np.concatenate([x1 + np.array([0.0, 0.0, k * L], np.float32) for k in range(6)])
+    q = np.concatenate([q1] * 6)
+    box = (L, L, 6 * L)
+    _, _, _, _, info = compare("tallwater/plain", xyz.astype(np.float32), q, box, 0.45 * L,
+                               (16, 16, 96), 1e-6, 1e-5)
+    assert len(q) / (info["ncell"][0] * info["ncell"][1]) > 256
+
+
 def test_non_neutral_and_single_charge():
     """A net charge Q couples to the near-uniform (k ~ 0) part of the FP32
     rounding of the widest convolution terms: the energy error grows like
