@@ -14,8 +14,10 @@
 // concatenated ranges are walked 8 charges per step: lane (a, b) =
 // (lane / 8, lane % 8) holds i-charge a and j-charge b of the step, so every
 // lane evaluates one pair per step and no lane waits on another's branch.
-// The two wavefronts take alternate chunks of 32 steps, each staging its
-// chunk in LDS with coalesced loads issued one chunk ahead.  The force on
+// The two wavefronts take alternate chunks of 256 candidates, each loading
+// its chunk one chunk ahead with coalesced loads and staging in LDS only the
+// candidates within r_c of the i-cluster's bounding box (about 58% of them
+// in water), so the steps skip most pairs that cannot be in range.  The force on
 // charge a is summed over its 8 lanes by shuffles, then over the two
 // wavefronts in a fixed order.
 //
@@ -239,17 +241,62 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     const float irc2w = cubic ? a.inv_rc2 * sx * sx : a.inv_rc2;
     const float qw = cubic ? qi * sx : qi;
     const float ctop = to_vgpr(P.c[DEG]), dtop = to_vgpr(P.d[DEG]);
+
+    // bounding box of the i-cluster (fixed point, offsets from its first
+    // charge), as a centre and half extents.  Per axis the periodic distance
+    // of a candidate from any i-charge is at least its periodic distance from
+    // the centre minus the half extent, so a candidate whose such distances
+    // put it r_c or more from the box meets no i-charge within r_c and is
+    // dropped before the pair steps (the margin covers the FP32 rounding of
+    // the test: the pair set is unchanged)
+    const uint4 c0 = sorted[ii.x];
+    int bl[3], bh[3];
+    bl[0] = bh[0] = ivalid ? (int)(ci.x - c0.x) : 0;
+    bl[1] = bh[1] = ivalid ? (int)(ci.y - c0.y) : 0;
+    bl[2] = bh[2] = ivalid ? (int)(ci.z - c0.z) : 0;
+#pragma unroll
+    for (int off = 8; off < 64; off <<= 1)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            bl[k] = min(bl[k], __shfl_xor(bl[k], off, 64));
+            bh[k] = max(bh[k], __shfl_xor(bh[k], off, 64));
+        }
+    const uint32_t cenx = c0.x + (uint32_t)((bl[0] + bh[0]) / 2);
+    const uint32_t ceny = c0.y + (uint32_t)((bl[1] + bh[1]) / 2);
+    const uint32_t cenz = c0.z + (uint32_t)((bl[2] + bh[2]) / 2);
+    const float hx = (float)((bh[0] - bl[0]) / 2 + 1) * sx;
+    const float hy = (float)((bh[1] - bl[1]) / 2 + 1) * sy;
+    const float hz = (float)((bh[2] - bl[2]) / 2 + 1) * sz;
+    const float rcm = sqrtf(a.rc2) + 1e-3f;
+    const float rcm2 = rcm * rcm;
+    auto near_box = [&](const uint4& cj) {
+        const float ex = fmaxf(0.0f, fabsf((float)(int)(cj.x - cenx) * sx) - hx);
+        const float ey = fmaxf(0.0f, fabsf((float)(int)(cj.y - ceny) * sy) - hy);
+        const float ez = fmaxf(0.0f, fabsf((float)(int)(cj.z - cenz) * sz) - hz);
+        return fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < rcm2;
+    };
+
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     double e = 0.0;                      // FP32 pair energies, flushed to FP64 per chunk
     const int nchunks = (total + kChunkCharges - 1) / kChunkCharges;
     uint4 pre[kChunkCharges / 64];
     if (w < nchunks) fetch(w, pre);
     for (int c = w; c < nchunks; c += kPairWaves) {
+        // keep the candidates near the box, compacted in candidate order,
+        // padded with zero charges to whole steps of 8
+        int kept = 0;
 #pragma unroll
-        for (int u = 0; u < kChunkCharges / 64; ++u) stage[w][u * 64 + lane] = pre[u];
+        for (int u = 0; u < kChunkCharges / 64; ++u) {
+            const int p = c * kChunkCharges + u * 64 + lane;
+            const bool keep = p < total && near_box(pre[u]);
+            const uint64_t m = __ballot(keep);
+            if (keep) stage[w][kept + __popcll(m & ((1ull << lane) - 1ull))] = pre[u];
+            kept += __popcll(m);
+        }
+        if (lane < ((kept + 7) & ~7) - kept) stage[w][kept + lane] = make_uint4(0, 0, 0, 0);
         wave_sync();
         if (c + kPairWaves < nchunks) fetch(c + kPairWaves, pre);   // in flight during the steps
-        const int nsteps = min(kChunk, (total - c * kChunkCharges + 7) >> 3);
+        const int nsteps = (kept + 7) >> 3;
         float ec = 0.0f;
         if (cubic)
             pair_steps<DEG, true>(P, stage[w], ja, nsteps, ci, qw, sx, sx, sx, rc2w, irc2w, isx,
