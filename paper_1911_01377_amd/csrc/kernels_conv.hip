@@ -32,6 +32,7 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kMaxTiles = kMaxGrid / 16;
 constexpr int kStageBatch = 16;   // global loads issued together per thread when staging
+constexpr int kStageBatchZ = 8;   // the same for BF16 conv_z (its Kz fragment is live meanwhile)
 
 __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -162,36 +163,40 @@ __device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid,
 
 // kx/ky/kz hold, per term, the hi matrix followed by the lo matrix (bf16 bits).
 //
-// Wavefront w owns the output tile columns w, w + 4 of each product (at most
-// two: padded edges up to 128 = 8 tiles) and keeps the matching fragments of
-// the constant matrix in registers for the whole item, loaded together with
-// the staging of the plane, so the MFMA loops read only LDS and registers.
+constexpr int kBfWaves = 8;
+constexpr int kBfThreads = 64 * kBfWaves;
 constexpr int kMaxKSteps = kMaxGrid / 32;   // K steps of 32 (BF16 MFMA)
-constexpr int kTilesPerWave = kMaxTiles / 4;
 
-struct Frags {
-    u16x8 h[kTilesPerWave][kMaxKSteps], l[kTilesPerWave][kMaxKSteps];
+// wavefronts sharing one output tile column when `tiles` divides kBfWaves
+// (they split that column's strips), else 1
+__host__ __device__ inline int tile_groups(int tiles) {
+    return (tiles <= kBfWaves && kBfWaves % tiles == 0) ? kBfWaves / tiles : 1;
+}
+
+struct Frag {
+    u16x8 h[kMaxKSteps], l[kMaxKSteps];
 };
 
-// fragments of rows tile*16 + li, k = 32 ks + 8 lk .. + 7, of the gp x gp
-// matrices mh / ml (row-major), for the tiles w, w + 4 below ntiles
-__device__ __forceinline__ void load_frags(Frags& f, const unsigned short* __restrict__ mh,
-                                           const unsigned short* __restrict__ ml, int gp,
-                                           int ntiles, int w, int li, int lk) {
+// fragment of rows tile*16 + li, k = 32 ks + 8 lk .. + 7, of the gp x gp
+// matrices mh / ml (row-major)
+__device__ __forceinline__ void load_frag(Frag& f, const unsigned short* __restrict__ mh,
+                                          const unsigned short* __restrict__ ml, int gp, int tile,
+                                          int li, int lk) {
 #pragma unroll
-    for (int j = 0; j < kTilesPerWave; ++j) {
-        const int tile = w + 4 * j;
-#pragma unroll
-        for (int ks = 0; ks < kMaxKSteps; ++ks) {
-            if (tile < ntiles && 32 * ks < gp) {
-                const size_t o = (size_t)(tile * 16 + li) * gp + 32 * ks + 8 * lk;
-                f.h[j][ks] = *reinterpret_cast<const u16x8*>(mh + o);
-                f.l[j][ks] = *reinterpret_cast<const u16x8*>(ml + o);
-            }
+    for (int ks = 0; ks < kMaxKSteps; ++ks) {
+        if (32 * ks < gp) {
+            const size_t o = (size_t)(tile * 16 + li) * gp + 32 * ks + 8 * lk;
+            f.h[ks] = *reinterpret_cast<const u16x8*>(mh + o);
+            f.l[ks] = *reinterpret_cast<const u16x8*>(ml + o);
         }
     }
 }
 
+// Blocks of eight wavefronts.  In each product wavefront w owns the output
+// tile column w mod n_tiles (and, when n_tiles divides 8, every G-th of its
+// strips, G = 8 / n_tiles) and keeps the matching fragments of the constant
+// matrix in registers for the whole item, loaded together with the staging
+// of the plane, so the MFMA loops read only LDS and registers.
 __device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int t, float* smem,
                                                   const float* __restrict__ rho,
                                                   const unsigned short* __restrict__ kx,
@@ -207,24 +212,28 @@ __device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int 
     unsigned short* ul = uh + p0 * ldb;                              // U^T lo
     const size_t mx = (size_t)p0 * p0, my = (size_t)p1 * p1;
     const int tx_n = p0 / 16, ty_n = p1 / 16;
-    // B of U = rho Kx: Kx[j][k] (Kx symmetric), tiles j owned; A of T = Ky U: Ky rows owned
-    Frags bx, ay;
-    load_frags(bx, kx + 2 * mx * t, kx + 2 * mx * t + mx, p0, tx_n, w, li, lk);
-    load_frags(ay, ky + 2 * my * t, ky + 2 * my * t + my, p1, ty_n, w, li, lk);
+    const int G1 = tile_groups(tx_n), G2 = tile_groups(ty_n);
+    const bool act1 = w < tx_n * G1, act2 = w < ty_n * G2;
+    const int tx = w % tx_n, s0 = w / tx_n;      // U = rho Kx: column tile, first strip
+    const int ty = w % ty_n, c0 = w / ty_n;      // T = Ky U: row tile, first column strip
+    // B of U = rho Kx: Kx[j][k] (Kx symmetric); A of T = Ky U: Ky rows
+    Frag bx, ay;
+    if (act1) load_frag(bx, kx + 2 * mx * t, kx + 2 * mx * t + mx, p0, tx, li, lk);
+    if (act2) load_frag(ay, ky + 2 * my * t, ky + 2 * my * t + my, p1, ty, li, lk);
     const float* src = rho + (size_t)z * g1 * g0;
     const float ip0 = 1.0f / (float)p0;
     // the loads of a pass are issued together, then split and stored
-    for (int base = threadIdx.x; base < p1 * p0; base += 256 * kStageBatch) {
+    for (int base = threadIdx.x; base < p1 * p0; base += kBfThreads * kStageBatch) {
         float v[kStageBatch];
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u) {
-            const int idx = base + 256 * u;
+            const int idx = base + kBfThreads * u;
             const int y = small_div(idx, ip0), x = idx - y * p0;
             v[u] = (idx < p1 * p0 && y < g1 && x < g0) ? src[y * g0 + x] : 0.0f;
         }
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u) {
-            const int idx = base + 256 * u;
+            const int idx = base + kBfThreads * u;
             const int y = small_div(idx, ip0), x = idx - y * p0;
             if (idx < p1 * p0) {
                 unsigned short h, lo;
@@ -235,65 +244,63 @@ __device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int 
         }
     }
     __syncthreads();
-    // U = rho Kx: tiles (strip s, column tile tx = w + 4j); U stored transposed, split
-    for (int s = 0; s < ty_n; ++s) {
+    // U = rho Kx: tiles (strip s, column tile tx); U stored transposed, split
+    if (act1)
+        for (int s = s0; s < ty_n; s += G1) {
+            f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int j = 0; j < kTilesPerWave; ++j) {
-            const int tx = w + 4 * j;
-            if (tx < tx_n) {
-                f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                for (int ks = 0; ks < kMaxKSteps; ++ks) {
-                    if (32 * ks < p0) {
-                        const int ao = (s * 16 + li) * ldb + 32 * ks + 8 * lk;
-                        const u16x8 ah = *reinterpret_cast<const u16x8*>(ph + ao);
-                        const u16x8 al = *reinterpret_cast<const u16x8*>(pl + ao);
-                        acc = mfma3(ah, al, bx.h[j][ks], bx.l[j][ks], acc);
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    unsigned short h, lo;
-                    split(acc[r], &h, &lo);
-                    const int o = (tx * 16 + li) * ldb + s * 16 + 4 * lk + r;
-                    uh[o] = h;
-                    ul[o] = lo;
+            for (int ks = 0; ks < kMaxKSteps; ++ks) {
+                if (32 * ks < p0) {
+                    const int ao = (s * 16 + li) * ldb + 32 * ks + 8 * lk;
+                    const u16x8 ah = *reinterpret_cast<const u16x8*>(ph + ao);
+                    const u16x8 al = *reinterpret_cast<const u16x8*>(pl + ao);
+                    acc = mfma3(ah, al, bx.h[ks], bx.l[ks], acc);
                 }
             }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                unsigned short h, lo;
+                split(acc[r], &h, &lo);
+                const int o = (tx * 16 + li) * ldb + s * 16 + 4 * lk + r;
+                uh[o] = h;
+                ul[o] = lo;
+            }
         }
-    }
     __syncthreads();
-    // T = Ky U: tiles (row tile ty = w + 4j, column strip c); B[k][j] = U^T[x][y']
+    // T = Ky U: tiles (row tile ty, column strip c); B[k][j] = U^T[x][y']
     float* dst = tgrid + ((size_t)t * a.g[2] + z) * g1 * g0;
-    for (int c = 0; c < tx_n; ++c) {
-        const int x = c * 16 + li;
+    if (act2)
+        for (int c = c0; c < tx_n; c += G2) {
+            const int x = c * 16 + li;
+            f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int j = 0; j < kTilesPerWave; ++j) {
-            const int ty = w + 4 * j;
-            if (ty < ty_n) {
-                f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                for (int ks = 0; ks < kMaxKSteps; ++ks) {
-                    if (32 * ks < p1) {
-                        const int bo = (c * 16 + li) * ldb + 32 * ks + 8 * lk;
-                        const u16x8 bh = *reinterpret_cast<const u16x8*>(uh + bo);
-                        const u16x8 bl = *reinterpret_cast<const u16x8*>(ul + bo);
-                        acc = mfma3(ay.h[j][ks], ay.l[j][ks], bh, bl, acc);
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int y = ty * 16 + 4 * lk + r;
-                    if (y < g1 && x < g0) dst[y * g0 + x] = acc[r];
+            for (int ks = 0; ks < kMaxKSteps; ++ks) {
+                if (32 * ks < p1) {
+                    const int bo = (c * 16 + li) * ldb + 32 * ks + 8 * lk;
+                    const u16x8 bh = *reinterpret_cast<const u16x8*>(uh + bo);
+                    const u16x8 bl = *reinterpret_cast<const u16x8*>(ul + bo);
+                    acc = mfma3(ay.h[ks], ay.l[ks], bh, bl, acc);
                 }
             }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int y = ty * 16 + 4 * lk + r;
+                if (y < g1 && x < g0) dst[y * g0 + x] = acc[r];
+            }
         }
-    }
 }
 
-// phi[:, c] = sum_t Kz_t T_t[:, c] for 16 grid columns c: every term's
-// columns are staged (transposed to [col][z'], split) at once; the Kz
-// fragments of term t + 1 are loaded while term t is multiplied.
+// wavefront groups of a conv_z block (each takes every G-th term)
+__host__ __device__ inline int conv_z_groups(const ConvArgs& a) {
+    return a.bf16x3 ? tile_groups(a.gp[2] / 16) : 1;
+}
+
+// phi[:, c] = sum_t Kz_t T_t[:, c] for the block's 16 grid columns c.  Every
+// term's columns are staged (transposed to [col][z'], split) at once.  The
+// wavefronts form G groups; in a group wavefront w owns row tile w mod n_tiles
+// and the group takes terms grp, grp + G, ..., loading the Kz fragment of its
+// next term while it multiplies the current one.  The groups' partial sums are
+// added in group order through LDS.
 __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, float* smem,
                                                  const float* __restrict__ tgrid,
                                                  const unsigned short* __restrict__ kz,
@@ -302,68 +309,79 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
     const int li = l & 15, lk = l >> 4;
     const int g2 = a.g[2], p2 = a.gp[2], ld = p2 + 8;
     const int ncol = a.g[0] * a.g[1];
+    const int tz_n = p2 / 16, G = tile_groups(tz_n);
     const int c0 = bid * 16;
-    const int tz_n = p2 / 16;
+    const bool act = w < tz_n * G;
+    const int tz = w % tz_n, grp = w / tz_n;
     const size_t mz = (size_t)p2 * p2;
     unsigned short* th = reinterpret_cast<unsigned short*>(smem);   // [t][16][ld] hi
     unsigned short* tl = th + (size_t)a.nterms * 16 * ld;           // lo
-    Frags cur, nxt;
-    load_frags(cur, kz, kz + mz, p2, tz_n, w, li, lk);
-    // per term, the loads of a pass are issued together, then split and stored
-    for (int t = 0; t < a.nterms; ++t) {
-        const float* T = tgrid + (size_t)t * g2 * ncol;
-        for (int base = threadIdx.x; base < 16 * p2; base += 256 * kStageBatch) {
-            float v[kStageBatch];
+    Frag cur, nxt;
+    if (act && grp < a.nterms)
+        load_frag(cur, kz + 2 * mz * grp, kz + 2 * mz * grp + mz, p2, tz, li, lk);
+    // the loads of a pass (over all terms) are issued together, then split and stored
+    const int nst = a.nterms * 16 * p2;
+    for (int base = threadIdx.x; base < nst; base += kBfThreads * kStageBatchZ) {
+        float v[kStageBatchZ];
 #pragma unroll
-            for (int u = 0; u < kStageBatch; ++u) {
-                const int r = base + 256 * u;
-                const int zp = r >> 4, c = r & 15;
-                v[u] = (r < 16 * p2 && zp < g2 && c0 + c < ncol) ? T[(size_t)zp * ncol + c0 + c]
-                                                                  : 0.0f;
-            }
+        for (int u = 0; u < kStageBatchZ; ++u) {
+            const int r = base + kBfThreads * u;
+            const int tz_ = r >> 4, c = r & 15;          // tz_ = t p2 + z'
+            const int t = small_div(tz_, 1.0f / (float)p2), zp = tz_ - t * p2;
+            v[u] = (r < nst && zp < g2 && c0 + c < ncol)
+                       ? tgrid[((size_t)t * g2 + zp) * ncol + c0 + c]
+                       : 0.0f;
+        }
 #pragma unroll
-            for (int u = 0; u < kStageBatch; ++u) {
-                const int r = base + 256 * u;
-                const int zp = r >> 4, c = r & 15;
-                if (r < 16 * p2) {
-                    unsigned short h, lo;
-                    split(v[u], &h, &lo);
-                    th[((size_t)t * 16 + c) * ld + zp] = h;
-                    tl[((size_t)t * 16 + c) * ld + zp] = lo;
-                }
+        for (int u = 0; u < kStageBatchZ; ++u) {
+            const int r = base + kBfThreads * u;
+            const int tz_ = r >> 4, c = r & 15;
+            const int t = small_div(tz_, 1.0f / (float)p2), zp = tz_ - t * p2;
+            if (r < nst) {
+                unsigned short h, lo;
+                split(v[u], &h, &lo);
+                th[((size_t)t * 16 + c) * ld + zp] = h;
+                tl[((size_t)t * 16 + c) * ld + zp] = lo;
             }
         }
     }
     __syncthreads();
-    f32x4 acc[kTilesPerWave];
+    f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    if (act) {
+        for (int t = grp; t < a.nterms; t += G) {
+            if (t + G < a.nterms)
+                load_frag(nxt, kz + 2 * mz * (t + G), kz + 2 * mz * (t + G) + mz, p2, tz, li, lk);
+            const unsigned short* bhp = th + ((size_t)t * 16 + li) * ld + 8 * lk;
+            const unsigned short* blp = tl + ((size_t)t * 16 + li) * ld + 8 * lk;
 #pragma unroll
-    for (int j = 0; j < kTilesPerWave; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int t = 0; t < a.nterms; ++t) {
-        if (t + 1 < a.nterms)
-            load_frags(nxt, kz + 2 * mz * (t + 1), kz + 2 * mz * (t + 1) + mz, p2, tz_n, w, li, lk);
-        const unsigned short* bhp = th + ((size_t)t * 16 + li) * ld + 8 * lk;
-        const unsigned short* blp = tl + ((size_t)t * 16 + li) * ld + 8 * lk;
-#pragma unroll
-        for (int ks = 0; ks < kMaxKSteps; ++ks) {
-            if (32 * ks < p2) {
-                const u16x8 bh = *reinterpret_cast<const u16x8*>(bhp + 32 * ks);
-                const u16x8 bl = *reinterpret_cast<const u16x8*>(blp + 32 * ks);
-#pragma unroll
-                for (int j = 0; j < kTilesPerWave; ++j)
-                    if (w + 4 * j < tz_n) acc[j] = mfma3(cur.h[j][ks], cur.l[j][ks], bh, bl, acc[j]);
+            for (int ks = 0; ks < kMaxKSteps; ++ks) {
+                if (32 * ks < p2) {
+                    const u16x8 bh = *reinterpret_cast<const u16x8*>(bhp + 32 * ks);
+                    const u16x8 bl = *reinterpret_cast<const u16x8*>(blp + 32 * ks);
+                    acc = mfma3(cur.h[ks], cur.l[ks], bh, bl, acc);
+                }
             }
+            cur = nxt;
         }
-        cur = nxt;
     }
-    const int col = c0 + li;
+    if (G > 1) {
+        // partial sums of groups 1 .. G-1: [grp-1][tz][lane][4], summed in group order
+        __syncthreads();
+        f32x4* red = reinterpret_cast<f32x4*>(smem);
+        if (act && grp > 0) red[((grp - 1) * tz_n + tz) * 64 + l] = acc;
+        __syncthreads();
+        if (act && grp == 0)
+            for (int g = 1; g < G; ++g) {
+                const f32x4 o = red[((g - 1) * tz_n + tz) * 64 + l];
 #pragma unroll
-    for (int j = 0; j < kTilesPerWave; ++j) {
-        const int tz = w + 4 * j;
-        if (tz < tz_n)
-            for (int r = 0; r < 4; ++r) {
-                const int zz = tz * 16 + 4 * lk + r;
-                if (zz < g2 && col < ncol) phi[(size_t)zz * ncol + col] = acc[j][r];
+                for (int r = 0; r < 4; ++r) acc[r] += o[r];
             }
+    }
+    if (!act || grp != 0) return;
+    const int col = c0 + li;
+    for (int r = 0; r < 4; ++r) {
+        const int zz = tz * 16 + 4 * lk + r;
+        if (zz < g2 && col < ncol) phi[(size_t)zz * ncol + col] = acc[r];
     }
 }
 
@@ -383,7 +401,7 @@ __global__ void __launch_bounds__(256) k_conv_z_f32(ConvArgs a, const float* __r
     conv_z_f32_body(a, blockIdx.x, tgrid, kz, phi);
 }
 
-__global__ void __launch_bounds__(256) k_conv_xy_bf16(ConvArgs a, const float* __restrict__ rho,
+__global__ void __launch_bounds__(kBfThreads) k_conv_xy_bf16(ConvArgs a, const float* __restrict__ rho,
                                                       const unsigned short* __restrict__ kx,
                                                       const unsigned short* __restrict__ ky,
                                                       float* __restrict__ tgrid) {
@@ -391,7 +409,7 @@ __global__ void __launch_bounds__(256) k_conv_xy_bf16(ConvArgs a, const float* _
     conv_xy_bf16_body(a, blockIdx.x, blockIdx.y, dyn_lds, rho, kx, ky, tgrid);
 }
 
-__global__ void __launch_bounds__(256) k_conv_z_bf16(ConvArgs a, const float* __restrict__ tgrid,
+__global__ void __launch_bounds__(kBfThreads) k_conv_z_bf16(ConvArgs a, const float* __restrict__ tgrid,
                                                      const unsigned short* __restrict__ kz,
                                                      float* __restrict__ phi) {
     extern __shared__ float dyn_lds[];
@@ -400,7 +418,7 @@ __global__ void __launch_bounds__(256) k_conv_z_bf16(ConvArgs a, const float* __
 
 // batched: item = t * g_z + z (conv_xy), 16-column group (conv_z)
 template <int BF16>
-__global__ void __launch_bounds__(256) k_conv_xy_batch(const BatchTable* __restrict__ tab,
+__global__ void __launch_bounds__(BF16 ? kBfThreads : 256) k_conv_xy_batch(const BatchTable* __restrict__ tab,
                                                        const BoxDesc* __restrict__ desc) {
     extern __shared__ float dyn_lds[];
     batch_for(tab, BK_CONV_XY, [&](int i, int item) {
@@ -417,7 +435,7 @@ __global__ void __launch_bounds__(256) k_conv_xy_batch(const BatchTable* __restr
 }
 
 template <int BF16>
-__global__ void __launch_bounds__(256) k_conv_z_batch(const BatchTable* __restrict__ tab,
+__global__ void __launch_bounds__(BF16 ? kBfThreads : 256) k_conv_z_batch(const BatchTable* __restrict__ tab,
                                                       const BoxDesc* __restrict__ desc) {
     extern __shared__ float dyn_lds[];
     batch_for(tab, BK_CONV_Z, [&](int i, int item) {
@@ -442,14 +460,18 @@ size_t conv_xy_lds_bytes(const ConvArgs& a) {
 
 size_t conv_z_lds_bytes(const ConvArgs& a) {
     if (!a.bf16x3) return 0;
-    return (size_t)2 * a.nterms * 16 * (a.gp[2] + 8) * sizeof(unsigned short);
+    const size_t stage = (size_t)2 * a.nterms * 16 * (a.gp[2] + 8) * sizeof(unsigned short);
+    const size_t red = (size_t)(conv_z_groups(a) - 1) * (a.gp[2] / 16) * 64 * 4 * sizeof(float);
+    return stage > red ? stage : red;
 }
+
+int conv_z_blocks(const ConvArgs& a) { return (a.g[0] * a.g[1] + 15) / 16; }
 
 hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx, const float* ky,
                           float* tgrid, hipStream_t st) {
     const size_t lds = conv_xy_lds_bytes(a);
     if (a.bf16x3)
-        hipLaunchKernelGGL(k_conv_xy_bf16, dim3(a.g[2], a.nterms), dim3(256), lds, st, a, rho,
+        hipLaunchKernelGGL(k_conv_xy_bf16, dim3(a.g[2], a.nterms), dim3(kBfThreads), lds, st, a, rho,
                            reinterpret_cast<const unsigned short*>(kx),
                            reinterpret_cast<const unsigned short*>(ky), tgrid);
     else
@@ -460,11 +482,10 @@ hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx, 
 
 hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz, float* phi,
                          hipStream_t st) {
-    const int ncol = a.g[0] * a.g[1];
-    const int nb = (ncol + 15) / 16;
+    const int nb = conv_z_blocks(a);
     if (a.bf16x3)
-        hipLaunchKernelGGL(k_conv_z_bf16, dim3(nb), dim3(256), conv_z_lds_bytes(a), st, a, tgrid,
-                           reinterpret_cast<const unsigned short*>(kz), phi);
+        hipLaunchKernelGGL(k_conv_z_bf16, dim3(nb), dim3(kBfThreads), conv_z_lds_bytes(a), st, a,
+                           tgrid, reinterpret_cast<const unsigned short*>(kz), phi);
     else
         hipLaunchKernelGGL(k_conv_z_f32, dim3(nb), dim3(256), 0, st, a, tgrid, kz, phi);
     return hipGetLastError();
@@ -473,7 +494,7 @@ hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz,
 hipError_t launch_conv_xy_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3,
                                 size_t lds, int grid, hipStream_t st) {
     if (bf16x3)
-        hipLaunchKernelGGL(k_conv_xy_batch<1>, dim3(grid), dim3(256), lds, st, tab, desc);
+        hipLaunchKernelGGL(k_conv_xy_batch<1>, dim3(grid), dim3(kBfThreads), lds, st, tab, desc);
     else
         hipLaunchKernelGGL(k_conv_xy_batch<0>, dim3(grid), dim3(256), lds, st, tab, desc);
     return hipGetLastError();
@@ -482,7 +503,7 @@ hipError_t launch_conv_xy_batch(const BatchTable* tab, const BoxDesc* desc, int 
 hipError_t launch_conv_z_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3, size_t lds,
                                int grid, hipStream_t st) {
     if (bf16x3)
-        hipLaunchKernelGGL(k_conv_z_batch<1>, dim3(grid), dim3(256), lds, st, tab, desc);
+        hipLaunchKernelGGL(k_conv_z_batch<1>, dim3(grid), dim3(kBfThreads), lds, st, tab, desc);
     else
         hipLaunchKernelGGL(k_conv_z_batch<0>, dim3(grid), dim3(256), 0, st, tab, desc);
     return hipGetLastError();

@@ -748,7 +748,7 @@ int useries_submit(useries_server_t S, const useries_request* req, uint64_t* tic
     R->items[BK_SPREAD] = ((hp.grid[0] + kB - 1) / kB) * ((hp.grid[1] + kB - 1) / kB) *
                           ((hp.grid[2] + kB - 1) / kB);
     R->items[BK_CONV_XY] = hp.grid[2] * hp.nterms;
-    R->items[BK_CONV_Z] = (hp.grid[0] * hp.grid[1] + 15) / 16;
+    R->items[BK_CONV_Z] = conv_z_blocks(hp.conv);
     R->items[BK_GATHER] = hp.fin.n_gather_parts;
     R->items[BK_FINAL] = 1;
     R->items[BK_DISPLACE] = nq;

@@ -132,6 +132,8 @@ void choose_columns(HostPlan* hp, int n);
 // dynamic LDS bytes of the conv_xy and conv_z kernels for a grid shape
 size_t conv_xy_lds_bytes(const ConvArgs& a);
 size_t conv_z_lds_bytes(const ConvArgs& a);
+// blocks of the conv_z kernel (grid columns per block depend on the form and n_z)
+int conv_z_blocks(const ConvArgs& a);
 
 // Blocks of the pair kernel for n charges (an upper bound of the clusters)
 // and of the gather kernel (its bricks)
