@@ -8,7 +8,7 @@ N = 4 far terms), inputs resident in HBM.
 
 Prints one JSON line:
   value        evaluations/s of the chosen form (default: BF16X3 convolutions,
-               8^3 spreading stencil; --form plain for the FP32 path);
+               6^3 spreading stencil; --form plain for the FP32 path);
   roofline     the dominant kernel's achieved rate vs the MI355X peak, timed
                with HIP events on the evaluation stream;
   kernels      every kernel's HIP-event time, algorithmic flop and bytes, and the

@@ -69,7 +69,7 @@ enum {
 enum {
     USERIES_PLAIN_FP32 = 0,     /* FP32 MFMA convolutions, 10^3 spreading stencil */
     USERIES_BF16X3 = 1          /* BF16 MFMA with 3-product split precision,
-                                   8^3 spreading stencil */
+                                   6^3 spreading stencil */
 };
 
 /*
@@ -78,9 +78,9 @@ enum {
  *   precision        USERIES_PLAIN_FP32 or USERIES_BF16X3.
  *   sigma_s_over_h   width of the Gaussian that spreads charges to the grid,
  *                    in units of the grid spacing of each axis; <= 0 picks
- *                    the default of the precision (0.9 plain, 0.83 BF16X3).
+ *                    the default of the precision (0.9 plain, 0.74 BF16X3).
  *   stencil_half     P: each charge touches 2P grid points per axis; <= 0
- *                    picks the default (5 plain, 4 BF16X3).  1 <= P <= 8.
+ *                    picks the default (5 plain, 3 BF16X3).  1 <= P <= 8.
  *   nterms_tol       relative far-energy truncation bound (eq. 33) used to
  *                    choose N when useries_plan gets n_terms <= 0.
  *   poly_degree      degree in r^2 of the polynomials that represent the

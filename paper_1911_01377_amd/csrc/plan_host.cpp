@@ -42,8 +42,8 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     if (o.precision != USERIES_PLAIN_FP32 && o.precision != USERIES_BF16X3)
         return fail(err, USERIES_EINVAL, "unknown precision");
     const bool bf = o.precision == USERIES_BF16X3;
-    const double ratio = o.sigma_s_over_h > 0 ? o.sigma_s_over_h : (bf ? 0.83 : 0.9);
-    const int P = o.stencil_half > 0 ? o.stencil_half : (bf ? 4 : 5);
+    const double ratio = o.sigma_s_over_h > 0 ? o.sigma_s_over_h : (bf ? 0.74 : 0.9);
+    const int P = o.stencil_half > 0 ? o.stencil_half : (bf ? 3 : 5);
     const int deg = o.poly_degree > 0 ? o.poly_degree : 7;
     if (P < 1 || P > kMaxStencilHalf) return fail(err, USERIES_EINVAL, "stencil_half out of [1, 8]");
     if (deg < 4 || deg > kMaxPolyDeg) return fail(err, USERIES_EINVAL, "poly_degree out of [4, 14]");
