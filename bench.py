@@ -238,7 +238,7 @@ def main():
     for _ in range(nprof):
         plan.eval(x, qq, forces, energy)
     torch.cuda.synchronize()
-    ktimes = {name: tot / max(cnt, 1) for name, tot, cnt in plan.timing()}
+    ktimes = {name: tot / cnt for name, tot, cnt in plan.timing() if cnt > 0}
     plan.timing(False)
     log("kernel ms: " + ", ".join("%s %.4f" % kv for kv in ktimes.items()))
 

@@ -1,6 +1,6 @@
 // C ABI of the library: plan construction (host FP64 math + one upload),
 // device workspace, and the evaluation sequence
-//   encode -> scan -> scatter -> colsort -> pair (near part)
+//   encode -> [scan, only for very many columns] -> scatter -> colsort -> pair (near part)
 //   -> spread -> conv_xy -> conv_z -> gather (far part, + near forces)
 //   -> finalize (FP64 energy).
 #include <hip/hip_runtime.h>
@@ -248,8 +248,9 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
         delete p;
         return fail(USERIES_ENOMEM, std::string("plan allocation: ") + hipGetErrorString(e));
     }
-    // the column counters start at zero; each evaluation's scan clears them again
-    if ((e = hipMemset(p->col_count, 0, sizeof(int) * hp.ncol_max))) {
+    // the column counters start at zero; each evaluation's colsort clears them again
+    if ((e = hipMemset(p->col_count, 0, sizeof(int) * hp.ncol_max)) ||
+        (e = hipMemset(p->col_fill, 0, sizeof(int) * hp.ncol_max))) {
         delete p;
         return hip_fail(e, "memset");
     }
@@ -290,6 +291,7 @@ static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float*
 
     if (p->counts_dirty) {
         hipError_t e = hipMemsetAsync(p->col_count, 0, sizeof(int) * hp.ncol_max, st);
+        if (!e) e = hipMemsetAsync(p->col_fill, 0, sizeof(int) * hp.ncol_max, st);
         if (e) return hip_fail(e, "memset");
         p->counts_dirty = false;
     }
@@ -319,12 +321,15 @@ static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float*
     const float* kz = (const float*)p->kz;
     USERIES_STEP(0, st, launch_encode(hp.bin, xyz, q, p->coord, p->col_of, p->col_count, p->qpart,
                                       nq, st));
-    USERIES_STEP(1, st, launch_scan(ncol, p->col_count, p->col_start, p->clus_start, p->col_fill,
-                                    p->qpart, nq, p->qstats, st));
-    USERIES_STEP(2, st, launch_scatter(ni, ncol, p->col_of, p->col_start, p->col_fill, p->slots, st));
+    if (!scan_fused(ni, ncol))
+        USERIES_STEP(1, st, launch_scan(ncol, p->col_count, p->col_start, p->clus_start,
+                                        p->col_fill, p->qpart, nq, p->qstats, st));
+    USERIES_STEP(2, st, launch_scatter(ni, ncol, p->col_of, p->col_count, p->col_start,
+                                       p->clus_start, p->col_fill, p->slots, p->qpart, nq,
+                                       p->qstats, st));
     USERIES_STEP(3, st, launch_colsort(ncol, p->col_start, p->clus_start, p->slots, p->coord,
                                        p->perm, p->sorted, p->cl_info, p->cl_col, p->cl_z,
-                                       hp.grid[2], p->zbin, st));
+                                       hp.grid[2], p->zbin, p->col_count, p->col_fill, st));
     USERIES_STEP(4, st, launch_pair(hp.pair, npb, p->sorted, p->clus_start, p->cl_info, p->cl_col,
                                     p->cl_z, p->zbin, p->fnear, p->pair_parts, st));
     USERIES_STEP(5, st, launch_spread(hp.gridargs, p->sorted, p->zbin, p->qstats, p->rho, st));

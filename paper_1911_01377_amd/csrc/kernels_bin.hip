@@ -9,7 +9,13 @@
 //
 // encode -> scan (column and cluster offsets) -> scatter (atomic slots) ->
 // colsort (per column, sort by (z, input index): deterministic order; write
-// the permutation, the sorted positions and the cluster table).
+// the permutation, the sorted positions and the cluster table).  When the
+// column counts fit in LDS and are few enough to be read by every scatter
+// block, each scatter block takes the offsets itself (block 0 also publishes
+// them) and the scan launch is skipped; colsort clears the counters either
+// way, ready for the next evaluation.
+#include <algorithm>
+
 #include "useries_internal.h"
 #include "device_common.h"
 
@@ -176,42 +182,118 @@ __global__ void __launch_bounds__(1024) k_scan_batch(const BatchTable* __restric
 
 // Slots inside a column: the rank among the block's charges of that column
 // (LDS atomic) plus a base reserved once per (block, column).  The order they
-// produce is arbitrary; colsort makes it deterministic.
-__device__ __forceinline__ void scatter_body(int n, int ncol, int bid,
+// produce is arbitrary; colsort makes it deterministic.  With `fused`, the
+// block first takes the exclusive prefix sums of the column counts (256
+// threads, a contiguous run of at most kHistCols / 256 columns each) as its
+// column starts; block 0 also writes them, the cluster starts and the charge
+// sums, in place of the scan kernel.
+constexpr int kPrefixRun = kHistCols / 256;
+
+__device__ __forceinline__ void scatter_body(int n, int ncol, int bid, bool fused,
                                              const int* __restrict__ col_of,
-                                             const int* __restrict__ start,
-                                             int* __restrict__ fill, int* __restrict__ slots) {
+                                             const int* __restrict__ count,
+                                             int* __restrict__ start, int* __restrict__ cstart,
+                                             int* __restrict__ fill, int* __restrict__ slots,
+                                             const double* __restrict__ qpart, int nqpart,
+                                             double* __restrict__ qstats) {
     __shared__ int hist[kHistCols];
     __shared__ int base[kHistCols];
+    __shared__ int wsum[2][4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const bool local = ncol <= kHistCols;
     if (local)
-        for (int k = threadIdx.x; k < ncol; k += 256) hist[k] = 0;
-    __syncthreads();
-    const int i = bid * 256 + threadIdx.x;
-    int c = 0, r = 0;
-    if (i < n) {
-        c = col_of[i];
-        r = local ? atomicAdd(&hist[c], 1) : atomicAdd(&fill[c], 1);
+        for (int k = t; k < ncol; k += 256) hist[k] = 0;
+    const int i = bid * 256 + t;
+    const int c = i < n ? col_of[i] : 0;
+    if (fused) {
+        const int run_len = (ncol + 255) / 256;
+        const int lo = min(t * run_len, ncol), hi = min(lo + run_len, ncol);
+        int kc[kPrefixRun];
+        int s = 0, sc = 0;
+#pragma unroll
+        for (int u = 0; u < kPrefixRun; ++u) kc[u] = lo + u < hi ? count[lo + u] : 0;
+#pragma unroll
+        for (int u = 0; u < kPrefixRun; ++u) {
+            s += kc[u];
+            sc += (kc[u] + 7) >> 3;
+        }
+        int v = s, vc = sc;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int x = __shfl_up(v, off, 64), xc = __shfl_up(vc, off, 64);
+            if (lane >= off) {
+                v += x;
+                vc += xc;
+            }
+        }
+        if (lane == 63) {
+            wsum[0][wv] = v;
+            wsum[1][wv] = vc;
+        }
+        __syncthreads();
+        int run = v - s, runc = vc - sc;   // exclusive prefixes
+        for (int u = 0; u < wv; ++u) {
+            run += wsum[0][u];
+            runc += wsum[1][u];
+        }
+#pragma unroll
+        for (int u = 0; u < kPrefixRun; ++u) {
+            if (lo + u < hi) {
+                base[lo + u] = run;
+                if (bid == 0) {
+                    start[lo + u] = run;
+                    cstart[lo + u] = runc;
+                }
+                run += kc[u];
+                runc += (kc[u] + 7) >> 3;
+            }
+        }
+        if (bid == 0 && t == 255) {
+            start[ncol] = run;
+            cstart[ncol] = runc;
+        }
+        if (bid == 0 && wv == 1) {
+            double qa = 0.0, qb = 0.0;
+            for (int k = lane; k < nqpart; k += 64) {
+                qa += qpart[2 * k];
+                qb += qpart[2 * k + 1];
+            }
+            qa = wave_sum_d(qa);
+            qb = wave_sum_d(qb);
+            if (lane == 0) {
+                qstats[0] = qa;
+                qstats[1] = qb;
+            }
+        }
     }
     __syncthreads();
-    if (local)
-        for (int k = threadIdx.x; k < ncol; k += 256)
-            if (hist[k] > 0) base[k] = atomicAdd(&fill[k], hist[k]);
+    int r = 0;
+    if (i < n) r = local ? atomicAdd(&hist[c], 1) : atomicAdd(&fill[c], 1);
     __syncthreads();
-    if (i < n) slots[start[c] + (local ? base[c] : 0) + r] = i;
+    if (local)
+        for (int k = t; k < ncol; k += 256)
+            if (hist[k] > 0) base[k] = (fused ? base[k] : start[k]) + atomicAdd(&fill[k], hist[k]);
+    __syncthreads();
+    if (i < n) slots[(local ? base[c] : start[c]) + r] = i;
 }
 
-__global__ void __launch_bounds__(256) k_scatter(int n, int ncol, const int* __restrict__ col_of,
-                                                 const int* __restrict__ start,
-                                                 int* __restrict__ fill, int* __restrict__ slots) {
-    scatter_body(n, ncol, blockIdx.x, col_of, start, fill, slots);
+__global__ void __launch_bounds__(256) k_scatter(int n, int ncol, int fused,
+                                                 const int* __restrict__ col_of,
+                                                 const int* __restrict__ count,
+                                                 int* __restrict__ start, int* __restrict__ cstart,
+                                                 int* __restrict__ fill, int* __restrict__ slots,
+                                                 const double* __restrict__ qpart, int nqpart,
+                                                 double* __restrict__ qstats) {
+    scatter_body(n, ncol, blockIdx.x, fused != 0, col_of, count, start, cstart, fill, slots, qpart,
+                 nqpart, qstats);
 }
 
 __global__ void __launch_bounds__(256) k_scatter_batch(const BatchTable* __restrict__ tab,
                                                        const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_SCATTER, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        scatter_body(d.bin.n, d.ncol, item, d.col_of, d.col_start, d.col_fill, d.slots);
+        scatter_body(d.bin.n, d.ncol, item, false, d.col_of, d.col_count, d.col_start,
+                     d.clus_start, d.col_fill, d.slots, d.qpart, d.nq, d.qstats);
     });
 }
 
@@ -229,11 +311,16 @@ __device__ __forceinline__ void colsort_body(int col, const int* __restrict__ st
                                              int* __restrict__ perm, uint4* __restrict__ sorted,
                                              int2* __restrict__ cl_info, int* __restrict__ cl_col,
                                              uint2* __restrict__ cl_z, int gz,
-                                             int* __restrict__ zbin) {
+                                             int* __restrict__ zbin, int* __restrict__ count,
+                                             int* __restrict__ fill) {
     __shared__ unsigned long long key[kSortCap];
     __shared__ uint32_t skz[kSortCap];         // z of the sorted charges
     const int t = threadIdx.x;
     const int lo = start[col], cnt = start[col + 1] - lo;
+    if (t == 0) {   // the column's counters, cleared for the next evaluation
+        count[col] = 0;
+        fill[col] = 0;
+    }
     int* zrow = zbin + (size_t)col * (gz + 1);
     if (cnt == 0) {
         for (int b = t; b <= gz; b += 256) zrow[b] = lo;
@@ -340,9 +427,10 @@ __global__ void __launch_bounds__(256) k_colsort(const int* __restrict__ start,
                                                  int2* __restrict__ cl_info,
                                                  int* __restrict__ cl_col,
                                                  uint2* __restrict__ cl_z, int gz,
-                                                 int* __restrict__ zbin) {
+                                                 int* __restrict__ zbin, int* __restrict__ count,
+                                                 int* __restrict__ fill) {
     colsort_body(blockIdx.x, start, cstart, slots, coord, perm, sorted, cl_info, cl_col, cl_z, gz,
-                 zbin);
+                 zbin, count, fill);
 }
 
 __global__ void __launch_bounds__(256) k_colsort_batch(const BatchTable* __restrict__ tab,
@@ -350,7 +438,7 @@ __global__ void __launch_bounds__(256) k_colsort_batch(const BatchTable* __restr
     batch_for(tab, BK_COLSORT, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
         colsort_body(item, d.col_start, d.clus_start, d.slots, d.coord, d.perm, d.sorted,
-                     d.cl_info, d.cl_col, d.cl_z, d.grid.g[2], d.zbin);
+                     d.cl_info, d.cl_col, d.cl_z, d.grid.g[2], d.zbin, d.col_count, d.col_fill);
     });
 }
 
@@ -370,19 +458,30 @@ hipError_t launch_scan(int ncol, int* col_count, int* col_start, int* clus_start
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(int n, int ncol, const int* col_of, const int* col_start, int* col_fill,
-                          int* slots, hipStream_t st) {
-    if (n > 0)
-        hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, st, n, ncol, col_of,
-                           col_start, col_fill, slots);
+bool scan_fused(int n, int ncol) {
+    const long long nb = (n + 255) / 256;
+    return ncol <= kHistCols && nb * ncol <= (1ll << 22);
+}
+
+hipError_t launch_scatter(int n, int ncol, const int* col_of, const int* col_count, int* col_start,
+                          int* clus_start, int* col_fill, int* slots, const double* qpart,
+                          int nqpart, double* qstats, hipStream_t st) {
+    const int fused = scan_fused(n, ncol) ? 1 : 0;
+    // with no charges the fused prefix still has to run once (all columns empty)
+    const int nb = std::max(1, (n + 255) / 256);
+    if (n > 0 || fused)
+        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, st, n, ncol, fused, col_of,
+                           col_count, col_start, clus_start, col_fill, slots, qpart, nqpart,
+                           qstats);
     return hipGetLastError();
 }
 
 hipError_t launch_colsort(int ncol, const int* col_start, const int* clus_start, const int* slots,
                           const uint4* coord, int* perm, uint4* sorted, int2* cl_info,
-                          int* cl_col, uint2* cl_z, int gz, int* zbin, hipStream_t st) {
+                          int* cl_col, uint2* cl_z, int gz, int* zbin, int* col_count,
+                          int* col_fill, hipStream_t st) {
     hipLaunchKernelGGL(k_colsort, dim3(ncol), dim3(256), 0, st, col_start, clus_start, slots,
-                       coord, perm, sorted, cl_info, cl_col, cl_z, gz, zbin);
+                       coord, perm, sorted, cl_info, cl_col, cl_z, gz, zbin, col_count, col_fill);
     return hipGetLastError();
 }
 

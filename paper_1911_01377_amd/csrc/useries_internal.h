@@ -214,11 +214,17 @@ hipError_t launch_encode(const BinArgs& a, const float* xyz, const float* q, uin
 hipError_t launch_scan(int ncol, int* col_count, int* col_start, int* clus_start,
                        int* col_fill, const double* qpart, int nqpart, double* qstats,
                        hipStream_t st);
-hipError_t launch_scatter(int n, int ncol, const int* col_of, const int* col_start, int* col_fill,
-                          int* slots, hipStream_t st);
+// true when scatter takes the column offsets itself (no scan launch): the
+// counts fit in its LDS and every block can afford to read them
+bool scan_fused(int n, int ncol);
+hipError_t launch_scatter(int n, int ncol, const int* col_of, const int* col_count, int* col_start,
+                          int* clus_start, int* col_fill, int* slots, const double* qpart,
+                          int nqpart, double* qstats, hipStream_t st);
+// also clears col_count and col_fill of the ncol columns
 hipError_t launch_colsort(int ncol, const int* col_start, const int* clus_start, const int* slots,
                           const uint4* coord, int* perm, uint4* sorted, int2* cl_info,
-                          int* cl_col, uint2* cl_z, int gz, int* zbin, hipStream_t st);
+                          int* cl_col, uint2* cl_z, int gz, int* zbin, int* col_count,
+                          int* col_fill, hipStream_t st);
 hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, const int* clus_start,
                        const int2* cl_info, const int* cl_col, const uint2* cl_z, const int* zbin,
                        float4* fnear, double* epart, hipStream_t st);

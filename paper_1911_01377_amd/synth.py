@@ -83,6 +83,18 @@ def random_cube(n=512, L=24.0, seed=1377):
     return _wrap(xyz, (L, L, L)), q.astype(np.float32), (L, L, L)
 
 
+def random_box(n, box, seed):
+    """n charges uniform in an orthorhombic box, q ~ U[-1, 1] made neutral."""
+    rng = np.random.default_rng(seed)
+    box = tuple(float(v) for v in box)
+    xyz = rng.uniform(0.0, 1.0, (n, 3)) * np.array(box)
+    q = rng.uniform(-1.0, 1.0, n)
+    q = _quantise(q - q.mean())
+    if n > 0:
+        q[-1] = -np.sum(q[:-1])
+    return _wrap(xyz, box), q.astype(np.float32), box
+
+
 def water_box(n_mol=None, L=64.0, seed=1378, jitter=0.3):
     """3-site water at 0.0334 molecules/A^3 in a cubic box: molecular centres
     are a random subset of a cubic lattice (jittered by U(+-jitter)), each

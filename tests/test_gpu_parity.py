@@ -10,10 +10,13 @@ exact image sums also contains the spreading discretisation (about 2e-6 in
 force at the default 10^3 stencil with sigma_s = 0.9 h, under 1e-4 at the
 BF16X3 default 6^3 with 0.74 h).
 """
+import math
+
 import numpy as np
 import pytest
 
-from gpu_util import compare, gpu_eval, log, oracle_eval, rel_rms
+import oracle
+from gpu_util import compare, gpu_eval, log, oracle_eval, oracle_params, rel_rms
 
 pytestmark = pytest.mark.gpu
 
@@ -78,6 +81,31 @@ def test_tall_box_long_columns():
     _, _, _, _, info = compare("tallwater/plain", xyz.astype(np.float32), q, box, 0.45 * L,
                                (16, 16, 96), 1e-6, 1e-5)
     assert len(q) / (info["ncell"][0] * info["ncell"][1]) > 256
+
+
+def test_many_columns_global_binning():
+    """A flat 256 x 256 x 19 A cell of 200,000 random charges: 69 x 69
+    columns, more than the 4096 whose counts the binning kernels keep in LDS,
+    so the column counts, the slot counters and the offsets (scan kernel) take
+    their global-memory paths.  The oracle's full O(n^2) sum is out of reach
+    at this size: forces on 128 sampled charges are compared (each an O(n)
+    oracle sum), and the force sum must vanish up to rounding.  The x-y grid
+    spacing is 2 A (0.95 A in z)."""
+    xyz, q, box = synth.random_box(200000, (256.0, 256.0, 19.0), seed=31)
+    rc, grid = 9.0, (128, 128, 20)
+    log("case manycols/plain: n=%d box=%s rc=%g grid=%s" % (len(q), box, rc, grid))
+    _, gf, info = gpu_eval(xyz, q, box, rc, grid)
+    ncol = info["ncell"][0] * info["ncell"][1]
+    assert ncol > 4096, info["ncell"]
+    idx = np.random.default_rng(3).choice(len(q), 128, replace=False)
+    fo = oracle.forces_subset(xyz.astype(np.float64), q.astype(np.float64), box,
+                              oracle_params(info, rc), idx)
+    df = rel_rms(gf[idx], fo)
+    rms = float(np.sqrt(np.mean(np.sum(gf ** 2, axis=1))))
+    fsum = float(np.linalg.norm(gf.sum(axis=0)))
+    log("   columns %s, dF(128 sampled)=%.2e, |sum F|=%.3e (rms %.3e)" % (info["ncell"], df, fsum, rms))
+    assert df <= 1e-5
+    assert fsum <= 1e-3 * math.sqrt(len(q)) * rms
 
 
 def test_non_neutral_and_single_charge():
