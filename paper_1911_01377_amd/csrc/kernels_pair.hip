@@ -15,7 +15,8 @@
 // (lane / 8, lane % 8) holds i-charge a and j-charge b of the step, so every
 // lane evaluates one pair per step and no lane waits on another's branch.
 // The two wavefronts take alternate chunks of 256 candidates, each loading
-// its chunk one chunk ahead with coalesced loads and staging in LDS only the
+// its chunk one chunk ahead (4 consecutive candidates per lane, so a lane
+// searches the range list once per chunk) and staging in LDS only the
 // candidates within r_c of the i-cluster's bounding box (about 58% of them
 // in water), so the steps skip most pairs that cannot be in range.  The force on
 // charge a is summed over its 8 lanes by shuffles, then over the two
@@ -34,6 +35,7 @@ namespace {
 constexpr int kPairWaves = 2;         // wavefronts per i-cluster
 constexpr int kChunk = 32;            // steps of 8 j-charges staged per pass (4 KB of LDS)
 constexpr int kChunkCharges = 8 * kChunk;
+constexpr int kPerLane = kChunkCharges / 64;   // consecutive candidates loaded per lane
 
 // a loop-invariant value held in a vector register (lets a polynomial step
 // take its two coefficients from one scalar and one vector operand)
@@ -130,11 +132,12 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
                                           float4* __restrict__ fnear,
                                           double* __restrict__ epart) {
     __shared__ uint4 stage[kPairWaves][kChunkCharges];
-    __shared__ int rbeg[2 * kMaxStencilCols];       // first sorted charge of each range
+    __shared__ int rbeg[2 * kMaxStencilCols];       // first sorted charge of each non-empty range
     __shared__ int roff[2 * kMaxStencilCols + 1];   // prefix sums of the range lengths
-    __shared__ int wtot[kPairWaves];
+    __shared__ int wtot[kPairWaves][2];
     __shared__ float4 fother[8];
     __shared__ double eother;
+    static_assert(kMaxStencilCols <= 64 * kPairWaves, "one stencil column per thread");
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int ia = lane >> 3, ja = lane & 7;
     const int ncx = a.nc[0], ncy = a.nc[1], gz = a.gz;
@@ -151,15 +154,16 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     const int nxs = fullx ? ncx : 2 * a.R[0] + 1, nys = fully ? ncy : 2 * a.R[1] + 1;
     const int NC = nxs * nys;
 
-    // candidate charge ranges, two slots per stencil column
-    for (int k = tid; k < NC; k += 64 * kPairWaves) {
+    // candidate charge ranges of stencil column k = tid: at most two (the
+    // second only where the z window wraps)
+    int rb0 = 0, n0 = 0, rb1 = 0, n1 = 0;
+    if (tid < NC) {
         int colx, coly, dx, dy;
-        stencil_col(k % nxs, cx, a.R[0], ncx, fullx, &colx, &dx);
-        stencil_col(k / nxs, cy, a.R[1], ncy, fully, &coly, &dy);
+        stencil_col(tid % nxs, cx, a.R[0], ncx, fullx, &colx, &dx);
+        stencil_col(tid / nxs, cy, a.R[1], ncy, fully, &coly, &dy);
         const float gx = (float)max(0, abs(dx) - 1) * a.cw[0];
         const float gy = (float)max(0, abs(dy) - 1) * a.cw[1];
         const float d2 = gx * gx + gy * gy;
-        int c0 = 0, n0 = 0, c1 = 0, n1 = 0;
         if (d2 < a.rc2) {
             // grid z-planes of the window [zI.x - rz, zI.y + rz] (fixed point,
             // periodic), then the column's charges of those planes
@@ -169,61 +173,91 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
             const int len = (int)(phi - plo) + 1;
             const int* zr = zbin + (size_t)(coly * ncx + colx) * (gz + 1);
             if (len >= gz) {
-                c0 = zr[0];
-                n0 = zr[gz] - c0;
+                rb0 = zr[0];
+                n0 = zr[gz] - rb0;
             } else {
                 const int zs = (int)(plo < 0 ? plo + gz : (plo >= gz ? plo - gz : plo));
                 const int ze = zs + len;
-                c0 = zr[zs];
+                rb0 = zr[zs];
                 if (ze <= gz) {
-                    n0 = zr[ze] - c0;
+                    n0 = zr[ze] - rb0;
                 } else {
-                    n0 = zr[gz] - c0;
-                    c1 = zr[0];
-                    n1 = zr[ze - gz] - c1;
+                    n0 = zr[gz] - rb0;
+                    rb1 = zr[0];
+                    n1 = zr[ze - gz] - rb1;
                 }
             }
         }
-        rbeg[2 * k] = c0;
-        rbeg[2 * k + 1] = c1;
-        roff[2 * k + 1] = n0;
-        roff[2 * k + 2] = n1;
     }
-    __syncthreads();
-    // inclusive prefix of the nr <= 2 * kMaxStencilCols range lengths, two per thread
-    const int nr = 2 * NC;
+    // non-empty ranges stored compactly: exclusive scans over the threads of
+    // (ranges, charges), then each thread writes its ranges
     {
-        const int r0 = 2 * tid, r1 = 2 * tid + 1;
-        const int v0 = r0 < nr ? roff[r0 + 1] : 0, v1 = r1 < nr ? roff[r1 + 1] : 0;
-        int incl = v0 + v1;
+        const int m = (n0 > 0) + (n1 > 0), len = n0 + n1;
+        int im = m, il = len;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            const int t = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += t;
+            const int x = __shfl_up(im, off, 64), y = __shfl_up(il, off, 64);
+            if (lane >= off) {
+                im += x;
+                il += y;
+            }
         }
-        if (lane == 63) wtot[w] = incl;
+        if (lane == 63) {
+            wtot[w][0] = im;
+            wtot[w][1] = il;
+        }
         __syncthreads();
-        const int excl = (w > 0 ? wtot[0] : 0) + incl - v0 - v1;
-        if (r0 < nr) roff[r0 + 1] = excl + v0;
-        if (r1 < nr) roff[r1 + 1] = excl + v0 + v1;
-        if (tid == 0) roff[0] = 0;
-        __syncthreads();
+        int M = im - m, O = il - len;
+        for (int v = 0; v < w; ++v) {
+            M += wtot[v][0];
+            O += wtot[v][1];
+        }
+        if (n0 > 0) {
+            rbeg[M] = rb0;
+            roff[M] = O;
+        }
+        if (n1 > 0) {
+            rbeg[M + (n0 > 0)] = rb1;
+            roff[M + (n0 > 0)] = O + n0;
+        }
     }
-    const int total = __builtin_amdgcn_readfirstlane(roff[nr]);   // uniform: loop bounds in SGPRs
-
-    // candidate u of a chunk, loaded by this lane (q = 0 and position 0 past the end)
-    auto fetch = [&](int c, uint4* out) {
+    int nr = 0, tot = 0;
 #pragma unroll
-        for (int u = 0; u < kChunkCharges / 64; ++u) {
-            const int p = c * kChunkCharges + u * 64 + lane;
+    for (int v = 0; v < kPairWaves; ++v) {
+        nr += wtot[v][0];
+        tot += wtot[v][1];
+    }
+    if (tid == 0) roff[nr] = tot;
+    __syncthreads();
+    const int total = __builtin_amdgcn_readfirstlane(tot);   // uniform: loop bounds in SGPRs
+
+    // candidates p0 .. p0 + 3 of a chunk (p0 = chunk start + 4 lane), loaded by
+    // this lane: one search for the range of p0, then at most one range
+    // boundary per step (ranges are non-empty); q = 0 and position 0 past the end
+    auto fetch = [&](int c, uint4* out) {
+        const int p0 = c * kChunkCharges + kPerLane * lane;
+        int r = 0;
+        if (p0 < total) {
+            int lo = 0, hi = nr;                 // range r with roff[r] <= p0 < roff[r + 1]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (roff[mid] <= p0) lo = mid; else hi = mid;
+            }
+            r = lo;
+        }
+        int end = roff[r + 1];
+        int b = rbeg[r] - roff[r];
+#pragma unroll
+        for (int u = 0; u < kPerLane; ++u) {
+            const int p = p0 + u;
             out[u] = make_uint4(0, 0, 0, 0);
             if (p < total) {
-                int lo = 0, hi = nr;             // range r with roff[r] <= p < roff[r + 1]
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (roff[mid] <= p) lo = mid; else hi = mid;
+                if (p >= end) {
+                    ++r;
+                    b = rbeg[r] - roff[r];
+                    end = roff[r + 1];
                 }
-                out[u] = sorted[rbeg[lo] + (p - roff[lo])];
+                out[u] = sorted[b + p];
             }
         }
     };
@@ -279,15 +313,15 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     double e = 0.0;                      // FP32 pair energies, flushed to FP64 per chunk
     const int nchunks = (total + kChunkCharges - 1) / kChunkCharges;
-    uint4 pre[kChunkCharges / 64];
+    uint4 pre[kPerLane];
     if (w < nchunks) fetch(w, pre);
     for (int c = w; c < nchunks; c += kPairWaves) {
         // keep the candidates near the box, compacted in candidate order,
         // padded with zero charges to whole steps of 8
         int kept = 0;
 #pragma unroll
-        for (int u = 0; u < kChunkCharges / 64; ++u) {
-            const int p = c * kChunkCharges + u * 64 + lane;
+        for (int u = 0; u < kPerLane; ++u) {
+            const int p = c * kChunkCharges + kPerLane * lane + u;
             const bool keep = p < total && near_box(pre[u]);
             const uint64_t m = __ballot(keep);
             if (keep) stage[w][kept + __popcll(m & ((1ull << lane) - 1ull))] = pre[u];
