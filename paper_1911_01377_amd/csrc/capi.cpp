@@ -63,7 +63,7 @@ struct useries_plan_s {
     int64_t cap = 0;
     bool fixed_cap = false;
     uint4 *coord = nullptr, *sorted = nullptr;
-    int *col_of = nullptr, *perm = nullptr, *slots = nullptr;
+    int *perm = nullptr, *slots = nullptr;
     int2* cl_info = nullptr;
     int* cl_col = nullptr;
     uint2* cl_z = nullptr;
@@ -83,7 +83,6 @@ struct useries_plan_s {
     void free_atoms() {
         hipFree(coord);
         hipFree(sorted);
-        hipFree(col_of);
         hipFree(cl_info);
         hipFree(cl_col);
         hipFree(cl_z);
@@ -93,7 +92,7 @@ struct useries_plan_s {
         hipFree(fnear);
         hipFree(qpart);
         coord = sorted = nullptr;
-        col_of = perm = slots = cl_col = nullptr;
+        perm = slots = cl_col = nullptr;
         cl_info = nullptr;
         cl_z = nullptr;
         pair_parts = nullptr;
@@ -108,7 +107,7 @@ struct useries_plan_s {
         // clusters: at most sum over columns of ceil(count / 8)
         const int64_t clmax = pair_blocks((int)c, hp.ncol_max);
         hipError_t e;
-        if ((e = dalloc(&coord, c)) || (e = dalloc(&sorted, c)) || (e = dalloc(&col_of, c)) ||
+        if ((e = dalloc(&coord, c)) || (e = dalloc(&sorted, c)) ||
             (e = dalloc(&perm, c)) || (e = dalloc(&slots, c)) || (e = dalloc(&cl_info, clmax)) ||
             (e = dalloc(&cl_col, clmax)) || (e = dalloc(&cl_z, clmax)) ||
             (e = dalloc(&pair_parts, clmax)) || (e = dalloc(&fnear, c)) ||
@@ -319,12 +318,12 @@ static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float*
     const float* kx = (const float*)p->kx;
     const float* ky = (const float*)p->ky;
     const float* kz = (const float*)p->kz;
-    USERIES_STEP(0, st, launch_encode(hp.bin, xyz, q, p->coord, p->col_of, p->col_count, p->qpart,
+    USERIES_STEP(0, st, launch_encode(hp.bin, xyz, q, p->coord, p->col_count, p->qpart,
                                       nq, st));
     if (!scan_fused(ni, ncol))
         USERIES_STEP(1, st, launch_scan(ncol, p->col_count, p->col_start, p->clus_start,
                                         p->col_fill, p->qpart, nq, p->qstats, st));
-    USERIES_STEP(2, st, launch_scatter(ni, ncol, p->col_of, p->col_count, p->col_start,
+    USERIES_STEP(2, st, launch_scatter(hp.bin, p->coord, p->sorted, p->col_count, p->col_start,
                                        p->clus_start, p->col_fill, p->slots, p->qpart, nq,
                                        p->qstats, st));
     USERIES_STEP(3, st, launch_colsort(ncol, p->col_start, p->clus_start, p->slots, p->coord,

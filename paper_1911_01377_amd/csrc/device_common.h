@@ -67,78 +67,6 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return v;
 }
 
-// deterministic FP64 sum of one value per thread over a block of NT threads;
-// the result is valid in thread 0
-template <int NT>
-__device__ __forceinline__ double block_sum_d(double v, double* smem) {
-    smem[threadIdx.x] = v;
-    __syncthreads();
-#pragma unroll
-    for (int w = NT / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) smem[threadIdx.x] += smem[threadIdx.x + w];
-        __syncthreads();
-    }
-    return smem[0];
-}
-
-}  // namespace useries
-
-namespace useries {
-
-// Clusters of one column whose z extent [zmin, zmax] meets the fixed-point
-// window [lo, hi] (inclusive, may extend below 0 or above 2^32 - 1 by less
-// than 2^32: periodic).  Clusters of a column are z-sorted, so each piece of
-// the window is a contiguous cluster range [b, b + l).  At most two pieces.
-__device__ __forceinline__ void zrange_lower_upper(const uint2* __restrict__ cl_z, int c0, int c1,
-                                                   uint32_t A, uint32_t B, int* b, int* l) {
-    // first cluster with zmax >= A
-    int lo = c0, hi = c1;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (cl_z[mid].y < A) lo = mid + 1; else hi = mid;
-    }
-    const int f = lo;
-    // first cluster with zmin > B
-    lo = f;
-    hi = c1;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (cl_z[mid].x <= B) lo = mid + 1; else hi = mid;
-    }
-    *b = f;
-    *l = lo - f;
-}
-
-__device__ __forceinline__ void column_zrange(const uint2* __restrict__ cl_z, int c0, int c1,
-                                              long long lo, long long hi, int* b0, int* l0,
-                                              int* b1, int* l1) {
-    const long long full = 4294967296ll;
-    *b1 = c0;
-    *l1 = 0;
-    if (c1 <= c0) {
-        *b0 = c0;
-        *l0 = 0;
-    } else if (hi - lo + 1 >= full) {
-        *b0 = c0;
-        *l0 = c1 - c0;
-    } else if (lo < 0 || hi >= full) {
-        // the window wraps: [lo', 2^32) at the top and [0, hi'] at the bottom
-        const uint32_t top = (uint32_t)(lo < 0 ? lo + full : lo);
-        const uint32_t bot = (uint32_t)(hi >= full ? hi - full : hi);
-        zrange_lower_upper(cl_z, c0, c1, top, 0xffffffffu, b0, l0);
-        zrange_lower_upper(cl_z, c0, c1, 0u, bot, b1, l1);
-        // a cluster spanning both ends would be counted twice: the two pieces
-        // then cover the whole column
-        if (*l1 > 0 && *l0 > 0 && *b1 + *l1 > *b0) {
-            *b0 = c0;
-            *l0 = c1 - c0;
-            *l1 = 0;
-        }
-    } else {
-        zrange_lower_upper(cl_z, c0, c1, (uint32_t)lo, (uint32_t)hi, b0, l0);
-    }
-}
-
 }  // namespace useries
 
 namespace useries {

@@ -27,10 +27,10 @@ constexpr int kHistCols = 4096;
 
 __device__ __forceinline__ void encode_body(const BinArgs& a, int bid, const float* __restrict__ xyz,
                                             const float* __restrict__ q,
-                                            uint4* __restrict__ coord, int* __restrict__ col_of,
+                                            uint4* __restrict__ coord,
                                             int* __restrict__ col_count,
                                             double* __restrict__ qpart) {
-    __shared__ double red[256];
+    __shared__ double red[2][4];
     __shared__ int hist[kHistCols];
     const int ncol = a.nc[0] * a.nc[1];
     const bool local = ncol <= kHistCols;
@@ -46,7 +46,6 @@ __device__ __forceinline__ void encode_body(const BinArgs& a, int bid, const flo
         const float qi = q[i];
         const int c = cell_coord(u[1], a.nc[1]) * a.nc[0] + cell_coord(u[0], a.nc[0]);
         coord[i] = make_uint4(u[0], u[1], u[2], __float_as_uint(qi));
-        col_of[i] = c;
         if (local) atomicAdd(&hist[c], 1);
         else atomicAdd(&col_count[c], 1);
         qs = qi;
@@ -56,29 +55,34 @@ __device__ __forceinline__ void encode_body(const BinArgs& a, int bid, const flo
     if (local)
         for (int k = threadIdx.x; k < ncol; k += 256)
             if (hist[k] > 0) atomicAdd(&col_count[k], hist[k]);
-    const double s1 = block_sum_d<256>(qs, red);
+    // charge sums: wavefront shuffles, then the 4 wavefront sums in order
+    qs = wave_sum_d(qs);
+    q2 = wave_sum_d(q2);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wv] = qs;
+        red[1][wv] = q2;
+    }
     __syncthreads();
-    const double s2 = block_sum_d<256>(q2, red);
     if (threadIdx.x == 0) {
-        qpart[2 * bid] = s1;
-        qpart[2 * bid + 1] = s2;
+        qpart[2 * bid] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+        qpart[2 * bid + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
     }
 }
 
 __global__ void __launch_bounds__(256) k_encode(BinArgs a, const float* __restrict__ xyz,
                                                 const float* __restrict__ q,
                                                 uint4* __restrict__ coord,
-                                                int* __restrict__ col_of,
                                                 int* __restrict__ col_count,
                                                 double* __restrict__ qpart) {
-    encode_body(a, blockIdx.x, xyz, q, coord, col_of, col_count, qpart);
+    encode_body(a, blockIdx.x, xyz, q, coord, col_count, qpart);
 }
 
 __global__ void __launch_bounds__(256) k_encode_batch(const BatchTable* __restrict__ tab,
                                                       const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_ENCODE, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        encode_body(d.bin, item, d.xyz, d.q, d.coord, d.col_of, d.col_count, d.qpart);
+        encode_body(d.bin, item, d.xyz, d.q, d.coord, d.col_count, d.qpart);
     });
 }
 
@@ -182,15 +186,18 @@ __global__ void __launch_bounds__(1024) k_scan_batch(const BatchTable* __restric
 
 // Slots inside a column: the rank among the block's charges of that column
 // (LDS atomic) plus a base reserved once per (block, column).  The order they
-// produce is arbitrary; colsort makes it deterministic.  With `fused`, the
+// produce is arbitrary; colsort makes it deterministic.  Each slot gets the
+// charge's input index and its encoded record (the record into `sorted`,
+// which colsort then reorders within the column).  With `fused`, the
 // block first takes the exclusive prefix sums of the column counts (256
 // threads, a contiguous run of at most kHistCols / 256 columns each) as its
 // column starts; block 0 also writes them, the cluster starts and the charge
 // sums, in place of the scan kernel.
 constexpr int kPrefixRun = kHistCols / 256;
 
-__device__ __forceinline__ void scatter_body(int n, int ncol, int bid, bool fused,
-                                             const int* __restrict__ col_of,
+__device__ __forceinline__ void scatter_body(const BinArgs& a, int bid, bool fused,
+                                             const uint4* __restrict__ coord,
+                                             uint4* __restrict__ sorted,
                                              const int* __restrict__ count,
                                              int* __restrict__ start, int* __restrict__ cstart,
                                              int* __restrict__ fill, int* __restrict__ slots,
@@ -200,11 +207,13 @@ __device__ __forceinline__ void scatter_body(int n, int ncol, int bid, bool fuse
     __shared__ int base[kHistCols];
     __shared__ int wsum[2][4];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int n = a.n, ncol = a.nc[0] * a.nc[1];
     const bool local = ncol <= kHistCols;
     if (local)
         for (int k = t; k < ncol; k += 256) hist[k] = 0;
     const int i = bid * 256 + t;
-    const int c = i < n ? col_of[i] : 0;
+    const uint4 rec = i < n ? coord[i] : make_uint4(0, 0, 0, 0);
+    const int c = cell_coord(rec.y, a.nc[1]) * a.nc[0] + cell_coord(rec.x, a.nc[0]);
     if (fused) {
         const int run_len = (ncol + 255) / 256;
         const int lo = min(t * run_len, ncol), hi = min(lo + run_len, ncol);
@@ -274,25 +283,30 @@ __device__ __forceinline__ void scatter_body(int n, int ncol, int bid, bool fuse
         for (int k = t; k < ncol; k += 256)
             if (hist[k] > 0) base[k] = (fused ? base[k] : start[k]) + atomicAdd(&fill[k], hist[k]);
     __syncthreads();
-    if (i < n) slots[(local ? base[c] : start[c]) + r] = i;
+    if (i < n) {
+        const int slot = (local ? base[c] : start[c]) + r;
+        slots[slot] = i;
+        sorted[slot] = rec;
+    }
 }
 
-__global__ void __launch_bounds__(256) k_scatter(int n, int ncol, int fused,
-                                                 const int* __restrict__ col_of,
+__global__ void __launch_bounds__(256) k_scatter(BinArgs a, int fused,
+                                                 const uint4* __restrict__ coord,
+                                                 uint4* __restrict__ sorted,
                                                  const int* __restrict__ count,
                                                  int* __restrict__ start, int* __restrict__ cstart,
                                                  int* __restrict__ fill, int* __restrict__ slots,
                                                  const double* __restrict__ qpart, int nqpart,
                                                  double* __restrict__ qstats) {
-    scatter_body(n, ncol, blockIdx.x, fused != 0, col_of, count, start, cstart, fill, slots, qpart,
-                 nqpart, qstats);
+    scatter_body(a, blockIdx.x, fused != 0, coord, sorted, count, start, cstart, fill, slots,
+                 qpart, nqpart, qstats);
 }
 
 __global__ void __launch_bounds__(256) k_scatter_batch(const BatchTable* __restrict__ tab,
                                                        const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_SCATTER, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        scatter_body(d.bin.n, d.ncol, item, false, d.col_of, d.col_count, d.col_start,
+        scatter_body(d.bin, item, false, d.coord, d.sorted, d.col_count, d.col_start,
                      d.clus_start, d.col_fill, d.slots, d.qpart, d.nq, d.qstats);
     });
 }
@@ -331,9 +345,9 @@ __device__ __forceinline__ void colsort_body(int col, const int* __restrict__ st
         unsigned long long mine = ~0ull;
         uint4 c = make_uint4(0, 0, 0, 0);
         int i = 0;
-        if (t < cnt) {
+        if (t < cnt) {   // the column's records as scatter left them (read before any write)
             i = slots[lo + t];
-            c = coord[i];
+            c = sorted[lo + t];
             mine = ((unsigned long long)c.z << 32) | (unsigned)i;
             key[t] = mine;
         }
@@ -443,10 +457,10 @@ __global__ void __launch_bounds__(256) k_colsort_batch(const BatchTable* __restr
 }
 
 hipError_t launch_encode(const BinArgs& a, const float* xyz, const float* q, uint4* coord,
-                         int* col_of, int* col_count, double* qpart, int nqpart, hipStream_t st) {
+                         int* col_count, double* qpart, int nqpart, hipStream_t st) {
     if (a.n > 0)
-        hipLaunchKernelGGL(k_encode, dim3(nqpart), dim3(256), 0, st, a, xyz, q, coord, col_of,
-                           col_count, qpart);
+        hipLaunchKernelGGL(k_encode, dim3(nqpart), dim3(256), 0, st, a, xyz, q, coord, col_count,
+                           qpart);
     return hipGetLastError();
 }
 
@@ -463,14 +477,15 @@ bool scan_fused(int n, int ncol) {
     return ncol <= kHistCols && nb * ncol <= (1ll << 22);
 }
 
-hipError_t launch_scatter(int n, int ncol, const int* col_of, const int* col_count, int* col_start,
-                          int* clus_start, int* col_fill, int* slots, const double* qpart,
-                          int nqpart, double* qstats, hipStream_t st) {
+hipError_t launch_scatter(const BinArgs& a, const uint4* coord, uint4* sorted, const int* col_count,
+                          int* col_start, int* clus_start, int* col_fill, int* slots,
+                          const double* qpart, int nqpart, double* qstats, hipStream_t st) {
+    const int n = a.n, ncol = a.nc[0] * a.nc[1];
     const int fused = scan_fused(n, ncol) ? 1 : 0;
     // with no charges the fused prefix still has to run once (all columns empty)
     const int nb = std::max(1, (n + 255) / 256);
     if (n > 0 || fused)
-        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, st, n, ncol, fused, col_of,
+        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, st, a, fused, coord, sorted,
                            col_count, col_start, clus_start, col_fill, slots, qpart, nqpart,
                            qstats);
     return hipGetLastError();

@@ -1,9 +1,6 @@
-// Total energy in FP64 (one block, fixed summation order):
-//   E = E_near + E_far - E_self + E_bg,
-//   E_self = 1/2 F(0) sum q^2            (u-series analogue of eq. 10's self term),
-//   E_bg   = -Q^2/(2V) int N(r) d^3r     (uniform neutralising background; 0 if Q = 0).
-#include "useries_internal.h"
-#include "device_common.h"
+// Total energy in FP64 as its own launch after the gather kernel (one block
+// per box).
+#include "energy_total.h"
 
 namespace useries {
 
@@ -12,28 +9,8 @@ __device__ __forceinline__ void finalize_body(const FinalArgs& a, const double* 
                                               const double* __restrict__ qstats,
                                               double* __restrict__ energy,
                                               double* __restrict__ parts) {
-    __shared__ double red[1024];
-    double s = 0.0;
-    for (int k = threadIdx.x; k < a.n_pair_parts; k += 1024) s += pp[k];
-    const double en = block_sum_d<1024>(s, red);
-    __syncthreads();
-    s = 0.0;
-    for (int k = threadIdx.x; k < a.n_gather_parts; k += 1024) s += gp[k];
-    const double ef = block_sum_d<1024>(s, red);
-    if (threadIdx.x == 0) {
-        const double Q = qstats[0], q2 = qstats[1];
-        const double es = 0.5 * a.f_inf0 * q2;
-        const double eb = -0.5 * Q * Q * a.near_int_over_v;
-        const double e = en + ef - es + eb;
-        if (energy) energy[0] = e;
-        if (parts) {
-            parts[0] = en;
-            parts[1] = ef;
-            parts[2] = es;
-            parts[3] = eb;
-            parts[4] = e;
-        }
-    }
+    __shared__ double wred[2 * 1024 / 64];
+    energy_total<1024>(a, pp, gp, qstats, energy, parts, wred);
 }
 
 __global__ void __launch_bounds__(1024) k_finalize(FinalArgs a, const double* __restrict__ pp,

@@ -83,7 +83,7 @@ private:
 
 // Byte offsets of one request's resident device workspace
 struct Layout {
-    size_t xyz, q, forces, energies, coord, sorted, col_of, perm, slots, cl_info, cl_col, cl_z,
+    size_t xyz, q, forces, energies, coord, sorted, perm, slots, cl_info, cl_col, cl_z,
         fnear, qpart, pair_parts, gather_parts, qstats, col_count, col_start, col_fill,
         clus_start, zbin, rho, tgrid, phi, mat[3], total;
 };
@@ -106,7 +106,6 @@ Layout make_layout(const HostPlan& hp, int n, int n_evals) {
     L.energies = take(8 * (size_t)n_evals);
     L.coord = take(16 * c);
     L.sorted = take(16 * c);
-    L.col_of = take(4 * c);
     L.perm = take(4 * c);
     L.slots = take(4 * c);
     L.cl_info = take(8 * clmax);
@@ -341,7 +340,6 @@ struct useries_server_s {
         d.energies = (double*)(base + L.energies);
         d.coord = (uint4*)(base + L.coord);
         d.sorted = (uint4*)(base + L.sorted);
-        d.col_of = (int*)(base + L.col_of);
         d.perm = (int*)(base + L.perm);
         d.slots = (int*)(base + L.slots);
         d.cl_col = (int*)(base + L.cl_col);

@@ -171,7 +171,7 @@ struct BoxDesc {
     double* energies;          // [n_evals]
     // workspace
     uint4 *coord, *sorted;
-    int *col_of, *perm, *slots, *cl_col;
+    int *perm, *slots, *cl_col;
     int2* cl_info;
     uint2* cl_z;
     float4* fnear;
@@ -210,16 +210,18 @@ hipError_t launch_displace_batch(const BatchTable* tab, const BoxDesc* desc, int
 // ------------------------------------------------------------ kernel launchers
 // All launchers enqueue on `st` and return hipGetLastError().
 hipError_t launch_encode(const BinArgs& a, const float* xyz, const float* q, uint4* coord,
-                         int* col_of, int* col_count, double* qpart, int nqpart, hipStream_t st);
+                         int* col_count, double* qpart, int nqpart, hipStream_t st);
 hipError_t launch_scan(int ncol, int* col_count, int* col_start, int* clus_start,
                        int* col_fill, const double* qpart, int nqpart, double* qstats,
                        hipStream_t st);
 // true when scatter takes the column offsets itself (no scan launch): the
 // counts fit in its LDS and every block can afford to read them
 bool scan_fused(int n, int ncol);
-hipError_t launch_scatter(int n, int ncol, const int* col_of, const int* col_count, int* col_start,
-                          int* clus_start, int* col_fill, int* slots, const double* qpart,
-                          int nqpart, double* qstats, hipStream_t st);
+// writes each charge's input index to `slots` and its record to `sorted`, in
+// column order (colsort then sorts each column in place)
+hipError_t launch_scatter(const BinArgs& a, const uint4* coord, uint4* sorted, const int* col_count,
+                          int* col_start, int* clus_start, int* col_fill, int* slots,
+                          const double* qpart, int nqpart, double* qstats, hipStream_t st);
 // also clears col_count and col_fill of the ncol columns
 hipError_t launch_colsort(int ncol, const int* col_start, const int* clus_start, const int* slots,
                           const uint4* coord, int* perm, uint4* sorted, int2* cl_info,
