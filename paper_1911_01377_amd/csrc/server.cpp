@@ -81,11 +81,14 @@ private:
     std::map<size_t, size_t> free_;
 };
 
-// Byte offsets of one request's resident device workspace
+// Byte offsets of one request's resident device workspace.  It opens with
+// what goes up at admission (charges, matrices, zeroed column counters,
+// positions: one copy) followed by what comes down at the end (positions,
+// forces, energies: one copy); the slot's pinned staging mirrors that prefix.
 struct Layout {
-    size_t xyz, q, forces, energies, coord, sorted, perm, slots, cl_info, cl_col, cl_z,
-        fnear, qpart, pair_parts, gather_parts, qstats, col_count, col_start, col_fill,
-        clus_start, zbin, rho, tgrid, phi, mat[3], total;
+    size_t q, mat[3], col_count, xyz, forces, energies, up_bytes, prefix, coord, sorted, perm,
+        slots, cl_info, cl_col, cl_z, fnear, qpart, pair_parts, gather_parts, qstats, col_start,
+        col_fill, clus_start, zbin, rho, tgrid, phi, total;
 };
 
 Layout make_layout(const HostPlan& hp, int n, int n_evals) {
@@ -100,10 +103,14 @@ Layout make_layout(const HostPlan& hp, int n, int n_evals) {
     const size_t ncm = (size_t)hp.ncol_max;
     const size_t clmax = (size_t)pair_blocks(n, hp.ncol_max);
     const size_t ng = (size_t)hp.grid[0] * hp.grid[1] * hp.grid[2];
-    L.xyz = take(12 * c);
     L.q = take(4 * c);
+    for (int a = 0; a < 3; ++a) L.mat[a] = take(hp.mats[a].size());
+    L.col_count = take(4 * ncm);
+    L.xyz = take(12 * c);
+    L.up_bytes = L.xyz + 12 * c;
     L.forces = take(12 * c);
     L.energies = take(8 * (size_t)n_evals);
+    L.prefix = L.energies + 8 * (size_t)n_evals;
     L.coord = take(16 * c);
     L.sorted = take(16 * c);
     L.perm = take(4 * c);
@@ -116,7 +123,6 @@ Layout make_layout(const HostPlan& hp, int n, int n_evals) {
     L.pair_parts = take(8 * clmax);
     L.gather_parts = take(8 * (size_t)gather_blocks(hp.gridargs));
     L.qstats = take(16);
-    L.col_count = take(4 * ncm);
     L.col_start = take(4 * (ncm + 1));
     L.col_fill = take(4 * ncm);
     L.clus_start = take(4 * (ncm + 1));
@@ -124,32 +130,8 @@ Layout make_layout(const HostPlan& hp, int n, int n_evals) {
     L.rho = take(4 * ng);
     L.tgrid = take(4 * ng * (size_t)hp.nterms);
     L.phi = take(4 * ng);
-    for (int a = 0; a < 3; ++a) L.mat[a] = take(hp.mats[a].size());
     L.total = o;
     return L;
-}
-
-// Pinned staging of one slot: inputs and matrices going up, outputs coming down
-struct Staging {
-    size_t xyz, q, mat[3], out_forces, out_xyz, out_energies, total;
-};
-
-Staging make_staging(const HostPlan& hp, int n, int n_evals) {
-    Staging S{};
-    size_t o = 0;
-    auto take = [&](size_t bytes) {
-        const size_t r = o;
-        o += align_up(std::max<size_t>(bytes, 1));
-        return r;
-    };
-    S.xyz = take(12 * (size_t)n);
-    S.q = take(4 * (size_t)n);
-    for (int a = 0; a < 3; ++a) S.mat[a] = take(hp.mats[a].size());
-    S.out_forces = take(12 * (size_t)n);
-    S.out_xyz = take(12 * (size_t)n);
-    S.out_energies = take(8 * (size_t)n_evals);
-    S.total = o;
-    return S;
 }
 
 struct Req {
@@ -157,7 +139,6 @@ struct Req {
     useries_request r{};
     HostPlan hp;
     Layout lay{};
-    Staging stg{};
     int items[BK_COUNT] = {0};
     size_t lds = 0, lds_z = 0;   // dynamic LDS of conv_xy and conv_z
     // shared with API threads (under the server mutex)
@@ -182,8 +163,6 @@ double seconds_since(std::chrono::steady_clock::time_point t0) {
 struct useries_server_s {
     int device = 0;
     hipStream_t st = nullptr;
-    hipStream_t side = nullptr;                 // far part of a step
-    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     int precision = USERIES_PLAIN_FP32;
     int max_slots = 1;
     useries_server_opts o{};
@@ -191,10 +170,14 @@ struct useries_server_s {
     size_t budget = 0;
     char* arena_base = nullptr;
     Arena arena;
-    BoxDesc* d_desc = nullptr;
+    // the batch table and the slots' box descriptors, uploaded together each
+    // step from a ring of pinned copies: [table | max_slots descriptors]
+    char* d_tabdesc = nullptr;
     BatchTable* d_table = nullptr;
-    BoxDesc* h_desc = nullptr;     // pinned [max_slots]
-    BatchTable* h_tab = nullptr;   // pinned [kRing]
+    BoxDesc* d_desc = nullptr;
+    BoxDesc* h_desc = nullptr;     // current descriptors (host) [max_slots]
+    char* h_ring = nullptr;        // pinned [kRing][ring_stride]
+    size_t ring_stride = 0;
     hipEvent_t ring_ev[kRing] = {};
     bool ring_used[kRing] = {};
     int ring_next = 0;
@@ -204,6 +187,8 @@ struct useries_server_s {
         size_t cap = 0;
     };
     std::vector<Slot> slots;
+    std::vector<char*> old_staging;   // outgrown pinned buffers, freed at destruction (a free would
+                                      // wait for the device)
     int grid[BK_COUNT] = {0};
     int lds_limit = 0;
     std::map<std::pair<size_t, size_t>, hipGraphExec_t> graphs;   // by the conv LDS sizes
@@ -308,11 +293,12 @@ struct useries_server_s {
         const HostPlan& hp = R->hp;
         const int n = (int)R->r.n;
         hipError_t e;
-        if (S.cap < R->stg.total) {
-            if (S.staging) hipHostFree(S.staging);
+        const Layout& L = R->lay;
+        if (S.cap < L.prefix) {
+            if (S.staging) old_staging.push_back(S.staging);
             S.staging = nullptr;
             S.cap = 0;
-            const size_t want = R->stg.total + R->stg.total / 4;
+            const size_t want = L.prefix + L.prefix / 2;
             if ((e = hipHostMalloc((void**)&S.staging, want, hipHostMallocDefault))) return e;
             S.cap = want;
         }
@@ -333,7 +319,6 @@ struct useries_server_s {
         d.disp_sigma = (float)R->r.disp_sigma;
         d.key[0] = (uint32_t)R->r.seed;
         d.key[1] = (uint32_t)(R->r.seed >> 32);
-        const Layout& L = R->lay;
         d.xyz = (float*)(base + L.xyz);
         d.q = (const float*)(base + L.q);
         d.forces = (float*)(base + L.forces);
@@ -362,24 +347,14 @@ struct useries_server_s {
         d.ky = (const float*)(base + L.mat[1]);
         d.kz = (const float*)(base + L.mat[2]);
 
-        std::memcpy(stg + R->stg.xyz, R->r.xyz, 12 * (size_t)n);
-        std::memcpy(stg + R->stg.q, R->r.q, 4 * (size_t)n);
+        // one upload: charges, matrices, zeroed column counters, positions (the
+        // descriptor goes up with the next step's batch table)
+        std::memcpy(stg + L.q, R->r.q, 4 * (size_t)n);
         for (int a = 0; a < 3; ++a)
-            std::memcpy(stg + R->stg.mat[a], hp.mats[a].data(), hp.mats[a].size());
-        if ((e = hipMemcpyAsync(base + L.xyz, stg + R->stg.xyz, 12 * (size_t)n,
-                                hipMemcpyHostToDevice, st)))
-            return e;
-        if ((e = hipMemcpyAsync(base + L.q, stg + R->stg.q, 4 * (size_t)n, hipMemcpyHostToDevice,
-                                st)))
-            return e;
-        for (int a = 0; a < 3; ++a)
-            if ((e = hipMemcpyAsync(base + L.mat[a], stg + R->stg.mat[a], hp.mats[a].size(),
-                                    hipMemcpyHostToDevice, st)))
-                return e;
-        // column counters start at zero (each evaluation's scan clears them again)
-        if ((e = hipMemsetAsync(base + L.col_count, 0, 4 * (size_t)hp.ncol_max, st))) return e;
-        if ((e = hipMemcpyAsync(d_desc + s, &d, sizeof(BoxDesc), hipMemcpyHostToDevice, st)))
-            return e;
+            std::memcpy(stg + L.mat[a], hp.mats[a].data(), hp.mats[a].size());
+        std::memset(stg + L.col_count, 0, 4 * (size_t)hp.ncol_max);
+        std::memcpy(stg + L.xyz, R->r.xyz, 12 * (size_t)n);
+        if ((e = hipMemcpyAsync(base, stg, L.up_bytes, hipMemcpyHostToDevice, st))) return e;
         R->slot = s;
         R->off = off;
         R->step = 0;
@@ -422,7 +397,8 @@ struct useries_server_s {
         ring_next = (ring_next + 1) % kRing;
         hipError_t e;
         if (ring_used[r] && (e = hipEventSynchronize(ring_ev[r]))) return e;
-        BatchTable& T = h_tab[r];
+        char* ring = h_ring + (size_t)r * ring_stride;
+        BatchTable& T = *reinterpret_cast<BatchTable*>(ring);
         const int nb = (int)active.size();
         T.nbox = nb;
         for (int k = 0; k < BK_COUNT; ++k) T.off[k][0] = 0;
@@ -440,7 +416,8 @@ struct useries_server_s {
             lds = std::max(lds, R->lds);
             lds_z = std::max(lds_z, R->lds_z);
         }
-        if ((e = hipMemcpyAsync(d_table, &T, sizeof(BatchTable), hipMemcpyHostToDevice, st)))
+        std::memcpy(ring + align_up(sizeof(BatchTable)), h_desc, sizeof(BoxDesc) * max_slots);
+        if ((e = hipMemcpyAsync(d_tabdesc, ring, ring_stride, hipMemcpyHostToDevice, st)))
             return e;
         if (o.use_graph) {
             hipGraphExec_t ex = nullptr;
@@ -470,14 +447,9 @@ struct useries_server_s {
             char* base = arena_base + R->off;
             char* stg = slots[R->slot].staging;
             const size_t n = (size_t)R->r.n;
-            if ((e = hipMemcpyAsync(stg + R->stg.out_forces, base + R->lay.forces, 12 * n,
-                                    hipMemcpyDeviceToHost, st)))
-                return e;
-            if ((e = hipMemcpyAsync(stg + R->stg.out_energies, base + R->lay.energies,
-                                    8 * (size_t)R->r.n_evals, hipMemcpyDeviceToHost, st)))
-                return e;
-            if (R->r.xyz_final &&
-                (e = hipMemcpyAsync(stg + R->stg.out_xyz, base + R->lay.xyz, 12 * n,
+            // one download: [positions,] forces, energies
+            const size_t from = R->r.xyz_final ? R->lay.xyz : R->lay.forces;
+            if ((e = hipMemcpyAsync(stg + from, base + from, R->lay.prefix - from,
                                     hipMemcpyDeviceToHost, st)))
                 return e;
             R->done_ev = get_event();
@@ -501,9 +473,9 @@ struct useries_server_s {
             if (q != hipSuccess) return q;
             const char* stg = slots[R->slot].staging;
             const size_t n = (size_t)R->r.n;
-            std::memcpy(R->r.forces, stg + R->stg.out_forces, 12 * n);
-            std::memcpy(R->r.energies, stg + R->stg.out_energies, 8 * (size_t)R->r.n_evals);
-            if (R->r.xyz_final) std::memcpy(R->r.xyz_final, stg + R->stg.out_xyz, 12 * n);
+            std::memcpy(R->r.forces, stg + R->lay.forces, 12 * n);
+            std::memcpy(R->r.energies, stg + R->lay.energies, 8 * (size_t)R->r.n_evals);
+            if (R->r.xyz_final) std::memcpy(R->r.xyz_final, stg + R->lay.xyz, 12 * n);
             ev_pool.push_back(R->done_ev);
             R->done_ev = nullptr;
             arena.release(R->off, R->lay.total);
@@ -612,7 +584,6 @@ struct useries_server_s {
             worker.join();
         }
         if (st) hipStreamSynchronize(st);
-        if (side) hipStreamSynchronize(side);
         for (auto& g : graphs) hipGraphExecDestroy(g.second);
         for (auto g : graph_objs) hipGraphDestroy(g);
         for (auto e : ev_pool) hipEventDestroy(e);
@@ -620,14 +591,11 @@ struct useries_server_s {
             if (e) hipEventDestroy(e);
         for (auto& s : slots)
             if (s.staging) hipHostFree(s.staging);
-        if (h_desc) hipHostFree(h_desc);
-        if (h_tab) hipHostFree(h_tab);
-        hipFree(d_desc);
-        hipFree(d_table);
+        for (char* b : old_staging) hipHostFree(b);
+        delete[] h_desc;
+        if (h_ring) hipHostFree(h_ring);
+        hipFree(d_tabdesc);
         hipFree(arena_base);
-        if (fork_ev) hipEventDestroy(fork_ev);
-        if (join_ev) hipEventDestroy(join_ev);
-        if (side) hipStreamDestroy(side);
         if (st) hipStreamDestroy(st);
     }
 };
@@ -690,15 +658,14 @@ int useries_server_create(useries_server_t* out, size_t hbm_budget_bytes, int ma
     S->grid[BK_GATHER] = 4 * cu;
     S->grid[BK_FINAL] = max_slots;
     S->grid[BK_DISPLACE] = 2 * cu;
+    S->ring_stride = align_up(sizeof(BatchTable)) + align_up(sizeof(BoxDesc) * max_slots);
+    S->h_desc = new BoxDesc[max_slots]();
     if ((e = hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking)) ||
-        (e = hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking)) ||
-        (e = hipEventCreateWithFlags(&S->fork_ev, hipEventDisableTiming)) ||
-        (e = hipEventCreateWithFlags(&S->join_ev, hipEventDisableTiming)) ||
-        (e = hipMalloc((void**)&S->d_desc, sizeof(BoxDesc) * max_slots)) ||
-        (e = hipMalloc((void**)&S->d_table, sizeof(BatchTable))) ||
-        (e = hipHostMalloc((void**)&S->h_desc, sizeof(BoxDesc) * max_slots, hipHostMallocDefault)) ||
-        (e = hipHostMalloc((void**)&S->h_tab, sizeof(BatchTable) * kRing, hipHostMallocDefault)))
+        (e = hipMalloc((void**)&S->d_tabdesc, S->ring_stride)) ||
+        (e = hipHostMalloc((void**)&S->h_ring, S->ring_stride * kRing, hipHostMallocDefault)))
         return set_last_error(USERIES_EHIP, std::string("server setup: ") + hipGetErrorString(e));
+    S->d_table = reinterpret_cast<BatchTable*>(S->d_tabdesc);
+    S->d_desc = reinterpret_cast<BoxDesc*>(S->d_tabdesc + align_up(sizeof(BatchTable)));
     for (auto& ev : S->ring_ev)
         if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)))
             return set_last_error(USERIES_EHIP, hipGetErrorString(e));
@@ -733,7 +700,6 @@ int useries_submit(useries_server_t S, const useries_request* req, uint64_t* tic
     if (S->lds_limit > 0 && std::max(R->lds, R->lds_z) > (size_t)S->lds_limit)
         return set_last_error(USERIES_EINVAL, "grid and term count need more LDS than the device has");
     R->lay = make_layout(hp, n, r.n_evals);
-    R->stg = make_staging(hp, n, r.n_evals);
     if (R->lay.total > S->budget)
         return set_last_error(USERIES_ENOMEM, "request workspace exceeds the server's budget");
     const int nq = (n + 255) / 256;
