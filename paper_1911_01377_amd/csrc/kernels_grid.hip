@@ -185,21 +185,29 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
             nst += wtot[v];
         }
         if (touch) {
+            // the 3 x 8 brick weights of the charge: zero, then the 2P stencil
+            // points of each axis at their brick positions (k - k0) mod g
             const int slot = before + __popcll(m & ((1ull << lane) - 1ull));
+            float* row = sw[slot];
+#pragma unroll
+            for (int b = 0; b < 3 * kBrick; b += 4)
+                *reinterpret_cast<float4*>(row + b) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
                 const int k0 = wrap1(X0s[ax] - gi[ax] + P - 1, a.g[ax]);
+                const float c = (float)(P - 1) + f[ax];
+                const float sc = ax == 1 ? a.cw[ax] * qj : a.cw[ax];
+                const float e2 = -a.hs[ax] * 1.44269504f;   // exp(-t^2 hs) = 2^(t^2 e2)
 #pragma unroll
-                for (int b = 0; b < kBrick; ++b) {
-                    float wv = 0.0f;
-                    int k = k0 + b;
-                    if (k >= a.g[ax]) k -= a.g[ax];
-                    if (b < Bs[ax] && k < 2 * P) {
-                        const float tt = (float)(k - P + 1) - f[ax];
-                        wv = a.cw[ax] * __expf(-tt * tt * a.hs[ax]);
+                for (int k = 0; k < 2 * kMaxStencilHalf; ++k) {
+                    if (k < 2 * P) {
+                        int b = k - k0;
+                        if (b < 0) b += a.g[ax];
+                        if (b < Bs[ax]) {
+                            const float t = (float)k - c;
+                            row[ax * kBrick + b] = sc * __builtin_amdgcn_exp2f(t * t * e2);
+                        }
                     }
-                    if (ax == 1) wv *= qj;
-                    sw[slot][ax * kBrick + b] = wv;
                 }
             }
         }
@@ -278,6 +286,7 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
     __shared__ int pbeg[kGatherMaxPieces];
     __shared__ int poff[kGatherMaxPieces + 1];
     __shared__ float sw[kGatherWaves][4][6][16];
+    __shared__ int2 rowtab[4 * kMaxStencilHalf * kMaxStencilHalf];   // stencil row r: {offset, ky | kz << 16}
     __shared__ int wtot[kGatherWaves];
     __shared__ double se[kGatherWaves];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -308,6 +317,11 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
             const int idx = base + kGatherThreads * u;
             if (idx < nh) sphi[idx] = v[u];
         }
+    }
+    // stencil rows (ky, kz) of a charge and their offsets in the halo, once per block
+    for (int r = tid; r < P2 * P2; r += kGatherThreads) {
+        const int ky = r % P2, kz = r / P2;
+        rowtab[r] = make_int2((kz * E1 + ky) * E0, ky | (kz << 16));
     }
     // columns overlapping the brick's cells in x and y
     const int cxl = X0 * a.nc[0] / a.g[0], cxh = ((X0 + B0) * a.nc[0] + a.g[0] - 1) / a.g[0] - 1;
@@ -401,14 +415,19 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                 const float* W = &sw[wave][g][0][0];
                 // stencil point k of the charge is halo point (gi - brick origin) + k
                 const int lx = gi[0] - X0, ly = gi[1] - Y0, lz = gi[2] - Z0;
+                const float* obase = sphi + (lz * E1 + ly) * E0 + lx;
                 for (int r = l16; r < P2 * P2; r += 16) {
-                    const int ky = r % P2, kz = r / P2;
-                    const float* rowp = sphi + ((lz + kz) * E1 + (ly + ky)) * E0 + lx;
+                    const int2 rt = rowtab[r];
+                    const int ky = rt.y & 0xffff, kz = rt.y >> 16;
+                    const float* rowp = obase + rt.x;
                     float sx = 0.0f, dsx = 0.0f;
-                    for (int k = 0; k < P2; ++k) {
-                        const float v = rowp[k];
-                        sx = fmaf(W[k], v, sx);
-                        dsx = fmaf(W[3 * 16 + k], v, dsx);
+#pragma unroll
+                    for (int k = 0; k < 2 * kMaxStencilHalf; ++k) {
+                        if (k < P2) {
+                            const float v = rowp[k];
+                            sx = fmaf(W[k], v, sx);
+                            dsx = fmaf(W[3 * 16 + k], v, dsx);
+                        }
                     }
                     const float wy = W[16 + ky], wz = W[32 + kz];
                     const float wyz = wy * wz;
