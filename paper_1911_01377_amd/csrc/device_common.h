@@ -54,6 +54,16 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Work item of block i of a launch of xcd_blocks(nb) blocks.  Consecutive
+// blocks go to the 8 XCDs in turn, so this gives each XCD a contiguous range
+// of items: neighbouring items (nearby clusters or bricks) then share that
+// XCD's L2.  Items >= nb are padding.
+constexpr int kXcds = 8;
+__host__ __device__ inline int xcd_blocks(int nb) { return (nb + kXcds - 1) / kXcds * kXcds; }
+__device__ __forceinline__ int xcd_item(int i, int nb) {
+    return (i % kXcds) * (xcd_blocks(nb) / kXcds) + i / kXcds;
+}
+
 // sum over the 64 lanes of a wavefront (every lane gets the result)
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll

@@ -239,12 +239,13 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
     }
 }
 
-__global__ void __launch_bounds__(64 * kSpreadWaves) k_spread(GridArgs a,
+__global__ void __launch_bounds__(64 * kSpreadWaves) k_spread(GridArgs a, int nb,
                                                               const uint4* __restrict__ sorted,
                                                               const int* __restrict__ zbin,
                                                               const double* __restrict__ qstats,
                                                               float* __restrict__ rho) {
-    spread_body(a, blockIdx.x, sorted, zbin, qstats, rho);
+    const int item = xcd_item(blockIdx.x, nb);
+    if (item < nb) spread_body(a, item, sorted, zbin, qstats, rho);
 }
 
 __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread_batch(
@@ -469,14 +470,16 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
     }
 }
 
-__global__ void __launch_bounds__(kGatherThreads) k_gather(GridArgs a, const uint4* __restrict__ sorted,
+__global__ void __launch_bounds__(kGatherThreads) k_gather(GridArgs a, int nb,
+                                                const uint4* __restrict__ sorted,
                                                 const int* __restrict__ perm,
                                                 const int* __restrict__ zbin,
                                                 const float* __restrict__ phi,
                                                 const float4* __restrict__ fnear,
                                                 float* __restrict__ forces,
                                                 double* __restrict__ epart) {
-    gather_body(a, blockIdx.x, sorted, perm, zbin, phi, fnear, forces, epart);
+    const int item = xcd_item(blockIdx.x, nb);
+    if (item < nb) gather_body(a, item, sorted, perm, zbin, phi, fnear, forces, epart);
 }
 
 __global__ void __launch_bounds__(kGatherThreads) k_gather_batch(const BatchTable* __restrict__ tab,
@@ -492,8 +495,8 @@ hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* zbin
                          const double* qstats, float* rho, hipStream_t st) {
     const int nb = ((a.g[0] + kBrick - 1) / kBrick) * ((a.g[1] + kBrick - 1) / kBrick) *
                    ((a.g[2] + kBrick - 1) / kBrick);
-    hipLaunchKernelGGL(k_spread, dim3(nb), dim3(64 * kSpreadWaves), 0, st, a, sorted, zbin,
-                       qstats, rho);
+    hipLaunchKernelGGL(k_spread, dim3(xcd_blocks(nb)), dim3(64 * kSpreadWaves), 0, st, a, nb,
+                       sorted, zbin, qstats, rho);
     return hipGetLastError();
 }
 
@@ -505,8 +508,9 @@ int gather_blocks(const GridArgs& a) {
 hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm, const int* zbin,
                          const float* phi, const float4* fnear, float* forces, double* epart,
                          hipStream_t st) {
-    hipLaunchKernelGGL(k_gather, dim3(gather_blocks(a)), dim3(kGatherThreads), 0, st, a, sorted, perm, zbin,
-                       phi, fnear, forces, epart);
+    const int nb = gather_blocks(a);
+    hipLaunchKernelGGL(k_gather, dim3(xcd_blocks(nb)), dim3(kGatherThreads), 0, st, a, nb, sorted,
+                       perm, zbin, phi, fnear, forces, epart);
     return hipGetLastError();
 }
 

@@ -366,7 +366,8 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
 }
 
 template <int DEG>
-__global__ void __launch_bounds__(64 * kPairWaves) k_pair(PairArgs a, const uint4* __restrict__ sorted,
+__global__ void __launch_bounds__(64 * kPairWaves) k_pair(PairArgs a, int nb,
+                                             const uint4* __restrict__ sorted,
                                              const int* __restrict__ clus_start,
                                              const int2* __restrict__ cl_info,
                                              const int* __restrict__ cl_col,
@@ -374,7 +375,9 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pair(PairArgs a, const uint
                                              const int* __restrict__ zbin,
                                              float4* __restrict__ fnear,
                                              double* __restrict__ epart) {
-    pair_body<DEG>(a, blockIdx.x, sorted, clus_start, cl_info, cl_col, cl_z, zbin, fnear, epart);
+    const int item = xcd_item(blockIdx.x, nb);
+    if (item < nb)
+        pair_body<DEG>(a, item, sorted, clus_start, cl_info, cl_col, cl_z, zbin, fnear, epart);
 }
 
 template <int DEG>
@@ -391,12 +394,12 @@ hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, cons
                        const int2* cl_info, const int* cl_col, const uint2* cl_z, const int* zbin,
                        float4* fnear, double* epart, hipStream_t st) {
     if (nblocks <= 0) return hipSuccess;
-    const dim3 grid(nblocks), block(64 * kPairWaves);
+    const dim3 grid(xcd_blocks(nblocks)), block(64 * kPairWaves);
     switch (a.deg) {
 #define USERIES_PAIR_DEG(D)                                                                   \
     case D:                                                                                   \
-        hipLaunchKernelGGL(k_pair<D>, grid, block, 0, st, a, sorted, clus_start, cl_info,     \
-                           cl_col, cl_z, zbin, fnear, epart);                                 \
+        hipLaunchKernelGGL(k_pair<D>, grid, block, 0, st, a, nblocks, sorted, clus_start,     \
+                           cl_info, cl_col, cl_z, zbin, fnear, epart);                        \
         break;
         USERIES_PAIR_DEG(4) USERIES_PAIR_DEG(5) USERIES_PAIR_DEG(6) USERIES_PAIR_DEG(7)
         USERIES_PAIR_DEG(8) USERIES_PAIR_DEG(9) USERIES_PAIR_DEG(10) USERIES_PAIR_DEG(11)
