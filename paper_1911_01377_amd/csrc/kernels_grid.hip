@@ -72,7 +72,9 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
                                             const double* __restrict__ qstats,
                                             float* __restrict__ rho) {
     __shared__ float sw[kSpreadChunk][3 * kBrick];
-    __shared__ float red[kSpreadWaves - 1][kBrick][64];
+    static_assert((kSpreadWaves - 1) * kBrick * 64 <= kSpreadChunk * 3 * kBrick, "red fits in sw");
+    // the wavefronts' partial bricks, summed after the last chunk (reuses sw)
+    float (*red)[kBrick][64] = reinterpret_cast<float (*)[kBrick][64]>(&sw[0][0]);
     __shared__ int pbeg[2 * kMaxWindowCols];       // first charge of each column piece
     __shared__ int poff[2 * kMaxWindowCols + 1];   // prefix sums of the piece lengths
     __shared__ int wtot[kSpreadWaves];
@@ -264,13 +266,40 @@ __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread_batch(
 // thread and the owners compacted in thread order.  A wavefront evaluates
 // four owners at a time, 16 lanes each: a lane owns stencil rows (y, z) and
 // reads the 2P x points of each from LDS; the 16-lane groups then reduce.
-constexpr int kGatherMaxEdge = 19;        // halo edge: 8 + 2*5 - 1 = 17, 4 + 2*8 - 1 = 19
 constexpr int kGatherMaxPieces = 256;     // columns overlapping a brick
 constexpr int kGatherWaves = 8;           // wavefronts per brick
 constexpr int kGatherThreads = 64 * kGatherWaves;
 constexpr int kGatherBatch = 8;           // halo loads issued together per thread
 
 __host__ __device__ inline int gather_brick(int P) { return P <= 5 ? 8 : 4; }
+
+// Dynamic LDS of a gather block for stencil half width P (byte offsets): the
+// halo of edge brick + 2P - 1 and the per-owner weights are sized by P.
+struct GatherLds {
+    int own, ownf, ownp, sphi, sw, rowtab, pbeg, poff, wtot, se, total;
+};
+__host__ __device__ inline GatherLds gather_lds(int P) {
+    const int E = gather_brick(P) + 2 * P - 1;
+    GatherLds L{};
+    int o = 0;
+    auto take = [&](int bytes) {
+        const int r = o;
+        o += (bytes + 15) & ~15;
+        return r;
+    };
+    L.own = take(16 * kGatherThreads);                 // owner records
+    L.ownf = take(16 * kGatherThreads);                // owners' near forces
+    L.ownp = take(4 * kGatherThreads);                 // owners' input indices
+    L.sphi = take(4 * E * E * E);                      // potential on brick + halo
+    L.sw = take(4 * kGatherWaves * 4 * 6 * 2 * P);     // weights, derivatives [wave][owner][6][2P]
+    L.rowtab = take(8 * 4 * P * P);                    // stencil rows {offset, ky | kz << 16}
+    L.pbeg = take(4 * kGatherMaxPieces);
+    L.poff = take(4 * (kGatherMaxPieces + 1));
+    L.wtot = take(4 * kGatherWaves);
+    L.se = take(8 * kGatherWaves);
+    L.total = o;
+    return L;
+}
 
 __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                                             const uint4* __restrict__ sorted,
@@ -279,20 +308,21 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                                             const float* __restrict__ phi,
                                             const float4* __restrict__ fnear,
                                             float* __restrict__ forces,
-                                            double* __restrict__ epart) {
-    __shared__ float sphi[kGatherMaxEdge * kGatherMaxEdge * kGatherMaxEdge];
-    __shared__ uint4 own[kGatherThreads];
-    __shared__ float4 ownf[kGatherThreads];   // near force of the owner
-    __shared__ int ownp[kGatherThreads];      // input index of the owner
-    __shared__ int pbeg[kGatherMaxPieces];
-    __shared__ int poff[kGatherMaxPieces + 1];
-    __shared__ float sw[kGatherWaves][4][6][16];
-    __shared__ int2 rowtab[4 * kMaxStencilHalf * kMaxStencilHalf];   // stencil row r: {offset, ky | kz << 16}
-    __shared__ int wtot[kGatherWaves];
-    __shared__ double se[kGatherWaves];
+                                            double* __restrict__ epart, char* lds) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, l16 = lane & 15;
     const int P = a.P, P2 = 2 * P, GB = gather_brick(P);
+    const GatherLds LL = gather_lds(P);
+    uint4* own = reinterpret_cast<uint4*>(lds + LL.own);
+    float4* ownf = reinterpret_cast<float4*>(lds + LL.ownf);
+    int* ownp = reinterpret_cast<int*>(lds + LL.ownp);
+    float* sphi = reinterpret_cast<float*>(lds + LL.sphi);
+    float* swb = reinterpret_cast<float*>(lds + LL.sw);
+    int2* rowtab = reinterpret_cast<int2*>(lds + LL.rowtab);
+    int* pbeg = reinterpret_cast<int*>(lds + LL.pbeg);
+    int* poff = reinterpret_cast<int*>(lds + LL.poff);
+    int* wtot = reinterpret_cast<int*>(lds + LL.wtot);
+    double* se = reinterpret_cast<double*>(lds + LL.se);
     const int nbx = (a.g[0] + GB - 1) / GB, nby = (a.g[1] + GB - 1) / GB;
     const int X0 = (bid % nbx) * GB, Y0 = ((bid / nbx) % nby) * GB, Z0 = (bid / (nbx * nby)) * GB;
     const int B0 = min(GB, a.g[0] - X0), B1 = min(GB, a.g[1] - Y0), B2 = min(GB, a.g[2] - Z0);
@@ -405,15 +435,15 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                     for (int ax = 0; ax < 3; ++ax) {
                         const float tt = (float)(l16 - P + 1) - f[ax];
                         const float w = a.cw[ax] * __expf(-tt * tt * a.hs[ax]);
-                        sw[wave][g][ax][l16] = w;
-                        sw[wave][g][3 + ax][l16] = w * tt * a.dws[ax];
+                        swb[((wave * 4 + g) * 6 + ax) * P2 + l16] = w;
+                        swb[((wave * 4 + g) * 6 + 3 + ax) * P2 + l16] = w * tt * a.dws[ax];
                     }
                 }
             }
             wave_sync();
             float pe = 0.0f, px = 0.0f, py = 0.0f, pz = 0.0f;
             if (valid) {
-                const float* W = &sw[wave][g][0][0];
+                const float* W = swb + (wave * 4 + g) * 6 * P2;   // [6][2P]
                 // stencil point k of the charge is halo point (gi - brick origin) + k
                 const int lx = gi[0] - X0, ly = gi[1] - Y0, lz = gi[2] - Z0;
                 const float* obase = sphi + (lz * E1 + ly) * E0 + lx;
@@ -427,15 +457,15 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                         if (k < P2) {
                             const float v = rowp[k];
                             sx = fmaf(W[k], v, sx);
-                            dsx = fmaf(W[3 * 16 + k], v, dsx);
+                            dsx = fmaf(W[3 * P2 + k], v, dsx);
                         }
                     }
-                    const float wy = W[16 + ky], wz = W[32 + kz];
+                    const float wy = W[P2 + ky], wz = W[2 * P2 + kz];
                     const float wyz = wy * wz;
                     pe = fmaf(wyz, sx, pe);
                     px = fmaf(wyz, dsx, px);
-                    py = fmaf(W[64 + ky] * wz, sx, py);
-                    pz = fmaf(wy * W[80 + kz], sx, pz);
+                    py = fmaf(W[4 * P2 + ky] * wz, sx, py);
+                    pz = fmaf(wy * W[5 * P2 + kz], sx, pz);
                 }
             }
 #pragma unroll
@@ -478,16 +508,18 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(GridArgs a, int nb,
                                                 const float4* __restrict__ fnear,
                                                 float* __restrict__ forces,
                                                 double* __restrict__ epart) {
+    extern __shared__ char dyn[];
     const int item = xcd_item(blockIdx.x, nb);
-    if (item < nb) gather_body(a, item, sorted, perm, zbin, phi, fnear, forces, epart);
+    if (item < nb) gather_body(a, item, sorted, perm, zbin, phi, fnear, forces, epart, dyn);
 }
 
 __global__ void __launch_bounds__(kGatherThreads) k_gather_batch(const BatchTable* __restrict__ tab,
                                                       const BoxDesc* __restrict__ desc) {
+    extern __shared__ char dyn[];
     batch_for(tab, BK_GATHER, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
         gather_body(d.grid, item, d.sorted, d.perm, d.zbin, d.phi, d.fnear, d.forces,
-                    d.gather_parts);
+                    d.gather_parts, dyn);
     });
 }
 
@@ -509,8 +541,9 @@ hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm
                          const float* phi, const float4* fnear, float* forces, double* epart,
                          hipStream_t st) {
     const int nb = gather_blocks(a);
-    hipLaunchKernelGGL(k_gather, dim3(xcd_blocks(nb)), dim3(kGatherThreads), 0, st, a, nb, sorted,
-                       perm, zbin, phi, fnear, forces, epart);
+    hipLaunchKernelGGL(k_gather, dim3(xcd_blocks(nb)), dim3(kGatherThreads),
+                       gather_lds(a.P).total, st, a, nb, sorted, perm, zbin, phi, fnear, forces,
+                       epart);
     return hipGetLastError();
 }
 
@@ -520,9 +553,11 @@ hipError_t launch_spread_batch(const BatchTable* tab, const BoxDesc* desc, int g
     return hipGetLastError();
 }
 
-hipError_t launch_gather_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
+size_t gather_lds_bytes(int P) { return (size_t)gather_lds(P).total; }
+
+hipError_t launch_gather_batch(const BatchTable* tab, const BoxDesc* desc, size_t lds, int grid,
                                hipStream_t st) {
-    hipLaunchKernelGGL(k_gather_batch, dim3(grid), dim3(kGatherThreads), 0, st, tab, desc);
+    hipLaunchKernelGGL(k_gather_batch, dim3(grid), dim3(kGatherThreads), lds, st, tab, desc);
     return hipGetLastError();
 }
 

@@ -65,18 +65,17 @@ struct Poly {
 
 // column k of an axis window around the i-column ci and its minimum-image
 // distance (in columns) to ci; a full axis (few columns) is walked once
-__device__ __forceinline__ void stencil_col(int k, int ci, int R, int nc, bool full, int* col,
-                                            int* d) {
+struct StencilCol {
+    int col, d;
+};
+__device__ __forceinline__ StencilCol stencil_col(int k, int ci, int R, int nc, bool full) {
     if (full) {
-        *col = k;
         int v = k - ci;
         if (2 * v > nc) v -= nc;
         if (2 * v < -nc) v += nc;
-        *d = v;
-    } else {
-        *d = k - R;
-        *col = wrapi(ci + k - R, nc);
+        return {k, v};
     }
+    return {wrapi(ci + k - R, nc), k - R};
 }
 
 }  // namespace
@@ -158,9 +157,9 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     // second only where the z window wraps)
     int rb0 = 0, n0 = 0, rb1 = 0, n1 = 0;
     if (tid < NC) {
-        int colx, coly, dx, dy;
-        stencil_col(tid % nxs, cx, a.R[0], ncx, fullx, &colx, &dx);
-        stencil_col(tid / nxs, cy, a.R[1], ncy, fully, &coly, &dy);
+        const StencilCol sx = stencil_col(tid % nxs, cx, a.R[0], ncx, fullx);
+        const StencilCol sy = stencil_col(tid / nxs, cy, a.R[1], ncy, fully);
+        const int colx = sx.col, coly = sy.col, dx = sx.d, dy = sy.d;
         const float gx = (float)max(0, abs(dx) - 1) * a.cw[0];
         const float gy = (float)max(0, abs(dy) - 1) * a.cw[1];
         const float d2 = gx * gx + gy * gy;

@@ -201,7 +201,11 @@ hipError_t launch_conv_xy_batch(const BatchTable* tab, const BoxDesc* desc, int 
                                 size_t lds, int grid, hipStream_t st);
 hipError_t launch_conv_z_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3, size_t lds,
                                int grid, hipStream_t st);
-hipError_t launch_gather_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
+// lds >= gather_lds_bytes(P) of every box in the batch
+hipError_t launch_gather_batch(const BatchTable* tab, const BoxDesc* desc, size_t lds, int grid,
+                               hipStream_t st);
+// dynamic LDS of one gather block for stencil half width P
+size_t gather_lds_bytes(int P);
 hipError_t launch_finalize_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
                                  hipStream_t st);
 hipError_t launch_displace_batch(const BatchTable* tab, const BoxDesc* desc, int grid,

@@ -59,6 +59,22 @@ def test_small_water_bf16x3():
             precision=USERIES_BF16X3)
 
 
+@pytest.mark.parametrize("P,ratio", [(6, 0.9), (8, 0.9), (4, 0.83)])
+def test_stencil_widths(P, ratio):
+    """Non-default spreading stencils through the plain path: P = 6 and 8 take
+    the gather kernel's 4^3 bricks (P > 5) and larger halos; every width sizes
+    the gather kernel's LDS.  P >= 5 at sigma_s = 0.9 h meets the plain
+    contract; the 8^3 stencil at 0.83 h (about 2e-5 in force on water) is held
+    to 1e-4."""
+    n_mol = 500
+    L = (n_mol / synth.WATER_DENSITY) ** (1 / 3)
+    xyz, q, box = synth.water_box(n_mol=n_mol, L=L, seed=61)
+    g = int(np.ceil(L))
+    tol = (1e-6, 1e-5) if P >= 5 else (1e-4, 1e-4)
+    compare("water500/plain/P%d" % P, xyz, q, box, min(9.0, 0.45 * L), (g, g, g), tol[0], tol[1],
+            stencil_half=P, sigma_s_over_h=ratio)
+
+
 def test_orthorhombic_box_and_grid():
     rng = np.random.default_rng(4)
     box = (20.0, 23.5, 27.0)
