@@ -8,7 +8,11 @@ N = 4 far terms), inputs resident in HBM.
 
 Prints one JSON line:
   value        evaluations/s of the chosen form (default: BF16X3 convolutions,
-               6^3 spreading stencil; --form plain for the FP32 path);
+               6^3 spreading stencil; --form plain for the FP32 path), back to back
+               on one stream (the rate of one evaluation captured in a HIP graph
+               and replayed is reported beside it: slower here);
+  batched_copies  evaluations/s with B copies of the box submitted together to
+               the server (continuous batching, one graph replay per step);
   roofline     the dominant kernel's achieved rate vs the MI355X peak, timed
                with HIP events on the evaluation stream;
   kernels      every kernel's HIP-event time, algorithmic flop and bytes, and the
@@ -157,6 +161,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests in the serving stream (0: skip serving)")
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--batch-copies", type=int, default=8,
+                    help="copies of the box evaluated together through the server (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="Poisson arrival rate as a fraction of the closed-loop capacity")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -212,13 +218,34 @@ def main():
         log("copy probe: %d bytes read, %d bytes written" % (nb, nb))
         del src, dst
 
+    def timed_graph(plan, steps, warmup):
+        """One evaluation captured in a HIP graph, replayed back to back."""
+        plan.eval(x, qq, forces, energy)      # workspace sized before capture
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plan.eval(x, qq, forces, energy)
+        stream = torch.cuda.current_stream(dev)
+        for _ in range(warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(steps):
+            graph.replay()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / steps
+
     forms = {"bf16x3": USERIES_BF16X3, "plain": USERIES_PLAIN_FP32}
     plans = {k: Plan(box, rc, grid, precision=v) for k, v in forms.items()}
-    results = {}
+    results, graphed = {}, {}
     for k, plan in plans.items():
-        ms = timed(plan, args.steps, args.warmup)
-        results[k] = ms
-        log("form %s: %.4f ms/eval, %.1f evals/s" % (k, ms, 1e3 / ms))
+        results[k] = timed(plan, args.steps, args.warmup)
+        graphed[k] = timed_graph(plan, args.steps, args.warmup)
+        log("form %s: %.4f ms/eval (%.1f evals/s) eager launches, %.4f ms/eval graph replay"
+            % (k, results[k], 1e3 / results[k], graphed[k]))
     plan = plans[args.form]
     ms = results[args.form]
 
@@ -360,6 +387,36 @@ def main():
             cpu = {"value": None, "unit": "evals/s", "cores": None, "kind": "oracle",
                    "sample": "failed: %s" % e}
 
+    # B independent copies of the box per step through the server (continuous batching)
+    batched = None
+    if args.batch_copies > 0:
+        try:
+            from paper_1911_01377_amd import Server
+            free, _ = torch.cuda.mem_get_info()
+            srv = Server(int(min(0.8 * free, 8 << 30)), max_slots=max(args.batch_copies, 1),
+                         precision=forms[args.form])
+            nev = 100
+            srv.hold(True)              # admit all copies into the same steps
+            for rep in range(2):        # the first pass builds the server's graph
+                tk = [srv.submit(xyz, q, box, rc, grid, n_evals=nev, seed=c)
+                      for c in range(args.batch_copies)]
+                srv.hold(False)
+                for t_ in tk:
+                    srv.result(t_)
+                tm = np.array([srv.times(t_) for t_ in tk])
+                srv.hold(True)
+            wall = tm[:, 2].max() - tm[:, 1].min()
+            st = srv.stats()
+            srv.close()
+            batched = {"copies": args.batch_copies, "evals_per_request": nev,
+                       "evals_per_s": args.batch_copies * nev / wall,
+                       "ms_per_step": wall / nev * 1e3, "max_batch": st["max_batch"],
+                       "what": "B copies of the box admitted together into the server; "
+                               "from admission to the last result on the host"}
+            log("batched copies: %s" % batched)
+        except Exception as e:
+            batched = {"error": str(e)}
+
     serving = None
     if cells:
         try:
@@ -383,9 +440,12 @@ def main():
         "config": {"workload": "water box, 8756 3-site waters = 26268 charges, L=64 A, "
                                "r_c=9 A, 64^3 grid, b=2 C1, N=%d" % info["n_terms"],
                    "form": args.form, "stencil": "%d^3" % (2 * P)},
+        "timing": "back-to-back evaluations on one stream (eager launches), HIP events",
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "what": "one synchronised evaluation, host wall clock"},
         "other_form_evals_per_s": {k: 1e3 / v for k, v in results.items()},
+        "graph_replay_evals_per_s": {k: 1e3 / v for k, v in graphed.items()},
+        "batched_copies": batched,
         "kernel_ms": ktimes,
         "kernels": kernels,
         "accuracy": acc,

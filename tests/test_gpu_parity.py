@@ -191,3 +191,36 @@ def test_near_and_far_parts_separately():
     assert abs(gp[0] - op["near"]) <= 1e-6 * scale
     assert abs(gp[1] - op["far"]) <= 1e-6 * scale
     assert abs(gp[2] - op["self"]) <= 1e-12 * op["self"]
+
+
+def test_graph_replay_matches_eager():
+    """One evaluation captured in a HIP graph (as the benchmark times it):
+    every replay, with eager evaluations between them, gives the eager result
+    bitwise."""
+    from paper_1911_01377_amd import Plan
+    xyz, q, box = synth.water_box(n_mol=400, L=(400 / synth.WATER_DENSITY) ** (1 / 3), seed=71)
+    g = int(np.ceil(box[0]))
+    log("case graph replay: n=%d grid=%d" % (len(q), g))
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(xyz).to(dev)
+    qq = torch.from_numpy(q).to(dev)
+    for prec in (0, USERIES_BF16X3):
+        plan = Plan(box, min(9.0, 0.45 * box[0]), (g, g, g), precision=prec)
+        e_ref, f_ref, _ = plan.eval(x, qq)
+        torch.cuda.synchronize()
+        e_ref, f_ref = e_ref.clone(), f_ref.clone()
+        forces = torch.empty_like(f_ref)
+        energy = torch.empty_like(e_ref)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plan.eval(x, qq, forces, energy)
+        for rep in range(4):
+            forces.zero_()
+            energy.zero_()
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(forces, f_ref) and torch.equal(energy, e_ref), (prec, rep)
+            e2, f2, _ = plan.eval(x, qq)       # eager work between replays
+            torch.cuda.synchronize()
+            assert torch.equal(f2, f_ref) and torch.equal(e2, e_ref)
+        plan.close()
