@@ -326,7 +326,8 @@ static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float*
     USERIES_STEP(2, st, launch_scatter(hp.bin, p->coord, p->sorted, p->col_count, p->col_start,
                                        p->clus_start, p->col_fill, p->slots, p->qpart, nq,
                                        p->qstats, st));
-    USERIES_STEP(3, st, launch_colsort(ncol, p->col_start, p->clus_start, p->slots, p->coord,
+    USERIES_STEP(3, st, launch_colsort(ncol, hp.bin.nc[0], p->col_start, p->clus_start, p->slots,
+                                       p->coord,
                                        p->perm, p->sorted, p->cl_info, p->cl_col, p->cl_z,
                                        hp.grid[2], p->zbin, p->col_count, p->col_fill, st));
     USERIES_STEP(4, st, launch_pair(hp.pair, npb, p->sorted, p->clus_start, p->cl_info, p->cl_col,

@@ -324,6 +324,7 @@ __device__ __forceinline__ void colsort_body(int col, const int* __restrict__ st
                                              const uint4* __restrict__ coord,
                                              int* __restrict__ perm, uint4* __restrict__ sorted,
                                              int2* __restrict__ cl_info, int* __restrict__ cl_col,
+                                             int ncx,
                                              uint2* __restrict__ cl_z, int gz,
                                              int* __restrict__ zbin, int* __restrict__ count,
                                              int* __restrict__ fill) {
@@ -420,13 +421,15 @@ __device__ __forceinline__ void colsort_body(int col, const int* __restrict__ st
         }
         zrow[b] = lo + l;
     }
-    // clusters: 8 consecutive charges of the column (the last may be short)
+    // clusters: 8 consecutive charges of the column (the last may be short);
+    // the column is stored as its coordinates cx | cy << 16
     const int c0 = cstart[col], nclus = (cnt + 7) >> 3;
+    const int cyx = (col % ncx) | ((col / ncx) << 16);
     for (int k = t; k < nclus; k += 256) {
         const int b = lo + 8 * k;
         const int nk = min(8, cnt - 8 * k);
         cl_info[c0 + k] = make_int2(b, nk);
-        cl_col[c0 + k] = col;
+        cl_col[c0 + k] = cyx;
         cl_z[c0 + k] = in_lds ? make_uint2(skz[8 * k], skz[8 * k + nk - 1])
                               : make_uint2(sorted[b].z, sorted[b + nk - 1].z);
     }
@@ -439,11 +442,11 @@ __global__ void __launch_bounds__(256) k_colsort(const int* __restrict__ start,
                                                  int* __restrict__ perm,
                                                  uint4* __restrict__ sorted,
                                                  int2* __restrict__ cl_info,
-                                                 int* __restrict__ cl_col,
+                                                 int* __restrict__ cl_col, int ncx,
                                                  uint2* __restrict__ cl_z, int gz,
                                                  int* __restrict__ zbin, int* __restrict__ count,
                                                  int* __restrict__ fill) {
-    colsort_body(blockIdx.x, start, cstart, slots, coord, perm, sorted, cl_info, cl_col, cl_z, gz,
+    colsort_body(blockIdx.x, start, cstart, slots, coord, perm, sorted, cl_info, cl_col, ncx, cl_z, gz,
                  zbin, count, fill);
 }
 
@@ -452,7 +455,8 @@ __global__ void __launch_bounds__(256) k_colsort_batch(const BatchTable* __restr
     batch_for(tab, BK_COLSORT, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
         colsort_body(item, d.col_start, d.clus_start, d.slots, d.coord, d.perm, d.sorted,
-                     d.cl_info, d.cl_col, d.cl_z, d.grid.g[2], d.zbin, d.col_count, d.col_fill);
+                     d.cl_info, d.cl_col, d.bin.nc[0], d.cl_z, d.grid.g[2], d.zbin, d.col_count,
+                     d.col_fill);
     });
 }
 
@@ -491,12 +495,13 @@ hipError_t launch_scatter(const BinArgs& a, const uint4* coord, uint4* sorted, c
     return hipGetLastError();
 }
 
-hipError_t launch_colsort(int ncol, const int* col_start, const int* clus_start, const int* slots,
-                          const uint4* coord, int* perm, uint4* sorted, int2* cl_info,
-                          int* cl_col, uint2* cl_z, int gz, int* zbin, int* col_count,
-                          int* col_fill, hipStream_t st) {
+hipError_t launch_colsort(int ncol, int ncx, const int* col_start, const int* clus_start,
+                          const int* slots, const uint4* coord, int* perm, uint4* sorted,
+                          int2* cl_info, int* cl_col, uint2* cl_z, int gz, int* zbin,
+                          int* col_count, int* col_fill, hipStream_t st) {
     hipLaunchKernelGGL(k_colsort, dim3(ncol), dim3(256), 0, st, col_start, clus_start, slots,
-                       coord, perm, sorted, cl_info, cl_col, cl_z, gz, zbin, col_count, col_fill);
+                       coord, perm, sorted, cl_info, cl_col, ncx, cl_z, gz, zbin, col_count,
+                       col_fill);
     return hipGetLastError();
 }
 

@@ -64,7 +64,8 @@ struct Poly {
 };
 
 // column k of an axis window around the i-column ci and its minimum-image
-// distance (in columns) to ci; a full axis (few columns) is walked once
+// distance (in columns) to ci; a full axis (few columns) is walked once, else
+// the window has 2R + 1 < nc columns, so one wrap suffices
 struct StencilCol {
     int col, d;
 };
@@ -75,7 +76,7 @@ __device__ __forceinline__ StencilCol stencil_col(int k, int ci, int R, int nc, 
         if (2 * v < -nc) v += nc;
         return {k, v};
     }
-    return {wrapi(ci + k - R, nc), k - R};
+    return {wrap1(ci + k - R, nc), k - R};
 }
 
 }  // namespace
@@ -146,9 +147,9 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     }
     const Poly<DEG> P(a);
     const int2 ii = cl_info[I];
-    const int C = cl_col[I];
+    const int C = cl_col[I];                  // cx | cy << 16
     const uint2 zI = cl_z[I];
-    const int cx = C % ncx, cy = C / ncx;
+    const int cx = C & 0xffff, cy = C >> 16;
     const bool fullx = 2 * a.R[0] + 1 >= ncx, fully = 2 * a.R[1] + 1 >= ncy;
     const int nxs = fullx ? ncx : 2 * a.R[0] + 1, nys = fully ? ncy : 2 * a.R[1] + 1;
     const int NC = nxs * nys;
@@ -157,25 +158,30 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     // second only where the z window wraps)
     int rb0 = 0, n0 = 0, rb1 = 0, n1 = 0;
     if (tid < NC) {
-        const StencilCol sx = stencil_col(tid % nxs, cx, a.R[0], ncx, fullx);
-        const StencilCol sy = stencil_col(tid / nxs, cy, a.R[1], ncy, fully);
+        const int ky = small_div(tid, 1.0f / (float)nxs);   // tid < 128, nxs <= 128
+        const StencilCol sx = stencil_col(tid - ky * nxs, cx, a.R[0], ncx, fullx);
+        const StencilCol sy = stencil_col(ky, cy, a.R[1], ncy, fully);
         const int colx = sx.col, coly = sy.col, dx = sx.d, dy = sy.d;
         const float gx = (float)max(0, abs(dx) - 1) * a.cw[0];
         const float gy = (float)max(0, abs(dy) - 1) * a.cw[1];
         const float d2 = gx * gx + gy * gy;
         if (d2 < a.rc2) {
             // grid z-planes of the window [zI.x - rz, zI.y + rz] (fixed point,
-            // periodic), then the column's charges of those planes
-            const long long rz = (long long)(sqrtf(a.rc2 - d2) * a.zinv) + 2;
-            const long long plo = (((long long)zI.x - rz) * gz) >> 32;
-            const long long phi = (((long long)zI.y + rz) * gz) >> 32;
-            const int len = (int)(phi - plo) + 1;
+            // periodic; rz < 2^31 as r_c < L/2, widened by 1e-6 relative to
+            // cover the rounding of the square root and product), then the
+            // column's charges of those planes
+            const uint32_t rz =
+                (uint32_t)(__builtin_amdgcn_sqrtf(a.rc2 - d2) * a.zinv * 1.000001f) + 2u;
+            const uint32_t zlo = zI.x - rz, zhi = zI.y + rz;   // modulo 2^32: periodic
+            const int zs = (int)__umulhi(zlo, (uint32_t)gz);
+            const int zhp = (int)__umulhi(zhi, (uint32_t)gz);
+            const bool whole = (uint64_t)(zI.y - zI.x) + 2ull * rz >= (1ull << 32);
+            const int len = (zhi >= zlo ? zhp - zs : zhp + gz - zs) + 1;
             const int* zr = zbin + (size_t)(coly * ncx + colx) * (gz + 1);
-            if (len >= gz) {
+            if (whole || len >= gz) {
                 rb0 = zr[0];
                 n0 = zr[gz] - rb0;
             } else {
-                const int zs = (int)(plo < 0 ? plo + gz : (plo >= gz ? plo - gz : plo));
                 const int ze = zs + len;
                 rb0 = zr[zs];
                 if (ze <= gz) {

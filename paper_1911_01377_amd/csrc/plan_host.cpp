@@ -127,7 +127,8 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     for (int a = 0; a < 2; ++a) {
         const double h = box[a] / grid[a];
         const double wmin = std::max(0.25 * r_c, (8 + 2 * P - 1) * h / 14.0);
-        p.ncmax[a] = std::max(1, (int)std::floor(box[a] / wmin));
+        // at most 65535 per axis: a cluster's column is stored as cx | cy << 16
+        p.ncmax[a] = std::max(1, (int)std::min(65535.0, std::floor(box[a] / wmin)));
     }
     while ((int64_t)p.ncmax[0] * p.ncmax[1] > (1 << 20)) {
         const int am = p.ncmax[1] > p.ncmax[0] ? 1 : 0;

@@ -227,10 +227,11 @@ hipError_t launch_scatter(const BinArgs& a, const uint4* coord, uint4* sorted, c
                           int* col_start, int* clus_start, int* col_fill, int* slots,
                           const double* qpart, int nqpart, double* qstats, hipStream_t st);
 // also clears col_count and col_fill of the ncol columns
-hipError_t launch_colsort(int ncol, const int* col_start, const int* clus_start, const int* slots,
-                          const uint4* coord, int* perm, uint4* sorted, int2* cl_info,
-                          int* cl_col, uint2* cl_z, int gz, int* zbin, int* col_count,
-                          int* col_fill, hipStream_t st);
+// cl_col holds each cluster's column as cx | cy << 16 (ncx columns along x)
+hipError_t launch_colsort(int ncol, int ncx, const int* col_start, const int* clus_start,
+                          const int* slots, const uint4* coord, int* perm, uint4* sorted,
+                          int2* cl_info, int* cl_col, uint2* cl_z, int gz, int* zbin,
+                          int* col_count, int* col_fill, hipStream_t st);
 hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, const int* clus_start,
                        const int2* cl_info, const int* cl_col, const uint2* cl_z, const int* zbin,
                        float4* fnear, double* epart, hipStream_t st);
