@@ -46,7 +46,8 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 
-# algorithmic work per unit ("Measurement")
+# algorithmic work per unit: the near kernel's polynomial F and F'/r in r^2,
+# 1/r, the force vector and the energy add up to 45 flop per unique pair
 FLOP_PER_PAIR = 45.0          # near part: one unique pair within r_c
 FLOP_PER_SPREAD_POINT = 2.0   # one FMA per charge and stencil point
 FLOP_PER_GATHER_POINT = 8.0   # four FMAs (value + gradient) per charge and stencil point
@@ -170,9 +171,9 @@ def main():
                          "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the u-series hot path here is a single-GPU "
-              "build (see DESIGN.md for how it would shard); run with --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: this u-series library runs each evaluation "
+              "on one GPU (independent boxes would be spread over GPUs by the host); run "
+              "with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     # serving inputs are generated before the process touches the device
@@ -321,7 +322,7 @@ def main():
                 "kernel_ms": ktimes[dom], "algorithmic_flop": flop}
 
     # every kernel against its roofline: algorithmic flop and bytes per launch
-    # over the HIP-event time; for the convolutions also the MFMA
+    # (the counts below) over the HIP-event time; for the convolutions also the MFMA
     # work actually issued (padded tiles, three BF16 products per BF16X3 product)
     bf = args.form == "bf16x3"
     pad = 32 if bf else 16
