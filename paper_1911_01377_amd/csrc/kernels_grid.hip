@@ -388,15 +388,20 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
         const int t = base + tid;
         bool mine = false;
         uint4 c = make_uint4(0, 0, 0, 0);
-        int j = 0;
+        float4 fn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        int pj = 0;
         if (t < total) {
             int l = 0, h = np;
             while (h - l > 1) {
                 const int mid = (l + h) >> 1;
                 if (poff[mid] <= t) l = mid; else h = mid;
             }
-            j = pbeg[l] + (t - poff[l]);
+            const int j = pbeg[l] + (t - poff[l]);
+            // the near force and input index load with the record (most
+            // candidates are owners), saving a round trip after the ballot
             c = sorted[j];
+            fn = fnear[j];
+            pj = perm[j];
             const int gx = cell_coord(c.x, a.g[0]), gy = cell_coord(c.y, a.g[1]);
             mine = gx >= X0 && gx < X0 + B0 && gy >= Y0 && gy < Y0 + B1;
         }
@@ -412,8 +417,8 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
         if (mine) {
             const int slot = before + __popcll(m & ((1ull << lane) - 1ull));
             own[slot] = c;
-            ownf[slot] = fnear[j];
-            ownp[slot] = perm[j];
+            ownf[slot] = fn;
+            ownp[slot] = pj;
         }
         __syncthreads();
         // four owners per wavefront pass, groups dealt round-robin to the wavefronts
