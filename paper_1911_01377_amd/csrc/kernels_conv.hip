@@ -64,10 +64,53 @@ __device__ __forceinline__ f32x4 mfma3(u16x8 ah, u16x8 al, u16x8 bh, u16x8 bl, f
 
 }  // namespace
 
+// Both forms run blocks of eight wavefronts.  In each product wavefront w owns
+// the output tile column w mod n_tiles (and, when n_tiles divides 8, every
+// G-th of its strips, G = 8 / n_tiles) and keeps the matching fragments of
+// the constant matrix in registers for the whole item, loaded together with
+// the staging of the grid operand, so the MFMA loops read only LDS and
+// registers.
+constexpr int kConvWaves = 8;
+constexpr int kConvThreads = 64 * kConvWaves;
+
+// wavefronts sharing one output tile column when `tiles` divides kConvWaves
+// (they split that column's strips), else 1
+__host__ __device__ inline int tile_groups(int tiles) {
+    return (tiles <= kConvWaves && kConvWaves % tiles == 0) ? kConvWaves / tiles : 1;
+}
+
 // ------------------------------------------------------------------ FP32
 
-// plane z, term t; sp: the dynamic LDS (conv_xy_lds_bytes)
-__device__ __forceinline__ void conv_xy_f32_body(const ConvArgs& a, int z, int t, float* sp,
+// The contraction index of a 16x16x4 step is permuted so that every operand
+// is read as a float4: in k-chunk j (16 values) lane group lk supplies
+// k = 16 j + 4 lk + e at the chunk's step e = 0..3.
+constexpr int kMaxChunks = kMaxGrid / 16;
+
+struct Frag32 {
+    f32x4 v[kMaxChunks];
+};
+
+// rows tile*16 + li of the row-major gp x gp matrix m, in the chunk order above
+__device__ __forceinline__ void load_frag32(Frag32& f, const float* __restrict__ m, int gp,
+                                            int tile, int li, int lk) {
+#pragma unroll
+    for (int j = 0; j < kMaxChunks; ++j)
+        if (16 * j < gp)
+            f.v[j] = *reinterpret_cast<const f32x4*>(m + (size_t)(tile * 16 + li) * gp + 16 * j +
+                                                     4 * lk);
+}
+
+__device__ __forceinline__ f32x4 mfma_chunk(f32x4 a, f32x4 b, f32x4 c) {
+    c = mfma4(a[0], b[0], c);
+    c = mfma4(a[1], b[1], c);
+    c = mfma4(a[2], b[2], c);
+    return mfma4(a[3], b[3], c);
+}
+
+// plane z, term t; smem: the dynamic LDS (conv_xy_lds_bytes).  The plane is
+// staged as [y][x]; U = rho Kx is kept transposed ([x][y]) so that both
+// products read their LDS operand along the contraction index.
+__device__ __forceinline__ void conv_xy_f32_body(const ConvArgs& a, int z, int t, float* smem,
                                                  const float* __restrict__ rho,
                                                  const float* __restrict__ kx,
                                                  const float* __restrict__ ky,
@@ -75,103 +118,171 @@ __device__ __forceinline__ void conv_xy_f32_body(const ConvArgs& a, int z, int t
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int li = l & 15, lk = l >> 4;
     const int g0 = a.g[0], g1 = a.g[1], p0 = a.gp[0], p1 = a.gp[1];
-    const int ld = p0 + 4;
+    const int ld = (p0 > p1 ? p0 : p1) + 4;     // floats per LDS row
+    float* rp = smem;                            // [p1][ld] rho plane
+    float* ut = rp + p1 * ld;                    // [p0][ld] U^T
+    const int tx_n = p0 / 16, ty_n = p1 / 16;
+    const int G1 = tile_groups(tx_n), G2 = tile_groups(ty_n);
+    const bool act1 = w < tx_n * G1, act2 = w < ty_n * G2;
+    const int tx = w % tx_n, s0 = w / tx_n;      // U = rho Kx: column tile, first strip
+    const int ty = w % ty_n, c0 = w / ty_n;      // T = Ky U: row tile, first column strip
+    // B of U = rho Kx: Kx[j][k] (Kx symmetric); A of T = Ky U: Ky rows
+    Frag32 bx, ay;
+    if (act1) load_frag32(bx, kx + (size_t)p0 * p0 * t, p0, tx, li, lk);
+    if (act2) load_frag32(ay, ky + (size_t)p1 * p1 * t, p1, ty, li, lk);
     const float* src = rho + (size_t)z * g1 * g0;
     const float ip0 = 1.0f / (float)p0;
     // the loads of a pass are issued together, then stored
-    for (int base = threadIdx.x; base < p1 * p0; base += 256 * kStageBatch) {
+    for (int base = threadIdx.x; base < p1 * p0; base += kConvThreads * kStageBatch) {
         float v[kStageBatch];
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u) {
-            const int idx = base + 256 * u;
+            const int idx = base + kConvThreads * u;
             const int y = small_div(idx, ip0), x = idx - y * p0;
             v[u] = (idx < p1 * p0 && y < g1 && x < g0) ? src[y * g0 + x] : 0.0f;
         }
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u) {
-            const int idx = base + 256 * u;
+            const int idx = base + kConvThreads * u;
             const int y = small_div(idx, ip0), x = idx - y * p0;
-            if (idx < p1 * p0) sp[y * ld + x] = v[u];
+            if (idx < p1 * p0) rp[y * ld + x] = v[u];
         }
     }
     __syncthreads();
-    const float* Kx = kx + (size_t)t * p0 * p0;
-    const float* Ky = ky + (size_t)t * p1 * p1;
-    const int tx_n = p0 / 16, ty_n = p1 / 16;
-    // U = rho[z] Kx, one 16-row strip per wave, written back in place
-    for (int s = w; s < ty_n; s += 4) {
-        f32x4 acc[kMaxTiles];
-        for (int tx = 0; tx < tx_n; ++tx) acc[tx] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int k0 = 0; k0 < p0; k0 += 4) {
-            const float av = sp[(s * 16 + li) * ld + k0 + lk];
-            const float* kr = Kx + (size_t)(k0 + lk) * p0 + li;
-            for (int tx = 0; tx < tx_n; ++tx) acc[tx] = mfma4(av, kr[tx * 16], acc[tx]);
+    if (act1)
+        for (int s = s0; s < ty_n; s += G1) {
+            f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            const float* ar = rp + (s * 16 + li) * ld + 4 * lk;
+#pragma unroll
+            for (int j = 0; j < kMaxChunks; ++j)
+                if (16 * j < p0)
+                    acc = mfma_chunk(*reinterpret_cast<const f32x4*>(ar + 16 * j), bx.v[j], acc);
+            // acc[r] = U[s*16 + 4 lk + r][tx*16 + li]
+            *reinterpret_cast<f32x4*>(ut + (tx * 16 + li) * ld + s * 16 + 4 * lk) = acc;
         }
-        for (int tx = 0; tx < tx_n; ++tx)
-            for (int r = 0; r < 4; ++r) sp[(s * 16 + 4 * lk + r) * ld + tx * 16 + li] = acc[tx][r];
-    }
     __syncthreads();
-    // T = Ky U, one 16-column strip per wave
     float* dst = tgrid + ((size_t)t * a.g[2] + z) * g1 * g0;
-    for (int c = w; c < tx_n; c += 4) {
-        f32x4 acc[kMaxTiles];
-        for (int ty = 0; ty < ty_n; ++ty) acc[ty] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int k0 = 0; k0 < p1; k0 += 4) {
-            const float bv = sp[(k0 + lk) * ld + c * 16 + li];
-            const float* kr = Ky + (size_t)li * p1 + k0 + lk;
-            for (int ty = 0; ty < ty_n; ++ty) acc[ty] = mfma4(kr[ty * 16 * p1], bv, acc[ty]);
-        }
-        const int x = c * 16 + li;
-        for (int ty = 0; ty < ty_n; ++ty)
+    if (act2)
+        for (int c = c0; c < tx_n; c += G2) {
+            f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            const float* br = ut + (c * 16 + li) * ld + 4 * lk;
+#pragma unroll
+            for (int j = 0; j < kMaxChunks; ++j)
+                if (16 * j < p1)
+                    acc = mfma_chunk(ay.v[j], *reinterpret_cast<const f32x4*>(br + 16 * j), acc);
+            const int x = c * 16 + li;
+#pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int y = ty * 16 + 4 * lk + r;
-                if (y < g1 && x < g0) dst[y * g0 + x] = acc[ty][r];
+                if (y < g1 && x < g0) dst[y * g0 + x] = acc[r];
             }
-    }
+        }
 }
 
-__device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid,
+// wavefront groups of a conv_z block (each takes every G-th term)
+__host__ __device__ inline int conv_z_groups(const ConvArgs& a) {
+    return tile_groups(a.gp[2] / 16);
+}
+
+// terms whose columns the FP32 conv_z stages in LDS at once: all of them when
+// they fit in 80 KiB, else the largest multiple of the group count that does
+__host__ __device__ inline int conv_z_f32_chunk(const ConvArgs& a) {
+    const int per = 16 * (a.gp[2] + 4) * (int)sizeof(float);
+    const int G = conv_z_groups(a);
+    int tc = (80 * 1024) / per;
+    if (tc >= a.nterms) return a.nterms;
+    tc -= tc % G;
+    return tc > 0 ? tc : 1;
+}
+
+// wavefront partial sums of groups 1 .. G-1 added to group 0's, in group order
+__device__ __forceinline__ f32x4 conv_z_reduce(f32x4 acc, float* smem, bool act, int grp, int G,
+                                               int tz, int tz_n, int l) {
+    __syncthreads();
+    f32x4* red = reinterpret_cast<f32x4*>(smem);
+    if (act && grp > 0) red[((grp - 1) * tz_n + tz) * 64 + l] = acc;
+    __syncthreads();
+    if (act && grp == 0)
+        for (int g = 1; g < G; ++g) {
+            const f32x4 o = red[((g - 1) * tz_n + tz) * 64 + l];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] += o[r];
+        }
+    return acc;
+}
+
+// phi[:, c] = sum_t Kz_t T_t[:, c] for the block's 16 grid columns c.  The
+// columns of a chunk of terms are staged transposed ([t][col][z']); the
+// wavefronts form G groups, in a group wavefront w owns row tile w mod n_tiles
+// and the group takes the chunk's terms grp, grp + G, ..., loading the Kz
+// fragment of its next term while it multiplies the current one.
+__device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid, float* smem,
                                                 const float* __restrict__ tgrid,
                                                 const float* __restrict__ kz,
                                                 float* __restrict__ phi) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int li = l & 15, lk = l >> 4;
-    const int g2 = a.g[2], p2 = a.gp[2];
+    const int g2 = a.g[2], p2 = a.gp[2], ld = p2 + 4;
     const int ncol = a.g[0] * a.g[1];
-    const int col = bid * 16 + li;
-    const int tz_n = p2 / 16;
-    f32x4 acc[kMaxTiles / 4];
-    for (int m = 0; m < kMaxTiles / 4; ++m) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int t = 0; t < a.nterms; ++t) {
-        const float* T = tgrid + (size_t)t * g2 * ncol;
-        const float* Kz = kz + (size_t)t * p2 * p2;
-        for (int k0 = 0; k0 < p2; k0 += 4) {
-            const int zp = k0 + lk;
-            const float bv = (zp < g2 && col < ncol) ? T[(size_t)zp * ncol + col] : 0.0f;
-            for (int m = 0, tz = w; tz < tz_n; ++m, tz += 4)
-                acc[m] = mfma4(Kz[(size_t)(tz * 16 + li) * p2 + zp], bv, acc[m]);
+    const int tz_n = p2 / 16, G = conv_z_groups(a);
+    const int cb = bid * 16;
+    const bool act = w < tz_n * G;
+    const int tz = w % tz_n, grp = w / tz_n;
+    const size_t mz = (size_t)p2 * p2;
+    const int tc = conv_z_f32_chunk(a);
+    const float ip2 = 1.0f / (float)p2;
+    f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t0 = 0; t0 < a.nterms; t0 += tc) {
+        const int nt = (a.nterms - t0 < tc) ? a.nterms - t0 : tc;
+        Frag32 cur, nxt;
+        if (act && grp < nt) load_frag32(cur, kz + mz * (t0 + grp), p2, tz, li, lk);
+        if (t0 > 0) __syncthreads();     // the previous chunk's columns are consumed
+        const int nst = nt * 16 * p2;
+        for (int base = threadIdx.x; base < nst; base += kConvThreads * kStageBatchZ) {
+            float v[kStageBatchZ];
+#pragma unroll
+            for (int u = 0; u < kStageBatchZ; ++u) {
+                const int r = base + kConvThreads * u;
+                const int q = r >> 4, c = r & 15;          // q = t p2 + z'
+                const int t = small_div(q, ip2), zp = q - t * p2;
+                v[u] = (r < nst && zp < g2 && cb + c < ncol)
+                           ? tgrid[((size_t)(t0 + t) * g2 + zp) * ncol + cb + c]
+                           : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kStageBatchZ; ++u) {
+                const int r = base + kConvThreads * u;
+                const int q = r >> 4, c = r & 15;
+                const int t = small_div(q, ip2), zp = q - t * p2;
+                if (r < nst) smem[(t * 16 + c) * ld + zp] = v[u];
+            }
         }
+        __syncthreads();
+        if (act)
+            for (int t = grp; t < nt; t += G) {
+                if (t + G < nt) load_frag32(nxt, kz + mz * (t0 + t + G), p2, tz, li, lk);
+                const float* br = smem + (t * 16 + li) * ld + 4 * lk;
+#pragma unroll
+                for (int j = 0; j < kMaxChunks; ++j)
+                    if (16 * j < p2)
+                        acc = mfma_chunk(cur.v[j], *reinterpret_cast<const f32x4*>(br + 16 * j), acc);
+                cur = nxt;
+            }
     }
-    for (int m = 0, tz = w; tz < tz_n; ++m, tz += 4)
-        for (int r = 0; r < 4; ++r) {
-            const int zz = tz * 16 + 4 * lk + r;
-            if (zz < g2 && col < ncol) phi[(size_t)zz * ncol + col] = acc[m][r];
-        }
+    if (G > 1) acc = conv_z_reduce(acc, smem, act, grp, G, tz, tz_n, l);
+    if (!act || grp != 0) return;
+    const int col = cb + li;
+    for (int r = 0; r < 4; ++r) {
+        const int zz = tz * 16 + 4 * lk + r;
+        if (zz < g2 && col < ncol) phi[(size_t)zz * ncol + col] = acc[r];
+    }
 }
 
 // ------------------------------------------------------------------ BF16X3
 
 // kx/ky/kz hold, per term, the hi matrix followed by the lo matrix (bf16 bits).
 //
-constexpr int kBfWaves = 8;
-constexpr int kBfThreads = 64 * kBfWaves;
 constexpr int kMaxKSteps = kMaxGrid / 32;   // K steps of 32 (BF16 MFMA)
-
-// wavefronts sharing one output tile column when `tiles` divides kBfWaves
-// (they split that column's strips), else 1
-__host__ __device__ inline int tile_groups(int tiles) {
-    return (tiles <= kBfWaves && kBfWaves % tiles == 0) ? kBfWaves / tiles : 1;
-}
 
 struct Frag {
     u16x8 h[kMaxKSteps], l[kMaxKSteps];
@@ -192,11 +303,6 @@ __device__ __forceinline__ void load_frag(Frag& f, const unsigned short* __restr
     }
 }
 
-// Blocks of eight wavefronts.  In each product wavefront w owns the output
-// tile column w mod n_tiles (and, when n_tiles divides 8, every G-th of its
-// strips, G = 8 / n_tiles) and keeps the matching fragments of the constant
-// matrix in registers for the whole item, loaded together with the staging
-// of the plane, so the MFMA loops read only LDS and registers.
 __device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int t, float* smem,
                                                   const float* __restrict__ rho,
                                                   const unsigned short* __restrict__ kx,
@@ -223,17 +329,17 @@ __device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int 
     const float* src = rho + (size_t)z * g1 * g0;
     const float ip0 = 1.0f / (float)p0;
     // the loads of a pass are issued together, then split and stored
-    for (int base = threadIdx.x; base < p1 * p0; base += kBfThreads * kStageBatch) {
+    for (int base = threadIdx.x; base < p1 * p0; base += kConvThreads * kStageBatch) {
         float v[kStageBatch];
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u) {
-            const int idx = base + kBfThreads * u;
+            const int idx = base + kConvThreads * u;
             const int y = small_div(idx, ip0), x = idx - y * p0;
             v[u] = (idx < p1 * p0 && y < g1 && x < g0) ? src[y * g0 + x] : 0.0f;
         }
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u) {
-            const int idx = base + kBfThreads * u;
+            const int idx = base + kConvThreads * u;
             const int y = small_div(idx, ip0), x = idx - y * p0;
             if (idx < p1 * p0) {
                 unsigned short h, lo;
@@ -290,11 +396,6 @@ __device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int 
         }
 }
 
-// wavefront groups of a conv_z block (each takes every G-th term)
-__host__ __device__ inline int conv_z_groups(const ConvArgs& a) {
-    return a.bf16x3 ? tile_groups(a.gp[2] / 16) : 1;
-}
-
 // phi[:, c] = sum_t Kz_t T_t[:, c] for the block's 16 grid columns c.  Every
 // term's columns are staged (transposed to [col][z'], split) at once.  The
 // wavefronts form G groups; in a group wavefront w owns row tile w mod n_tiles
@@ -321,11 +422,11 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
         load_frag(cur, kz + 2 * mz * grp, kz + 2 * mz * grp + mz, p2, tz, li, lk);
     // the loads of a pass (over all terms) are issued together, then split and stored
     const int nst = a.nterms * 16 * p2;
-    for (int base = threadIdx.x; base < nst; base += kBfThreads * kStageBatchZ) {
+    for (int base = threadIdx.x; base < nst; base += kConvThreads * kStageBatchZ) {
         float v[kStageBatchZ];
 #pragma unroll
         for (int u = 0; u < kStageBatchZ; ++u) {
-            const int r = base + kBfThreads * u;
+            const int r = base + kConvThreads * u;
             const int tz_ = r >> 4, c = r & 15;          // tz_ = t p2 + z'
             const int t = small_div(tz_, 1.0f / (float)p2), zp = tz_ - t * p2;
             v[u] = (r < nst && zp < g2 && c0 + c < ncol)
@@ -334,7 +435,7 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
         }
 #pragma unroll
         for (int u = 0; u < kStageBatchZ; ++u) {
-            const int r = base + kBfThreads * u;
+            const int r = base + kConvThreads * u;
             const int tz_ = r >> 4, c = r & 15;
             const int t = small_div(tz_, 1.0f / (float)p2), zp = tz_ - t * p2;
             if (r < nst) {
@@ -364,19 +465,7 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
             cur = nxt;
         }
     }
-    if (G > 1) {
-        // partial sums of groups 1 .. G-1: [grp-1][tz][lane][4], summed in group order
-        __syncthreads();
-        f32x4* red = reinterpret_cast<f32x4*>(smem);
-        if (act && grp > 0) red[((grp - 1) * tz_n + tz) * 64 + l] = acc;
-        __syncthreads();
-        if (act && grp == 0)
-            for (int g = 1; g < G; ++g) {
-                const f32x4 o = red[((g - 1) * tz_n + tz) * 64 + l];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r] += o[r];
-            }
-    }
+    if (G > 1) acc = conv_z_reduce(acc, smem, act, grp, G, tz, tz_n, l);
     if (!act || grp != 0) return;
     const int col = c0 + li;
     for (int r = 0; r < 4; ++r) {
@@ -387,7 +476,7 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
 
 // ------------------------------------------------------------------ kernels
 
-__global__ void __launch_bounds__(256) k_conv_xy_f32(ConvArgs a, const float* __restrict__ rho,
+__global__ void __launch_bounds__(kConvThreads) k_conv_xy_f32(ConvArgs a, const float* __restrict__ rho,
                                                      const float* __restrict__ kx,
                                                      const float* __restrict__ ky,
                                                      float* __restrict__ tgrid) {
@@ -395,13 +484,15 @@ __global__ void __launch_bounds__(256) k_conv_xy_f32(ConvArgs a, const float* __
     conv_xy_f32_body(a, blockIdx.x, blockIdx.y, dyn_lds, rho, kx, ky, tgrid);
 }
 
-__global__ void __launch_bounds__(256) k_conv_z_f32(ConvArgs a, const float* __restrict__ tgrid,
-                                                    const float* __restrict__ kz,
-                                                    float* __restrict__ phi) {
-    conv_z_f32_body(a, blockIdx.x, tgrid, kz, phi);
+__global__ void __launch_bounds__(kConvThreads) k_conv_z_f32(ConvArgs a,
+                                                             const float* __restrict__ tgrid,
+                                                             const float* __restrict__ kz,
+                                                             float* __restrict__ phi) {
+    extern __shared__ float dyn_lds[];
+    conv_z_f32_body(a, blockIdx.x, dyn_lds, tgrid, kz, phi);
 }
 
-__global__ void __launch_bounds__(kBfThreads) k_conv_xy_bf16(ConvArgs a, const float* __restrict__ rho,
+__global__ void __launch_bounds__(kConvThreads) k_conv_xy_bf16(ConvArgs a, const float* __restrict__ rho,
                                                       const unsigned short* __restrict__ kx,
                                                       const unsigned short* __restrict__ ky,
                                                       float* __restrict__ tgrid) {
@@ -409,7 +500,7 @@ __global__ void __launch_bounds__(kBfThreads) k_conv_xy_bf16(ConvArgs a, const f
     conv_xy_bf16_body(a, blockIdx.x, blockIdx.y, dyn_lds, rho, kx, ky, tgrid);
 }
 
-__global__ void __launch_bounds__(kBfThreads) k_conv_z_bf16(ConvArgs a, const float* __restrict__ tgrid,
+__global__ void __launch_bounds__(kConvThreads) k_conv_z_bf16(ConvArgs a, const float* __restrict__ tgrid,
                                                      const unsigned short* __restrict__ kz,
                                                      float* __restrict__ phi) {
     extern __shared__ float dyn_lds[];
@@ -418,7 +509,7 @@ __global__ void __launch_bounds__(kBfThreads) k_conv_z_bf16(ConvArgs a, const fl
 
 // batched: item = t * g_z + z (conv_xy), 16-column group (conv_z)
 template <int BF16>
-__global__ void __launch_bounds__(BF16 ? kBfThreads : 256) k_conv_xy_batch(const BatchTable* __restrict__ tab,
+__global__ void __launch_bounds__(kConvThreads) k_conv_xy_batch(const BatchTable* __restrict__ tab,
                                                        const BoxDesc* __restrict__ desc) {
     extern __shared__ float dyn_lds[];
     batch_for(tab, BK_CONV_XY, [&](int i, int item) {
@@ -435,7 +526,7 @@ __global__ void __launch_bounds__(BF16 ? kBfThreads : 256) k_conv_xy_batch(const
 }
 
 template <int BF16>
-__global__ void __launch_bounds__(BF16 ? kBfThreads : 256) k_conv_z_batch(const BatchTable* __restrict__ tab,
+__global__ void __launch_bounds__(kConvThreads) k_conv_z_batch(const BatchTable* __restrict__ tab,
                                                       const BoxDesc* __restrict__ desc) {
     extern __shared__ float dyn_lds[];
     batch_for(tab, BK_CONV_Z, [&](int i, int item) {
@@ -444,7 +535,7 @@ __global__ void __launch_bounds__(BF16 ? kBfThreads : 256) k_conv_z_batch(const 
             conv_z_bf16_body(d.conv, item, dyn_lds, d.tgrid,
                              reinterpret_cast<const unsigned short*>(d.kz), d.phi);
         else
-            conv_z_f32_body(d.conv, item, d.tgrid, d.kz, d.phi);
+            conv_z_f32_body(d.conv, item, dyn_lds, d.tgrid, d.kz, d.phi);
     });
 }
 
@@ -455,12 +546,14 @@ size_t conv_xy_lds_bytes(const ConvArgs& a) {
         const int ldb = (a.gp[0] > a.gp[1] ? a.gp[0] : a.gp[1]) + 8;
         return (size_t)2 * ldb * (a.gp[0] + a.gp[1]) * sizeof(unsigned short);
     }
-    return (size_t)a.gp[1] * (a.gp[0] + 4) * sizeof(float);
+    const int ld = (a.gp[0] > a.gp[1] ? a.gp[0] : a.gp[1]) + 4;
+    return (size_t)ld * (a.gp[0] + a.gp[1]) * sizeof(float);
 }
 
 size_t conv_z_lds_bytes(const ConvArgs& a) {
-    if (!a.bf16x3) return 0;
-    const size_t stage = (size_t)2 * a.nterms * 16 * (a.gp[2] + 8) * sizeof(unsigned short);
+    const size_t stage =
+        a.bf16x3 ? (size_t)2 * a.nterms * 16 * (a.gp[2] + 8) * sizeof(unsigned short)
+                 : (size_t)conv_z_f32_chunk(a) * 16 * (a.gp[2] + 4) * sizeof(float);
     const size_t red = (size_t)(conv_z_groups(a) - 1) * (a.gp[2] / 16) * 64 * 4 * sizeof(float);
     return stage > red ? stage : red;
 }
@@ -471,12 +564,12 @@ hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx, 
                           float* tgrid, hipStream_t st) {
     const size_t lds = conv_xy_lds_bytes(a);
     if (a.bf16x3)
-        hipLaunchKernelGGL(k_conv_xy_bf16, dim3(a.g[2], a.nterms), dim3(kBfThreads), lds, st, a, rho,
+        hipLaunchKernelGGL(k_conv_xy_bf16, dim3(a.g[2], a.nterms), dim3(kConvThreads), lds, st, a, rho,
                            reinterpret_cast<const unsigned short*>(kx),
                            reinterpret_cast<const unsigned short*>(ky), tgrid);
     else
-        hipLaunchKernelGGL(k_conv_xy_f32, dim3(a.g[2], a.nterms), dim3(256), lds, st, a, rho, kx,
-                           ky, tgrid);
+        hipLaunchKernelGGL(k_conv_xy_f32, dim3(a.g[2], a.nterms), dim3(kConvThreads), lds, st, a,
+                           rho, kx, ky, tgrid);
     return hipGetLastError();
 }
 
@@ -484,28 +577,29 @@ hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz,
                          hipStream_t st) {
     const int nb = conv_z_blocks(a);
     if (a.bf16x3)
-        hipLaunchKernelGGL(k_conv_z_bf16, dim3(nb), dim3(kBfThreads), conv_z_lds_bytes(a), st, a,
+        hipLaunchKernelGGL(k_conv_z_bf16, dim3(nb), dim3(kConvThreads), conv_z_lds_bytes(a), st, a,
                            tgrid, reinterpret_cast<const unsigned short*>(kz), phi);
     else
-        hipLaunchKernelGGL(k_conv_z_f32, dim3(nb), dim3(256), 0, st, a, tgrid, kz, phi);
+        hipLaunchKernelGGL(k_conv_z_f32, dim3(nb), dim3(kConvThreads), conv_z_lds_bytes(a), st, a,
+                           tgrid, kz, phi);
     return hipGetLastError();
 }
 
 hipError_t launch_conv_xy_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3,
                                 size_t lds, int grid, hipStream_t st) {
     if (bf16x3)
-        hipLaunchKernelGGL(k_conv_xy_batch<1>, dim3(grid), dim3(kBfThreads), lds, st, tab, desc);
+        hipLaunchKernelGGL(k_conv_xy_batch<1>, dim3(grid), dim3(kConvThreads), lds, st, tab, desc);
     else
-        hipLaunchKernelGGL(k_conv_xy_batch<0>, dim3(grid), dim3(256), lds, st, tab, desc);
+        hipLaunchKernelGGL(k_conv_xy_batch<0>, dim3(grid), dim3(kConvThreads), lds, st, tab, desc);
     return hipGetLastError();
 }
 
 hipError_t launch_conv_z_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3, size_t lds,
                                int grid, hipStream_t st) {
     if (bf16x3)
-        hipLaunchKernelGGL(k_conv_z_batch<1>, dim3(grid), dim3(kBfThreads), lds, st, tab, desc);
+        hipLaunchKernelGGL(k_conv_z_batch<1>, dim3(grid), dim3(kConvThreads), lds, st, tab, desc);
     else
-        hipLaunchKernelGGL(k_conv_z_batch<0>, dim3(grid), dim3(256), 0, st, tab, desc);
+        hipLaunchKernelGGL(k_conv_z_batch<0>, dim3(grid), dim3(kConvThreads), lds, st, tab, desc);
     return hipGetLastError();
 }
 
