@@ -8,7 +8,8 @@ N = 4 far terms), inputs resident in HBM.
 
 Prints one JSON line:
   value        evaluations/s of the chosen form (default: BF16X3 convolutions,
-               6^3 spreading stencil; --form plain for the FP32 path), back to back
+               6^3 spreading stencil, degree-5 near polynomials; --form plain for
+               the FP32 path), back to back
                on one stream (the rate of one evaluation captured in a HIP graph
                and replayed is reported beside it: slower here);
   batched_copies  evaluations/s with B copies of the box submitted together to
@@ -46,9 +47,15 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 
-# algorithmic work per unit: the near kernel's polynomial F and F'/r in r^2,
-# 1/r, the force vector and the energy add up to 45 flop per unique pair
-FLOP_PER_PAIR = 45.0          # near part: one unique pair within r_c
+# algorithmic work per unit.  Near part, per unique pair within r_c: the two
+# Horner polynomials F and F'/r of degree d in r^2 (4 d flop) plus 17 flop
+# for the distance, r^2, 1/r, the energy and the force vector.
+def flop_per_pair(degree):
+    return 4.0 * degree + 17.0
+
+
+# near polynomial degree of each form (the library's defaults, passed explicitly)
+POLY_DEGREE = {"bf16x3": 5, "plain": 7}
 FLOP_PER_SPREAD_POINT = 2.0   # one FMA per charge and stencil point
 FLOP_PER_GATHER_POINT = 8.0   # four FMAs (value + gradient) per charge and stencil point
 
@@ -240,7 +247,8 @@ def main():
         return t0.elapsed_time(t1) / steps
 
     forms = {"bf16x3": USERIES_BF16X3, "plain": USERIES_PLAIN_FP32}
-    plans = {k: Plan(box, rc, grid, precision=v) for k, v in forms.items()}
+    plans = {k: Plan(box, rc, grid, precision=v, poly_degree=POLY_DEGREE[k])
+             for k, v in forms.items()}
     results, graphed = {}, {}
     for k, plan in plans.items():
         results[k] = timed(plan, args.steps, args.warmup)
@@ -299,7 +307,7 @@ def main():
     npairs = count_pairs(xyz, np.array(box), rc)
     G = grid[0] * grid[1] * grid[2]
     work = {
-        "pair": ("alu", npairs * FLOP_PER_PAIR, PEAK_FP32_TFLOPS),
+        "pair": ("alu", npairs * flop_per_pair(POLY_DEGREE[args.form]), PEAK_FP32_TFLOPS),
         "spread": ("alu", n * (2 * P) ** 3 * FLOP_PER_SPREAD_POINT, PEAK_FP32_TFLOPS),
         "gather": ("alu", n * (2 * P) ** 3 * FLOP_PER_GATHER_POINT, PEAK_FP32_TFLOPS),
         "conv_xy": ("mfma", 2.0 * nt * G * (grid[0] + grid[1]),
@@ -440,7 +448,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "water box, 8756 3-site waters = 26268 charges, L=64 A, "
                                "r_c=9 A, 64^3 grid, b=2 C1, N=%d" % info["n_terms"],
-                   "form": args.form, "stencil": "%d^3" % (2 * P)},
+                   "form": args.form, "stencil": "%d^3" % (2 * P),
+                   "near_poly_degree": POLY_DEGREE[args.form]},
         "timing": "back-to-back evaluations on one stream (eager launches), HIP events",
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "what": "one synchronised evaluation, host wall clock"},

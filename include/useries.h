@@ -85,8 +85,10 @@ enum {
  *                    choose N when useries_plan gets n_terms <= 0.
  *   poly_degree      degree in r^2 of the polynomials that represent the
  *                    infinite far series F and F'(r)/r inside the cutoff
- *                    (near part); <= 0 picks 7 (fit error ~4e-8 of max |F|,
- *                    FP32 level).  4 <= degree <= 14.
+ *                    (near part); <= 0 picks the default of the precision:
+ *                    7 plain (fit error ~7e-8 of max |F|, FP32 level), 5
+ *                    BF16X3 (~2e-5, well inside that form's 1e-3 budget).
+ *                    4 <= degree <= 14.
  *   max_atoms        workspace capacity in charges; <= 0 grows on demand
  *                    (a growth reallocates and synchronises the device).
  */
@@ -162,12 +164,15 @@ int useries_eval_parts(useries_plan_t plan, int64_t n, const float *xyz, const f
  *   column grid used by the latest evaluation, chosen per evaluation from
  *   the number of charges; third entry 1; zeros before the first
  *   evaluation), poly_maxerr (max relative error of the near polynomial on
- *   [0, r_c], measured in FP64 on the host).
+ *   [0, r_c], measured in FP64 on the host), n_terms_grid (the leading far
+ *   terms evaluated on the grid: a term whose periodised Gaussian has every
+ *   non-zero Fourier mode below 2^-60 of its k = 0 mode is, to double
+ *   precision, only that mode, which the far part removes, so it is skipped).
  */
 int useries_plan_info(useries_plan_t plan, double *b, double *sigma, double *r0, double *w0,
                       double *s0, int *n_terms, double *eq33, double *f_inf0,
                       double *c1_slope, double *sigma_s, int *stencil_half, int ncell[3],
-                      double *poly_maxerr);
+                      double *poly_maxerr, int *n_terms_grid);
 
 /* Release a plan and its device memory.  The caller must ensure that no
  * evaluation on it is still running. */
@@ -252,7 +257,7 @@ typedef struct {
 /*
  * Server options (useries_server_default_opts fills the defaults).
  *   construction, b, nterms_tol, poly_degree: as in useries_opts / useries_plan
- *              (defaults C1, b = 2, 1e-8, 7).
+ *              (defaults C1, b = 2, 1e-8, 0 = the precision's degree).
  *   use_graph  1: one captured HIP graph per step (default); 0: the same
  *              kernels launched one by one.
  *   inflight   steps enqueued ahead of the device (1..4, default 2).

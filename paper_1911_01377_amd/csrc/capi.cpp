@@ -243,7 +243,7 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
         (e = dalloc(&p->qstats, 2)) ||
         (e = dalloc(&p->gather_parts, (size_t)gather_blocks(hp.gridargs))) ||
         (e = dalloc(&p->parts_tmp, 5)) || (e = dalloc(&p->rho, ng)) ||
-        (e = dalloc(&p->tgrid, ng * hp.nterms)) || (e = dalloc(&p->phi, ng))) {
+        (e = dalloc(&p->tgrid, ng * hp.conv.nterms)) || (e = dalloc(&p->phi, ng))) {
         delete p;
         return fail(USERIES_ENOMEM, std::string("plan allocation: ") + hipGetErrorString(e));
     }
@@ -357,7 +357,8 @@ int useries_eval_parts(useries_plan_t p, int64_t n, const float* xyz, const floa
 
 int useries_plan_info(useries_plan_t p, double* b, double* sigma, double* r0, double* w0,
                       double* s0, int* n_terms, double* eq33, double* f_inf0, double* c1_slope,
-                      double* sigma_s, int* stencil_half, int ncell[3], double* poly_maxerr) {
+                      double* sigma_s, int* stencil_half, int ncell[3], double* poly_maxerr,
+                      int* n_terms_grid) {
     if (!p) return fail(USERIES_EINVAL, "NULL plan");
     const HostPlan& hp = p->hp;
     if (b) *b = hp.b;
@@ -377,6 +378,7 @@ int useries_plan_info(useries_plan_t p, double* b, double* sigma, double* r0, do
         ncell[2] = 1;
     }
     if (poly_maxerr) *poly_maxerr = hp.poly_maxerr;
+    if (n_terms_grid) *n_terms_grid = hp.conv.nterms;
     return USERIES_OK;
 }
 

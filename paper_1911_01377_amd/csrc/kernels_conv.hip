@@ -184,12 +184,14 @@ __host__ __device__ inline int conv_z_groups(const ConvArgs& a) {
     return tile_groups(a.gp[2] / 16);
 }
 
-// terms whose columns the FP32 conv_z stages in LDS at once: all of them when
-// they fit in 80 KiB, else the largest multiple of the group count that does
-__host__ __device__ inline int conv_z_f32_chunk(const ConvArgs& a) {
-    const int per = 16 * (a.gp[2] + 4) * (int)sizeof(float);
+// Terms whose 16 columns a conv_z block stages in LDS at once: all of them
+// when they fit in 20 KiB, else the largest multiple of the group count that
+// does (at least one).  A staged column takes 4 bytes per z' in both forms
+// (FP32, or BF16 hi + lo), rows padded by 4 (FP32) or 8 (BF16) values.
+__host__ __device__ inline int conv_z_chunk(const ConvArgs& a) {
+    const int per = 16 * (a.gp[2] + (a.bf16x3 ? 8 : 4)) * 4;
     const int G = conv_z_groups(a);
-    int tc = (80 * 1024) / per;
+    int tc = (20 * 1024) / per;
     if (tc >= a.nterms) return a.nterms;
     tc -= tc % G;
     return tc > 0 ? tc : 1;
@@ -229,7 +231,7 @@ __device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid, floa
     const bool act = w < tz_n * G;
     const int tz = w % tz_n, grp = w / tz_n;
     const size_t mz = (size_t)p2 * p2;
-    const int tc = conv_z_f32_chunk(a);
+    const int tc = conv_z_chunk(a);
     const float ip2 = 1.0f / (float)p2;
     f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int t0 = 0; t0 < a.nterms; t0 += tc) {
@@ -396,12 +398,12 @@ __device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int 
         }
 }
 
-// phi[:, c] = sum_t Kz_t T_t[:, c] for the block's 16 grid columns c.  Every
-// term's columns are staged (transposed to [col][z'], split) at once.  The
-// wavefronts form G groups; in a group wavefront w owns row tile w mod n_tiles
-// and the group takes terms grp, grp + G, ..., loading the Kz fragment of its
-// next term while it multiplies the current one.  The groups' partial sums are
-// added in group order through LDS.
+// phi[:, c] = sum_t Kz_t T_t[:, c] for the block's 16 grid columns c, as in
+// the FP32 form: the columns of a chunk of terms are staged (transposed to
+// [col][z'], split); the wavefronts form G groups, in a group wavefront w owns
+// row tile w mod n_tiles and the group takes the chunk's terms grp, grp + G,
+// ..., loading the Kz fragment of its next term while it multiplies the
+// current one.  The groups' partial sums are added in group order through LDS.
 __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, float* smem,
                                                  const float* __restrict__ tgrid,
                                                  const unsigned short* __restrict__ kz,
@@ -415,55 +417,61 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
     const bool act = w < tz_n * G;
     const int tz = w % tz_n, grp = w / tz_n;
     const size_t mz = (size_t)p2 * p2;
+    const int tc = conv_z_chunk(a);
+    const float ip2 = 1.0f / (float)p2;
     unsigned short* th = reinterpret_cast<unsigned short*>(smem);   // [t][16][ld] hi
-    unsigned short* tl = th + (size_t)a.nterms * 16 * ld;           // lo
-    Frag cur, nxt;
-    if (act && grp < a.nterms)
-        load_frag(cur, kz + 2 * mz * grp, kz + 2 * mz * grp + mz, p2, tz, li, lk);
-    // the loads of a pass (over all terms) are issued together, then split and stored
-    const int nst = a.nterms * 16 * p2;
-    for (int base = threadIdx.x; base < nst; base += kConvThreads * kStageBatchZ) {
-        float v[kStageBatchZ];
-#pragma unroll
-        for (int u = 0; u < kStageBatchZ; ++u) {
-            const int r = base + kConvThreads * u;
-            const int tz_ = r >> 4, c = r & 15;          // tz_ = t p2 + z'
-            const int t = small_div(tz_, 1.0f / (float)p2), zp = tz_ - t * p2;
-            v[u] = (r < nst && zp < g2 && c0 + c < ncol)
-                       ? tgrid[((size_t)t * g2 + zp) * ncol + c0 + c]
-                       : 0.0f;
-        }
-#pragma unroll
-        for (int u = 0; u < kStageBatchZ; ++u) {
-            const int r = base + kConvThreads * u;
-            const int tz_ = r >> 4, c = r & 15;
-            const int t = small_div(tz_, 1.0f / (float)p2), zp = tz_ - t * p2;
-            if (r < nst) {
-                unsigned short h, lo;
-                split(v[u], &h, &lo);
-                th[((size_t)t * 16 + c) * ld + zp] = h;
-                tl[((size_t)t * 16 + c) * ld + zp] = lo;
-            }
-        }
-    }
-    __syncthreads();
+    unsigned short* tl = th + (size_t)tc * 16 * ld;                 // lo
     f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    if (act) {
-        for (int t = grp; t < a.nterms; t += G) {
-            if (t + G < a.nterms)
-                load_frag(nxt, kz + 2 * mz * (t + G), kz + 2 * mz * (t + G) + mz, p2, tz, li, lk);
-            const unsigned short* bhp = th + ((size_t)t * 16 + li) * ld + 8 * lk;
-            const unsigned short* blp = tl + ((size_t)t * 16 + li) * ld + 8 * lk;
+    for (int t0 = 0; t0 < a.nterms; t0 += tc) {
+        const int nt = (a.nterms - t0 < tc) ? a.nterms - t0 : tc;
+        Frag cur, nxt;
+        if (act && grp < nt)
+            load_frag(cur, kz + 2 * mz * (t0 + grp), kz + 2 * mz * (t0 + grp) + mz, p2, tz, li, lk);
+        if (t0 > 0) __syncthreads();     // the previous chunk's columns are consumed
+        // the loads of a pass are issued together, then split and stored
+        const int nst = nt * 16 * p2;
+        for (int base = threadIdx.x; base < nst; base += kConvThreads * kStageBatchZ) {
+            float v[kStageBatchZ];
 #pragma unroll
-            for (int ks = 0; ks < kMaxKSteps; ++ks) {
-                if (32 * ks < p2) {
-                    const u16x8 bh = *reinterpret_cast<const u16x8*>(bhp + 32 * ks);
-                    const u16x8 bl = *reinterpret_cast<const u16x8*>(blp + 32 * ks);
-                    acc = mfma3(cur.h[ks], cur.l[ks], bh, bl, acc);
+            for (int u = 0; u < kStageBatchZ; ++u) {
+                const int r = base + kConvThreads * u;
+                const int q = r >> 4, c = r & 15;          // q = t p2 + z'
+                const int t = small_div(q, ip2), zp = q - t * p2;
+                v[u] = (r < nst && zp < g2 && c0 + c < ncol)
+                           ? tgrid[((size_t)(t0 + t) * g2 + zp) * ncol + c0 + c]
+                           : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kStageBatchZ; ++u) {
+                const int r = base + kConvThreads * u;
+                const int q = r >> 4, c = r & 15;
+                const int t = small_div(q, ip2), zp = q - t * p2;
+                if (r < nst) {
+                    unsigned short h, lo;
+                    split(v[u], &h, &lo);
+                    th[(t * 16 + c) * ld + zp] = h;
+                    tl[(t * 16 + c) * ld + zp] = lo;
                 }
             }
-            cur = nxt;
         }
+        __syncthreads();
+        if (act)
+            for (int t = grp; t < nt; t += G) {
+                if (t + G < nt)
+                    load_frag(nxt, kz + 2 * mz * (t0 + t + G), kz + 2 * mz * (t0 + t + G) + mz, p2,
+                              tz, li, lk);
+                const unsigned short* bhp = th + (t * 16 + li) * ld + 8 * lk;
+                const unsigned short* blp = tl + (t * 16 + li) * ld + 8 * lk;
+#pragma unroll
+                for (int ks = 0; ks < kMaxKSteps; ++ks) {
+                    if (32 * ks < p2) {
+                        const u16x8 bh = *reinterpret_cast<const u16x8*>(bhp + 32 * ks);
+                        const u16x8 bl = *reinterpret_cast<const u16x8*>(blp + 32 * ks);
+                        acc = mfma3(cur.h[ks], cur.l[ks], bh, bl, acc);
+                    }
+                }
+                cur = nxt;
+            }
     }
     if (G > 1) acc = conv_z_reduce(acc, smem, act, grp, G, tz, tz_n, l);
     if (!act || grp != 0) return;
@@ -551,9 +559,7 @@ size_t conv_xy_lds_bytes(const ConvArgs& a) {
 }
 
 size_t conv_z_lds_bytes(const ConvArgs& a) {
-    const size_t stage =
-        a.bf16x3 ? (size_t)2 * a.nterms * 16 * (a.gp[2] + 8) * sizeof(unsigned short)
-                 : (size_t)conv_z_f32_chunk(a) * 16 * (a.gp[2] + 4) * sizeof(float);
+    const size_t stage = (size_t)conv_z_chunk(a) * 16 * (a.gp[2] + (a.bf16x3 ? 8 : 4)) * 4;
     const size_t red = (size_t)(conv_z_groups(a) - 1) * (a.gp[2] / 16) * 64 * 4 * sizeof(float);
     return stage > red ? stage : red;
 }

@@ -44,7 +44,7 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     const bool bf = o.precision == USERIES_BF16X3;
     const double ratio = o.sigma_s_over_h > 0 ? o.sigma_s_over_h : (bf ? 0.74 : 0.9);
     const int P = o.stencil_half > 0 ? o.stencil_half : (bf ? 3 : 5);
-    const int deg = o.poly_degree > 0 ? o.poly_degree : 7;
+    const int deg = o.poly_degree > 0 ? o.poly_degree : (bf ? 5 : 7);
     if (P < 1 || P > kMaxStencilHalf) return fail(err, USERIES_EINVAL, "stencil_half out of [1, 8]");
     if (deg < 4 || deg > kMaxPolyDeg) return fail(err, USERIES_EINVAL, "poly_degree out of [4, 14]");
     if (!(o.nterms_tol > 0)) return fail(err, USERIES_EINVAL, "nterms_tol must be > 0");
@@ -141,14 +141,27 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     }
     pa.zinv = (float)(4294967296.0 / box[2]);
 
-    // far part
+    // far part.  A term so wide that every non-zero Fourier mode of its
+    // periodised Gaussian lies below 2^-60 of the k = 0 mode equals, to double
+    // precision, that mode alone, which the far part removes (uniform
+    // background): it would add nothing but rounding, so the grid evaluates
+    // only the leading terms narrower than that (terms widen with t).
+    const double pi = 3.14159265358979323846;
+    int ngrid = 0;
+    for (int t = 0; t < p.nterms; ++t) {
+        double at, st;
+        s.term(t, &at, &st);
+        const double u = 2.0 * pi * st / lmax;
+        if (0.5 * u * u > 60.0 * std::log(2.0)) break;
+        ngrid = t + 1;
+    }
+    p.nterms_grid = std::max(1, ngrid);
     GridArgs& ga = p.gridargs;
     ga.P = P;
     ga.inv_ngrid = 1.0 / ((double)grid[0] * grid[1] * grid[2]);
     ConvArgs& ca = p.conv;
-    ca.nterms = p.nterms;
+    ca.nterms = p.nterms_grid;
     ca.bf16x3 = bf ? 1 : 0;
-    const double pi = 3.14159265358979323846;
     for (int a = 0; a < 3; ++a) {
         const double h = box[a] / grid[a];
         const double ss = ratio * h;
@@ -163,13 +176,13 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
         const size_t m = (size_t)gp * gp;
         // per term the circulant M[i][j] = col[(i - j) mod g], zero-padded to gp x gp
         if (bf)
-            p.mats[a].assign(2 * m * p.nterms * sizeof(uint16_t), 0);
+            p.mats[a].assign(2 * m * p.nterms_grid * sizeof(uint16_t), 0);
         else
-            p.mats[a].assign(m * p.nterms * sizeof(float), 0);
+            p.mats[a].assign(m * p.nterms_grid * sizeof(float), 0);
         std::vector<double> col(g);
         std::vector<float> colf(g);
         std::vector<uint16_t> chi(g), clo(g);
-        for (int t = 0; t < p.nterms; ++t) {
+        for (int t = 0; t < p.nterms_grid; ++t) {
             double at, st;
             s.term(t, &at, &st);
             const double sk2 = st * st - 2.0 * ss * ss;

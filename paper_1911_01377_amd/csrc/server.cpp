@@ -129,7 +129,7 @@ Layout make_layout(const HostPlan& hp, int n, int n_evals) {
     L.clus_start = take(4 * (ncm + 1));
     L.zbin = take(4 * ncm * (size_t)(hp.grid[2] + 1));
     L.rho = take(4 * ng);
-    L.tgrid = take(4 * ng * (size_t)hp.nterms);
+    L.tgrid = take(4 * ng * (size_t)hp.conv.nterms);
     L.phi = take(4 * ng);
     L.total = o;
     return L;
@@ -609,7 +609,7 @@ int useries_server_default_opts(useries_server_opts* o) {
     o->construction = USERIES_C1;
     o->b = 2.0;
     o->nterms_tol = 1e-8;
-    o->poly_degree = 7;
+    o->poly_degree = 0;
     o->use_graph = 1;
     o->inflight = 2;
     return USERIES_OK;
@@ -629,6 +629,7 @@ int useries_server_create(useries_server_t* out, size_t hbm_budget_bytes, int ma
     useries_server_default_opts(&o);
     if (opts) o = *opts;
     if (o.inflight < 1 || o.inflight > 4) return set_last_error(USERIES_EINVAL, "inflight out of [1, 4]");
+    if (o.poly_degree <= 0) o.poly_degree = precision == USERIES_BF16X3 ? 5 : 7;
     if (o.poly_degree < 4 || o.poly_degree > kMaxPolyDeg)
         return set_last_error(USERIES_EINVAL, "poly_degree out of [4, 14]");
 
@@ -714,7 +715,7 @@ int useries_submit(useries_server_t S, const useries_request* req, uint64_t* tic
     R->items[BK_PAIR] = hp.fin.n_pair_parts;
     R->items[BK_SPREAD] = ((hp.grid[0] + kB - 1) / kB) * ((hp.grid[1] + kB - 1) / kB) *
                           ((hp.grid[2] + kB - 1) / kB);
-    R->items[BK_CONV_XY] = hp.grid[2] * hp.nterms;
+    R->items[BK_CONV_XY] = hp.grid[2] * hp.conv.nterms;
     R->items[BK_CONV_Z] = conv_z_blocks(hp.conv);
     R->items[BK_GATHER] = hp.fin.n_gather_parts;
     R->items[BK_FINAL] = 1;

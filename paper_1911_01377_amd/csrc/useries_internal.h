@@ -104,6 +104,7 @@ struct HostPlan {
     double rc = 0, b = 2, sigma = 1, r0 = 1, w0 = 1, s0 = 1;
     int construction = USERIES_C1, precision = USERIES_PLAIN_FP32;
     int nterms = 0, P = 5, deg = 8;
+    int nterms_grid = 0;   // leading terms evaluated on the grid (the rest: k = 0 only)
     int grid[3] = {0, 0, 0};
     double eq33 = 0, f_inf0 = 0, c1_slope = 0, poly_maxerr = 0, sigma_s[3] = {0, 0, 0};
     int ncmax[2] = {1, 1};   // bounds of the x-y column grid (chosen per evaluation)

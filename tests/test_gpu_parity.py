@@ -124,6 +124,49 @@ def test_many_columns_global_binning():
     assert fsum <= 1e-3 * math.sqrt(len(q)) * rms
 
 
+FORMS = [(0, (1e-6, 1e-5)), (USERIES_BF16X3, (1e-3, 1e-3))]
+
+
+def _form(precision):
+    return "bf16x3" if precision else "plain"
+
+
+@pytest.mark.parametrize("precision,tol", FORMS)
+def test_terms_staged_in_chunks(precision, tol):
+    """N = 4 on grids of 128 z points: a z-convolution block stages the columns
+    of at most 2 terms at once (20 KiB of LDS), so it runs over two chunks of
+    terms, in both forms.  A 32 A water box (32 x 32 x 128 grid) is held to
+    the form's tolerances.  The second chunk's terms (16 and 32 A wide) must
+    be in the result: for 2000 random charges in a 32 A cube, whose far energy
+    they move by about 1%, the far energy lies within a fifth of the gap
+    between the oracle's 4-term value and its value from the first 2 terms."""
+    xyz, q, box = synth.water_box(None, 32.0, seed=23)
+    _, _, _, _, info = compare("chunks/%s" % _form(precision), xyz, q, box, 8.0, (32, 32, 128),
+                               tol[0], tol[1], n_terms=4, precision=precision)
+    assert info["n_terms"] == 4 and info["n_terms_grid"] == 4
+    xyz, q, box = synth.random_cube(2000, 32.0, seed=5)
+    gp, _, info = gpu_eval(xyz, q, box, 8.0, (48, 48, 128), n_terms=4, precision=precision)
+    x64, q64 = xyz.astype(np.float64), q.astype(np.float64)
+    far4, _ = oracle.eval_far(x64, q64, box, oracle_params(info, 8.0))
+    far2, _ = oracle.eval_far(x64, q64, box, oracle_params(dict(info, n_terms=2), 8.0))
+    log("   random2000 far energy: gpu %.9f, oracle 4 terms %.9f, first 2 only %.9f"
+        % (gp[1], far4, far2))
+    assert abs(gp[1] - far4) < 0.2 * abs(far4 - far2)
+
+
+@pytest.mark.parametrize("precision,tol", FORMS)
+def test_terms_wider_than_the_box_are_skipped(precision, tol):
+    """N = 8 in a 30 A water box: terms 4..7 (64 to 515 A wide) have every
+    non-zero Fourier mode below 2^-60 of their k = 0 mode, so the grid
+    evaluates terms 0..3 only; the oracle sums all eight.  Evaluated on the
+    grid, those terms' nearly constant values would only add FP32 rounding
+    (about 5e-6 of the far energy at N = 8)."""
+    xyz, q, box = synth.water_box(None, 30.0, seed=24)
+    _, _, _, _, info = compare("wide/%s" % _form(precision), xyz, q, box, 8.0, (32, 32, 32),
+                               tol[0], tol[1], n_terms=8, precision=precision)
+    assert info["n_terms"] == 8 and info["n_terms_grid"] == 4
+
+
 def test_non_neutral_and_single_charge():
     """A net charge Q couples to the near-uniform (k ~ 0) part of the FP32
     rounding of the widest convolution terms: the energy error grows like
