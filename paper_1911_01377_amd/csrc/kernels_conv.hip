@@ -492,12 +492,16 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_xy_f32(ConvArgs a, const 
     conv_xy_f32_body(a, blockIdx.x, blockIdx.y, dyn_lds, rho, kx, ky, tgrid);
 }
 
-__global__ void __launch_bounds__(kConvThreads) k_conv_z_f32(ConvArgs a,
+// conv_z launches take xcd_blocks(nb) blocks: neighbouring column groups,
+// which share 128-byte lines of T, then run on one XCD and share its L2
+__global__ void __launch_bounds__(kConvThreads) k_conv_z_f32(ConvArgs a, int nb,
                                                              const float* __restrict__ tgrid,
                                                              const float* __restrict__ kz,
                                                              float* __restrict__ phi) {
     extern __shared__ float dyn_lds[];
-    conv_z_f32_body(a, blockIdx.x, dyn_lds, tgrid, kz, phi);
+    const int item = xcd_item(blockIdx.x, nb);
+    if (item >= nb) return;
+    conv_z_f32_body(a, item, dyn_lds, tgrid, kz, phi);
 }
 
 __global__ void __launch_bounds__(kConvThreads) k_conv_xy_bf16(ConvArgs a, const float* __restrict__ rho,
@@ -508,11 +512,14 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_xy_bf16(ConvArgs a, const
     conv_xy_bf16_body(a, blockIdx.x, blockIdx.y, dyn_lds, rho, kx, ky, tgrid);
 }
 
-__global__ void __launch_bounds__(kConvThreads) k_conv_z_bf16(ConvArgs a, const float* __restrict__ tgrid,
-                                                     const unsigned short* __restrict__ kz,
-                                                     float* __restrict__ phi) {
+__global__ void __launch_bounds__(kConvThreads) k_conv_z_bf16(ConvArgs a, int nb,
+                                                              const float* __restrict__ tgrid,
+                                                              const unsigned short* __restrict__ kz,
+                                                              float* __restrict__ phi) {
     extern __shared__ float dyn_lds[];
-    conv_z_bf16_body(a, blockIdx.x, dyn_lds, tgrid, kz, phi);
+    const int item = xcd_item(blockIdx.x, nb);
+    if (item >= nb) return;
+    conv_z_bf16_body(a, item, dyn_lds, tgrid, kz, phi);
 }
 
 // batched: item = t * g_z + z (conv_xy), 16-column group (conv_z)
@@ -583,11 +590,12 @@ hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz,
                          hipStream_t st) {
     const int nb = conv_z_blocks(a);
     if (a.bf16x3)
-        hipLaunchKernelGGL(k_conv_z_bf16, dim3(nb), dim3(kConvThreads), conv_z_lds_bytes(a), st, a,
-                           tgrid, reinterpret_cast<const unsigned short*>(kz), phi);
+        hipLaunchKernelGGL(k_conv_z_bf16, dim3(xcd_blocks(nb)), dim3(kConvThreads),
+                           conv_z_lds_bytes(a), st, a, nb, tgrid,
+                           reinterpret_cast<const unsigned short*>(kz), phi);
     else
-        hipLaunchKernelGGL(k_conv_z_f32, dim3(nb), dim3(kConvThreads), conv_z_lds_bytes(a), st, a,
-                           tgrid, kz, phi);
+        hipLaunchKernelGGL(k_conv_z_f32, dim3(xcd_blocks(nb)), dim3(kConvThreads),
+                           conv_z_lds_bytes(a), st, a, nb, tgrid, kz, phi);
     return hipGetLastError();
 }
 
