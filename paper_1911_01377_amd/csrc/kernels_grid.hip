@@ -66,6 +66,9 @@ __device__ __forceinline__ void cell_window(int X0, int bn, int P, int g, int nc
 // 3 x 8 weights in LDS, and wavefront w accumulates the staged charges w, w + W, ...
 // (W wavefronts) into its partial brick; the partial bricks are summed in a
 // fixed order at the end.
+// PT > 0: the stencil half width as a compile-time constant; PT = 0 takes it
+// from a.P.
+template <int PT>
 __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
                                             const uint4* __restrict__ sorted,
                                             const int* __restrict__ zbin,
@@ -85,7 +88,8 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
               Z0 = (bid / (nbx * nby)) * kBrick;
     const int B0 = min(kBrick, a.g[0] - X0), B1 = min(kBrick, a.g[1] - Y0),
               B2 = min(kBrick, a.g[2] - Z0);
-    const int P = a.P, gz = a.g[2];
+    const int P = PT > 0 ? PT : a.P, gz = a.g[2];
+    constexpr int KMAX = PT > 0 ? 2 * PT : 2 * kMaxStencilHalf;   // stencil points per axis
     int lo[2], cnt[2];
     cell_window(X0, B0, P, a.g[0], a.nc[0], &lo[0], &cnt[0]);
     cell_window(Y0, B1, P, a.g[1], a.nc[1], &lo[1], &cnt[1]);
@@ -201,8 +205,8 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
                 const float sc = ax == 1 ? a.cw[ax] * qj : a.cw[ax];
                 const float e2 = -a.hs[ax] * 1.44269504f;   // exp(-t^2 hs) = 2^(t^2 e2)
 #pragma unroll
-                for (int k = 0; k < 2 * kMaxStencilHalf; ++k) {
-                    if (k < 2 * P) {
+                for (int k = 0; k < KMAX; ++k) {
+                    if (PT > 0 || k < 2 * P) {
                         int b = k - k0;
                         if (b < 0) b += a.g[ax];
                         if (b < Bs[ax]) {
@@ -241,20 +245,21 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
     }
 }
 
+template <int PT>
 __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread(GridArgs a, int nb,
                                                               const uint4* __restrict__ sorted,
                                                               const int* __restrict__ zbin,
                                                               const double* __restrict__ qstats,
                                                               float* __restrict__ rho) {
     const int item = xcd_item(blockIdx.x, nb);
-    if (item < nb) spread_body(a, item, sorted, zbin, qstats, rho);
+    if (item < nb) spread_body<PT>(a, item, sorted, zbin, qstats, rho);
 }
 
 __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread_batch(
         const BatchTable* __restrict__ tab, const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_SPREAD, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        spread_body(d.grid, item, d.sorted, d.zbin, d.qstats, d.rho);
+        spread_body<0>(d.grid, item, d.sorted, d.zbin, d.qstats, d.rho);
     });
 }
 
@@ -301,6 +306,25 @@ __host__ __device__ inline GatherLds gather_lds(int P) {
     return L;
 }
 
+// Sum over each 16-lane row of the wavefront, every lane of the row receiving
+// it: pairs within quads, then the quads, then the half rows, all by DPP lane
+// moves (no LDS round trip), in a fixed order.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                  CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row_sum16(float v) {
+    v += dpp_move<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141>(v);   // row_half_mirror
+    v += dpp_move<0x140>(v);   // row_mirror
+    return v;
+}
+
+// PT > 0: the stencil half width as a compile-time constant (fully unrolled
+// stencil rows, weights held in registers); PT = 0 takes it from a.P.
+template <int PT>
 __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                                             const uint4* __restrict__ sorted,
                                             const int* __restrict__ perm,
@@ -311,7 +335,8 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                                             double* __restrict__ epart, char* lds) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, l16 = lane & 15;
-    const int P = a.P, P2 = 2 * P, GB = gather_brick(P);
+    const int P = PT > 0 ? PT : a.P, P2 = 2 * P, GB = gather_brick(P);
+    constexpr int KMAX = PT > 0 ? 2 * PT : 2 * kMaxStencilHalf;   // x points per stencil row
     const GatherLds LL = gather_lds(P);
     uint4* own = reinterpret_cast<uint4*>(lds + LL.own);
     float4* ownf = reinterpret_cast<float4*>(lds + LL.ownf);
@@ -458,8 +483,8 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                     const float* rowp = obase + rt.x;
                     float sx = 0.0f, dsx = 0.0f;
 #pragma unroll
-                    for (int k = 0; k < 2 * kMaxStencilHalf; ++k) {
-                        if (k < P2) {
+                    for (int k = 0; k < KMAX; ++k) {
+                        if (PT > 0 || k < P2) {
                             const float v = rowp[k];
                             sx = fmaf(W[k], v, sx);
                             dsx = fmaf(W[3 * P2 + k], v, dsx);
@@ -473,13 +498,10 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                     pz = fmaf(wy * W[5 * P2 + kz], sx, pz);
                 }
             }
-#pragma unroll
-            for (int off = 8; off > 0; off >>= 1) {
-                pe += __shfl_xor(pe, off, 64);
-                px += __shfl_xor(px, off, 64);
-                py += __shfl_xor(py, off, 64);
-                pz += __shfl_xor(pz, off, 64);
-            }
+            pe = row_sum16(pe);
+            px = row_sum16(px);
+            py = row_sum16(py);
+            pz = row_sum16(pz);
             if (valid && l16 == 0) {
                 const float4 fn = ownf[o];    // near force from the pair kernel
                 const int oi = ownp[o];
@@ -505,6 +527,7 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
     }
 }
 
+template <int PT>
 __global__ void __launch_bounds__(kGatherThreads) k_gather(GridArgs a, int nb,
                                                 const uint4* __restrict__ sorted,
                                                 const int* __restrict__ perm,
@@ -515,7 +538,7 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(GridArgs a, int nb,
                                                 double* __restrict__ epart) {
     extern __shared__ char dyn[];
     const int item = xcd_item(blockIdx.x, nb);
-    if (item < nb) gather_body(a, item, sorted, perm, zbin, phi, fnear, forces, epart, dyn);
+    if (item < nb) gather_body<PT>(a, item, sorted, perm, zbin, phi, fnear, forces, epart, dyn);
 }
 
 __global__ void __launch_bounds__(kGatherThreads) k_gather_batch(const BatchTable* __restrict__ tab,
@@ -523,8 +546,19 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather_batch(const BatchTabl
     extern __shared__ char dyn[];
     batch_for(tab, BK_GATHER, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        gather_body(d.grid, item, d.sorted, d.perm, d.zbin, d.phi, d.fnear, d.forces,
-                    d.gather_parts, dyn);
+        switch (d.grid.P) {
+            case 3:
+                gather_body<3>(d.grid, item, d.sorted, d.perm, d.zbin, d.phi, d.fnear, d.forces,
+                               d.gather_parts, dyn);
+                break;
+            case 5:
+                gather_body<5>(d.grid, item, d.sorted, d.perm, d.zbin, d.phi, d.fnear, d.forces,
+                               d.gather_parts, dyn);
+                break;
+            default:
+                gather_body<0>(d.grid, item, d.sorted, d.perm, d.zbin, d.phi, d.fnear, d.forces,
+                               d.gather_parts, dyn);
+        }
     });
 }
 
@@ -532,8 +566,13 @@ hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* zbin
                          const double* qstats, float* rho, hipStream_t st) {
     const int nb = ((a.g[0] + kBrick - 1) / kBrick) * ((a.g[1] + kBrick - 1) / kBrick) *
                    ((a.g[2] + kBrick - 1) / kBrick);
-    hipLaunchKernelGGL(k_spread, dim3(xcd_blocks(nb)), dim3(64 * kSpreadWaves), 0, st, a, nb,
-                       sorted, zbin, qstats, rho);
+    const dim3 grid(xcd_blocks(nb)), block(64 * kSpreadWaves);
+    if (a.P == 3)
+        hipLaunchKernelGGL(k_spread<3>, grid, block, 0, st, a, nb, sorted, zbin, qstats, rho);
+    else if (a.P == 5)
+        hipLaunchKernelGGL(k_spread<5>, grid, block, 0, st, a, nb, sorted, zbin, qstats, rho);
+    else
+        hipLaunchKernelGGL(k_spread<0>, grid, block, 0, st, a, nb, sorted, zbin, qstats, rho);
     return hipGetLastError();
 }
 
@@ -546,9 +585,18 @@ hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm
                          const float* phi, const float4* fnear, float* forces, double* epart,
                          hipStream_t st) {
     const int nb = gather_blocks(a);
-    hipLaunchKernelGGL(k_gather, dim3(xcd_blocks(nb)), dim3(kGatherThreads),
-                       gather_lds(a.P).total, st, a, nb, sorted, perm, zbin, phi, fnear, forces,
-                       epart);
+    const dim3 grid(xcd_blocks(nb)), block(kGatherThreads);
+    const size_t lds = gather_lds(a.P).total;
+    // the default stencils of the two forms (P = 3, 5) have their own code
+    if (a.P == 3)
+        hipLaunchKernelGGL(k_gather<3>, grid, block, lds, st, a, nb, sorted, perm, zbin, phi, fnear,
+                           forces, epart);
+    else if (a.P == 5)
+        hipLaunchKernelGGL(k_gather<5>, grid, block, lds, st, a, nb, sorted, perm, zbin, phi, fnear,
+                           forces, epart);
+    else
+        hipLaunchKernelGGL(k_gather<0>, grid, block, lds, st, a, nb, sorted, perm, zbin, phi, fnear,
+                           forces, epart);
     return hipGetLastError();
 }
 
