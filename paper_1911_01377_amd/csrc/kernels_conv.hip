@@ -30,7 +30,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kMaxTiles = kMaxGrid / 16;
 constexpr int kStageBatch = 16;   // global loads issued together per thread when staging
 constexpr int kStageBatchZ = 8;   // the same for BF16 conv_z (its Kz fragment is live meanwhile)
 
