@@ -255,11 +255,13 @@ __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread(GridArgs a, int nb
     if (item < nb) spread_body<PT>(a, item, sorted, zbin, qstats, rho);
 }
 
+// PT > 0 only when every box of the batch has stencil half width PT
+template <int PT>
 __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread_batch(
         const BatchTable* __restrict__ tab, const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_SPREAD, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        spread_body<0>(d.grid, item, d.sorted, d.zbin, d.qstats, d.rho);
+        spread_body<PT>(d.grid, item, d.sorted, d.zbin, d.qstats, d.rho);
     });
 }
 
@@ -541,24 +543,15 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(GridArgs a, int nb,
     if (item < nb) gather_body<PT>(a, item, sorted, perm, zbin, phi, fnear, forces, epart, dyn);
 }
 
+// PT > 0 only when every box of the batch has stencil half width PT
+template <int PT>
 __global__ void __launch_bounds__(kGatherThreads) k_gather_batch(const BatchTable* __restrict__ tab,
                                                       const BoxDesc* __restrict__ desc) {
     extern __shared__ char dyn[];
     batch_for(tab, BK_GATHER, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        switch (d.grid.P) {
-            case 3:
-                gather_body<3>(d.grid, item, d.sorted, d.perm, d.zbin, d.phi, d.fnear, d.forces,
-                               d.gather_parts, dyn);
-                break;
-            case 5:
-                gather_body<5>(d.grid, item, d.sorted, d.perm, d.zbin, d.phi, d.fnear, d.forces,
-                               d.gather_parts, dyn);
-                break;
-            default:
-                gather_body<0>(d.grid, item, d.sorted, d.perm, d.zbin, d.phi, d.fnear, d.forces,
-                               d.gather_parts, dyn);
-        }
+        gather_body<PT>(d.grid, item, d.sorted, d.perm, d.zbin, d.phi, d.fnear, d.forces,
+                        d.gather_parts, dyn);
     });
 }
 
@@ -600,17 +593,29 @@ hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm
     return hipGetLastError();
 }
 
-hipError_t launch_spread_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
+hipError_t launch_spread_batch(const BatchTable* tab, const BoxDesc* desc, int P, int grid,
                                hipStream_t st) {
-    hipLaunchKernelGGL(k_spread_batch, dim3(grid), dim3(64 * kSpreadWaves), 0, st, tab, desc);
+    const dim3 g(grid), b(64 * kSpreadWaves);
+    if (P == 3)
+        hipLaunchKernelGGL(k_spread_batch<3>, g, b, 0, st, tab, desc);
+    else if (P == 5)
+        hipLaunchKernelGGL(k_spread_batch<5>, g, b, 0, st, tab, desc);
+    else
+        hipLaunchKernelGGL(k_spread_batch<0>, g, b, 0, st, tab, desc);
     return hipGetLastError();
 }
 
 size_t gather_lds_bytes(int P) { return (size_t)gather_lds(P).total; }
 
-hipError_t launch_gather_batch(const BatchTable* tab, const BoxDesc* desc, size_t lds, int grid,
-                               hipStream_t st) {
-    hipLaunchKernelGGL(k_gather_batch, dim3(grid), dim3(kGatherThreads), lds, st, tab, desc);
+hipError_t launch_gather_batch(const BatchTable* tab, const BoxDesc* desc, int P, size_t lds,
+                               int grid, hipStream_t st) {
+    const dim3 g(grid), b(kGatherThreads);
+    if (P == 3)
+        hipLaunchKernelGGL(k_gather_batch<3>, g, b, lds, st, tab, desc);
+    else if (P == 5)
+        hipLaunchKernelGGL(k_gather_batch<5>, g, b, lds, st, tab, desc);
+    else
+        hipLaunchKernelGGL(k_gather_batch<0>, g, b, lds, st, tab, desc);
     return hipGetLastError();
 }
 

@@ -142,6 +142,7 @@ struct Req {
     Layout lay{};
     int items[BK_COUNT] = {0};
     size_t lds = 0, lds_z = 0, lds_g = 0;   // dynamic LDS of conv_xy, conv_z and gather
+    int P = 0;                               // stencil half width
     // shared with API threads (under the server mutex)
     int state = USERIES_PENDING;
     int err_code = USERIES_OK;
@@ -192,7 +193,8 @@ struct useries_server_s {
                                       // wait for the device)
     int grid[BK_COUNT] = {0};
     int lds_limit = 0;
-    std::map<std::tuple<size_t, size_t, size_t>, hipGraphExec_t> graphs;   // by the dynamic LDS sizes
+    // by the dynamic LDS sizes and the stencil half width
+    std::map<std::tuple<size_t, size_t, size_t, int>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_objs;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
@@ -240,7 +242,8 @@ struct useries_server_s {
     }
 
     // the kernels of one step, in order, on the server stream
-    hipError_t enqueue_kernels(size_t lds, size_t lds_z, size_t lds_g) {
+    // P: the stencil half width shared by the step's boxes, 0 if they differ
+    hipError_t enqueue_kernels(size_t lds, size_t lds_z, size_t lds_g, int P) {
         const bool bf = precision == USERIES_BF16X3;
         hipError_t e;
         if ((e = launch_encode_batch(d_table, d_desc, grid[BK_ENCODE], st))) return e;
@@ -248,16 +251,16 @@ struct useries_server_s {
         if ((e = launch_scatter_batch(d_table, d_desc, grid[BK_SCATTER], st))) return e;
         if ((e = launch_colsort_batch(d_table, d_desc, grid[BK_COLSORT], st))) return e;
         if ((e = launch_pair_batch(d_table, d_desc, popts.poly_degree, grid[BK_PAIR], st))) return e;
-        if ((e = launch_spread_batch(d_table, d_desc, grid[BK_SPREAD], st))) return e;
+        if ((e = launch_spread_batch(d_table, d_desc, P, grid[BK_SPREAD], st))) return e;
         if ((e = launch_conv_xy_batch(d_table, d_desc, bf, lds, grid[BK_CONV_XY], st))) return e;
         if ((e = launch_conv_z_batch(d_table, d_desc, bf, lds_z, grid[BK_CONV_Z], st))) return e;
-        if ((e = launch_gather_batch(d_table, d_desc, lds_g, grid[BK_GATHER], st))) return e;
+        if ((e = launch_gather_batch(d_table, d_desc, P, lds_g, grid[BK_GATHER], st))) return e;
         if ((e = launch_finalize_batch(d_table, d_desc, grid[BK_FINAL], st))) return e;
         return launch_displace_batch(d_table, d_desc, grid[BK_DISPLACE], st);
     }
 
-    hipError_t graph_for(size_t lds, size_t lds_z, size_t lds_g, hipGraphExec_t* out) {
-        const std::tuple<size_t, size_t, size_t> key(lds, lds_z, lds_g);
+    hipError_t graph_for(size_t lds, size_t lds_z, size_t lds_g, int P, hipGraphExec_t* out) {
+        const std::tuple<size_t, size_t, size_t, int> key(lds, lds_z, lds_g, P);
         auto it = graphs.find(key);
         if (it != graphs.end()) {
             *out = it->second;
@@ -265,7 +268,7 @@ struct useries_server_s {
         }
         hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e) return e;
-        const hipError_t el = enqueue_kernels(lds, lds_z, lds_g);
+        const hipError_t el = enqueue_kernels(lds, lds_z, lds_g, P);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(st, &g);
         if (el) {
@@ -404,6 +407,7 @@ struct useries_server_s {
         T.nbox = nb;
         for (int k = 0; k < BK_COUNT; ++k) T.off[k][0] = 0;
         size_t lds = 0, lds_z = 0, lds_g = 0;
+        int P = -1;
         for (int i = 0; i < nb; ++i) {
             Req* R = active[i];
             T.slot[i] = R->slot;
@@ -417,15 +421,17 @@ struct useries_server_s {
             lds = std::max(lds, R->lds);
             lds_z = std::max(lds_z, R->lds_z);
             lds_g = std::max(lds_g, R->lds_g);
+            P = (P < 0 || P == R->P) ? R->P : 0;
         }
+        P = std::max(P, 0);
         std::memcpy(ring + align_up(sizeof(BatchTable)), h_desc, sizeof(BoxDesc) * max_slots);
         if ((e = hipMemcpyAsync(d_tabdesc, ring, ring_stride, hipMemcpyHostToDevice, st)))
             return e;
         if (o.use_graph) {
             hipGraphExec_t ex = nullptr;
-            if ((e = graph_for(lds, lds_z, lds_g, &ex))) return e;
+            if ((e = graph_for(lds, lds_z, lds_g, P, &ex))) return e;
             if ((e = hipGraphLaunch(ex, st))) return e;
-        } else if ((e = enqueue_kernels(lds, lds_z, lds_g))) {
+        } else if ((e = enqueue_kernels(lds, lds_z, lds_g, P))) {
             return e;
         }
         if ((e = hipEventRecord(ring_ev[r], st))) return e;
@@ -701,6 +707,7 @@ int useries_submit(useries_server_t S, const useries_request* req, uint64_t* tic
     R->lds = conv_xy_lds_bytes(hp.conv);
     R->lds_z = conv_z_lds_bytes(hp.conv);
     R->lds_g = gather_lds_bytes(hp.P);
+    R->P = hp.P;
     if (S->lds_limit > 0 && std::max({R->lds, R->lds_z, R->lds_g}) > (size_t)S->lds_limit)
         return set_last_error(USERIES_EINVAL, "grid and term count need more LDS than the device has");
     R->lay = make_layout(hp, n, r.n_evals);

@@ -197,14 +197,17 @@ hipError_t launch_scatter_batch(const BatchTable* tab, const BoxDesc* desc, int 
 hipError_t launch_colsort_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
 hipError_t launch_pair_batch(const BatchTable* tab, const BoxDesc* desc, int deg, int grid,
                              hipStream_t st);
-hipError_t launch_spread_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
+// P: the stencil half width of every box in the batch (compiled code for 3
+// and 5), or 0 when they differ
+hipError_t launch_spread_batch(const BatchTable* tab, const BoxDesc* desc, int P, int grid,
+                               hipStream_t st);
 hipError_t launch_conv_xy_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3,
                                 size_t lds, int grid, hipStream_t st);
 hipError_t launch_conv_z_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3, size_t lds,
                                int grid, hipStream_t st);
 // lds >= gather_lds_bytes(P) of every box in the batch
-hipError_t launch_gather_batch(const BatchTable* tab, const BoxDesc* desc, size_t lds, int grid,
-                               hipStream_t st);
+hipError_t launch_gather_batch(const BatchTable* tab, const BoxDesc* desc, int P, size_t lds,
+                               int grid, hipStream_t st);
 // dynamic LDS of one gather block for stencil half width P
 size_t gather_lds_bytes(int P);
 hipError_t launch_finalize_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
