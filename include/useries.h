@@ -67,9 +67,10 @@ enum {
 
 /* arithmetic of the far-part convolutions */
 enum {
-    USERIES_PLAIN_FP32 = 0,     /* FP32 MFMA convolutions, 10^3 spreading stencil */
+    USERIES_PLAIN_FP32 = 0,     /* FP32 MFMA convolutions, 10^3 spreading stencil,
+                                   degree-7 near polynomials */
     USERIES_BF16X3 = 1          /* BF16 MFMA with 3-product split precision,
-                                   6^3 spreading stencil */
+                                   6^3 spreading stencil, degree-5 near polynomials */
 };
 
 /*
@@ -119,7 +120,9 @@ int useries_default_opts(useries_opts *opts);
  *            part continuous at r_c (its slope then need not vanish).  The
  *            presets require sigma <= 0 or sigma = r_c / r0 within 1e-12.
  *   n_terms  N, the far Gaussians kept (Sec. V); <= 0 picks the smallest N
- *            whose eq. 33 bound is <= opts->nterms_tol.  At most 32.
+ *            whose eq. 33 bound is <= opts->nterms_tol.  At most 32.  Terms
+ *            that are constant on the cell to 2^-60 besides their k = 0 mode
+ *            are not evaluated on the grid (n_terms_grid, useries_plan_info).
  *   grid     host [3]: far-part grid points per axis, 2P <= n <= 128.
  *            Each axis needs its grid spacing h with
  *            s_0^2 > 2 (sigma_s_over_h * h)^2 (the spreading Gaussians must
