@@ -302,7 +302,9 @@ struct useries_server_s {
             if (S.staging) old_staging.push_back(S.staging);
             S.staging = nullptr;
             S.cap = 0;
-            const size_t want = L.prefix + L.prefix / 2;
+            // pinned allocations take milliseconds: at least 2 MiB (a 60k-charge
+            // box), twice the need beyond that
+            const size_t want = std::max<size_t>(2 * L.prefix, (size_t)2 << 20);
             if ((e = hipHostMalloc((void**)&S.staging, want, hipHostMallocDefault))) return e;
             S.cap = want;
         }
