@@ -13,7 +13,7 @@ Prints one JSON line:
                on one stream (the rate of one evaluation captured in a HIP graph
                and replayed is reported beside it: slower here);
   batched_copies  evaluations/s with B copies of the box submitted together to
-               the server (continuous batching, one graph replay per step);
+               the server (continuous batching, the step's kernels launched eagerly);
   roofline     the dominant kernel's achieved rate vs the MI355X peak, timed
                with HIP events on the evaluation stream;
   kernels      every kernel's HIP-event time, algorithmic flop and bytes, and the

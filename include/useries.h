@@ -261,8 +261,11 @@ typedef struct {
  * Server options (useries_server_default_opts fills the defaults).
  *   construction, b, nterms_tol, poly_degree: as in useries_opts / useries_plan
  *              (defaults C1, b = 2, 1e-8, 0 = the precision's degree).
- *   use_graph  1: one captured HIP graph per step (default); 0: the same
- *              kernels launched one by one.
+ *   use_graph  0: the step's kernels launched one by one (default); 1: one
+ *              captured HIP graph per step (a graph is captured per set of
+ *              dynamic LDS sizes and stencil width).  Launching a graph whose
+ *              previous launch is still running blocks the host here, so the
+ *              default keeps the worker free for admissions and retirements.
  *   inflight   steps enqueued ahead of the device (1..4, default 2).
  */
 typedef struct {

@@ -3,7 +3,8 @@
 // A worker thread owns one HIP stream.  Each step advances every running
 // request by one evaluation with one pass of the batched kernels (the same
 // kernel bodies as a one-box evaluation, driven by a device table of the
-// boxes in the batch), replayed from a captured HIP graph.  Between steps the
+// boxes in the batch), launched one by one or replayed from a captured HIP
+// graph (option use_graph).  Between steps the
 // worker retires finished requests (their outputs copied back through pinned
 // staging) and admits waiting ones into free batch slots when their resident
 // workspace fits in the device arena.
@@ -618,7 +619,7 @@ int useries_server_default_opts(useries_server_opts* o) {
     o->b = 2.0;
     o->nterms_tol = 1e-8;
     o->poly_degree = 0;
-    o->use_graph = 1;
+    o->use_graph = 0;
     o->inflight = 2;
     return USERIES_OK;
 }

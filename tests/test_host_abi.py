@@ -124,7 +124,7 @@ def test_server_arguments_are_rejected_before_any_device_call():
             N.useries_server_create(budget, slots, prec)
         assert e.value.code == N.USERIES_EINVAL
     o = N.useries_server_default_opts()
-    assert o.use_graph == 1 and o.inflight == 2 and o.poly_degree == 0 and o.b == 2.0
+    assert o.use_graph == 0 and o.inflight == 2 and o.poly_degree == 0 and o.b == 2.0
     o.inflight = 9
     with pytest.raises(N.UseriesError):
         N.useries_server_create(1 << 30, 4, N.USERIES_BF16X3, o)
