@@ -385,8 +385,11 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pair(PairArgs a, int nb,
         pair_body<DEG>(a, item, sorted, clus_start, cl_info, cl_col, cl_z, zbin, fnear, epart);
 }
 
+// Held to 80 registers (6 wavefronts per SIMD instead of 5; the batch walk
+// costs 8-12 bytes of spill per lane): about 2% more batched evaluations/s.
 template <int DEG>
-__global__ void __launch_bounds__(64 * kPairWaves) k_pair_batch(const BatchTable* __restrict__ tab,
+__global__ void __launch_bounds__(64 * kPairWaves) __attribute__((amdgpu_waves_per_eu(6)))
+k_pair_batch(const BatchTable* __restrict__ tab,
                                                    const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_PAIR, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
