@@ -354,8 +354,18 @@ __device__ __forceinline__ void colsort_body(int col, const int* __restrict__ st
         }
         __syncthreads();
         if (t < cnt) {
-            int r = 0;
-            for (int m = 0; m < cnt; ++m) r += key[m] < mine;
+            // four independent counts, so that consecutive comparisons do not
+            // wait on each other's sums (one wavefront per SIMD here)
+            int r0 = 0, r1 = 0, r2 = 0, r3 = 0, m = 0;
+#pragma unroll 4
+            for (; m + 4 <= cnt; m += 4) {
+                r0 += key[m] < mine;
+                r1 += key[m + 1] < mine;
+                r2 += key[m + 2] < mine;
+                r3 += key[m + 3] < mine;
+            }
+            for (; m < cnt; ++m) r0 += key[m] < mine;
+            const int r = (r0 + r1) + (r2 + r3);
             perm[lo + r] = i;
             sorted[lo + r] = c;
             skz[r] = c.z;
