@@ -71,6 +71,34 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// DPP lane moves within 16-lane rows (no LDS round trip).  CTRL: 0xB1 and
+// 0x4E swap neighbours and pairs within quads (quad_perm [1,0,3,2], [2,3,0,1]),
+// 0x141 mirrors each half row (lane i <- 7 - i), 0x140 mirrors the row
+// (i <- 15 - i), 0x128 rotates the row by 8 (i <- i xor 8).
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                  CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+// sum over each group of 8 lanes (lanes 8g .. 8g + 7), every lane of the group
+// receiving it, in a fixed order
+__device__ __forceinline__ float sum8(float v) {
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
+    return v + dpp_move<0x141>(v);
+}
+
+// sum over each 16-lane row, every lane of the row receiving it
+__device__ __forceinline__ float row_sum16(float v) {
+    v = sum8(v);
+    return v + dpp_move<0x140>(v);
+}
+
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

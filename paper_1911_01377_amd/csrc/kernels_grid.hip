@@ -308,22 +308,6 @@ __host__ __device__ inline GatherLds gather_lds(int P) {
     return L;
 }
 
-// Sum over each 16-lane row of the wavefront, every lane of the row receiving
-// it: pairs within quads, then the quads, then the half rows, all by DPP lane
-// moves (no LDS round trip), in a fixed order.
-template <int CTRL>
-__device__ __forceinline__ float dpp_move(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                  CTRL, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float row_sum16(float v) {
-    v += dpp_move<0xB1>(v);    // quad_perm [1, 0, 3, 2]
-    v += dpp_move<0x4E>(v);    // quad_perm [2, 3, 0, 1]
-    v += dpp_move<0x141>(v);   // row_half_mirror
-    v += dpp_move<0x140>(v);   // row_mirror
-    return v;
-}
-
 // PT > 0: the stencil half width as a compile-time constant (fully unrolled
 // stencil rows, weights held in registers); PT = 0 takes it from a.P.
 template <int PT>

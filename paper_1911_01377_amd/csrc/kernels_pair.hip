@@ -293,8 +293,15 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     bl[0] = bh[0] = ivalid ? (int)(ci.x - c0.x) : 0;
     bl[1] = bh[1] = ivalid ? (int)(ci.y - c0.y) : 0;
     bl[2] = bh[2] = ivalid ? (int)(ci.z - c0.z) : 0;
+    // extremes over the i-charges (lanes l, l ^ 8, l ^ 16, l ^ 32): the xor-8
+    // partner by a DPP row rotation, the other two by permutes
 #pragma unroll
-    for (int off = 8; off < 64; off <<= 1)
+    for (int k = 0; k < 3; ++k) {
+        bl[k] = min(bl[k], dpp_move<0x128>(bl[k]));
+        bh[k] = max(bh[k], dpp_move<0x128>(bh[k]));
+    }
+#pragma unroll
+    for (int off = 16; off < 64; off <<= 1)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             bl[k] = min(bl[k], __shfl_xor(bl[k], off, 64));
@@ -347,12 +354,9 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         wave_sync();
     }
     // force on i-charge a: sum over its 8 lanes, then over the wavefronts
-#pragma unroll
-    for (int off = 1; off < 8; off <<= 1) {
-        fx += __shfl_xor(fx, off, 64);
-        fy += __shfl_xor(fy, off, 64);
-        fz += __shfl_xor(fz, off, 64);
-    }
+    fx = sum8(fx);
+    fy = sum8(fy);
+    fz = sum8(fz);
     // the cubic path summed (q_i u) q_j (...): back to q_i q_j
     const double es = wave_sum_d(e) * (cubic ? 1.0 / (double)sx : 1.0);
     if (w == 1) {
