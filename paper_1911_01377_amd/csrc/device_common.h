@@ -85,6 +85,23 @@ __device__ __forceinline__ int dpp_move(int v) {
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
 
+// inclusive prefix sum over the 64 lanes by DPP: a doubling scan within each
+// 16-lane row (shifts 1, 2, 4, 8; lanes shifted in from outside the row add
+// 0), then the last lane of row 0 added to row 1 and of row 2 to row 3
+// (row_bcast:15), then lane 31 added to rows 2 and 3 (row_bcast:31)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_add_in(int v) {
+    return v + __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
+}
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    v = dpp_add_in<0x111, 0xF>(v);   // row_shr:1
+    v = dpp_add_in<0x112, 0xF>(v);   // row_shr:2
+    v = dpp_add_in<0x114, 0xF>(v);   // row_shr:4
+    v = dpp_add_in<0x118, 0xF>(v);   // row_shr:8
+    v = dpp_add_in<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    return dpp_add_in<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+}
+
 // sum over each group of 8 lanes (lanes 8g .. 8g + 7), every lane of the group
 // receiving it, in a fixed order
 __device__ __forceinline__ float sum8(float v) {

@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(256) k_encode_batch(const BatchTable* __restri
 
 // One block of 1024 threads: exclusive scans of the column counts and of the
 // cluster counts ceil(count / 8) (each thread owns a contiguous chunk;
-// wavefront scans by shuffles, then a scan of the 16 wavefront totals), zero
+// wavefront scans by DPP lane moves, then a scan of the 16 wavefront totals), zero
 // the fill counters, and reduce the charge partials in a fixed order.  The
 // column counts are cleared once read, ready for the next evaluation (they
 // start at zero when the workspace is allocated).
@@ -107,31 +107,15 @@ __device__ __forceinline__ void scan_body(int ncol, int* __restrict__ count,
         s += k;
         sc += (k + 7) >> 3;
     }
-    int v = s, vc = sc;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int u = __shfl_up(v, off, 64), uc = __shfl_up(vc, off, 64);
-        if (lane >= off) {
-            v += u;
-            vc += uc;
-        }
-    }
+    const int v = wave_incl_scan(s), vc = wave_incl_scan(sc);
     if (lane == 63) {
         wsum[0][wv] = v;
         wsum[1][wv] = vc;
     }
     __syncthreads();
     if (wv == 0) {
-        int x = lane < 16 ? wsum[0][lane] : 0, xc = lane < 16 ? wsum[1][lane] : 0;
-        const int own = x, ownc = xc;
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-            const int u = __shfl_up(x, off, 64), uc = __shfl_up(xc, off, 64);
-            if (lane >= off) {
-                x += u;
-                xc += uc;
-            }
-        }
+        const int own = lane < 16 ? wsum[0][lane] : 0, ownc = lane < 16 ? wsum[1][lane] : 0;
+        const int x = wave_incl_scan(own), xc = wave_incl_scan(ownc);
         if (lane < 16) {
             wsum[0][lane] = x - own;
             wsum[1][lane] = xc - ownc;
@@ -226,15 +210,7 @@ __device__ __forceinline__ void scatter_body(const BinArgs& a, int bid, bool fus
             s += kc[u];
             sc += (kc[u] + 7) >> 3;
         }
-        int v = s, vc = sc;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int x = __shfl_up(v, off, 64), xc = __shfl_up(vc, off, 64);
-            if (lane >= off) {
-                v += x;
-                vc += xc;
-            }
-        }
+        const int v = wave_incl_scan(s), vc = wave_incl_scan(sc);
         if (lane == 63) {
             wsum[0][wv] = v;
             wsum[1][wv] = vc;

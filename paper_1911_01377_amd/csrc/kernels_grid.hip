@@ -124,12 +124,7 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
     {
         const int r0 = 2 * tid, r1 = 2 * tid + 1;
         const int v0 = r0 < np ? poff[r0 + 1] : 0, v1 = r1 < np ? poff[r1 + 1] : 0;
-        int incl = v0 + v1;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int u = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += u;
-        }
+        const int incl = wave_incl_scan(v0 + v1);
         if (lane == 63) wtot[w] = incl;
         __syncthreads();
         int wbase = 0;
@@ -379,12 +374,7 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
     __syncthreads();
     {
         const int v = tid < np ? poff[tid + 1] : 0;
-        int incl = v;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int u = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += u;
-        }
+        const int incl = wave_incl_scan(v);
         if (lane == 63) wtot[wave] = incl;
         __syncthreads();
         int wbase = 0;

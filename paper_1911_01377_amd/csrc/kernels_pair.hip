@@ -198,15 +198,7 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     // (ranges, charges), then each thread writes its ranges
     {
         const int m = (n0 > 0) + (n1 > 0), len = n0 + n1;
-        int im = m, il = len;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int x = __shfl_up(im, off, 64), y = __shfl_up(il, off, 64);
-            if (lane >= off) {
-                im += x;
-                il += y;
-            }
-        }
+        const int im = wave_incl_scan(m), il = wave_incl_scan(len);
         if (lane == 63) {
             wtot[w][0] = im;
             wtot[w][1] = il;
