@@ -64,13 +64,6 @@ __device__ __forceinline__ int xcd_item(int i, int nb) {
     return (i % kXcds) * (xcd_blocks(nb) / kXcds) + i / kXcds;
 }
 
-// sum over the 64 lanes of a wavefront (every lane gets the result)
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // DPP lane moves within 16-lane rows (no LDS round trip).  CTRL: 0xB1 and
 // 0x4E swap neighbours and pairs within quads (quad_perm [1,0,3,2], [2,3,0,1]),
 // 0x141 mirrors each half row (lane i <- 7 - i), 0x140 mirrors the row
@@ -116,10 +109,28 @@ __device__ __forceinline__ float row_sum16(float v) {
     return v + dpp_move<0x140>(v);
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = dpp_move<CTRL>((int)(uint32_t)u), hi = dpp_move<CTRL>((int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// sum over the 64 lanes of a wavefront (all lanes active), in a fixed order:
+// each 16-lane row by DPP moves, then the four row sums in order; every lane
+// gets the result
 __device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
+    v += dpp_move<0x141>(v);
+    v += dpp_move<0x140>(v);
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 }  // namespace useries

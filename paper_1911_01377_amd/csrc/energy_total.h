@@ -11,7 +11,7 @@
 namespace useries {
 
 // One block of NT threads: thread-strided sums of the pair and gather
-// partials, wavefront sums by shuffles, then the NT / 64 wavefront sums in
+// partials, wavefront sums (DPP), then the NT / 64 wavefront sums in
 // order.  wred holds 2 NT / 64 doubles of LDS.
 template <int NT>
 __device__ __forceinline__ void energy_total(const FinalArgs& a, const double* __restrict__ pp,

@@ -55,7 +55,7 @@ __device__ __forceinline__ void encode_body(const BinArgs& a, int bid, const flo
     if (local)
         for (int k = threadIdx.x; k < ncol; k += 256)
             if (hist[k] > 0) atomicAdd(&col_count[k], hist[k]);
-    // charge sums: wavefront shuffles, then the 4 wavefront sums in order
+    // charge sums: wavefront sums, then the 4 wavefront sums in order
     qs = wave_sum_d(qs);
     q2 = wave_sum_d(q2);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
