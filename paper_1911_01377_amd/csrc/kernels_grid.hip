@@ -486,10 +486,8 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                 forces[3 * oi + 2] = fn.z - qi * pz;
             }
             // the four charges' energies, in a fixed order
-            double ei = (valid && l16 == 0) ? 0.5 * (double)qi * (double)pe : 0.0;
-            ei += __shfl_xor(ei, 16, 64);
-            ei += __shfl_xor(ei, 32, 64);
-            e_wave += ei;
+            const double ei = (valid && l16 == 0) ? 0.5 * (double)qi * (double)pe : 0.0;
+            e_wave += (read_lane(ei, 0) + read_lane(ei, 16)) + (read_lane(ei, 32) + read_lane(ei, 48));
             wave_sync();
         }
         __syncthreads();
