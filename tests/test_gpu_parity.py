@@ -167,6 +167,21 @@ def test_terms_wider_than_the_box_are_skipped(precision, tol):
     assert info["n_terms"] == 8 and info["n_terms_grid"] == 4
 
 
+@pytest.mark.parametrize("k", range(6))
+@pytest.mark.parametrize("precision,tol", FORMS)
+def test_random_water_configurations(k, precision, tol):
+    """Seeded random water boxes: 200-1,200 molecules (L = 18-33 A), a grid
+    spacing drawn per axis from [0.75, 0.95] A (grids of any length, not
+    multiples of the tile sizes), r_c = min(9, 0.45 L), the default series."""
+    rng = np.random.default_rng(1000 + k)
+    n_mol = int(rng.integers(200, 1201))
+    L = (n_mol / synth.WATER_DENSITY) ** (1 / 3)
+    xyz, q, box = synth.water_box(n_mol=n_mol, L=L, seed=2000 + k)
+    grid = tuple(int(np.ceil(L / rng.uniform(0.75, 0.95))) for _ in range(3))
+    compare("randwater%d/%s" % (k, _form(precision)), xyz, q, box, min(9.0, 0.45 * L), grid,
+            tol[0], tol[1], precision=precision)
+
+
 def test_non_neutral_and_single_charge():
     """A net charge Q couples to the near-uniform (k ~ 0) part of the FP32
     rounding of the widest convolution terms: the energy error grows like
