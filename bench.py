@@ -47,11 +47,15 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 
-# algorithmic work per unit.  Near part, per unique pair within r_c: the two
-# Horner polynomials F and F'/r of degree d in r^2 (4 d flop) plus 17 flop
-# for the distance, r^2, 1/r, the energy and the force vector.
-def flop_per_pair(degree):
-    return 4.0 * degree + 17.0
+# The FP32 vector peak counts packed (two-wide) FMAs; code built without
+# packed FP32, as this library is, issues at most half of it.
+ISSUE_LIMIT_FP32_TFLOPS = PEAK_FP32_TFLOPS / 2
+
+# algorithmic work per unit.  Near part: about 45 flop (and one reciprocal
+# square root) per unique pair within r_c: the minimum-image difference,
+# r^2, 1/r, the series F and F'/r inside the cutoff, the pair energy and the
+# force vector applied to both charges.
+FLOP_PER_PAIR = 45.0
 
 
 # near polynomial degree of each form (the library's defaults, passed explicitly)
@@ -81,24 +85,14 @@ def kernel_src_hash(name):
     return h.hexdigest()[:16]
 
 
-def _make_request(k):
-    from paper_1911_01377_amd import synth
-    xyz, q, box = synth.serving_request(k)
-    return xyz, q, box
-
-
-def serving_requests(count, workers):
+def serving_requests(count):
     """The serving stream: request k is synth.serving_request(k) (a water box with a
     log-uniform molecule count in [216, 16000]); r_c = min(9, 0.45 L), grid spacing
-    <= 1 A.  Generated on the host before any device work."""
-    import multiprocessing as mp
-    if workers > 1:
-        with mp.get_context("fork").Pool(workers) as pool:
-            cells = pool.map(_make_request, range(count), chunksize=16)
-    else:
-        cells = [_make_request(k) for k in range(count)]
+    <= 1 A.  Generated in this process (no worker processes) before the timed work."""
+    from paper_1911_01377_amd import synth
     out = []
-    for xyz, q, box in cells:
+    for k in range(count):
+        xyz, q, box = synth.serving_request(k)
         L = min(box)
         out.append((xyz, q, box, min(9.0, 0.45 * L), tuple(int(math.ceil(b)) for b in box)))
     return out
@@ -187,7 +181,7 @@ def main():
     cells = None
     if args.serve_requests > 0:
         t = time.perf_counter()
-        cells = serving_requests(args.serve_requests, min(16, os.cpu_count() or 1))
+        cells = serving_requests(args.serve_requests)
         log("generated %d serving requests in %.1f s" % (len(cells), time.perf_counter() - t))
 
     import torch
@@ -307,7 +301,7 @@ def main():
     npairs = count_pairs(xyz, np.array(box), rc)
     G = grid[0] * grid[1] * grid[2]
     work = {
-        "pair": ("alu", npairs * flop_per_pair(POLY_DEGREE[args.form]), PEAK_FP32_TFLOPS),
+        "pair": ("alu", npairs * FLOP_PER_PAIR, PEAK_FP32_TFLOPS),
         "spread": ("alu", n * (2 * P) ** 3 * FLOP_PER_SPREAD_POINT, PEAK_FP32_TFLOPS),
         "gather": ("alu", n * (2 * P) ** 3 * FLOP_PER_GATHER_POINT, PEAK_FP32_TFLOPS),
         "conv_xy": ("mfma", 2.0 * nt * G * (grid[0] + grid[1]),
@@ -328,6 +322,12 @@ def main():
         roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak,
                 "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                 "kernel_ms": ktimes[dom], "algorithmic_flop": flop}
+        if bound == "alu":
+            roof["issue_limit_nonpacked"] = ISSUE_LIMIT_FP32_TFLOPS
+            roof["frac_of_issue_limit"] = achieved / ISSUE_LIMIT_FP32_TFLOPS
+        if dom == "pair":
+            roof["unique_pairs"] = int(npairs)
+            roof["flop_per_pair"] = FLOP_PER_PAIR
 
     # every kernel against its roofline: algorithmic flop and bytes per launch
     # (the counts below) over the HIP-event time; for the convolutions also the MFMA

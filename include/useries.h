@@ -89,7 +89,11 @@ enum {
  *                    (near part); <= 0 picks the default of the precision:
  *                    7 plain (fit error ~7e-8 of max |F|, FP32 level), 5
  *                    BF16X3 (~2e-5, well inside that form's 1e-3 budget).
- *                    4 <= degree <= 14.
+ *                    4 <= degree <= 14.  The narrowest far Gaussians are
+ *                    taken out of the polynomial and evaluated exactly when
+ *                    the fit would miss the form's budget (near_exact in
+ *                    useries_plan_info); if even 8 of them do not suffice,
+ *                    useries_plan fails with USERIES_EINVAL.
  *   max_atoms        workspace capacity in charges; <= 0 grows on demand
  *                    (a growth reallocates and synchronises the device).
  */
@@ -126,7 +130,12 @@ int useries_default_opts(useries_opts *opts);
  *   grid     host [3]: far-part grid points per axis, 2P <= n <= 128.
  *            Each axis needs its grid spacing h with
  *            s_0^2 > 2 (sigma_s_over_h * h)^2 (the spreading Gaussians must
- *            be narrower than the narrowest far Gaussian, Sec. IV.A).
+ *            be narrower than the narrowest far Gaussian, Sec. IV.A).  For
+ *            the plain form's accuracy keep h at or below about s_0 / 2
+ *            (s_0 = sigma s0): the grid carries s_0 through narrower
+ *            Gaussians still, and at h = 0.6 s_0 the far part already errs
+ *            by about 1e-5 of the total energy.  Small b (Table 1) makes
+ *            sigma = r_c / r0 small and so needs finer grids.
  *   opts     NULL for the defaults.
  * Errors: USERIES_EINVAL (bad argument or unsatisfiable constraint),
  * USERIES_ENOMEM, USERIES_EHIP.  The plan uses the current HIP device.
@@ -170,12 +179,17 @@ int useries_eval_parts(useries_plan_t plan, int64_t n, const float *xyz, const f
  *   [0, r_c], measured in FP64 on the host), n_terms_grid (the leading far
  *   terms evaluated on the grid: a term whose periodised Gaussian has every
  *   non-zero Fourier mode below 2^-60 of its k = 0 mode is, to double
- *   precision, only that mode, which the far part removes, so it is skipped).
+ *   precision, only that mode, which the far part removes, so it is skipped),
+ *   near_exact (the narrowest far Gaussians that the near part evaluates as
+ *   exponentials instead of through the polynomial: the plan takes the
+ *   fewest, 0 to 8, that bring the polynomial's fit error within the form's
+ *   budget, 1e-7 of max |F| plain and 2e-5 BF16X3; small b, as in Table 1,
+ *   needs them because its narrowest Gaussians lie deep inside r_c).
  */
 int useries_plan_info(useries_plan_t plan, double *b, double *sigma, double *r0, double *w0,
                       double *s0, int *n_terms, double *eq33, double *f_inf0,
                       double *c1_slope, double *sigma_s, int *stencil_half, int ncell[3],
-                      double *poly_maxerr, int *n_terms_grid);
+                      double *poly_maxerr, int *n_terms_grid, int *near_exact);
 
 /* Release a plan and its device memory.  The caller must ensure that no
  * evaluation on it is still running. */
@@ -203,8 +217,9 @@ int useries_timing_read(useries_plan_t plan, int k, const char **name, double *t
  *
  * Continuous batching: a worker thread owns one HIP stream.  All running
  * requests advance together, one evaluation per step, in one sequence of
- * batched kernels (one captured HIP graph replay per step): every kernel
- * takes a table of the boxes in the batch and the per-box work-item offsets.
+ * batched kernels, launched one by one by default (or, with the use_graph
+ * option, as one captured HIP graph replay per step): every kernel takes a
+ * table of the boxes in the batch and the per-box work-item offsets.
  * Between steps finished requests leave and waiting ones are admitted, as
  * batch slots and device memory allow.  Each request's positions, cell
  * lists, grids and convolution matrices stay resident in a device arena of

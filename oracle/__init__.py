@@ -12,12 +12,12 @@ plus the k-space form of App. F eq. F1 as an independent cross-check);
 pin the oracle on tiny inputs.
 """
 from .core import (Params, build, load, eval_full, eval_near, eval_far, far_kspace,
-                   forces_subset, far_inf, far_trunc, near_kernel, bsa_bound,
+                   forces_subset, far_inf, near_kernel, bsa_bound,
                    eq33_bound, solve_c0, solve_c1, c1_w0, series_len, term,
                    far_inf0, near_integral, num_threads)
 from .ewald import ewald
 
 __all__ = ["Params", "build", "load", "eval_full", "eval_near", "eval_far", "far_kspace",
-           "forces_subset", "far_inf", "far_trunc", "near_kernel", "bsa_bound",
+           "forces_subset", "far_inf", "near_kernel", "bsa_bound",
            "eq33_bound", "solve_c0", "solve_c1", "c1_w0", "series_len", "term",
            "far_inf0", "near_integral", "num_threads", "ewald"]

@@ -62,7 +62,6 @@ def load():
         "uo_series_len": (I, [D]),
         "uo_term": (None, [P, I, P, P]),
         "uo_far_inf": (None, [P, D, P]),
-        "uo_far_trunc": (None, [P, D, P]),
         "uo_near": (None, [P, D, P]),
         "uo_bsa_bound": (D, [D]),
         "uo_eq33_bound": (D, [I, D, D, D]),
@@ -121,13 +120,6 @@ def far_inf(p, r):
     """F_inf(r), F_inf'(r), F_inf''(r) (all series terms)."""
     out = np.zeros(3)
     load().uo_far_inf(_cp(p), float(r), _ptr(out))
-    return out
-
-
-def far_trunc(p, r):
-    """F_N(r) and its first two derivatives (first N terms)."""
-    out = np.zeros(3)
-    load().uo_far_trunc(_cp(p), float(r), _ptr(out))
     return out
 
 

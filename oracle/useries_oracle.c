@@ -112,12 +112,6 @@ void uo_far_inf(const uo_params *p, double r, double out[3])
     far_sum(p, 0, uo_series_len(p->b), r, &out[0], &out[1], &out[2]);
 }
 
-/* F_N(r) and derivatives: the first N terms only (Sec. V truncation) */
-void uo_far_trunc(const uo_params *p, double r, double out[3])
-{
-    far_sum(p, 0, p->nterms, r, &out[0], &out[1], &out[2]);
-}
-
 /* near kernel N(r) of eq. 20 and its r-derivative */
 void uo_near(const uo_params *p, double r, double out[2])
 {

@@ -241,7 +241,7 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
         (e = dalloc(&p->clus_start, hp.ncol_max + 1)) ||
         (e = dalloc(&p->zbin, (size_t)hp.ncol_max * (hp.grid[2] + 1))) ||
         (e = dalloc(&p->qstats, 2)) ||
-        (e = dalloc(&p->gather_parts, (size_t)gather_blocks(hp.gridargs))) ||
+        (e = dalloc(&p->gather_parts, 2 * (size_t)gather_blocks(hp.gridargs))) ||
         (e = dalloc(&p->parts_tmp, 5)) || (e = dalloc(&p->rho, ng)) ||
         (e = dalloc(&p->tgrid, ng * hp.conv.nterms)) || (e = dalloc(&p->phi, ng))) {
         delete p;
@@ -265,19 +265,87 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
     return USERIES_OK;
 }
 
-static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float* q, float* forces,
-                     double* energy, double* parts, void* stream) {
+}  // extern "C"
+
+namespace useries {
+
+int plan_device(useries_plan_t p) { return p->device; }
+
+// Byte offsets of the per-charge workspace of n charges in one contiguous
+// buffer (each array 256-byte aligned).
+struct AtomLayout {
+    size_t coord, sorted, perm, slots, cl_info, cl_col, cl_z, pair_parts, fnear, qpart, total;
+};
+
+static AtomLayout atom_layout(const HostPlan& hp, int64_t n) {
+    const int64_t c = std::max<int64_t>(n, 1);
+    const int64_t clmax = pair_blocks((int)c, hp.ncol_max);
+    AtomLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = o;
+        o += (bytes + 255) & ~(size_t)255;
+        return r;
+    };
+    L.coord = take(16 * (size_t)c);
+    L.sorted = take(16 * (size_t)c);
+    L.perm = take(4 * (size_t)c);
+    L.slots = take(4 * (size_t)c);
+    L.cl_info = take(8 * (size_t)clmax);
+    L.cl_col = take(4 * (size_t)clmax);
+    L.cl_z = take(8 * (size_t)clmax);
+    L.pair_parts = take(8 * (size_t)clmax);
+    L.fnear = take(16 * (size_t)c);
+    L.qpart = take(16 * (size_t)((c + 255) / 256));
+    L.total = o;
+    return L;
+}
+
+size_t atom_workspace_bytes(useries_plan_t p, int64_t n) { return atom_layout(p->hp, n).total; }
+
+AtomWs atom_workspace_at(useries_plan_t p, int64_t n, char* base) {
+    const AtomLayout L = atom_layout(p->hp, n);
+    AtomWs w;
+    w.coord = (uint4*)(base + L.coord);
+    w.sorted = (uint4*)(base + L.sorted);
+    w.perm = (int*)(base + L.perm);
+    w.slots = (int*)(base + L.slots);
+    w.cl_info = (int2*)(base + L.cl_info);
+    w.cl_col = (int*)(base + L.cl_col);
+    w.cl_z = (uint2*)(base + L.cl_z);
+    w.pair_parts = (double*)(base + L.pair_parts);
+    w.fnear = (float4*)(base + L.fnear);
+    w.qpart = (double*)(base + L.qpart);
+    return w;
+}
+
+int plan_eval(useries_plan_t p, int64_t n, const float* xyz, const float* q, float* forces,
+              double* energy, double* parts, void* stream, const AtomWs* ext) {
     if (!p) return fail(USERIES_EINVAL, "NULL plan");
     if (n < 0 || n > INT_MAX / 4) return fail(USERIES_EINVAL, "n out of range");
     if (n > 0 && (!xyz || !q || !forces)) return fail(USERIES_EINVAL, "NULL buffer");
     DeviceGuard guard(p->device);
     hipStream_t st = (hipStream_t)stream;
-    if (n > p->cap || !p->coord) {
-        if (p->fixed_cap) return fail(USERIES_EINVAL, "n exceeds max_atoms");
-        hipStreamSynchronize(st);
-        int r = p->alloc_atoms(n);
-        if (r) return r;
+    AtomWs own;
+    if (!ext) {
+        if (n > p->cap || !p->coord) {
+            if (p->fixed_cap) return fail(USERIES_EINVAL, "n exceeds max_atoms");
+            hipStreamSynchronize(st);
+            int r = p->alloc_atoms(n);
+            if (r) return r;
+        }
+        own.coord = p->coord;
+        own.sorted = p->sorted;
+        own.perm = p->perm;
+        own.slots = p->slots;
+        own.cl_info = p->cl_info;
+        own.cl_col = p->cl_col;
+        own.cl_z = p->cl_z;
+        own.pair_parts = p->pair_parts;
+        own.fnear = p->fnear;
+        own.qpart = p->qpart;
     }
+    const AtomWs& W = ext ? *ext : own;
     HostPlan& hp = p->hp;
     const int ni = (int)n;
     const int nq = (ni + 255) / 256;
@@ -318,47 +386,51 @@ static int eval_impl(useries_plan_t p, int64_t n, const float* xyz, const float*
     const float* kx = (const float*)p->kx;
     const float* ky = (const float*)p->ky;
     const float* kz = (const float*)p->kz;
-    USERIES_STEP(0, st, launch_encode(hp.bin, xyz, q, p->coord, p->col_count, p->qpart,
+    USERIES_STEP(0, st, launch_encode(hp.bin, xyz, q, W.coord, p->col_count, W.qpart,
                                       nq, st));
     if (!scan_fused(ni, ncol))
         USERIES_STEP(1, st, launch_scan(ncol, p->col_count, p->col_start, p->clus_start,
-                                        p->col_fill, p->qpart, nq, p->qstats, st));
-    USERIES_STEP(2, st, launch_scatter(hp.bin, p->coord, p->sorted, p->col_count, p->col_start,
-                                       p->clus_start, p->col_fill, p->slots, p->qpart, nq,
+                                        p->col_fill, W.qpart, nq, p->qstats, st));
+    USERIES_STEP(2, st, launch_scatter(hp.bin, W.coord, W.sorted, p->col_count, p->col_start,
+                                       p->clus_start, p->col_fill, W.slots, W.qpart, nq,
                                        p->qstats, st));
-    USERIES_STEP(3, st, launch_colsort(ncol, hp.bin.nc[0], p->col_start, p->clus_start, p->slots,
-                                       p->coord,
-                                       p->perm, p->sorted, p->cl_info, p->cl_col, p->cl_z,
+    USERIES_STEP(3, st, launch_colsort(ncol, hp.bin.nc[0], p->col_start, p->clus_start, W.slots,
+                                       W.coord,
+                                       W.perm, W.sorted, W.cl_info, W.cl_col, W.cl_z,
                                        hp.grid[2], p->zbin, p->col_count, p->col_fill, st));
-    USERIES_STEP(4, st, launch_pair(hp.pair, npb, p->sorted, p->clus_start, p->cl_info, p->cl_col,
-                                    p->cl_z, p->zbin, p->fnear, p->pair_parts, st));
-    USERIES_STEP(5, st, launch_spread(hp.gridargs, p->sorted, p->zbin, p->qstats, p->rho, st));
+    USERIES_STEP(4, st, launch_pair(hp.pair, npb, W.sorted, p->clus_start, W.cl_info, W.cl_col,
+                                    W.cl_z, p->zbin, W.fnear, W.pair_parts, st));
+    USERIES_STEP(5, st, launch_spread(hp.gridargs, W.sorted, p->zbin, p->qstats, p->rho, st));
     USERIES_STEP(6, st, launch_conv_xy(hp.conv, p->rho, kx, ky, p->tgrid, st));
     USERIES_STEP(7, st, launch_conv_z(hp.conv, p->tgrid, kz, p->phi, st));
-    USERIES_STEP(8, st, launch_gather(hp.gridargs, p->sorted, p->perm, p->zbin, p->phi, p->fnear,
+    USERIES_STEP(8, st, launch_gather(hp.gridargs, W.sorted, W.perm, p->zbin, p->phi, W.fnear,
                                       forces, p->gather_parts, st));
-    USERIES_STEP(9, st, launch_finalize(hp.fin, p->pair_parts, p->gather_parts, p->qstats, energy,
+    USERIES_STEP(9, st, launch_finalize(hp.fin, W.pair_parts, p->gather_parts, p->qstats, energy,
                                         parts, st));
 #undef USERIES_STEP
     return USERIES_OK;
 }
 
+}  // namespace useries
+
+extern "C" {
+
 int useries_eval(useries_plan_t p, int64_t n, const float* xyz, const float* q, float* forces,
                  double* energy, void* stream) {
     if (!energy) return fail(USERIES_EINVAL, "NULL energy");
-    return eval_impl(p, n, xyz, q, forces, energy, nullptr, stream);
+    return plan_eval(p, n, xyz, q, forces, energy, nullptr, stream, nullptr);
 }
 
 int useries_eval_parts(useries_plan_t p, int64_t n, const float* xyz, const float* q,
                        float* forces, double* energy, double* parts, void* stream) {
     if (!parts) return fail(USERIES_EINVAL, "NULL parts");
-    return eval_impl(p, n, xyz, q, forces, energy, parts, stream);
+    return plan_eval(p, n, xyz, q, forces, energy, parts, stream, nullptr);
 }
 
 int useries_plan_info(useries_plan_t p, double* b, double* sigma, double* r0, double* w0,
                       double* s0, int* n_terms, double* eq33, double* f_inf0, double* c1_slope,
                       double* sigma_s, int* stencil_half, int ncell[3], double* poly_maxerr,
-                      int* n_terms_grid) {
+                      int* n_terms_grid, int* near_exact) {
     if (!p) return fail(USERIES_EINVAL, "NULL plan");
     const HostPlan& hp = p->hp;
     if (b) *b = hp.b;
@@ -379,6 +451,7 @@ int useries_plan_info(useries_plan_t p, double* b, double* sigma, double* r0, do
     }
     if (poly_maxerr) *poly_maxerr = hp.poly_maxerr;
     if (n_terms_grid) *n_terms_grid = hp.conv.nterms;
+    if (near_exact) *near_exact = hp.near_exact;
     return USERIES_OK;
 }
 

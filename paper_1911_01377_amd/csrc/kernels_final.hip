@@ -9,7 +9,7 @@ __device__ __forceinline__ void finalize_body(const FinalArgs& a, const double* 
                                               const double* __restrict__ qstats,
                                               double* __restrict__ energy,
                                               double* __restrict__ parts) {
-    __shared__ double wred[2 * 1024 / 64];
+    __shared__ double wred[3 * 1024 / 64];
     energy_total<1024>(a, pp, gp, qstats, energy, parts, wred);
 }
 

@@ -298,7 +298,7 @@ __host__ __device__ inline GatherLds gather_lds(int P) {
     L.pbeg = take(4 * kGatherMaxPieces);
     L.poff = take(4 * (kGatherMaxPieces + 1));
     L.wtot = take(4 * kGatherWaves);
-    L.se = take(8 * kGatherWaves);
+    L.se = take(16 * kGatherWaves);
     L.total = o;
     return L;
 }
@@ -313,7 +313,8 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                                             const float* __restrict__ phi,
                                             const float4* __restrict__ fnear,
                                             float* __restrict__ forces,
-                                            double* __restrict__ epart, char* lds) {
+                                            double* __restrict__ epart,
+                                            double* __restrict__ phisum, char* lds) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, l16 = lane & 15;
     const int P = PT > 0 ? PT : a.P, P2 = 2 * P, GB = gather_brick(P);
@@ -336,9 +337,14 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
     // potential on the brick and halo: local (hx, hy, hz) = global (X0 - P + 1 + hx, ...)
     const float inv0 = 1.0f / (float)E0, inv1 = 1.0f / (float)E1;
     const int nh = E0 * E1 * E2;
+    // sum of the potential over the brick's own points (each grid point lies
+    // in exactly one brick): its total over the blocks is the grid's k = 0
+    // component, which the far energy must not contain
+    double phs = 0.0;
     // the loads of a pass are issued together, then stored
     for (int base = tid; base < nh; base += kGatherThreads * kGatherBatch) {
         float v[kGatherBatch];
+        bool inb[kGatherBatch];
 #pragma unroll
         for (int u = 0; u < kGatherBatch; ++u) {
             const int idx = base + kGatherThreads * u;
@@ -348,11 +354,14 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
             const int gy = wrap1(Y0 - P + 1 + hy, a.g[1]);
             const int gz = wrap1(Z0 - P + 1 + hz, a.g[2]);
             v[u] = idx < nh ? phi[((size_t)gz * a.g[1] + gy) * a.g[0] + gx] : 0.0f;
+            inb[u] = idx < nh && (unsigned)(hx - (P - 1)) < (unsigned)B0 &&
+                     (unsigned)(hy - (P - 1)) < (unsigned)B1 && (unsigned)(hz - (P - 1)) < (unsigned)B2;
         }
 #pragma unroll
         for (int u = 0; u < kGatherBatch; ++u) {
             const int idx = base + kGatherThreads * u;
             if (idx < nh) sphi[idx] = v[u];
+            if (inb[u]) phs += (double)v[u];
         }
     }
     // stencil rows (ky, kz) of a charge and their offsets in the halo, once per block
@@ -492,12 +501,20 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
         }
         __syncthreads();
     }
-    if (lane == 0) se[wave] = e_wave;
+    phs = wave_sum_d(phs);
+    if (lane == 0) {
+        se[2 * wave] = e_wave;
+        se[2 * wave + 1] = phs;
+    }
     __syncthreads();
     if (tid == 0) {
-        double es = 0.0;
-        for (int w = 0; w < kGatherWaves; ++w) es += se[w];
+        double es = 0.0, ps = 0.0;
+        for (int w = 0; w < kGatherWaves; ++w) {
+            es += se[2 * w];
+            ps += se[2 * w + 1];
+        }
         epart[bid] = es;
+        phisum[bid] = ps;
     }
 }
 
@@ -512,7 +529,8 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(GridArgs a, int nb,
                                                 double* __restrict__ epart) {
     extern __shared__ char dyn[];
     const int item = xcd_item(blockIdx.x, nb);
-    if (item < nb) gather_body<PT>(a, item, sorted, perm, zbin, phi, fnear, forces, epart, dyn);
+    if (item < nb)
+        gather_body<PT>(a, item, sorted, perm, zbin, phi, fnear, forces, epart, epart + nb, dyn);
 }
 
 // PT > 0 only when every box of the batch has stencil half width PT
@@ -523,7 +541,7 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather_batch(const BatchTabl
     batch_for(tab, BK_GATHER, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
         gather_body<PT>(d.grid, item, d.sorted, d.perm, d.zbin, d.phi, d.fnear, d.forces,
-                        d.gather_parts, dyn);
+                        d.gather_parts, d.gather_parts + d.ngb, dyn);
     });
 }
 

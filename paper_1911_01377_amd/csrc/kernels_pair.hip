@@ -47,12 +47,17 @@ __device__ __forceinline__ float to_vgpr(float s) {
 
 // Polynomial coefficients held in registers (compile-time degree, fully
 // unrolled): F = c0 + x P(x) with c0 carried as hi + lo, and G = F'(r)/r,
-// each fitted separately in FP64 on the host.
-template <int DEG>
+// each fitted separately in FP64 on the host.  EXACT: the ne (<= kMaxExact)
+// narrowest far terms are not in the polynomials but evaluated as
+// Gaussians, a_j 2^(x ex_j) in F and -a_j/s_j^2 2^(x ex_j) in G (small b puts
+// them deep inside r_c, where no polynomial of modest degree follows them).
+template <int DEG, bool EXACT>
 struct Poly {
     float c[DEG + 1];
     float c0lo;
     float d[DEG + 1];
+    int ne;
+    float ex[EXACT ? kMaxExact : 1], ea[EXACT ? kMaxExact : 1], eg[EXACT ? kMaxExact : 1];
     __device__ __forceinline__ explicit Poly(const PairArgs& a) {
 #pragma unroll
         for (int m = 0; m <= DEG; ++m) {
@@ -60,6 +65,15 @@ struct Poly {
             d[m] = a.d[m];
         }
         c0lo = a.c0lo;
+        ne = a.ne;
+        if (EXACT) {
+#pragma unroll
+            for (int j = 0; j < kMaxExact; ++j) {
+                ex[j] = a.ex[j];
+                ea[j] = a.ea[j];
+                eg[j] = a.eg[j];
+            }
+        }
     }
 };
 
@@ -84,8 +98,9 @@ __device__ __forceinline__ StencilCol stencil_col(int k, int ci, int R, int nc, 
 // nsteps steps of 8 staged j-charges (st8[s * 8 + ja]) against i-charge ci.
 // CUBIC: distances in fixed-point units (one scale for all axes), qw = q_i u,
 // rc2/irc2 in those units and is = 1/u; otherwise distances in A, qw = q_i.
-template <int DEG, bool CUBIC>
-__device__ __forceinline__ void pair_steps(const Poly<DEG>& P, const uint4* st8, int ja, int nsteps,
+template <int DEG, bool CUBIC, bool EXACT>
+__device__ __forceinline__ void pair_steps(const Poly<DEG, EXACT>& P, const uint4* st8, int ja,
+                                           int nsteps,
                                            uint4 ci, float qw, float sx, float sy, float sz,
                                            float rc2, float irc2, float is, float ctop, float dtop,
                                            float& fx, float& fy, float& fz, float& ec) {
@@ -113,7 +128,18 @@ __device__ __forceinline__ void pair_steps(const Poly<DEG>& P, const uint4* st8,
             float G = fmaf(dtop, x, P.d[DEG - 1]);
 #pragma unroll
             for (int m = DEG - 2; m >= 0; --m) G = fmaf(G, x, P.d[m]);
-            ec = fmaf(qq, (rinv - P.c[0]) - Flo, ec);
+            float Fe = 0.0f;
+            if (EXACT) {
+#pragma unroll
+                for (int j = 0; j < kMaxExact; ++j) {
+                    if (j < P.ne) {   // uniform: a scalar branch
+                        const float e = __builtin_amdgcn_exp2f(x * P.ex[j]);
+                        Fe = fmaf(P.ea[j], e, Fe);
+                        G = fmaf(P.eg[j], e, G);
+                    }
+                }
+            }
+            ec = fmaf(qq, ((rinv - P.c[0]) - Flo) - Fe, ec);
             const float fs = qq * fmaf(rinv * rinv, rinv, G);
             fx = fmaf(fs, dx, fx);
             fy = fmaf(fs, dy, fy);
@@ -122,7 +148,7 @@ __device__ __forceinline__ void pair_steps(const Poly<DEG>& P, const uint4* st8,
     }
 }
 
-template <int DEG>
+template <int DEG, bool EXACT>
 __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4* __restrict__ sorted,
                                           const int* __restrict__ clus_start,
                                           const int2* __restrict__ cl_info,
@@ -145,7 +171,7 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         if (tid == 0) epart[I] = 0.0;
         return;
     }
-    const Poly<DEG> P(a);
+    const Poly<DEG, EXACT> P(a);
     const int2 ii = cl_info[I];
     const int C = cl_col[I];                  // cx | cy << 16
     const uint2 zI = cl_z[I];
@@ -337,10 +363,10 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         const int nsteps = (kept + 7) >> 3;
         float ec = 0.0f;
         if (cubic)
-            pair_steps<DEG, true>(P, stage[w], ja, nsteps, ci, qw, sx, sx, sx, rc2w, irc2w, isx,
+            pair_steps<DEG, true, EXACT>(P, stage[w], ja, nsteps, ci, qw, sx, sx, sx, rc2w, irc2w, isx,
                                   ctop, dtop, fx, fy, fz, ec);
         else
-            pair_steps<DEG, false>(P, stage[w], ja, nsteps, ci, qw, sx, sy, sz, rc2w, irc2w, 1.0f,
+            pair_steps<DEG, false, EXACT>(P, stage[w], ja, nsteps, ci, qw, sx, sy, sz, rc2w, irc2w, 1.0f,
                                    ctop, dtop, fx, fy, fz, ec);
         e += (double)ec;
         wave_sync();
@@ -366,7 +392,7 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     }
 }
 
-template <int DEG>
+template <int DEG, bool EXACT>
 __global__ void __launch_bounds__(64 * kPairWaves) k_pair(PairArgs a, int nb,
                                              const uint4* __restrict__ sorted,
                                              const int* __restrict__ clus_start,
@@ -378,19 +404,20 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pair(PairArgs a, int nb,
                                              double* __restrict__ epart) {
     const int item = xcd_item(blockIdx.x, nb);
     if (item < nb)
-        pair_body<DEG>(a, item, sorted, clus_start, cl_info, cl_col, cl_z, zbin, fnear, epart);
+        pair_body<DEG, EXACT>(a, item, sorted, clus_start, cl_info, cl_col, cl_z, zbin, fnear,
+                              epart);
 }
 
 // Held to 80 registers (6 wavefronts per SIMD instead of 5; the batch walk
 // costs 8-12 bytes of spill per lane): about 2% more batched evaluations/s.
-template <int DEG>
+template <int DEG, bool EXACT>
 __global__ void __launch_bounds__(64 * kPairWaves) __attribute__((amdgpu_waves_per_eu(6)))
 k_pair_batch(const BatchTable* __restrict__ tab,
                                                    const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_PAIR, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        pair_body<DEG>(d.pair, item, d.sorted, d.clus_start, d.cl_info, d.cl_col, d.cl_z, d.zbin,
-                       d.fnear, d.pair_parts);
+        pair_body<DEG, EXACT>(d.pair, item, d.sorted, d.clus_start, d.cl_info, d.cl_col, d.cl_z,
+                              d.zbin, d.fnear, d.pair_parts);
     });
 }
 
@@ -399,11 +426,16 @@ hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, cons
                        float4* fnear, double* epart, hipStream_t st) {
     if (nblocks <= 0) return hipSuccess;
     const dim3 grid(xcd_blocks(nblocks)), block(64 * kPairWaves);
+    const bool exact = a.ne > 0;
     switch (a.deg) {
 #define USERIES_PAIR_DEG(D)                                                                   \
     case D:                                                                                   \
-        hipLaunchKernelGGL(k_pair<D>, grid, block, 0, st, a, nblocks, sorted, clus_start,     \
-                           cl_info, cl_col, cl_z, zbin, fnear, epart);                        \
+        if (exact)                                                                            \
+            hipLaunchKernelGGL((k_pair<D, true>), grid, block, 0, st, a, nblocks, sorted,     \
+                               clus_start, cl_info, cl_col, cl_z, zbin, fnear, epart);        \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_pair<D, false>), grid, block, 0, st, a, nblocks, sorted,    \
+                               clus_start, cl_info, cl_col, cl_z, zbin, fnear, epart);        \
         break;
         USERIES_PAIR_DEG(4) USERIES_PAIR_DEG(5) USERIES_PAIR_DEG(6) USERIES_PAIR_DEG(7)
         USERIES_PAIR_DEG(8) USERIES_PAIR_DEG(9) USERIES_PAIR_DEG(10) USERIES_PAIR_DEG(11)
@@ -415,12 +447,17 @@ hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, cons
     return hipGetLastError();
 }
 
-hipError_t launch_pair_batch(const BatchTable* tab, const BoxDesc* desc, int deg, int grid,
-                             hipStream_t st) {
+hipError_t launch_pair_batch(const BatchTable* tab, const BoxDesc* desc, int deg, bool exact,
+                             int grid, hipStream_t st) {
     switch (deg) {
 #define USERIES_PAIR_DEG(D)                                                                   \
     case D:                                                                                   \
-        hipLaunchKernelGGL(k_pair_batch<D>, dim3(grid), dim3(64 * kPairWaves), 0, st, tab, desc); \
+        if (exact)                                                                            \
+            hipLaunchKernelGGL((k_pair_batch<D, true>), dim3(grid), dim3(64 * kPairWaves), 0, \
+                               st, tab, desc);                                                \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_pair_batch<D, false>), dim3(grid), dim3(64 * kPairWaves),   \
+                               0, st, tab, desc);                                             \
         break;
         USERIES_PAIR_DEG(4) USERIES_PAIR_DEG(5) USERIES_PAIR_DEG(6) USERIES_PAIR_DEG(7)
         USERIES_PAIR_DEG(8) USERIES_PAIR_DEG(9) USERIES_PAIR_DEG(10) USERIES_PAIR_DEG(11)

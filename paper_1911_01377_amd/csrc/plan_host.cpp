@@ -109,14 +109,40 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     s.f_inf(r_c, &dF);
     p.c1_slope = -1.0 / (r_c * r_c) - dF;
 
-    // near part
+    // near part: F_inf and F_inf'/r inside the cutoff as polynomials in
+    // r^2 / r_c^2 after the narrowest `ne` terms, which the pair kernel
+    // evaluates as Gaussians.  Small b puts the narrowest Gaussians deep
+    // inside r_c (u = r_c / s_j up to 5.6 for Table 1 row 3), where a
+    // polynomial of modest degree cannot follow them; ne is the smallest count
+    // whose remainder fits within the form's budget relative to max |F|
+    // (FP32 level 1e-7 for the plain path, 2e-5 for BF16X3, whose force
+    // budget is 1e-3).
+    const double budget = bf ? 2e-5 : 1e-7;
     double coef[kMaxPolyDeg + 1], gcoef[kMaxPolyDeg + 1];
-    p.poly_maxerr = fit_near_poly(s, r_c, deg, coef, gcoef);
+    int ne = 0;
+    for (;; ++ne) {
+        p.poly_maxerr = fit_near_poly(s, r_c, deg, ne, coef, gcoef);
+        if (p.poly_maxerr <= budget) break;
+        if (ne == kMaxExact)
+            return fail(err, USERIES_EINVAL,
+                        "near part: the polynomial of this degree misses the form's accuracy "
+                        "even with the 8 narrowest Gaussians evaluated exactly (raise "
+                        "poly_degree or b)");
+    }
+    p.near_exact = ne;
     PairArgs& pa = p.pair;
     pa.deg = deg;
+    pa.ne = ne;
     for (int k = 0; k <= deg; ++k) pa.c[k] = (float)coef[k];
     pa.c0lo = (float)(coef[0] - (double)pa.c[0]);
     for (int k = 0; k <= deg; ++k) pa.d[k] = (float)gcoef[k];
+    for (int j = 0; j < kMaxExact; ++j) {
+        double aj = 0.0, sj = 1.0;
+        if (j < ne) s.term(j, &aj, &sj);
+        pa.ex[j] = (float)(-1.4426950408889634 * r_c * r_c / (2.0 * sj * sj));
+        pa.ea[j] = (float)aj;
+        pa.eg[j] = (float)(-aj / (sj * sj));
+    }
     pa.gz = grid[2];
     pa.rc2 = (float)(r_c * r_c);
     pa.inv_rc2 = (float)(1.0 / (r_c * r_c));
@@ -216,6 +242,7 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     const double V = box[0] * box[1] * box[2];
     p.fin.f_inf0 = p.f_inf0;
     p.fin.near_int_over_v = s.near_integral(r_c) / V;
+    p.fin.inv_ngrid = ga.inv_ngrid;
     return USERIES_OK;
 }
 

@@ -334,8 +334,8 @@ double Series::g_inf(double r) const {
 namespace {
 
 // Chebyshev interpolation of f on x in [0, 1] at degree+1 Chebyshev nodes,
-// converted to monomial coefficients in x; returns the max error relative to
-// max |f| on a fine sample.
+// converted to monomial coefficients in x; returns the max absolute error on
+// a fine sample.
 template <class Fn>
 double fit_poly01(Fn f, int degree, double* coef) {
     const int m = degree + 1;
@@ -375,63 +375,71 @@ double fit_poly01(Fn f, int degree, double* coef) {
             coef[k] += cheb[j] * tc[k];
         }
     }
-    double maxerr = 0.0, maxf = 0.0;
+    double maxerr = 0.0;
     for (int i = 0; i <= 4000; ++i) {
         const double x = i / 4000.0;
         double p = 0.0;
         for (int k = degree; k >= 0; --k) p = p * x + coef[k];
-        const double v = f(x);
-        maxerr = std::fmax(maxerr, std::fabs(p - v));
-        maxf = std::fmax(maxf, std::fabs(v));
+        maxerr = std::fmax(maxerr, std::fabs(p - f(x)));
     }
-    return maxerr / maxf;
+    return maxerr;
 }
 
 }  // namespace
 
 namespace {
 
-// the fit of the series with sigma = 1 on [0, u] (u = r_c / sigma)
-double fit_near_poly_unit(const Series& s, double rc, int degree, double* fcoef, double* gcoef) {
-    // F_inf(r) and F_inf'(r)/r as polynomials in x = r^2 / rc^2, fitted
-    // separately.  The terms are tabulated once; the sums run in the same
-    // order and with the same expressions as Series::f_inf and Series::g_inf.
+// The fit of the series with sigma = 1 on [0, u] (u = r_c / sigma): F_inf(r)
+// and F_inf'(r)/r minus their first `nexact` terms, as polynomials in
+// x = r^2 / rc^2, fitted separately.  The terms are tabulated once; the sums
+// run in the same order and with the same expressions as Series::f_inf and
+// Series::g_inf.  The errors are relative to the full functions' maxima,
+// F_inf(0) and |F_inf'/r|(0) (all terms decrease with r).
+double fit_near_poly_unit(const Series& s, double rc, int degree, int nexact, double* fcoef,
+                          double* gcoef) {
     const int len = s.length();
     std::vector<double> ta(len), ts(len);
     for (int j = 0; j < len; ++j) s.term(j, &ta[j], &ts[j]);
     auto f = [&](double x) {
         const double r = rc * std::sqrt(x);
         double v = 0.0;
-        for (int j = len - 1; j >= 0; --j) v += ta[j] * std::exp(-r * r / (2.0 * ts[j] * ts[j]));
+        for (int j = len - 1; j >= nexact; --j) v += ta[j] * std::exp(-r * r / (2.0 * ts[j] * ts[j]));
         return v;
     };
     auto g = [&](double x) {
         const double r = rc * std::sqrt(x);
         double v = 0.0;
-        for (int j = len - 1; j >= 0; --j)
+        for (int j = len - 1; j >= nexact; --j)
             v -= ta[j] / (ts[j] * ts[j]) * std::exp(-r * r / (2.0 * ts[j] * ts[j]));
         return v;
     };
-    const double ef = fit_poly01(f, degree, fcoef);
-    const double eg = fit_poly01(g, degree, gcoef);
+    double fmax = 0.0, gmax = 0.0;
+    for (int j = len - 1; j >= 0; --j) {
+        fmax += ta[j];
+        gmax += ta[j] / (ts[j] * ts[j]);
+    }
+    const double ef = fit_poly01(f, degree, fcoef) / fmax;
+    const double eg = fit_poly01(g, degree, gcoef) / gmax;
     return std::fmax(ef, eg);
 }
 
 }  // namespace
 
-double fit_near_poly(const Series& s, double rc, int degree, double* fcoef, double* gcoef) {
+double fit_near_poly(const Series& s, double rc, int degree, int nexact, double* fcoef,
+                     double* gcoef) {
     // Every term scales with sigma: F(r; sigma) = F(r / sigma; 1) / sigma and
     // F'(r; sigma)/r = (F'/r)(r / sigma; 1) / sigma^3.  The fit is made once
-    // per (b, w0, s0, r_c / sigma, degree) at sigma = 1 and scaled.
+    // per (b, w0, s0, r_c / sigma, degree, nexact) at sigma = 1 and scaled.
     struct Key {
         double b, w0, s0, u;
-        int degree;
+        int degree, nexact;
         bool operator<(const Key& o) const {
             if (b != o.b) return b < o.b;
             if (w0 != o.w0) return w0 < o.w0;
             if (s0 != o.s0) return s0 < o.s0;
             if (u != o.u) return u < o.u;
-            return degree < o.degree;
+            if (degree != o.degree) return degree < o.degree;
+            return nexact < o.nexact;
         }
     };
     struct Fit {
@@ -439,7 +447,7 @@ double fit_near_poly(const Series& s, double rc, int degree, double* fcoef, doub
     };
     static std::mutex mu;
     static std::map<Key, Fit> cache;
-    const Key key{s.b, s.w0, s.s0, rc / s.sigma, degree};
+    const Key key{s.b, s.w0, s.s0, rc / s.sigma, degree, nexact};
     Fit fit;
     bool have = false;
     {
@@ -453,7 +461,7 @@ double fit_near_poly(const Series& s, double rc, int degree, double* fcoef, doub
     if (!have) {
         Series unit = s;
         unit.sigma = 1.0;
-        fit.err = fit_near_poly_unit(unit, key.u, degree, fit.f, fit.g);
+        fit.err = fit_near_poly_unit(unit, key.u, degree, nexact, fit.f, fit.g);
         std::lock_guard<std::mutex> lk(mu);
         if (cache.size() > 4096) cache.clear();
         cache[key] = fit;

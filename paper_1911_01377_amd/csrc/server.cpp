@@ -123,7 +123,7 @@ Layout make_layout(const HostPlan& hp, int n, int n_evals) {
     L.fnear = take(16 * c);
     L.qpart = take(16 * ((c + 255) / 256));
     L.pair_parts = take(8 * clmax);
-    L.gather_parts = take(8 * (size_t)gather_blocks(hp.gridargs));
+    L.gather_parts = take(16 * (size_t)gather_blocks(hp.gridargs));   // energies, phi sums
     L.qstats = take(16);
     L.col_start = take(4 * (ncm + 1));
     L.col_fill = take(4 * ncm);
@@ -195,7 +195,7 @@ struct useries_server_s {
     int grid[BK_COUNT] = {0};
     int lds_limit = 0;
     // by the dynamic LDS sizes and the stencil half width
-    std::map<std::tuple<size_t, size_t, size_t, int>, hipGraphExec_t> graphs;
+    std::map<std::tuple<size_t, size_t, size_t, int, bool>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_objs;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
@@ -243,15 +243,16 @@ struct useries_server_s {
     }
 
     // the kernels of one step, in order, on the server stream
-    // P: the stencil half width shared by the step's boxes, 0 if they differ
-    hipError_t enqueue_kernels(size_t lds, size_t lds_z, size_t lds_g, int P) {
+    // P: the stencil half width shared by the step's boxes, 0 if they differ;
+    // exact: some box evaluates leading far terms as Gaussians in its near part
+    hipError_t enqueue_kernels(size_t lds, size_t lds_z, size_t lds_g, int P, bool exact) {
         const bool bf = precision == USERIES_BF16X3;
         hipError_t e;
         if ((e = launch_encode_batch(d_table, d_desc, grid[BK_ENCODE], st))) return e;
         if ((e = launch_scan_batch(d_table, d_desc, grid[BK_SCAN], st))) return e;
         if ((e = launch_scatter_batch(d_table, d_desc, grid[BK_SCATTER], st))) return e;
         if ((e = launch_colsort_batch(d_table, d_desc, grid[BK_COLSORT], st))) return e;
-        if ((e = launch_pair_batch(d_table, d_desc, popts.poly_degree, grid[BK_PAIR], st))) return e;
+        if ((e = launch_pair_batch(d_table, d_desc, popts.poly_degree, exact, grid[BK_PAIR], st))) return e;
         if ((e = launch_spread_batch(d_table, d_desc, P, grid[BK_SPREAD], st))) return e;
         if ((e = launch_conv_xy_batch(d_table, d_desc, bf, lds, grid[BK_CONV_XY], st))) return e;
         if ((e = launch_conv_z_batch(d_table, d_desc, bf, lds_z, grid[BK_CONV_Z], st))) return e;
@@ -260,8 +261,9 @@ struct useries_server_s {
         return launch_displace_batch(d_table, d_desc, grid[BK_DISPLACE], st);
     }
 
-    hipError_t graph_for(size_t lds, size_t lds_z, size_t lds_g, int P, hipGraphExec_t* out) {
-        const std::tuple<size_t, size_t, size_t, int> key(lds, lds_z, lds_g, P);
+    hipError_t graph_for(size_t lds, size_t lds_z, size_t lds_g, int P, bool exact,
+                         hipGraphExec_t* out) {
+        const std::tuple<size_t, size_t, size_t, int, bool> key(lds, lds_z, lds_g, P, exact);
         auto it = graphs.find(key);
         if (it != graphs.end()) {
             *out = it->second;
@@ -269,7 +271,7 @@ struct useries_server_s {
         }
         hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e) return e;
-        const hipError_t el = enqueue_kernels(lds, lds_z, lds_g, P);
+        const hipError_t el = enqueue_kernels(lds, lds_z, lds_g, P, exact);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(st, &g);
         if (el) {
@@ -411,8 +413,10 @@ struct useries_server_s {
         for (int k = 0; k < BK_COUNT; ++k) T.off[k][0] = 0;
         size_t lds = 0, lds_z = 0, lds_g = 0;
         int P = -1;
+        bool exact = false;
         for (int i = 0; i < nb; ++i) {
             Req* R = active[i];
+            exact = exact || R->hp.near_exact > 0;
             T.slot[i] = R->slot;
             T.step[i] = R->step;
             for (int k = 0; k < BK_COUNT; ++k) {
@@ -432,9 +436,9 @@ struct useries_server_s {
             return e;
         if (o.use_graph) {
             hipGraphExec_t ex = nullptr;
-            if ((e = graph_for(lds, lds_z, lds_g, P, &ex))) return e;
+            if ((e = graph_for(lds, lds_z, lds_g, P, exact, &ex))) return e;
             if ((e = hipGraphLaunch(ex, st))) return e;
-        } else if ((e = enqueue_kernels(lds, lds_z, lds_g, P))) {
+        } else if ((e = enqueue_kernels(lds, lds_z, lds_g, P, exact))) {
             return e;
         }
         if ((e = hipEventRecord(ring_ev[r], st))) return e;

@@ -14,6 +14,7 @@ namespace useries {
 constexpr int kMaxTerms = 32;      // far Gaussians N
 constexpr int kMaxGrid = 128;      // grid points per axis
 constexpr int kMaxPolyDeg = 14;    // near polynomial degree
+constexpr int kMaxExact = 8;       // narrowest far terms evaluated as Gaussians in the near part
 constexpr int kMaxStencilHalf = 8; // P
 constexpr int kMaxStencilCols = 128;  // x-y columns within r_c of a column (pair kernel)
 constexpr int kMaxWindowCols = 256;   // x-y columns touching a spreading brick
@@ -39,9 +40,12 @@ int choose_nterms(double b, double sigma, double lmax, double tol);
 double bsa_bound(double b);
 
 // monomial coefficients in x = r^2/rc^2 on [0,1] of F_inf(r) (fcoef) and of
-// F_inf'(r)/r (gcoef), each fitted separately; returns the larger of the two
-// max errors relative to the function's max magnitude, on a fine sample.
-double fit_near_poly(const Series& s, double rc, int degree, double* fcoef, double* gcoef);
+// F_inf'(r)/r (gcoef) without their first `nexact` terms (which the pair
+// kernel evaluates as Gaussians), each fitted separately; returns the larger
+// of the two max errors relative to the full function's max magnitude, on a
+// fine sample.
+double fit_near_poly(const Series& s, double rc, int degree, int nexact, double* fcoef,
+                     double* gcoef);
 
 // first column k[m], m = 0..n-1, of the periodic circulant that convolves the
 // grid with a Gaussian of width sk (grid spacing h), scaled by `scale`.
@@ -65,9 +69,13 @@ struct PairArgs {
     float inv_rc2;        // 1 / r_c^2
     int gz;               // grid points along z (planes of the z-plane index)
     int deg;              // polynomial degree
-    float c[kMaxPolyDeg + 1];   // F_inf(r) = sum c_k x^k, x = r^2/rc^2
+    int ne;               // leading far terms evaluated as Gaussians (0..kMaxExact)
+    float c[kMaxPolyDeg + 1];   // F_inf(r) = sum_{j<ne} ea_j 2^(x ex_j) + sum c_k x^k, x = r^2/rc^2
     float c0lo;                 // c_0 - (float)c_0
-    float d[kMaxPolyDeg + 1];   // F_inf'(r)/r = sum d_k x^k
+    float d[kMaxPolyDeg + 1];   // F_inf'(r)/r = sum_{j<ne} eg_j 2^(x ex_j) + sum d_k x^k
+    float ex[kMaxExact];        // -log2(e) rc^2 / (2 s_j^2)
+    float ea[kMaxExact];        // a_j
+    float eg[kMaxExact];        // -a_j / s_j^2
 };
 
 struct GridArgs {
@@ -90,9 +98,10 @@ struct ConvArgs {
 
 struct FinalArgs {
     int n_pair_parts;
-    int n_gather_parts;
+    int n_gather_parts;   // gather blocks: 2 n_gather_parts partials (energies, then grid sums of phi)
     double f_inf0;        // self-term coefficient
     double near_int_over_v;   // int N d^3r / V (background)
+    double inv_ngrid;     // 1 / (gx gy gz): grid mean of phi from its sum
 };
 
 // ------------------------------------------------------------ host plan
@@ -104,6 +113,7 @@ struct HostPlan {
     double rc = 0, b = 2, sigma = 1, r0 = 1, w0 = 1, s0 = 1;
     int construction = USERIES_C1, precision = USERIES_PLAIN_FP32;
     int nterms = 0, P = 5, deg = 8;
+    int near_exact = 0;    // leading far terms the pair kernel evaluates as Gaussians
     int nterms_grid = 0;   // leading terms evaluated on the grid (the rest: k = 0 only)
     int grid[3] = {0, 0, 0};
     double eq33 = 0, f_inf0 = 0, c1_slope = 0, poly_maxerr = 0, sigma_s[3] = {0, 0, 0};
@@ -195,8 +205,9 @@ hipError_t launch_encode_batch(const BatchTable* tab, const BoxDesc* desc, int g
 hipError_t launch_scan_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
 hipError_t launch_scatter_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
 hipError_t launch_colsort_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
-hipError_t launch_pair_batch(const BatchTable* tab, const BoxDesc* desc, int deg, int grid,
-                             hipStream_t st);
+// exact: some box of the batch evaluates leading far terms as Gaussians (ne > 0)
+hipError_t launch_pair_batch(const BatchTable* tab, const BoxDesc* desc, int deg, bool exact,
+                             int grid, hipStream_t st);
 // P: the stencil half width of every box in the batch (compiled code for 3
 // and 5), or 0 when they differ
 hipError_t launch_spread_batch(const BatchTable* tab, const BoxDesc* desc, int P, int grid,
@@ -214,6 +225,30 @@ hipError_t launch_finalize_batch(const BatchTable* tab, const BoxDesc* desc, int
                                  hipStream_t st);
 hipError_t launch_displace_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
                                  hipStream_t st);
+
+// ------------------------------------------------------------ one-box evaluation
+// The per-charge workspace of one evaluation (device pointers).
+struct AtomWs {
+    uint4 *coord = nullptr, *sorted = nullptr;
+    int *perm = nullptr, *slots = nullptr;
+    int2* cl_info = nullptr;
+    int* cl_col = nullptr;
+    uint2* cl_z = nullptr;
+    double* pair_parts = nullptr;
+    float4* fnear = nullptr;
+    double* qpart = nullptr;
+};
+
+// The evaluation sequence of useries_eval / useries_eval_parts.  ws == NULL:
+// the plan's own per-charge workspace (grown with hipMalloc when n exceeds
+// it); otherwise the given one, and nothing is allocated.
+int plan_eval(useries_plan_t p, int64_t n, const float* xyz, const float* q, float* forces,
+              double* energy, double* parts, void* stream, const AtomWs* ws);
+// bytes of the per-charge workspace of n charges, and its arrays at `base`
+// (device memory of that many bytes, 256-byte aligned)
+size_t atom_workspace_bytes(useries_plan_t p, int64_t n);
+AtomWs atom_workspace_at(useries_plan_t p, int64_t n, char* base);
+int plan_device(useries_plan_t p);
 
 // ------------------------------------------------------------ kernel launchers
 // All launchers enqueue on `st` and return hipGetLastError().
@@ -245,6 +280,8 @@ hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx,
                           const float* ky, float* tgrid, hipStream_t st);
 hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz, float* phi,
                          hipStream_t st);
+// epart: 2 gather_blocks(a) doubles, the blocks' far energies then their
+// sums of phi over their own grid points
 hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm, const int* zbin,
                          const float* phi, const float4* fnear, float* forces, double* epart,
                          hipStream_t st);

@@ -48,16 +48,56 @@ def rel_rms(f, g):
     return math.sqrt(np.sum((f - g) ** 2) / den) if den > 0 else math.sqrt(np.sum(f ** 2))
 
 
-def compare(tag, xyz, q, box, rc, grid, e_tol, f_tol, **kw):
+def max_atom_err(f, g):
+    """Largest per-charge force error, each relative to the larger of that
+    charge's reference force and the RMS reference force; returns (error,
+    index, |F_ref| / rms of that charge)."""
+    if len(g) == 0:
+        return 0.0, -1, 0.0
+    rms = math.sqrt(np.mean(np.sum(g ** 2, axis=1)))
+    mag = np.sqrt(np.sum(g ** 2, axis=1))
+    if rms == 0.0:    # forces that vanish by symmetry (one charge): absolute errors
+        err = np.sqrt(np.sum((f - g) ** 2, axis=1))
+        k = int(np.argmax(err))
+        return float(err[k]), k, 0.0
+    err = np.sqrt(np.sum((f - g) ** 2, axis=1)) / np.maximum(mag, rms)
+    k = int(np.argmax(err))
+    return float(err[k]), k, float(mag[k] / rms) if rms > 0 else 0.0
+
+
+# A single charge may err by at most this multiple of the RMS force tolerance,
+# relative to its own force or, for charges with less than the RMS force, to
+# the RMS force: an error confined to a few charges (a mis-binned charge at a
+# column or brick edge) does not show in the RMS.  (Random charges have a
+# heavy-tailed force distribution, close pairs with forces far above the
+# RMS, whose FP32 error is relative to their own force.)
+ATOM_FACTOR = 10.0
+
+
+def compare(tag, xyz, q, box, rc, grid, e_tol, f_tol, e_scale="total", **kw):
+    """GPU vs oracle on the same inputs.  The energy error is relative to
+    |E_total| (e_scale="total"), or, for random charges whose total is a
+    small difference of much larger parts, to |E_near| + |E_far| + |E_self|
+    (e_scale="parts"): each part carries its own rounding, relative to its
+    own size, whatever the cancellation between them."""
     log("case %s: n=%d box=%s rc=%g grid=%s %s" % (tag, len(q), tuple(box), rc, tuple(grid), kw))
     gparts, gf, info = gpu_eval(xyz, q, box, rc, grid, **kw)
     oparts, of = oracle_eval(xyz, q, box, info, rc)
-    de = abs(gparts[4] - oparts["total"]) / max(abs(oparts["total"]), 1e-300)
+    if e_scale == "parts":
+        escale = abs(oparts["near"]) + abs(oparts["far"]) + abs(oparts["self"])
+    else:
+        escale = abs(oparts["total"])
+    de = abs(gparts[4] - oparts["total"]) / max(escale, 1e-300)
     df = rel_rms(gf, of)
-    log("   E_gpu=%.12g E_oracle=%.12g dE=%.2e dF=%.2e" % (gparts[4], oparts["total"], de, df))
+    da, ka, ma = max_atom_err(gf, of)
+    log("   E_gpu=%.12g E_oracle=%.12g dE=%.2e (vs %s) dF=%.2e max_i|dF_i|/max(|F_i|,rms)=%.2e "
+        "(charge %d, |F|=%.2f rms) (N=%d, exact near terms %d)"
+        % (gparts[4], oparts["total"], de, e_scale, df, da, ka, ma, info["n_terms"],
+           info["near_exact"]))
     for k, name in enumerate(("near", "far", "self", "bg")):
         log("   %-4s gpu=%.15g oracle=%.15g diff=%.3e"
             % (name, gparts[k], oparts[name], gparts[k] - oparts[name]))
     assert de <= e_tol, (tag, de)
     assert df <= f_tol, (tag, df)
+    assert da <= ATOM_FACTOR * f_tol, (tag, da)
     return gparts, gf, oparts, of, info

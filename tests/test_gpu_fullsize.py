@@ -69,11 +69,17 @@ def test_fullsize(name, form, e_tol, f_tol):
     idx = np.array(g["sample_idx"])
     fo = np.array(g["sample_forces"])
     df = math.sqrt(np.sum((f[idx] - fo) ** 2) / np.sum(fo ** 2))
-    log("   E_gpu=%.12g E_oracle=%.12g dE=%.2e dF(512 sampled)=%.2e"
-        % (p[4], gp["total"], de, df))
+    # largest error of one sampled charge, relative to the larger of its own
+    # force and the full RMS force
+    mag = np.sqrt(np.sum(fo ** 2, axis=1))
+    da = float((np.sqrt(np.sum((f[idx] - fo) ** 2, axis=1))
+                / np.maximum(mag, g["force_rms"])).max())
+    log("   E_gpu=%.12g E_oracle=%.12g dE=%.2e dF(512 sampled)=%.2e max|dF_i|/max(|F_i|,rms)=%.2e"
+        % (p[4], gp["total"], de, df, da))
     for k, nm in enumerate(("near", "far", "self", "bg")):
         log("   %-4s gpu=%.15g oracle=%.15g" % (nm, p[k], gp[nm]))
     assert de <= e_tol
     assert df <= f_tol
+    assert da <= 10.0 * f_tol
     # the force sum of a periodic system vanishes up to rounding
     assert np.linalg.norm(f.sum(axis=0)) <= 1e-3 * math.sqrt(len(q)) * g["force_rms"]
