@@ -168,6 +168,24 @@ int useries_eval_parts(useries_plan_t plan, int64_t n, const float *xyz, const f
                        float *forces, double *energy, double *parts, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * useries_eval_parts (energy and parts may each be NULL, not both), with
+ * the per-charge workspace (encoded and sorted positions, permutation,
+ * cluster table, near forces, energy partials) in a fixed 16 MiB device
+ * array of the library instead of memory the plan allocates on demand; the
+ * call allocates nothing.  Enough for about 270,000 charges (the exact limit
+ * depends on the plan's column grid); a larger n fails with USERIES_EINVAL
+ * before anything is launched.  Each GPU holds one such array for the whole
+ * process, shared by every plan on it: calls that overlap on one GPU (other
+ * streams, other threads) race on it and must be ordered by the caller.
+ * Errors: as useries_eval_parts, and USERIES_EHIP if the array's device
+ * address cannot be obtained.
+ */
+int useries_eval_static(useries_plan_t plan, int64_t n, const float *xyz, const float *q,
+                        float *forces, double *energy, double *parts, void *stream);
+
+/*
  * Host copies of the plan's parameters (any pointer may be NULL):
  *   b, sigma, r0 (= r_c / sigma), w0, s0, n_terms, eq33 (the eq. 33 bound at
  *   n_terms with L = max edge), f_inf0 (F(0) of the infinite series, the

@@ -46,6 +46,7 @@ EXPORTED = [
     "useries_wait", "useries_request_times", "useries_server_stats", "useries_server_destroy",
     "useries_server_hold",
     "useries_philox4x32_10",
+    "useries_eval_static",
 ]
 
 
@@ -115,6 +116,7 @@ def lib():
         "useries_server_destroy": (I, [P]),
         "useries_server_hold": (I, [P, I]),
         "useries_philox4x32_10": (None, [P, P, P]),
+        "useries_eval_static": (I, [P, I64, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -169,6 +171,11 @@ def useries_eval(plan, n, xyz, q, forces, energy, stream=0):
 def useries_eval_parts(plan, n, xyz, q, forces, energy, parts, stream=0):
     _check(lib().useries_eval_parts(plan, int(n), xyz, q, forces, energy or None, parts,
                                     stream or None))
+
+
+def useries_eval_static(plan, n, xyz, q, forces, energy, parts, stream=0):
+    _check(lib().useries_eval_static(plan, int(n), xyz, q, forces, energy or None, parts or None,
+                                     stream or None))
 
 
 def useries_plan_info(plan):
