@@ -14,10 +14,12 @@ pin the oracle on tiny inputs.
 from .core import (Params, build, load, eval_full, eval_near, eval_far, far_kspace,
                    forces_subset, far_inf, near_kernel, bsa_bound,
                    eq33_bound, solve_c0, solve_c1, c1_w0, series_len, term,
-                   far_inf0, near_integral, num_threads)
+                   far_inf0, near_integral, num_threads, mellin_gauss, trunc_bound,
+                   c1_w0a, solve_c1a)
 from .ewald import ewald
 
 __all__ = ["Params", "build", "load", "eval_full", "eval_near", "eval_far", "far_kspace",
            "forces_subset", "far_inf", "near_kernel", "bsa_bound",
            "eq33_bound", "solve_c0", "solve_c1", "c1_w0", "series_len", "term",
-           "far_inf0", "near_integral", "num_threads", "ewald"]
+           "far_inf0", "near_integral", "num_threads", "mellin_gauss", "trunc_bound",
+           "c1_w0a", "solve_c1a", "ewald"]

@@ -21,22 +21,26 @@ _lib = None
 @dataclass
 class Params:
     """u-series parameters: base b, width sigma, narrowest weight w0 (eq. 24),
-    narrowest width factor s0 (eq. 28), cutoff r_c, far terms N (Sec. V)."""
+    narrowest width factor s0 (eq. 28), cutoff r_c, far terms N (Sec. V), and
+    the power alpha of the kernel 1/r^alpha (App. A; 1 = Coulomb)."""
     b: float
     sigma: float
     w0: float
     s0: float
     rc: float
     nterms: int
+    alpha: float = 1.0
 
 
 class _CParams(ctypes.Structure):
     _fields_ = [("b", ctypes.c_double), ("sigma", ctypes.c_double), ("w0", ctypes.c_double),
-                ("s0", ctypes.c_double), ("rc", ctypes.c_double), ("nterms", ctypes.c_int)]
+                ("s0", ctypes.c_double), ("rc", ctypes.c_double), ("nterms", ctypes.c_int),
+                ("alpha", ctypes.c_double)]
 
 
 def _cp(p):
-    return ctypes.byref(_CParams(p.b, p.sigma, p.w0, p.s0, p.rc, int(p.nterms)))
+    return ctypes.byref(_CParams(p.b, p.sigma, p.w0, p.s0, p.rc, int(p.nterms),
+                                 float(getattr(p, "alpha", 1.0))))
 
 
 def build(force=True):
@@ -76,6 +80,10 @@ def load():
         "uo_forces_subset": (I, [I, P, P, P, P, I, P, P]),
         "uo_far_kspace": (I, [I, P, P, P, P, P, P]),
         "uo_num_threads": (I, []),
+        "uo_mellin_gauss": (D, [D]),
+        "uo_trunc_bound": (D, [I, D, D, D, D]),
+        "uo_c1_w0a": (D, [D, D, D]),
+        "uo_solve_c1a": (I, [D, D, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -160,6 +168,29 @@ def solve_c0(b):
 def solve_c1(b):
     r0, w0 = ctypes.c_double(), ctypes.c_double()
     if load().uo_solve_c1(b, ctypes.byref(r0), ctypes.byref(w0)):
+        raise RuntimeError("no C1 root found")
+    return r0.value, w0.value
+
+
+def mellin_gauss(alpha):
+    """phi~(alpha) of eq. A1 for the unit Gaussian."""
+    return load().uo_mellin_gauss(float(alpha))
+
+
+def trunc_bound(n, b, alpha, sigma, lmax):
+    """Truncation bound of the 1/r^alpha far part at n terms (eq. 33 at alpha = 1)."""
+    return load().uo_trunc_bound(int(n), float(b), float(alpha), float(sigma), float(lmax))
+
+
+def c1_w0a(b, alpha, r):
+    """w0 of the C1 construction for 1/r^alpha at r (sigma = 1)."""
+    return load().uo_c1_w0a(float(b), float(alpha), float(r))
+
+
+def solve_c1a(b, alpha):
+    """(r0, w0) of the C1 construction for 1/r^alpha."""
+    r0, w0 = ctypes.c_double(), ctypes.c_double()
+    if load().uo_solve_c1a(float(b), float(alpha), ctypes.byref(r0), ctypes.byref(w0)):
         raise RuntimeError("no C1 root found")
     return r0.value, w0.value
 

@@ -42,6 +42,17 @@
  *
  *   E = E_near + E_far - E_self + E_bg,  F_i = -dE/dr_i.
  *
+ * Kernel 1/r^alpha (App. A; the paper's example is the dispersion 1/r^6):
+ * the BSA of eq. A2 with the Gaussian as scaling function, whose Mellin
+ * transform (eq. A1) is phi~(alpha) = 2^(alpha/2 - 1) Gamma(alpha/2), gives
+ *       a_j = ln b w_j b^(-alpha j) / (phi~(alpha) sigma^alpha),  s_j = sigma b^j,
+ * and the near part is 1/r^alpha - F_inf(r) below r_c.  The charges are then
+ * the coefficients c_i of E = 1/2 sum' c_i c_j / r^alpha.  For alpha > 3 the
+ * periodic lattice sum converges absolutely, so nothing is neutralised: the
+ * far part keeps every term's k = 0 component (the dropped terms j >= N
+ * contribute theirs analytically) and E_bg = 0.  Only alpha = 1 and
+ * alpha > 3 are accepted.
+ *
  * A second, independent form of E_far and its forces is the k-space sum of
  * Appendix F eq. F1 (equivalently eq. 32 with S^ = 1), related to the
  * real-space theta form by Poisson summation.
@@ -64,7 +75,21 @@ typedef struct {
     double s0;     /* width factor of the narrowest Gaussian, eq. 28 (1 for C0/C1) */
     double rc;     /* cutoff radius r_c of the near part, eq. 20 */
     int nterms;    /* N: terms kept in the far part, Sec. V */
+    double alpha;  /* kernel 1/r^alpha (App. A); 0 or 1: Coulomb */
 } uo_params;
+
+/* the power alpha of the kernel (0 stands for the Coulomb default 1) */
+static double kpow(const uo_params *p)
+{
+    return p->alpha > 0.0 ? p->alpha : 1.0;
+}
+
+/* Mellin transform of the unit Gaussian exp(-u^2/2), eq. A1:
+ * int_0^inf exp(-u^2/2) u^(alpha-1) du = 2^(alpha/2 - 1) Gamma(alpha/2) */
+double uo_mellin_gauss(double alpha)
+{
+    return pow(2.0, 0.5 * alpha - 1.0) * tgamma(0.5 * alpha);
+}
 
 /* ---------------------------------------------------------------- series */
 
@@ -74,15 +99,28 @@ int uo_series_len(double b)
     return (int)ceil(18.0 * log(10.0) / log(b)) + 1;
 }
 
-/* amplitude a_j and width s_j of Gaussian term j (eqs. 11, 24, 28) */
+/* the same for the 1/r^alpha series, whose weights fall as b^(-alpha j) */
+static int series_len_p(const uo_params *p)
+{
+    double al = kpow(p);
+    if (al == 1.0) return uo_series_len(p->b);
+    return (int)ceil(18.0 * log(10.0) / (al * log(p->b))) + 1;
+}
+
+/* amplitude a_j and width s_j of Gaussian term j (eqs. 11, 24, 28).
+ * For 1/r^alpha the BSA of eq. A2 with the Gaussian scaling function gives
+ * the prefactor ln b / (phi~(alpha) sigma^alpha) and weights b^(-alpha j);
+ * at alpha = 1, phi~(1) = sqrt(pi/2) and this is eq. 11's 2 ln b/(sqrt(2 pi) sigma). */
 void uo_term(const uo_params *p, int j, double *a, double *s)
 {
-    double pref = 2.0 * log(p->b) / (sqrt(2.0 * M_PI) * p->sigma);
+    double al = kpow(p);
+    double pref = al == 1.0 ? 2.0 * log(p->b) / (sqrt(2.0 * M_PI) * p->sigma)
+                            : log(p->b) / (uo_mellin_gauss(al) * pow(p->sigma, al));
     if (j == 0) {
         *a = pref * p->w0;
         *s = p->sigma * p->s0;
     } else {
-        *a = pref * pow(p->b, -(double)j);
+        *a = pref * pow(p->b, -al * (double)j);
         *s = p->sigma * pow(p->b, (double)j);
     }
 }
@@ -109,23 +147,40 @@ static void far_sum(const uo_params *p, int j0, int j1, double r,
 /* F_inf(r), F_inf'(r), F_inf''(r) (eq. 19 / 24 / 28, all terms) */
 void uo_far_inf(const uo_params *p, double r, double out[3])
 {
-    far_sum(p, 0, uo_series_len(p->b), r, &out[0], &out[1], &out[2]);
+    far_sum(p, 0, series_len_p(p), r, &out[0], &out[1], &out[2]);
 }
 
-/* near kernel N(r) of eq. 20 and its r-derivative */
+/* near kernel N(r) of eq. 20 and its r-derivative: 1/r^alpha - F_inf(r)
+ * below r_c */
 void uo_near(const uo_params *p, double r, double out[2])
 {
     if (r >= p->rc) { out[0] = 0.0; out[1] = 0.0; return; }
-    double f[3];
+    double f[3], al = kpow(p);
     uo_far_inf(p, r, f);
-    out[0] = 1.0 / r - f[0];
-    out[1] = -1.0 / (r * r) - f[1];
+    if (al == 1.0) {
+        out[0] = 1.0 / r - f[0];
+        out[1] = -1.0 / (r * r) - f[1];
+    } else {
+        out[0] = pow(r, -al) - f[0];
+        out[1] = -al * pow(r, -al - 1.0) - f[1];
+    }
 }
 
 /* BSA relative-error bound M_b, eq. 14 */
 double uo_bsa_bound(double b)
 {
     return pow(2.0, 1.5) * exp(-M_PI * M_PI / (2.0 * log(b)));
+}
+
+/* Truncation bound for 1/r^alpha: the k-space weight of the first dropped
+ * term relative to that of term 0 at the smallest wavevector 2 pi / L, the
+ * quantity that eq. 33 bounds for alpha = 1 (the k-space weight of term t
+ * is a_t (2 pi s_t^2)^(3/2) exp(-s_t^2 k^2 / 2), proportional to
+ * b^((3 - alpha) t) exp(-s_t^2 k^2 / 2)).  At alpha = 1 it is eq. 33. */
+double uo_trunc_bound(int n, double b, double alpha, double sigma, double lmax)
+{
+    return exp((3.0 - alpha) * n * log(b)
+               - 2.0 * (pow(b, 2.0 * n) - 1.0) * M_PI * M_PI * sigma * sigma / (lmax * lmax));
 }
 
 /* truncation bound for the far energy with N terms, eq. 33 (App. F, F4) */
@@ -164,6 +219,52 @@ static double c1_resid(double b, double r)
     double f[3];
     uo_far_inf(&p, r, f);
     return f[1] + 1.0 / (r * r);
+}
+
+/* C1 construction for 1/r^alpha at sigma = 1 (the analogue of eqs. 24-26):
+ * w0 makes the series equal r^-alpha at r (continuity of the near part), and
+ * r0 is the smallest r at which the slopes agree as well,
+ * r^(alpha+1) F'(r) + alpha = 0.  At alpha = 1 these are eqs. 25 and 26. */
+double uo_c1_w0a(double b, double alpha, double r)
+{
+    uo_params p = {b, 1.0, 1.0, 1.0, 0.0, 0, alpha};
+    double tail, a0, s0;
+    far_sum(&p, 1, series_len_p(&p), r, &tail, NULL, NULL);
+    uo_term(&p, 0, &a0, &s0);                                   /* a_0 at w0 = 1 */
+    return (pow(r, -alpha) - tail) / (a0 * exp(-r * r / 2.0));
+}
+
+static double c1a_resid(double b, double alpha, double r)
+{
+    uo_params p = {b, 1.0, uo_c1_w0a(b, alpha, r), 1.0, 0.0, 0, alpha};
+    double f[3];
+    uo_far_inf(&p, r, f);
+    return pow(r, alpha + 1.0) * f[1] + alpha;
+}
+
+/* (r0, w0) of the C1 construction for 1/r^alpha: smallest sign change of the
+ * slope residual on (0.5, 50), scanned in steps of 1e-3 and bisected.
+ * Returns 0 on success. */
+int uo_solve_c1a(double b, double alpha, double *r0, double *w0)
+{
+    double h = 1e-3, r = 0.5, gp = c1a_resid(b, alpha, r);
+    for (; r < 50.0; r += h) {
+        double gn = c1a_resid(b, alpha, r + h);
+        if ((gn < 0) != (gp < 0)) {
+            double lo = r, hi = r + h, glo = gp;
+            for (int it = 0; it < 200; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                double gm = c1a_resid(b, alpha, mid);
+                if ((gm < 0) == (glo < 0)) { lo = mid; glo = gm; } else { hi = mid; }
+            }
+            *r0 = 0.5 * (lo + hi);
+            *w0 = uo_c1_w0a(b, alpha, *r0);
+            return 0;
+        }
+        gp = gn;
+    }
+    return -1;
 }
 
 static double bisect(double (*g)(double, double), double b, double lo, double hi)
@@ -276,11 +377,39 @@ static double near_part(int n, const double *xyz, const double *q, const double 
     return e;
 }
 
-/* far energy/forces: N separable Gaussians, periodic theta products (eq. 31) */
+/* k = 0 mean of term t's periodised Gaussian over the cell: a_t (2 pi s_t^2)^(3/2) / V */
+static double term_mean(const uo_params *p, int t, double V)
+{
+    double a, s;
+    uo_term(p, t, &a, &s);
+    return a * pow(2.0 * M_PI * s * s, 1.5) / V;
+}
+
+/* sum_{j >= j0} of the terms' k = 0 means (alpha > 3).  For j >= 1 the means
+ * a_j (2 pi s_j^2)^(3/2) / V form a geometric series of ratio b^(3 - alpha)
+ * (a_j ~ b^(-alpha j), s_j^3 ~ b^(3 j)), summed here in closed form: it falls
+ * only as b^(-(alpha - 3) j), far slower than the series itself. */
+static double kzero_tail(const uo_params *p, int j0, double V)
+{
+    double m1 = term_mean(p, 1, V);                /* mean of term 1 */
+    double ratio = pow(p->b, 3.0 - kpow(p));
+    int j1 = j0 < 1 ? 1 : j0;
+    double tail = m1 * pow(ratio, (double)(j1 - 1)) / (1.0 - ratio);
+    return (j0 <= 0 ? term_mean(p, 0, V) : 0.0) + tail;
+}
+
+/* Far energy/forces: N separable Gaussians, periodic theta products (eq. 31).
+ * Coulomb (alpha = 1): the k = 0 component of every term is removed (the
+ * k != 0 sums of eqs. 4, 9, 10).  1/r^alpha with alpha > 3, whose lattice sum
+ * converges absolutely: every term keeps its k = 0 component, and the terms
+ * j >= N, dropped from the grid, still contribute theirs,
+ * 1/2 Q^2 sum_{j>=N} a_j (2 pi s_j^2)^(3/2) / V (their k != 0 parts are what
+ * the truncation bound measures). */
 static double far_part(int n, const double *xyz, const double *q, const double L[3],
                        const uo_params *p, double *frc)
 {
     double V = L[0] * L[1] * L[2];
+    int keep_k0 = kpow(p) > 3.0;
     int nth = 1;
 #ifdef _OPENMP
     nth = omp_get_max_threads();
@@ -288,12 +417,12 @@ static double far_part(int n, const double *xyz, const double *q, const double L
     double *fbuf = calloc((size_t)nth * n * 3, sizeof(double));
     double e = 0.0, qsum = 0.0;
     for (int i = 0; i < n; ++i) qsum += q[i];
+    if (keep_k0) e += 0.5 * qsum * qsum * kzero_tail(p, p->nterms, V);
     for (int t = 0; t < p->nterms; ++t) {
         double a, s;
         uo_term(p, t, &a, &s);
         /* k = 0 mean of the periodised Gaussian, removed (uniform background) */
-        double mean = a * pow(2.0 * M_PI * s * s, 1.5) / V;
-        e -= 0.5 * qsum * qsum * mean;
+        if (!keep_k0) e -= 0.5 * qsum * qsum * term_mean(p, t, V);
         double et = 0.0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+:et)
         for (int i = 0; i < n; ++i) {
@@ -379,6 +508,7 @@ int uo_eval(int n, const double *xyz, const double *q, const double box[3],
             const uo_params *p, double *forces, double parts[5])
 {
     if (n < 0 || p->b <= 1.0 || p->sigma <= 0.0 || p->nterms < 0) return -1;
+    if (kpow(p) != 1.0 && !(kpow(p) > 3.0)) return -1;   /* Coulomb or alpha > 3 */
     memset(forces, 0, sizeof(double) * 3 * (size_t)n);
     double en = near_part(n, xyz, q, box, p, forces);
     double ef = far_part(n, xyz, q, box, p, forces);
@@ -386,7 +516,9 @@ int uo_eval(int n, const double *xyz, const double *q, const double box[3],
     for (int i = 0; i < n; ++i) { q2 += q[i] * q[i]; qs += q[i]; }
     double es = 0.5 * uo_far_inf0(p) * q2;
     double V = box[0] * box[1] * box[2];
-    double eb = -0.5 * qs * qs * uo_near_integral(p) / V;
+    /* the neutralising background is a Coulomb matter; for alpha > 3 the
+     * far part keeps its k = 0 components instead */
+    double eb = kpow(p) == 1.0 ? -0.5 * qs * qs * uo_near_integral(p) / V : 0.0;
     parts[0] = en;
     parts[1] = ef;
     parts[2] = es;
@@ -463,7 +595,8 @@ int uo_forces_subset(int n, const double *xyz, const double *q, const double box
 
 /*
  * k-space form of the far part (App. F eq. F1; eq. 32 with S^ = 1):
- *   E_far = 1/(2V) sum_{k != 0} c(k) |S(k)|^2,
+ *   E_far = 1/(2V) sum_{k != 0} c(k) |S(k)|^2  (+ for alpha > 3 the k = 0
+ *           components of all terms, 1/2 Q^2 sum_j a_j (2 pi s_j^2)^(3/2) / V),
  *   c(k) = sum_{t<N} a_t (2 pi s_t^2)^{3/2} exp(-s_t^2 k^2 / 2),
  *   S(k) = sum_j q_j exp(i k.r_j),
  *   F_i  = (q_i / V) sum_{k != 0} c(k) k Im(exp(i k.r_i) conj(S(k))).
@@ -527,6 +660,12 @@ int uo_far_kspace(int n, const double *xyz, const double *q, const double box[3]
     }
     memcpy(forces, fr, sizeof(double) * 3 * (size_t)n);
     free(fr);
+    if (kpow(p) > 3.0) {
+        /* alpha > 3: the k = 0 components of all terms (no force) */
+        double qs = 0.0;
+        for (int j = 0; j < n; ++j) qs += q[j];
+        e += 0.5 * qs * qs * kzero_tail(p, 0, V);
+    }
     *energy = e;
     return 0;
 }

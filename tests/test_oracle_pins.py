@@ -362,3 +362,180 @@ def test_subset_forces_match_full(small_case):
     xyz, q, L, p, parts, F = small_case
     idx = [0, 5, 39]
     assert np.max(np.abs(O.forces_subset(xyz, q, L, p, idx) - F[idx])) < 1e-12
+
+
+# ---------------------------------------------------------------- 1/r^alpha (App. A)
+
+def test_mellin_transform_closed_forms():
+    """eq. A1 for the unit Gaussian at integer and half-integer points:
+    phi~(1) = sqrt(pi/2), phi~(2) = 1, phi~(3) = sqrt(pi/2), phi~(6) = 8."""
+    assert rel(O.mellin_gauss(1.0), math.sqrt(math.pi / 2)) < 1e-15
+    assert rel(O.mellin_gauss(2.0), 1.0) < 1e-15
+    assert rel(O.mellin_gauss(3.0), math.sqrt(math.pi / 2)) < 1e-15
+    assert rel(O.mellin_gauss(6.0), 8.0) < 1e-15
+
+
+def test_alpha1_reduces_to_coulomb_series():
+    """At alpha = 1 the 1/r^alpha series is the Coulomb one: the generalised
+    C1 solver returns Table 2's C1 row, and the series (amplitudes from
+    phi~(1)) equals eq. 11's."""
+    r0, w0 = O.solve_c1a(2.0, 1.0)
+    assert abs(r0 - T2["C1"]["r0"]) < 1e-9 and abs(w0 - T2["C1"]["w0"]) < 1e-9
+    p1 = O.Params(b=2.0, sigma=1.7, w0=T2["C1"]["w0"], s0=1.0, rc=3.0, nterms=4)
+    pa = O.Params(b=2.0, sigma=1.7, w0=T2["C1"]["w0"], s0=1.0, rc=3.0, nterms=4, alpha=1.0)
+    for r in (0.0, 0.5, 2.0, 7.0):
+        assert np.allclose(O.far_inf(p1, r), O.far_inf(pa, r), rtol=1e-15, atol=0)
+    assert rel(O.trunc_bound(4, 2.0, 1.0, 4.5, 64.0), O.eq33_bound(4, 2.0, 4.5, 64.0)) < 1e-14
+
+
+def _bsa_error_eqA3(alpha, b, r):
+    """The relative error of the BSA for 1/r^alpha from eq. A3 (Gaussian
+    scaling function, sigma = 1), summed over n = +-1..+-6 with scipy's
+    complex Gamma function."""
+    from scipy.special import gamma
+    D = math.log(b)
+    def mel(s):
+        return 2.0 ** (s / 2 - 1) * gamma(s / 2)
+    tot = 0.0
+    for n in list(range(-6, 0)) + list(range(1, 7)):
+        z = alpha + 2j * math.pi * n / D
+        tot += (mel(z) / mel(alpha) * np.exp(-2j * math.pi * n * math.log(r) / D)).real
+    return tot
+
+
+@pytest.mark.parametrize("alpha,b", [(6.0, 2.0), (6.0, 1.5), (4.0, 2.0)])
+def test_series_error_matches_eqA3(alpha, b):
+    """Far from the narrowest Gaussian the series is the BSA of eq. A2 (the
+    j < 0 terms and the C1 weight of term 0 are below 1e-13 there, and the
+    terms beyond the series length below 1e-13 of r^-alpha), so
+    r^alpha F_inf(r) - 1 must follow the explicit error formula A3.  This
+    pins the amplitude ln b / phi~(alpha) and the weights b^(-alpha j)."""
+    p = O.Params(b=b, sigma=1.0, w0=0.9, s0=1.0, rc=1.0, nterms=0, alpha=alpha)
+    worst = 0.0
+    for r in np.linspace(10.0, 20.0, 21):
+        got = r ** alpha * O.far_inf(p, r)[0] - 1.0
+        want = _bsa_error_eqA3(alpha, b, r)
+        worst = max(worst, abs(got - want))
+    assert worst < 1e-12, worst
+
+
+@pytest.mark.parametrize("b", [2.0, 1.5, 1.15])
+def test_alpha6_c1_construction(b):
+    """The C1 construction for 1/r^6: the near part 1/r^6 - F_inf vanishes at
+    r_c with zero slope, and inside r_c near + far is exactly 1/r^6."""
+    r0, w0 = O.solve_c1a(b, 6.0)
+    sigma = 1.3
+    p = O.Params(b=b, sigma=sigma, w0=w0, s0=1.0, rc=r0 * sigma, nterms=0, alpha=6.0)
+    rc = r0 * sigma
+    nk = O.near_kernel(p, rc * (1 - 1e-12))
+    scale = rc ** -6
+    assert abs(nk[0]) < 1e-9 * scale
+    assert abs(nk[1]) < 1e-8 * scale / rc
+    for r in (0.3, 1.0, 0.9 * rc):
+        assert rel(O.near_kernel(p, r)[0] + O.far_inf(p, r)[0], r ** -6) < 1e-13
+
+
+def _lattice(kind, ncell, a):
+    basis = {"sc": [(0, 0, 0)],
+             "fcc": [(0, 0, 0), (0.5, 0.5, 0), (0.5, 0, 0.5), (0, 0.5, 0.5)]}[kind]
+    pts = [((i + u) * a, (j + v) * a, (k + w) * a)
+           for i in range(ncell) for j in range(ncell) for k in range(ncell)
+           for (u, v, w) in basis]
+    return np.array(pts, float)
+
+
+@pytest.mark.parametrize("kind,ncell,a,dnn", [("sc", 3, 4.0, 4.0),
+                                              ("fcc", 2, 6.0, 6.0 / math.sqrt(2))])
+def test_alpha6_lattice_sums(kind, ncell, a, dnn):
+    """1/r^6 lattice sums: identical coefficients c = 1 on a simple-cubic or
+    face-centred-cubic lattice in a periodic cell of edge 12 A have energy
+    1/2 A6 / d^6 per site (A6 the textbook lattice sum, d the nearest-neighbour
+    distance).  With b = 1.15 the BSA error is below 1e-10, so the u-series
+    (near pairs inside r_c = 5.9 A, far Gaussians with their k = 0 parts, the
+    dropped terms' k = 0 parts, minus the self term) must give it.  No
+    neutralisation: the lattice sum of 1/r^6 converges absolutely."""
+    xyz = _lattice(kind, ncell, a)
+    L = ncell * a
+    r0, w0 = O.solve_c1a(1.15, 6.0)
+    rc = 5.9
+    sigma = rc / r0
+    n = 1
+    while O.trunc_bound(n, 1.15, 6.0, sigma, L) > 1e-16:
+        n += 1
+    p = O.Params(b=1.15, sigma=sigma, w0=w0, s0=1.0, rc=rc, nterms=n, alpha=6.0)
+    q = np.ones(len(xyz))
+    parts, f = O.eval_full(xyz, q, (L, L, L), p)
+    want = 0.5 * float(LC["lj_lattice_sum_a6"][kind]) / dnn ** 6 * len(xyz)
+    assert rel(parts["total"], want) < 1e-10, (parts, want)
+    assert parts["bg"] == 0.0
+    assert np.max(np.abs(f)) < 1e-10 * abs(want)       # forces vanish by symmetry
+
+
+def _alpha6_case(seed, n=12, L=14.0, b=2.0):
+    rng = np.random.default_rng(seed)
+    xyz = rng.uniform(0, L, (n, 3))
+    q = rng.uniform(0.2, 1.5, n)          # dispersion coefficients: no neutrality
+    r0, w0 = O.solve_c1a(b, 6.0)
+    rc = 6.0
+    sigma = rc / r0
+    nt = 1
+    while O.trunc_bound(nt, b, 6.0, sigma, L) > 1e-16:
+        nt += 1
+    return xyz, q, (L, L, L), O.Params(b=b, sigma=sigma, w0=w0, s0=1.0, rc=rc, nterms=nt,
+                                       alpha=6.0)
+
+
+def test_alpha6_matches_direct_lattice_sum():
+    """Random positive coefficients in a 14 A cell against the direct lattice
+    sum of 1/r^6 over images out to 30 cells (plus the continuum tail beyond
+    that sphere, 4 pi (sum c)^2 / (6 V R^3)).  The b = 2 series differs from
+    1/r^6 beyond r_c by up to ~10% (eq. A4), so the energy is held to 1e-2;
+    with b = 1.15 the same comparison holds to 1e-7."""
+    for b, tol in ((2.0, 1e-2), (1.15, 1e-7)):
+        xyz, q, box, p = _alpha6_case(5, b=b)
+        if b != 2.0:
+            r0, w0 = O.solve_c1a(b, 6.0)
+            p = O.Params(b=b, sigma=p.rc / r0, w0=w0, s0=1.0, rc=p.rc, nterms=40, alpha=6.0)
+        parts, _ = O.eval_full(xyz, q, box, p)
+        L = box[0]
+        M = 30
+        g = np.arange(-M, M + 1) * L
+        X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+        img = np.stack([X, Y, Z], -1).reshape(-1, 3)
+        img = img[np.sum(img ** 2, 1) <= (M * L) ** 2]
+        R = M * L
+        e = 0.0
+        for i in range(len(q)):
+            d = xyz[i] - xyz                       # [n, 3]
+            r2 = np.sum((d[:, None, :] + img[None, :, :]) ** 2, axis=2)
+            r2[i][r2[i] == 0] = np.inf
+            e += 0.5 * q[i] * np.sum(q[:, None] * r2 ** -3)
+        e += 0.5 * np.sum(q) ** 2 * 4 * math.pi / (3 * L ** 3 * R ** 3)
+        assert rel(parts["total"], e) < tol, (b, parts["total"], e)
+
+
+def test_alpha6_far_realspace_equals_kspace():
+    """The far part of 1/r^6 in both exact forms (theta products with every
+    term's k = 0 component; k-space sum plus the k = 0 components)."""
+    xyz, q, box, p = _alpha6_case(7)
+    e_r, f_r = O.eval_far(xyz, q, box, p)
+    e_k, f_k = O.far_kspace(xyz, q, box, p)
+    assert rel(e_r, e_k) < 1e-11
+    assert rel_rms(f_r, f_k) < 1e-10
+
+
+def test_alpha6_forces_are_minus_gradient_and_invariant():
+    xyz, q, box, p = _alpha6_case(9)
+    parts, f = O.eval_full(xyz, q, box, p)
+    h = 1e-4
+    for i in (0, 5):
+        for a in range(3):
+            xp, xm = xyz.copy(), xyz.copy()
+            xp[i, a] += h
+            xm[i, a] -= h
+            ep = O.eval_full(xp, q, box, p)[0]["total"]
+            em = O.eval_full(xm, q, box, p)[0]["total"]
+            assert abs(-(ep - em) / (2 * h) - f[i, a]) <= 1e-6 * np.max(np.abs(f))
+    assert np.linalg.norm(f.sum(0)) < 1e-10 * np.max(np.abs(f))
+    parts2, f2 = O.eval_full(xyz + np.array([1.1, -2.3, 0.7]), q, box, p)
+    assert rel(parts2["total"], parts["total"]) < 1e-12
