@@ -98,6 +98,147 @@ def serving_requests(count):
     return out
 
 
+CURVE_CONSTRUCTIONS = [("C1_b2", "USERIES_C1"), ("C2_b2", "USERIES_C2_B2"),
+                       ("T1_row1", "USERIES_TABLE1_ROW1"), ("T1_row2", "USERIES_TABLE1_ROW2"),
+                       ("T1_row3", "USERIES_TABLE1_ROW3")]
+
+
+def accuracy_curve(xyz, q, box, rc, forms, steps=100, warmup=10):
+    """Accuracy against cost through the same kernels: for each series of
+    Tables 1-2 (C1 and C2 at b = 2; the three C2 points of the C1 construction),
+    evaluations/s on the water box in both forms, and the errors against that
+    series' own FP64 oracle value and against the Coulomb reference (Table 1
+    row 3 at an eq. 33 bound of 1e-12: within ~4e-11 of 1/r).  The grid spacing
+    is at most 1 A and at most s_0 / 2 (s_0 = sigma s0, the narrowest far
+    Gaussian).  The oracle values were stored by tests/golden/make_curve.py."""
+    import torch
+    import paper_1911_01377_amd as U
+    from paper_1911_01377_amd import Plan
+    path = os.path.join(ROOT, "tests", "golden", "curve_water26k.json")
+    if not os.path.exists(path):
+        return None
+    gold = json.load(open(path))
+    ent = gold["entries"]
+    idx = np.array(gold["sample_idx"])
+    ref = ent.get("coulomb")
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(xyz).to(dev)
+    qq = torch.from_numpy(q).to(dev)
+    n = len(q)
+    forces = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    energy = torch.empty(1, dtype=torch.float64, device=dev)
+    out = []
+    for name, cname in CURVE_CONSTRUCTIONS:
+        if name not in ent:
+            continue
+        g = ent[name]
+        s0w = g["params"]["sigma"] * g["params"]["s0"]
+        gn = int(math.ceil(box[0] / min(1.0, 0.5 * s0w)))
+        for form, prec in forms.items():
+            plan = Plan(box, rc, (gn, gn, gn), construction=getattr(U, cname), precision=prec)
+            info = plan.info
+            if info["n_terms"] != g["params"]["nterms"] or \
+                    abs(info["sigma"] - g["params"]["sigma"]) > 1e-12 * g["params"]["sigma"]:
+                out.append({"construction": name, "form": form, "error": "plan parameters differ "
+                            "from the stored oracle's"})
+                plan.close()
+                continue
+            for _ in range(warmup):
+                plan.eval(x, qq, forces, energy)
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(steps):
+                plan.eval(x, qq, forces, energy)
+            t1.record()
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / steps
+            f = forces.cpu().numpy().astype(np.float64)[idx]
+            E = float(energy.cpu()[0])
+            fo = np.array(g["sample_forces"])
+            row = {"construction": name, "form": form, "b": info["b"], "sigma": info["sigma"],
+                   "n_terms": info["n_terms"], "near_exact": info["near_exact"],
+                   "grid": gn, "ms_per_eval": ms, "evals_per_s": 1e3 / ms,
+                   "force_err_vs_own_oracle": float(np.sqrt(np.sum((f - fo) ** 2) / np.sum(fo ** 2))),
+                   "energy_err_vs_own_oracle": abs(E - g["parts"]["total"]) / abs(g["parts"]["total"])}
+            if ref is not None:
+                fr = np.array(ref["sample_forces"])
+                row["force_err_vs_coulomb"] = float(np.sqrt(np.sum((f - fr) ** 2) / np.sum(fr ** 2)))
+                row["energy_err_vs_coulomb"] = abs(E - ref["parts"]["total"]) / abs(ref["parts"]["total"])
+                row["series_force_err_vs_coulomb"] = float(
+                    np.sqrt(np.sum((fo - fr) ** 2) / np.sum(fr ** 2)))
+            out.append(row)
+            log("curve %s/%s: %.4f ms, dF own %.2e, dF coulomb %s" % (
+                name, form, ms, row["force_err_vs_own_oracle"],
+                "%.2e" % row["force_err_vs_coulomb"] if "force_err_vs_coulomb" in row else "-"))
+            plan.close()
+    return out
+
+
+def conv_vs_nterms(xyz, q, box, rc, forms, steps=100):
+    """Cost of the far terms against their number N: ms per evaluation and the
+    convolution kernels' HIP-event time (conv_xy + conv_z, the latter
+    including the spectral core) on the water box for the series of Tables
+    1-2 (N = 4 to 20 at eq. 33 <= 1e-8, grid spacing at most 1 A and s_0 / 2),
+    every term as a dense circulant (spectral = 0) or the widest in spectral
+    form (spectral = 1)."""
+    import torch
+    import paper_1911_01377_amd as U
+    from paper_1911_01377_amd import Plan
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(xyz).to(dev)
+    qq = torch.from_numpy(q).to(dev)
+    forces = torch.empty((len(q), 3), dtype=torch.float32, device=dev)
+    energy = torch.empty(1, dtype=torch.float64, device=dev)
+    out = []
+    for form, prec in forms.items():
+        ref = {}
+        for name, cname in CURVE_CONSTRUCTIONS:
+            cons = getattr(U, cname)
+            _, r0, _, s0 = U._native.useries_solve_construction(cons, 2.0)
+            gn = int(math.ceil(box[0] / min(1.0, 0.5 * rc / r0 * s0)))
+            for spec in (0, 1):
+                plan = Plan(box, rc, (gn, gn, gn), construction=cons, precision=prec,
+                            spectral=spec)
+                info = plan.info
+                nt = info["n_terms"]
+                for _ in range(10):
+                    plan.eval(x, qq, forces, energy)
+                torch.cuda.synchronize()
+                t0 = torch.cuda.Event(enable_timing=True)
+                t1 = torch.cuda.Event(enable_timing=True)
+                t0.record()
+                for _ in range(steps):
+                    plan.eval(x, qq, forces, energy)
+                t1.record()
+                torch.cuda.synchronize()
+                ms = t0.elapsed_time(t1) / steps
+                plan.timing(True)
+                for _ in range(50):
+                    plan.eval(x, qq, forces, energy)
+                torch.cuda.synchronize()
+                kt = {k: tot / c for k, tot, c in plan.timing() if c}
+                plan.timing(False)
+                f = forces.cpu().numpy().astype(np.float64)
+                row = {"form": form, "construction": name, "n_terms": nt, "grid": gn,
+                       "n_terms_grid": info["n_terms_grid"], "spectral": spec,
+                       "n_terms_spectral": info["n_terms_spectral"],
+                       "spectral_rank": list(info["spectral_rank"]), "ms_per_eval": ms,
+                       "conv_ms": kt.get("conv_xy", 0.0) + kt.get("conv_z", 0.0)}
+                if spec == 0:
+                    ref[nt] = f
+                else:
+                    row["force_rel_diff_vs_dense"] = float(
+                        np.sqrt(np.sum((f - ref[nt]) ** 2) / np.sum(ref[nt] ** 2)))
+                out.append(row)
+                log("conv vs N: %s %s N=%d grid %d spectral=%d (%d terms, ranks %s): %.4f ms/eval, "
+                    "conv %.4f ms" % (form, name, nt, gn, spec, info["n_terms_spectral"],
+                                      info["spectral_rank"], ms, row["conv_ms"]))
+                plan.close()
+    return out
+
+
 def run_serving(cells, args, precision):
     """Closed loop (all requests queued at once) for the capacity, then Poisson
     arrivals at a fraction of it; latency = arrival -> last evaluation's outputs on
@@ -159,6 +300,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--form", choices=["bf16x3", "plain"], default="bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-curve", action="store_true",
+                    help="skip the accuracy-versus-cost curve over the series constructions")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests in the serving stream (0: skip serving)")
@@ -396,6 +539,20 @@ def main():
             cpu = {"value": None, "unit": "evals/s", "cores": None, "kind": "oracle",
                    "sample": "failed: %s" % e}
 
+    conv_n = None
+    if not args.no_curve:
+        try:
+            conv_n = conv_vs_nterms(xyz, q, box, rc, forms)
+        except Exception as e:
+            conv_n = {"error": str(e)}
+
+    curve = None
+    if not args.no_curve:
+        try:
+            curve = accuracy_curve(xyz, q, box, rc, forms)
+        except Exception as e:
+            curve = {"error": str(e)}
+
     # B independent copies of the box per step through the server (continuous batching)
     batched = None
     if args.batch_copies > 0:
@@ -456,6 +613,8 @@ def main():
         "other_form_evals_per_s": {k: 1e3 / v for k, v in results.items()},
         "graph_replay_evals_per_s": {k: 1e3 / v for k, v in graphed.items()},
         "batched_copies": batched,
+        "accuracy_curve": curve,
+        "conv_vs_nterms": conv_n,
         "kernel_ms": ktimes,
         "kernels": kernels,
         "accuracy": acc,

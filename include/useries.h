@@ -96,6 +96,28 @@ enum {
  *                    useries_plan fails with USERIES_EINVAL.
  *   max_atoms        workspace capacity in charges; <= 0 grows on demand
  *                    (a growth reallocates and synchronises the device).
+ *   alpha            kernel power: 1 (Coulomb 1/r, the default) or 6 (1/r^6,
+ *                    e.g. London dispersion; App. A).  With 6 the series is
+ *                    the BSA of eq. A2 with a Gaussian scaling function
+ *                    (a_j = ln b w_j b^(-6j) / (phi~(6) sigma^6), phi~(6) = 8),
+ *                    the construction must be USERIES_C1 (solved for 1/r^6 at
+ *                    any b > 1: continuity and zero slope at r_c), the
+ *                    "charges" are the coefficients c_i of
+ *                    E = 1/2 sum'_{i,j,images} c_i c_j / r^6 (no neutrality: the
+ *                    lattice sum converges absolutely, and every far term's
+ *                    k = 0 component is kept), and n_terms <= 0 takes the
+ *                    smallest N with b^(-3N) exp(-2 (b^(2N) - 1) pi^2 sigma^2
+ *                    / L^2) <= nterms_tol (eq. 33's form for 1/r^6).  The
+ *                    Table 1 and 2 presets are Coulomb series.
+ *   spectral         apply the widest far terms together in spectral form
+ *                    (a low-rank form of their circulants: the real Fourier
+ *                    modes each needs down to 1e-9 of its first mode, at most
+ *                    17 per axis and a quarter of the axis), so that the
+ *                    convolution cost stops growing with them.  < 0 (the
+ *                    default): when at least six terms qualify (fewer cost
+ *                    less as dense matrix-core convolutions); > 0: when at
+ *                    least two do; 0: every term as a dense circulant.  The
+ *                    count is n_terms_spectral in useries_plan_info.
  */
 typedef struct {
     int construction;
@@ -105,6 +127,8 @@ typedef struct {
     double nterms_tol;
     int poly_degree;
     int64_t max_atoms;
+    int alpha;
+    int spectral;
 } useries_opts;
 
 /* Fill *opts with the defaults: C1, PLAIN_FP32, nterms_tol 1e-8, the rest
@@ -202,12 +226,16 @@ int useries_eval_static(useries_plan_t plan, int64_t n, const float *xyz, const 
  *   exponentials instead of through the polynomial: the plan takes the
  *   fewest, 0 to 8, that bring the polynomial's fit error within the form's
  *   budget, 1e-7 of max |F| plain and 2e-5 BF16X3; small b, as in Table 1,
- *   needs them because its narrowest Gaussians lie deep inside r_c).
+ *   needs them because its narrowest Gaussians lie deep inside r_c),
+ *   n_terms_spectral (of the n_terms_grid terms, the widest ones applied in
+ *   spectral form; 0 unless opts->spectral) and spectral_rank[3] (the real
+ *   Fourier modes per axis they use; zeros when none).
  */
 int useries_plan_info(useries_plan_t plan, double *b, double *sigma, double *r0, double *w0,
                       double *s0, int *n_terms, double *eq33, double *f_inf0,
                       double *c1_slope, double *sigma_s, int *stencil_half, int ncell[3],
-                      double *poly_maxerr, int *n_terms_grid, int *near_exact);
+                      double *poly_maxerr, int *n_terms_grid, int *near_exact,
+                      int *n_terms_spectral, int spectral_rank[3]);
 
 /* Release a plan and its device memory.  The caller must ensure that no
  * evaluation on it is still running. */

@@ -60,7 +60,8 @@ class useries_opts(ctypes.Structure):
     _fields_ = [("construction", ctypes.c_int), ("precision", ctypes.c_int),
                 ("sigma_s_over_h", ctypes.c_double), ("stencil_half", ctypes.c_int),
                 ("nterms_tol", ctypes.c_double), ("poly_degree", ctypes.c_int),
-                ("max_atoms", ctypes.c_int64)]
+                ("max_atoms", ctypes.c_int64), ("alpha", ctypes.c_int),
+                ("spectral", ctypes.c_int)]
 
 
 class useries_request(ctypes.Structure):
@@ -96,7 +97,7 @@ def lib():
         "useries_plan": (I, [P, P, D, D, D, I, P, P]),
         "useries_eval": (I, [P, I64, P, P, P, P, P]),
         "useries_eval_parts": (I, [P, I64, P, P, P, P, P, P]),
-        "useries_plan_info": (I, [P] + [P] * 15),
+        "useries_plan_info": (I, [P] + [P] * 17),
         "useries_destroy": (I, [P]),
         "useries_timing_enable": (I, [P, I]),
         "useries_timing_read": (I, [P, I, P, P, P]),
@@ -180,19 +181,21 @@ def useries_eval_static(plan, n, xyz, q, forces, energy, parts, stream=0):
 
 def useries_plan_info(plan):
     vals = [ctypes.c_double() for _ in range(5)]
-    nt, ntg, nex = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    nt, ntg, nex, nsp = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    rk = (ctypes.c_int * 3)()
     eq33, f0, slope, ss, perr = (ctypes.c_double() for _ in range(5))
     P = ctypes.c_int()
     nc = (ctypes.c_int * 3)()
     _check(lib().useries_plan_info(plan, *[ctypes.byref(v) for v in vals], ctypes.byref(nt),
                                    ctypes.byref(eq33), ctypes.byref(f0), ctypes.byref(slope),
                                    ctypes.byref(ss), ctypes.byref(P), nc, ctypes.byref(perr),
-                                   ctypes.byref(ntg), ctypes.byref(nex)))
+                                   ctypes.byref(ntg), ctypes.byref(nex), ctypes.byref(nsp), rk))
     b, sigma, r0, w0, s0 = (v.value for v in vals)
     return dict(b=b, sigma=sigma, r0=r0, w0=w0, s0=s0, n_terms=nt.value, eq33=eq33.value,
                 f_inf0=f0.value, c1_slope=slope.value, sigma_s=ss.value,
                 stencil_half=P.value, ncell=tuple(nc), poly_maxerr=perr.value,
-                n_terms_grid=ntg.value, near_exact=nex.value)
+                n_terms_grid=ntg.value, near_exact=nex.value, n_terms_spectral=nsp.value,
+                spectral_rank=tuple(rk))
 
 
 def useries_destroy(plan):

@@ -54,6 +54,7 @@ struct useries_plan_s {
     bool counts_dirty = false;   // column counters may be non-zero (an evaluation failed midway)
     // device constants
     void *kx = nullptr, *ky = nullptr, *kz = nullptr;
+    float *ux = nullptr, *uy = nullptr, *uz = nullptr, *wspec = nullptr, *cspec = nullptr;
     // fixed workspace
     int *col_count = nullptr, *col_start = nullptr, *col_fill = nullptr, *clus_start = nullptr;
     int* zbin = nullptr;
@@ -150,6 +151,11 @@ struct useries_plan_s {
         hipFree(kx);
         hipFree(ky);
         hipFree(kz);
+        hipFree(ux);
+        hipFree(uy);
+        hipFree(uz);
+        hipFree(wspec);
+        hipFree(cspec);
         hipFree(col_count);
         hipFree(col_start);
         hipFree(col_fill);
@@ -191,6 +197,8 @@ int useries_default_opts(useries_opts* o) {
     o->nterms_tol = 1e-8;
     o->poly_degree = 0;
     o->max_atoms = 0;
+    o->alpha = 1;
+    o->spectral = -1;
     return USERIES_OK;
 }
 
@@ -233,6 +241,28 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
         if ((e = hipMemcpy(*dst[a], hp.mats[a].data(), hp.mats[a].size(), hipMemcpyHostToDevice))) {
             delete p;
             return hip_fail(e, "upload");
+        }
+    }
+    if (hp.conv.spec) {
+        // spectral wide terms: bases, weights and the planes' projections
+        float** ub[3] = {&p->ux, &p->uy, &p->uz};
+        for (int a = 0; a < 3; ++a) {
+            const size_t bytes = hp.ubasis[a].size() * sizeof(float);
+            if ((e = hipMalloc((void**)ub[a], bytes)) ||
+                (e = hipMemcpy(*ub[a], hp.ubasis[a].data(), bytes, hipMemcpyHostToDevice))) {
+                delete p;
+                return hip_fail(e, "spectral bases");
+            }
+        }
+        const size_t wb = hp.wspec.size() * sizeof(float);
+        // plane projections [g_z][r_y][r_x], then the core G [r_z][r_y][r_x]
+        const size_t cb = ((size_t)hp.grid[2] + hp.conv.rk[2]) * hp.conv.rk[1] * hp.conv.rk[0] *
+                          sizeof(float);
+        if ((e = hipMalloc((void**)&p->wspec, wb)) ||
+            (e = hipMemcpy(p->wspec, hp.wspec.data(), wb, hipMemcpyHostToDevice)) ||
+            (e = hipMalloc((void**)&p->cspec, cb))) {
+            delete p;
+            return hip_fail(e, "spectral weights");
         }
     }
     const size_t ng = (size_t)hp.grid[0] * hp.grid[1] * hp.grid[2];
@@ -401,8 +431,14 @@ int plan_eval(useries_plan_t p, int64_t n, const float* xyz, const float* q, flo
     USERIES_STEP(4, st, launch_pair(hp.pair, npb, W.sorted, p->clus_start, W.cl_info, W.cl_col,
                                     W.cl_z, p->zbin, W.fnear, W.pair_parts, st));
     USERIES_STEP(5, st, launch_spread(hp.gridargs, W.sorted, p->zbin, p->qstats, p->rho, st));
-    USERIES_STEP(6, st, launch_conv_xy(hp.conv, p->rho, kx, ky, p->tgrid, st));
-    USERIES_STEP(7, st, launch_conv_z(hp.conv, p->tgrid, kz, p->phi, st));
+    SpecPtrs sp;
+    sp.ux = p->ux;
+    sp.uy = p->uy;
+    sp.uz = p->uz;
+    sp.w = p->wspec;
+    sp.c = p->cspec;
+    USERIES_STEP(6, st, launch_conv_xy(hp.conv, p->rho, kx, ky, p->tgrid, sp, st));
+    USERIES_STEP(7, st, launch_conv_z(hp.conv, p->tgrid, kz, p->phi, sp, st));
     USERIES_STEP(8, st, launch_gather(hp.gridargs, W.sorted, W.perm, p->zbin, p->phi, W.fnear,
                                       forces, p->gather_parts, st));
     USERIES_STEP(9, st, launch_finalize(hp.fin, W.pair_parts, p->gather_parts, p->qstats, energy,
@@ -430,7 +466,8 @@ int useries_eval_parts(useries_plan_t p, int64_t n, const float* xyz, const floa
 int useries_plan_info(useries_plan_t p, double* b, double* sigma, double* r0, double* w0,
                       double* s0, int* n_terms, double* eq33, double* f_inf0, double* c1_slope,
                       double* sigma_s, int* stencil_half, int ncell[3], double* poly_maxerr,
-                      int* n_terms_grid, int* near_exact) {
+                      int* n_terms_grid, int* near_exact, int* n_terms_spectral,
+                      int spectral_rank[3]) {
     if (!p) return fail(USERIES_EINVAL, "NULL plan");
     const HostPlan& hp = p->hp;
     if (b) *b = hp.b;
@@ -450,8 +487,11 @@ int useries_plan_info(useries_plan_t p, double* b, double* sigma, double* r0, do
         ncell[2] = 1;
     }
     if (poly_maxerr) *poly_maxerr = hp.poly_maxerr;
-    if (n_terms_grid) *n_terms_grid = hp.conv.nterms;
+    if (n_terms_grid) *n_terms_grid = hp.nterms_grid;
     if (near_exact) *near_exact = hp.near_exact;
+    if (n_terms_spectral) *n_terms_spectral = hp.nterms_spec;
+    if (spectral_rank)
+        for (int a = 0; a < 3; ++a) spectral_rank[a] = hp.conv.rk[a];
     return USERIES_OK;
 }
 

@@ -50,6 +50,7 @@ __device__ __forceinline__ void energy_total(const FinalArgs& a, const double* _
         }
         const double Q = qstats[0], q2 = qstats[1];
         ef -= 0.5 * Q * phs * a.inv_ngrid;
+        ef += 0.5 * Q * Q * a.k0_far;        // 1/r^6: the k = 0 components (0 for 1/r)
         const double es = 0.5 * a.f_inf0 * q2;
         const double eb = -0.5 * Q * Q * a.near_int_over_v;
         const double e = en + ef - es + eb;

@@ -220,7 +220,8 @@ __device__ __forceinline__ f32x4 conv_z_reduce(f32x4 acc, float* smem, bool act,
 __device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid, float* smem,
                                                 const float* __restrict__ tgrid,
                                                 const float* __restrict__ kz,
-                                                float* __restrict__ phi) {
+                                                float* __restrict__ phi,
+                                                const float* ps = nullptr) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int li = l & 15, lk = l >> 4;
     const int g2 = a.g[2], p2 = a.gp[2], ld = p2 + 4;
@@ -275,7 +276,8 @@ __device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid, floa
     const int col = cb + li;
     for (int r = 0; r < 4; ++r) {
         const int zz = tz * 16 + 4 * lk + r;
-        if (zz < g2 && col < ncol) phi[(size_t)zz * ncol + col] = acc[r];
+        if (zz < g2 && col < ncol)
+            phi[(size_t)zz * ncol + col] = ps ? acc[r] + ps[li * g2 + zz] : acc[r];
     }
 }
 
@@ -406,7 +408,8 @@ __device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int 
 __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, float* smem,
                                                  const float* __restrict__ tgrid,
                                                  const unsigned short* __restrict__ kz,
-                                                 float* __restrict__ phi) {
+                                                 float* __restrict__ phi,
+                                                 const float* ps = nullptr) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int li = l & 15, lk = l >> 4;
     const int g2 = a.g[2], p2 = a.gp[2], ld = p2 + 8;
@@ -477,48 +480,210 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
     const int col = c0 + li;
     for (int r = 0; r < 4; ++r) {
         const int zz = tz * 16 + 4 * lk + r;
-        if (zz < g2 && col < ncol) phi[(size_t)zz * ncol + col] = acc[r];
+        if (zz < g2 && col < ncol)
+            phi[(size_t)zz * ncol + col] = ps ? acc[r] + ps[li * g2 + zz] : acc[r];
     }
+}
+
+// ------------------------------------------------------------------ spectral wide terms
+// The widest terms together as (U_z x U_y x U_x) diag(W) (U_z x U_y x U_x)^T rho
+// (ConvArgs::spec), in three steps, FP32 FMAs (a few hundred thousand per
+// step: no matrix cores needed):
+//   conv_xy, one extra block per plane:  C[z] = U_y^T rho[z] U_x        (r_y x r_x)
+//   spec_core, once:                     G = W o (sum_z U_z[z] C[z])     (r_z x r_y x r_x)
+//   conv_z, in each column block:        phi[z, c] += sum U_z[z] U_y[y_c] U_x[x_c] G
+
+// C[z] from the plane rho[z]; smem holds g_y g_x + g_y r_x + g_x r_x + g_y r_y floats
+__device__ __forceinline__ void spec_fwd_plane(const ConvArgs& a, int z, float* smem,
+                                               const float* __restrict__ rho, const SpecPtrs& sp) {
+    const int g0 = a.g[0], g1 = a.g[1], r0 = a.rk[0], r1 = a.rk[1];
+    const int t = threadIdx.x;
+    float* sr = smem;              // rho[z] as [y][x]
+    float* pp = sr + g1 * g0;      // P = rho[z] U_x as [y][ix]
+    float* ux = pp + g1 * r0;      // U_x [x][ix]
+    float* uy = ux + g0 * r0;      // U_y [y][iy]
+    const float* src = rho + (size_t)z * g1 * g0;
+    for (int i = t; i < g1 * g0; i += kConvThreads) sr[i] = src[i];
+    for (int i = t; i < g0 * r0; i += kConvThreads) ux[i] = sp.ux[i];
+    for (int i = t; i < g1 * r1; i += kConvThreads) uy[i] = sp.uy[i];
+    __syncthreads();
+    for (int o = t; o < g1 * r0; o += kConvThreads) {
+        const int y = o / r0, ix = o - y * r0;
+        const float* row = sr + y * g0;
+        float acc0 = 0.0f, acc1 = 0.0f;
+        int x = 0;
+        for (; x + 1 < g0; x += 2) {
+            acc0 = fmaf(row[x], ux[x * r0 + ix], acc0);
+            acc1 = fmaf(row[x + 1], ux[(x + 1) * r0 + ix], acc1);
+        }
+        if (x < g0) acc0 = fmaf(row[x], ux[x * r0 + ix], acc0);
+        pp[o] = acc0 + acc1;
+    }
+    __syncthreads();
+    for (int o = t; o < r1 * r0; o += kConvThreads) {
+        const int iy = o / r0, ix = o - iy * r0;
+        float acc0 = 0.0f, acc1 = 0.0f;
+        int y = 0;
+        for (; y + 1 < g1; y += 2) {
+            acc0 = fmaf(uy[y * r1 + iy], pp[y * r0 + ix], acc0);
+            acc1 = fmaf(uy[(y + 1) * r1 + iy], pp[(y + 1) * r0 + ix], acc1);
+        }
+        if (y < g1) acc0 = fmaf(uy[y * r1 + iy], pp[y * r0 + ix], acc0);
+        sp.c[(size_t)z * r1 * r0 + o] = acc0 + acc1;
+    }
+}
+
+// G = W o (U_z^T C).  A block takes 16 consecutive outputs (iz, o): thread
+// (slice, j) adds the planes z = slice, slice + 16, ... of output j (one
+// round of independent loads, 16 consecutive o per row of lanes), and the 16
+// slices are then summed in a fixed order.
+constexpr int kSpecCoreThreads = 256;
+__global__ void __launch_bounds__(kSpecCoreThreads) k_spec_core(ConvArgs a, SpecPtrs sp,
+                                                               float* __restrict__ g) {
+    __shared__ float red[16][17];
+    const int R = a.rk[1] * a.rk[0], r2 = a.rk[2], g2 = a.g[2];
+    const int j = threadIdx.x & 15, slice = threadIdx.x >> 4;
+    const int idx = blockIdx.x * 16 + j;
+    const bool valid = idx < r2 * R;
+    const int iz = valid ? idx / R : 0, o = valid ? idx - iz * R : 0;
+    constexpr int kMaxPer = kMaxGrid / 16;
+    float c[kMaxPer], u[kMaxPer];
+#pragma unroll
+    for (int k = 0; k < kMaxPer; ++k) {
+        const int z = slice + 16 * k;
+        const bool in = valid && z < g2;
+        c[k] = in ? sp.c[(size_t)z * R + o] : 0.0f;
+        u[k] = in ? sp.uz[z * r2 + iz] : 0.0f;
+    }
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kMaxPer; ++k) acc = fmaf(u[k], c[k], acc);
+    red[slice][j] = acc;
+    __syncthreads();
+    if (threadIdx.x < 16 && valid) {
+        float sum = 0.0f;
+        for (int sl = 0; sl < 16; ++sl) sum += red[sl][threadIdx.x];
+        g[idx] = sp.w[idx] * sum;
+    }
+}
+
+// rows of the block's 16 columns (consecutive, x fastest) for grid rows of g_x points
+__host__ __device__ inline int spec_rows(int gx) { return 15 / gx + 2; }
+
+// floats of LDS a conv_z block needs for the spectral part (0 without it)
+__host__ __device__ inline int spec_z_lds_floats(const ConvArgs& a) {
+    if (!a.spec) return 0;
+    const int r0 = a.rk[0], r1 = a.rk[1], r2 = a.rk[2];
+    return r2 * r1 * r0 + spec_rows(a.g[0]) * r2 * r0 + r2 * 16 + 16 * a.g[2] + a.g[0] * r0 +
+           a.g[2] * r2;
+}
+
+// the spectral terms' potential on the block's 16 columns, left in LDS as
+// ps[c][z] (returned); ls: spec_z_lds_floats(a) floats.  The columns share
+// at most spec_rows(g_x) grid rows y, so G is first contracted with U_y for
+// those rows only.
+__device__ __forceinline__ const float* spec_z_part(const ConvArgs& a, int bid, float* ls,
+                                                    const float* __restrict__ g,
+                                                    const SpecPtrs& sp) {
+    const int g0 = a.g[0], g2 = a.g[2], r0 = a.rk[0], r1 = a.rk[1], r2 = a.rk[2];
+    const int ncol = a.g[0] * a.g[1], cb = bid * 16, t = threadIdx.x;
+    const int nG = r2 * r1 * r0;
+    const int y0 = cb / g0, cl = min(cb + 15, ncol - 1), ny = cl / g0 - y0 + 1;
+    float* sg = ls;                                  // G [iz][iy][ix]
+    float* gy = sg + nG;                             // [jy][iz][ix], y = y0 + jy
+    float* sh = gy + spec_rows(g0) * r2 * r0;        // H [iz][c]
+    float* ps = sh + r2 * 16;                        // [c][z]
+    float* ux = ps + 16 * g2;                        // U_x [x][ix]
+    float* uz = ux + g0 * r0;                        // U_z [z][iz]
+    for (int i = t; i < nG; i += kConvThreads) sg[i] = g[i];
+    for (int i = t; i < g0 * r0; i += kConvThreads) ux[i] = sp.ux[i];
+    for (int i = t; i < g2 * r2; i += kConvThreads) uz[i] = sp.uz[i];
+    __syncthreads();
+    for (int o = t; o < ny * r2 * r0; o += kConvThreads) {
+        const int jy = o / (r2 * r0), rem = o - jy * r2 * r0;
+        const int iz = rem / r0, ix = rem - iz * r0;
+        const float* uyr = sp.uy + (size_t)(y0 + jy) * r1;
+        float acc = 0.0f;
+        for (int iy = 0; iy < r1; ++iy) acc = fmaf(uyr[iy], sg[(iz * r1 + iy) * r0 + ix], acc);
+        gy[o] = acc;
+    }
+    __syncthreads();
+    for (int o = t; o < r2 * 16; o += kConvThreads) {
+        const int iz = o >> 4, cc = o & 15, col = cb + cc;
+        float acc = 0.0f;
+        if (col < ncol) {
+            const int y = col / g0, x = col - y * g0;
+            const float* gr = gy + ((y - y0) * r2 + iz) * r0;
+            for (int ix = 0; ix < r0; ++ix) acc = fmaf(ux[x * r0 + ix], gr[ix], acc);
+        }
+        sh[o] = acc;
+    }
+    __syncthreads();
+    for (int o = t; o < 16 * g2; o += kConvThreads) {
+        const int cc = o / g2, z = o - cc * g2;
+        float acc = 0.0f;
+        for (int iz = 0; iz < r2; ++iz) acc = fmaf(uz[z * r2 + iz], sh[iz * 16 + cc], acc);
+        ps[o] = acc;
+    }
+    __syncthreads();
+    return ps;
 }
 
 // ------------------------------------------------------------------ kernels
 
+// blockIdx.y == a.nterms (only with spectral terms): the plane's projection
 __global__ void __launch_bounds__(kConvThreads) k_conv_xy_f32(ConvArgs a, const float* __restrict__ rho,
                                                      const float* __restrict__ kx,
                                                      const float* __restrict__ ky,
-                                                     float* __restrict__ tgrid) {
+                                                     float* __restrict__ tgrid, SpecPtrs sp) {
     extern __shared__ float dyn_lds[];
+    if ((int)blockIdx.y == a.nterms) {
+        spec_fwd_plane(a, blockIdx.x, dyn_lds, rho, sp);
+        return;
+    }
     conv_xy_f32_body(a, blockIdx.x, blockIdx.y, dyn_lds, rho, kx, ky, tgrid);
 }
 
 // conv_z launches take xcd_blocks(nb) blocks: neighbouring column groups,
-// which share 128-byte lines of T, then run on one XCD and share its L2
+// which share 128-byte lines of T, then run on one XCD and share its L2.
+// With spectral terms the dynamic LDS holds the dense staging and then the
+// spectral part (from float offset spec_off).
 __global__ void __launch_bounds__(kConvThreads) k_conv_z_f32(ConvArgs a, int nb,
                                                              const float* __restrict__ tgrid,
                                                              const float* __restrict__ kz,
-                                                             float* __restrict__ phi) {
+                                                             float* __restrict__ phi,
+                                                             const float* __restrict__ g,
+                                                             SpecPtrs sp, int spec_off) {
     extern __shared__ float dyn_lds[];
     const int item = xcd_item(blockIdx.x, nb);
     if (item >= nb) return;
-    conv_z_f32_body(a, item, dyn_lds, tgrid, kz, phi);
+    const float* ps = a.spec ? spec_z_part(a, item, dyn_lds + spec_off, g, sp) : nullptr;
+    conv_z_f32_body(a, item, dyn_lds, tgrid, kz, phi, ps);
 }
 
 __global__ void __launch_bounds__(kConvThreads) k_conv_xy_bf16(ConvArgs a, const float* __restrict__ rho,
                                                       const unsigned short* __restrict__ kx,
                                                       const unsigned short* __restrict__ ky,
-                                                      float* __restrict__ tgrid) {
+                                                      float* __restrict__ tgrid, SpecPtrs sp) {
     extern __shared__ float dyn_lds[];
+    if ((int)blockIdx.y == a.nterms) {
+        spec_fwd_plane(a, blockIdx.x, dyn_lds, rho, sp);
+        return;
+    }
     conv_xy_bf16_body(a, blockIdx.x, blockIdx.y, dyn_lds, rho, kx, ky, tgrid);
 }
 
 __global__ void __launch_bounds__(kConvThreads) k_conv_z_bf16(ConvArgs a, int nb,
                                                               const float* __restrict__ tgrid,
                                                               const unsigned short* __restrict__ kz,
-                                                              float* __restrict__ phi) {
+                                                              float* __restrict__ phi,
+                                                              const float* __restrict__ g,
+                                                              SpecPtrs sp, int spec_off) {
     extern __shared__ float dyn_lds[];
     const int item = xcd_item(blockIdx.x, nb);
     if (item >= nb) return;
-    conv_z_bf16_body(a, item, dyn_lds, tgrid, kz, phi);
+    const float* ps = a.spec ? spec_z_part(a, item, dyn_lds + spec_off, g, sp) : nullptr;
+    conv_z_bf16_body(a, item, dyn_lds, tgrid, kz, phi, ps);
 }
 
 // batched: item = t * g_z + z (conv_xy), 16-column group (conv_z)
@@ -556,45 +721,66 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_z_batch(const BatchTable*
 // ------------------------------------------------------------------ launch
 
 size_t conv_xy_lds_bytes(const ConvArgs& a) {
+    size_t dense;
     if (a.bf16x3) {
         const int ldb = (a.gp[0] > a.gp[1] ? a.gp[0] : a.gp[1]) + 8;
-        return (size_t)2 * ldb * (a.gp[0] + a.gp[1]) * sizeof(unsigned short);
+        dense = (size_t)2 * ldb * (a.gp[0] + a.gp[1]) * sizeof(unsigned short);
+    } else {
+        const int ld = (a.gp[0] > a.gp[1] ? a.gp[0] : a.gp[1]) + 4;
+        dense = (size_t)ld * (a.gp[0] + a.gp[1]) * sizeof(float);
     }
-    const int ld = (a.gp[0] > a.gp[1] ? a.gp[0] : a.gp[1]) + 4;
-    return (size_t)ld * (a.gp[0] + a.gp[1]) * sizeof(float);
+    if (!a.spec) return dense;
+    // the plane projection: rho[z], P, U_x, U_y
+    const size_t spec = sizeof(float) * ((size_t)a.g[1] * a.g[0] + (size_t)a.g[1] * a.rk[0] +
+                                         (size_t)a.g[0] * a.rk[0] + (size_t)a.g[1] * a.rk[1]);
+    return dense > spec ? dense : spec;
+}
+
+// the dense part's LDS (staging of the terms' columns, partial sums)
+static size_t conv_z_dense_lds_bytes(const ConvArgs& a) {
+    const size_t stage = (size_t)conv_z_chunk(a) * 16 * (a.gp[2] + (a.bf16x3 ? 8 : 4)) * 4;
+    const size_t red = (size_t)(conv_z_groups(a) - 1) * (a.gp[2] / 16) * 64 * 4 * sizeof(float);
+    return ((stage > red ? stage : red) + 15) & ~(size_t)15;
 }
 
 size_t conv_z_lds_bytes(const ConvArgs& a) {
-    const size_t stage = (size_t)conv_z_chunk(a) * 16 * (a.gp[2] + (a.bf16x3 ? 8 : 4)) * 4;
-    const size_t red = (size_t)(conv_z_groups(a) - 1) * (a.gp[2] / 16) * 64 * 4 * sizeof(float);
-    return stage > red ? stage : red;
+    return conv_z_dense_lds_bytes(a) + sizeof(float) * (size_t)spec_z_lds_floats(a);
 }
 
 int conv_z_blocks(const ConvArgs& a) { return (a.g[0] * a.g[1] + 15) / 16; }
 
 hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx, const float* ky,
-                          float* tgrid, hipStream_t st) {
+                          float* tgrid, const SpecPtrs& sp, hipStream_t st) {
     const size_t lds = conv_xy_lds_bytes(a);
+    const dim3 grid(a.g[2], a.nterms + (a.spec ? 1 : 0));
     if (a.bf16x3)
-        hipLaunchKernelGGL(k_conv_xy_bf16, dim3(a.g[2], a.nterms), dim3(kConvThreads), lds, st, a, rho,
+        hipLaunchKernelGGL(k_conv_xy_bf16, grid, dim3(kConvThreads), lds, st, a, rho,
                            reinterpret_cast<const unsigned short*>(kx),
-                           reinterpret_cast<const unsigned short*>(ky), tgrid);
+                           reinterpret_cast<const unsigned short*>(ky), tgrid, sp);
     else
-        hipLaunchKernelGGL(k_conv_xy_f32, dim3(a.g[2], a.nterms), dim3(kConvThreads), lds, st, a,
-                           rho, kx, ky, tgrid);
+        hipLaunchKernelGGL(k_conv_xy_f32, grid, dim3(kConvThreads), lds, st, a, rho, kx, ky, tgrid,
+                           sp);
     return hipGetLastError();
 }
 
 hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz, float* phi,
-                         hipStream_t st) {
+                         const SpecPtrs& sp, hipStream_t st) {
     const int nb = conv_z_blocks(a);
+    // the spectral core G goes to the plane-projection buffer's tail
+    float* g = a.spec ? sp.c + (size_t)a.g[2] * a.rk[1] * a.rk[0] : nullptr;
+    if (a.spec) {
+        const int n = a.rk[2] * a.rk[1] * a.rk[0];
+        hipLaunchKernelGGL(k_spec_core, dim3((n + 15) / 16), dim3(kSpecCoreThreads), 0, st, a, sp,
+                           g);
+    }
+    const int off = (int)(conv_z_dense_lds_bytes(a) / sizeof(float));
     if (a.bf16x3)
         hipLaunchKernelGGL(k_conv_z_bf16, dim3(xcd_blocks(nb)), dim3(kConvThreads),
                            conv_z_lds_bytes(a), st, a, nb, tgrid,
-                           reinterpret_cast<const unsigned short*>(kz), phi);
+                           reinterpret_cast<const unsigned short*>(kz), phi, g, sp, off);
     else
         hipLaunchKernelGGL(k_conv_z_f32, dim3(xcd_blocks(nb)), dim3(kConvThreads),
-                           conv_z_lds_bytes(a), st, a, nb, tgrid, kz, phi);
+                           conv_z_lds_bytes(a), st, a, nb, tgrid, kz, phi, g, sp, off);
     return hipGetLastError();
 }
 

@@ -339,8 +339,10 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
     const int nh = E0 * E1 * E2;
     // sum of the potential over the brick's own points (each grid point lies
     // in exactly one brick): its total over the blocks is the grid's k = 0
-    // component, which the far energy must not contain
-    double phs = 0.0;
+    // component, which the far energy must not contain.  A thread adds at
+    // most a handful of points in FP32; the sums over threads and blocks are
+    // FP64.
+    float phs = 0.0f;
     // the loads of a pass are issued together, then stored
     for (int base = tid; base < nh; base += kGatherThreads * kGatherBatch) {
         float v[kGatherBatch];
@@ -361,7 +363,7 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
         for (int u = 0; u < kGatherBatch; ++u) {
             const int idx = base + kGatherThreads * u;
             if (idx < nh) sphi[idx] = v[u];
-            if (inb[u]) phs += (double)v[u];
+            if (inb[u]) phs += v[u];
         }
     }
     // stencil rows (ky, kz) of a charge and their offsets in the halo, once per block
@@ -501,10 +503,10 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
         }
         __syncthreads();
     }
-    phs = wave_sum_d(phs);
+    const double phw = wave_sum_d((double)phs);
     if (lane == 0) {
         se[2 * wave] = e_wave;
-        se[2 * wave + 1] = phs;
+        se[2 * wave + 1] = phw;
     }
     __syncthreads();
     if (tid == 0) {

@@ -2,7 +2,8 @@
 //   energy  q_i q_j (1/r - F(r)),
 //   force   q_i q_j (1/r^3 + F'(r)/r) (r_i - r_j)  on charge i,
 // where F is the infinite far series (eq. 24), represented inside the cutoff
-// by a polynomial in x = r^2/r_c^2 fitted on the host in FP64.
+// by a polynomial in x = r^2/r_c^2 fitted on the host in FP64.  For the
+// kernel 1/r^6 (App. A) the same with 1/r^6 - F(r) and 6/r^8 + F'(r)/r.
 //
 // Layout: cluster-pair tiles.  Charges are binned into x-y columns, sorted
 // by z, and cut into clusters of up to 8 (see kernels_bin.hip).  One block of
@@ -98,7 +99,7 @@ __device__ __forceinline__ StencilCol stencil_col(int k, int ci, int R, int nc, 
 // nsteps steps of 8 staged j-charges (st8[s * 8 + ja]) against i-charge ci.
 // CUBIC: distances in fixed-point units (one scale for all axes), qw = q_i u,
 // rc2/irc2 in those units and is = 1/u; otherwise distances in A, qw = q_i.
-template <int DEG, bool CUBIC, bool EXACT>
+template <int DEG, bool CUBIC, bool EXACT, int ALPHA>
 __device__ __forceinline__ void pair_steps(const Poly<DEG, EXACT>& P, const uint4* st8, int ja,
                                            int nsteps,
                                            uint4 ci, float qw, float sx, float sy, float sz,
@@ -139,8 +140,16 @@ __device__ __forceinline__ void pair_steps(const Poly<DEG, EXACT>& P, const uint
                     }
                 }
             }
-            ec = fmaf(qq, ((rinv - P.c[0]) - Flo) - Fe, ec);
-            const float fs = qq * fmaf(rinv * rinv, rinv, G);
+            float fs;
+            if (ALPHA == 6) {
+                const float i2 = rinv * rinv;
+                const float i6 = i2 * i2 * i2;
+                ec = fmaf(qq, ((i6 - P.c[0]) - Flo) - Fe, ec);
+                fs = qq * fmaf(6.0f * i6, i2, G);
+            } else {
+                ec = fmaf(qq, ((rinv - P.c[0]) - Flo) - Fe, ec);
+                fs = qq * fmaf(rinv * rinv, rinv, G);
+            }
             fx = fmaf(fs, dx, fx);
             fy = fmaf(fs, dy, fy);
             fz = fmaf(fs, dz, fz);
@@ -148,7 +157,7 @@ __device__ __forceinline__ void pair_steps(const Poly<DEG, EXACT>& P, const uint
     }
 }
 
-template <int DEG, bool EXACT>
+template <int DEG, bool EXACT, int ALPHA>
 __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4* __restrict__ sorted,
                                           const int* __restrict__ clus_start,
                                           const int2* __restrict__ cl_info,
@@ -363,10 +372,12 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         const int nsteps = (kept + 7) >> 3;
         float ec = 0.0f;
         if (cubic)
-            pair_steps<DEG, true, EXACT>(P, stage[w], ja, nsteps, ci, qw, sx, sx, sx, rc2w, irc2w, isx,
+            pair_steps<DEG, true, EXACT, ALPHA>(P, stage[w], ja, nsteps, ci, qw, sx, sx, sx, rc2w, irc2w,
+                                                isx,
                                   ctop, dtop, fx, fy, fz, ec);
         else
-            pair_steps<DEG, false, EXACT>(P, stage[w], ja, nsteps, ci, qw, sx, sy, sz, rc2w, irc2w, 1.0f,
+            pair_steps<DEG, false, EXACT, ALPHA>(P, stage[w], ja, nsteps, ci, qw, sx, sy, sz, rc2w, irc2w,
+                                                 1.0f,
                                    ctop, dtop, fx, fy, fz, ec);
         e += (double)ec;
         wave_sync();
@@ -392,7 +403,7 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     }
 }
 
-template <int DEG, bool EXACT>
+template <int DEG, bool EXACT, int ALPHA>
 __global__ void __launch_bounds__(64 * kPairWaves) k_pair(PairArgs a, int nb,
                                              const uint4* __restrict__ sorted,
                                              const int* __restrict__ clus_start,
@@ -404,8 +415,8 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pair(PairArgs a, int nb,
                                              double* __restrict__ epart) {
     const int item = xcd_item(blockIdx.x, nb);
     if (item < nb)
-        pair_body<DEG, EXACT>(a, item, sorted, clus_start, cl_info, cl_col, cl_z, zbin, fnear,
-                              epart);
+        pair_body<DEG, EXACT, ALPHA>(a, item, sorted, clus_start, cl_info, cl_col, cl_z, zbin,
+                                     fnear, epart);
 }
 
 // Held to 80 registers (6 wavefronts per SIMD instead of 5; the batch walk
@@ -416,8 +427,8 @@ k_pair_batch(const BatchTable* __restrict__ tab,
                                                    const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_PAIR, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        pair_body<DEG, EXACT>(d.pair, item, d.sorted, d.clus_start, d.cl_info, d.cl_col, d.cl_z,
-                              d.zbin, d.fnear, d.pair_parts);
+        pair_body<DEG, EXACT, 1>(d.pair, item, d.sorted, d.clus_start, d.cl_info, d.cl_col, d.cl_z,
+                                 d.zbin, d.fnear, d.pair_parts);
     });
 }
 
@@ -427,20 +438,27 @@ hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, cons
     if (nblocks <= 0) return hipSuccess;
     const dim3 grid(xcd_blocks(nblocks)), block(64 * kPairWaves);
     const bool exact = a.ne > 0;
+    if (a.alpha != 1 && a.alpha != 6) return hipErrorInvalidValue;
     switch (a.deg) {
+#define USERIES_PAIR_LAUNCH(D, E, A)                                                          \
+    hipLaunchKernelGGL((k_pair<D, E, A>), grid, block, 0, st, a, nblocks, sorted, clus_start, \
+                       cl_info, cl_col, cl_z, zbin, fnear, epart)
 #define USERIES_PAIR_DEG(D)                                                                   \
     case D:                                                                                   \
-        if (exact)                                                                            \
-            hipLaunchKernelGGL((k_pair<D, true>), grid, block, 0, st, a, nblocks, sorted,     \
-                               clus_start, cl_info, cl_col, cl_z, zbin, fnear, epart);        \
-        else                                                                                  \
-            hipLaunchKernelGGL((k_pair<D, false>), grid, block, 0, st, a, nblocks, sorted,    \
-                               clus_start, cl_info, cl_col, cl_z, zbin, fnear, epart);        \
+        if (a.alpha == 6) {                                                                   \
+            if (exact) USERIES_PAIR_LAUNCH(D, true, 6);                                       \
+            else USERIES_PAIR_LAUNCH(D, false, 6);                                            \
+        } else if (exact) {                                                                   \
+            USERIES_PAIR_LAUNCH(D, true, 1);                                                  \
+        } else {                                                                              \
+            USERIES_PAIR_LAUNCH(D, false, 1);                                                 \
+        }                                                                                     \
         break;
         USERIES_PAIR_DEG(4) USERIES_PAIR_DEG(5) USERIES_PAIR_DEG(6) USERIES_PAIR_DEG(7)
         USERIES_PAIR_DEG(8) USERIES_PAIR_DEG(9) USERIES_PAIR_DEG(10) USERIES_PAIR_DEG(11)
         USERIES_PAIR_DEG(12) USERIES_PAIR_DEG(13) USERIES_PAIR_DEG(14)
 #undef USERIES_PAIR_DEG
+#undef USERIES_PAIR_LAUNCH
     default:
         return hipErrorInvalidValue;
     }

@@ -60,10 +60,19 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     if (!(r_c > 0) || !(r_c < 0.5 * lmin))
         return fail(err, USERIES_EINVAL, "need 0 < r_c < min(L)/2");
     if (n_terms > kMaxTerms) return fail(err, USERIES_EINVAL, "n_terms > 32");
+    const int alpha = o.alpha > 0 ? o.alpha : 1;
+    if (alpha != 1 && alpha != 6) return fail(err, USERIES_EINVAL, "alpha must be 1 or 6");
+    if (alpha != 1 && o.construction != USERIES_C1)
+        return fail(err, USERIES_EINVAL, "1/r^6 supports the C1 construction only");
 
     double bb, r0c, w0c, s0c;
     std::string e2;
-    const int rc = solve_construction(o.construction, b, &bb, &r0c, &w0c, &s0c, &e2);
+    const int rc = alpha == 1 ? solve_construction(o.construction, b, &bb, &r0c, &w0c, &s0c, &e2)
+                              : solve_c1_alpha(b, alpha, &r0c, &w0c, &e2);
+    if (alpha != 1) {
+        bb = b;
+        s0c = 1.0;
+    }
     if (rc) {
         if (err) *err = e2;
         return rc;
@@ -77,6 +86,7 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     p.s0 = s0c;
     p.construction = o.construction;
     p.precision = o.precision;
+    p.alpha = alpha;
     p.P = P;
     p.deg = deg;
     const bool preset = o.construction != USERIES_C0 && o.construction != USERIES_C1;
@@ -94,20 +104,21 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
         // continuity correction: keep r_c, re-solve w0 of eq. 25 at r0 = r_c / sigma
         p.sigma = sigma;
         p.r0 = r_c / sigma;
-        p.w0 = c1_w0_of_r0(bb, p.r0);
+        p.w0 = alpha == 1 ? c1_w0_of_r0(bb, p.r0) : c1_w0_of_r0_alpha(bb, alpha, p.r0);
     }
-    p.nterms = n_terms > 0 ? n_terms : choose_nterms(bb, p.sigma, lmax, o.nterms_tol);
-    p.eq33 = eq33_bound(p.nterms, bb, p.sigma, lmax);
+    p.nterms = n_terms > 0 ? n_terms : choose_nterms_alpha(bb, alpha, p.sigma, lmax, o.nterms_tol);
+    p.eq33 = trunc_bound(p.nterms, bb, alpha, p.sigma, lmax);
 
     Series s;
     s.b = bb;
     s.sigma = p.sigma;
     s.w0 = p.w0;
     s.s0 = p.s0;
+    s.alpha = alpha;
     p.f_inf0 = s.f_inf0();
     double dF;
     s.f_inf(r_c, &dF);
-    p.c1_slope = -1.0 / (r_c * r_c) - dF;
+    p.c1_slope = -(double)alpha * std::pow(r_c, -(double)alpha - 1.0) - dF;
 
     // near part: F_inf and F_inf'/r inside the cutoff as polynomials in
     // r^2 / r_c^2 after the narrowest `ne` terms, which the pair kernel
@@ -132,6 +143,7 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     p.near_exact = ne;
     PairArgs& pa = p.pair;
     pa.deg = deg;
+    pa.alpha = alpha;
     pa.ne = ne;
     for (int k = 0; k <= deg; ++k) pa.c[k] = (float)coef[k];
     pa.c0lo = (float)(coef[0] - (double)pa.c[0]);
@@ -186,8 +198,109 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     ga.P = P;
     ga.inv_ngrid = 1.0 / ((double)grid[0] * grid[1] * grid[2]);
     ConvArgs& ca = p.conv;
-    ca.nterms = p.nterms_grid;
     ca.bf16x3 = bf ? 1 : 0;
+    // every grid term's circulant column per axis (term amplitude folded into x)
+    std::vector<std::vector<double>> cols[3];
+    for (int a = 0; a < 3; ++a) {
+        const double h = box[a] / grid[a];
+        const double ss = ratio * h;
+        cols[a].resize(p.nterms_grid);
+        for (int t = 0; t < p.nterms_grid; ++t) {
+            double at, st;
+            s.term(t, &at, &st);
+            const double sk2 = st * st - 2.0 * ss * ss;
+            if (!(sk2 > 0))
+                return fail(err, USERIES_EINVAL,
+                            "grid too coarse: the spreading Gaussian must be narrower than "
+                            "s_0 / sqrt(2)");
+            const double sk = std::sqrt(sk2);
+            cols[a][t].resize(grid[a]);
+            circulant_column(grid[a], h, sk, (st / sk) * (a == 0 ? at : 1.0), cols[a][t].data());
+        }
+    }
+    // Spectral form of the wide terms (Sec. V leaves the wide terms' cost open;
+    // this is a low-rank form of their circulants).  A symmetric circulant is
+    // diagonal in the real Fourier basis: K = sum_k lambda(k) (c_k c_k^T +
+    // s_k s_k^T), lambda(k) = sum_m col[m] cos(2 pi k m / n).  A wide term's
+    // lambda(k) falls like exp(-2 pi^2 k^2 s^2 / L^2), so its modes k > K are
+    // below 1e-9 of its first mode for a small K.  From the first term t_d
+    // whose modes fit in r = 2K + 1 <= min(kMaxSpecRank, n/4) on every axis,
+    // all wider terms are applied together through that basis (at least two
+    // of them, else the dense form is kept).
+    int td = p.nterms_grid;
+    int rk[3] = {0, 0, 0};
+    std::vector<std::vector<double>> lam[3];
+    if (o.spectral) {
+        for (int a = 0; a < 3; ++a) {
+            const int g = grid[a], kh = g / 2;
+            lam[a].assign(p.nterms_grid, std::vector<double>(kh + 1, 0.0));
+            for (int t = 0; t < p.nterms_grid; ++t)
+                for (int k = 0; k <= kh; ++k) {
+                    double acc = 0.0;
+                    for (int m = 0; m < g; ++m)
+                        acc += cols[a][t][m] * std::cos(2.0 * pi * (double)k * m / g);
+                    lam[a][t][k] = acc;
+                }
+        }
+        auto rank_of = [&](int t, int a) {
+            const int kh = grid[a] / 2;
+            // modes below 1e-9 of the first one, or at the FP64 rounding level
+            // of the transform (1e-13 of the k = 0 gain; the dense circulants
+            // carry FP32 rounding of 1e-7 of it), are dropped
+            const double tau = std::max(1e-9 * std::fabs(lam[a][t][std::min(1, kh)]),
+                                        1e-13 * std::fabs(lam[a][t][0]));
+            int K = kh;
+            while (K > 0 && std::fabs(lam[a][t][K]) <= tau) --K;
+            return 2 * K + 1;
+        };
+        auto fits = [&](int t) {
+            for (int a = 0; a < 3; ++a) {
+                const int r = rank_of(t, a);
+                if (r > kMaxSpecRank || 4 * r > grid[a]) return false;
+            }
+            return true;
+        };
+        while (td > 1 && fits(td - 1)) --td;
+        // forced (spectral > 0): from two terms on; automatic (< 0): from six,
+        // below which the dense matrix-core convolutions of those few terms
+        // cost less than the spectral steps (measured on the 64 A water box)
+        if (p.nterms_grid - td < (o.spectral > 0 ? 2 : 6)) td = p.nterms_grid;
+        if (td < p.nterms_grid)
+            for (int a = 0; a < 3; ++a)
+                for (int t = td; t < p.nterms_grid; ++t) rk[a] = std::max(rk[a], rank_of(t, a));
+    }
+    p.nterms_spec = p.nterms_grid - td;
+    ca.nterms = td;
+    ca.spec = p.nterms_spec > 0 ? 1 : 0;
+    for (int a = 0; a < 3; ++a) ca.rk[a] = ca.spec ? rk[a] : 0;
+    if (ca.spec) {
+        for (int a = 0; a < 3; ++a) {
+            const int g = grid[a], r = rk[a];
+            auto& U = p.ubasis[a];
+            U.assign((size_t)g * r, 0.0f);
+            for (int i = 0; i < g; ++i) {
+                U[(size_t)i * r] = (float)(1.0 / std::sqrt((double)g));
+                for (int k = 1; 2 * k < r; ++k) {
+                    const double ph = 2.0 * pi * (double)k * i / g;
+                    U[(size_t)i * r + 2 * k - 1] = (float)(std::sqrt(2.0 / g) * std::cos(ph));
+                    U[(size_t)i * r + 2 * k] = (float)(std::sqrt(2.0 / g) * std::sin(ph));
+                }
+            }
+        }
+        // W[iz][iy][ix] = sum over the spectral terms of the products of their
+        // eigenvalues (basis column i carries mode (i + 1) / 2); k = 0 removed
+        p.wspec.assign((size_t)rk[0] * rk[1] * rk[2], 0.0f);
+        for (int iz = 0; iz < rk[2]; ++iz)
+            for (int iy = 0; iy < rk[1]; ++iy)
+                for (int ix = 0; ix < rk[0]; ++ix) {
+                    double acc = 0.0;
+                    if (iz || iy || ix)
+                        for (int t = td; t < p.nterms_grid; ++t)
+                            acc += lam[2][t][(iz + 1) / 2] * lam[1][t][(iy + 1) / 2] *
+                                   lam[0][t][(ix + 1) / 2];
+                    p.wspec[((size_t)iz * rk[1] + iy) * rk[0] + ix] = (float)acc;
+                }
+    }
     for (int a = 0; a < 3; ++a) {
         const double h = box[a] / grid[a];
         const double ss = ratio * h;
@@ -200,24 +313,15 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
         ga.dws[a] = (float)(h / (ss * ss));
         const int g = grid[a], gp = ca.gp[a];
         const size_t m = (size_t)gp * gp;
-        // per term the circulant M[i][j] = col[(i - j) mod g], zero-padded to gp x gp
+        // per dense term the circulant M[i][j] = col[(i - j) mod g], zero-padded to gp x gp
         if (bf)
-            p.mats[a].assign(2 * m * p.nterms_grid * sizeof(uint16_t), 0);
+            p.mats[a].assign(2 * m * ca.nterms * sizeof(uint16_t), 0);
         else
-            p.mats[a].assign(m * p.nterms_grid * sizeof(float), 0);
-        std::vector<double> col(g);
+            p.mats[a].assign(m * ca.nterms * sizeof(float), 0);
         std::vector<float> colf(g);
         std::vector<uint16_t> chi(g), clo(g);
-        for (int t = 0; t < p.nterms_grid; ++t) {
-            double at, st;
-            s.term(t, &at, &st);
-            const double sk2 = st * st - 2.0 * ss * ss;
-            if (!(sk2 > 0))
-                return fail(err, USERIES_EINVAL,
-                            "grid too coarse: the spreading Gaussian must be narrower than "
-                            "s_0 / sqrt(2)");
-            const double sk = std::sqrt(sk2);
-            circulant_column(g, h, sk, (st / sk) * (a == 0 ? at : 1.0), col.data());
+        for (int t = 0; t < ca.nterms; ++t) {
+            const std::vector<double>& col = cols[a][t];
             for (int k = 0; k < g; ++k) {
                 colf[k] = (float)col[k];
                 chi[k] = host_bf16(colf[k]);
@@ -241,7 +345,11 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     }
     const double V = box[0] * box[1] * box[2];
     p.fin.f_inf0 = p.f_inf0;
-    p.fin.near_int_over_v = s.near_integral(r_c) / V;
+    // Coulomb: the neutralising background of a net charge (k = 0 dropped);
+    // 1/r^6: no background, but the far terms' k = 0 components, which the
+    // grid removes, are added back for the net "charge" Q = sum c_i
+    p.fin.near_int_over_v = alpha == 1 ? s.near_integral(r_c) / V : 0.0;
+    p.fin.k0_far = alpha == 1 ? 0.0 : s.kzero_sum(V);
     p.fin.inv_ngrid = ga.inv_ngrid;
     return USERIES_OK;
 }

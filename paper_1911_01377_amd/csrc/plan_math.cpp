@@ -33,19 +33,42 @@ constexpr Preset kTable2C2 = {2.0, 2.39427106444012661, 0.892857784448501290,
 
 // ---------------------------------------------------------------- series
 
+double Series::pref() const {
+    // alpha = 1: eq. 11's 2 ln b / (sqrt(2 pi) sigma).  Otherwise eq. A2 with
+    // the Gaussian exp(-u^2/2) as scaling function: ln b / (phi~(alpha)
+    // sigma^alpha), phi~(alpha) = 2^(alpha/2 - 1) Gamma(alpha/2) its Mellin
+    // transform (eq. A1); phi~(1) = sqrt(pi/2) gives eq. 11 again.
+    if (alpha == 1) return 2.0 * std::log(b) / (std::sqrt(2.0 * kPi) * sigma);
+    const double mellin = std::pow(2.0, 0.5 * alpha - 1.0) * std::tgamma(0.5 * alpha);
+    return std::log(b) / (mellin * std::pow(sigma, alpha));
+}
+
 void Series::term(int j, double* a, double* s) const {
-    // eq. 11 / 24 / 28: 2 ln b b^-j G_sigma(b^-j r) = a_j exp(-r^2/(2 s_j^2))
-    const double pref = 2.0 * std::log(b) / (std::sqrt(2.0 * kPi) * sigma);
+    // eq. 11 / 24 / 28 (A2): a_j exp(-r^2/(2 s_j^2)), a_j = pref w_j b^(-alpha j)
+    const double p = pref();
     if (j == 0) {
-        *a = pref * w0;
+        *a = p * w0;
         *s = sigma * s0;
     } else {
-        *a = pref * std::pow(b, -j);
+        *a = p * std::pow(b, -(double)alpha * j);
         *s = sigma * std::pow(b, j);
     }
 }
 
-int Series::length() const { return (int)std::ceil(18.0 * std::log(10.0) / std::log(b)) + 1; }
+int Series::length() const {
+    return (int)std::ceil(18.0 * std::log(10.0) / (alpha * std::log(b))) + 1;
+}
+
+double Series::kzero_sum(double V) const {
+    // sum over all terms of a_j (2 pi s_j^2)^(3/2) / V; from j = 1 on a
+    // geometric series of ratio b^(3 - alpha), summed in closed form
+    double a0, s0_, a1, s1;
+    term(0, &a0, &s0_);
+    term(1, &a1, &s1);
+    const double m0 = a0 * std::pow(2.0 * kPi * s0_ * s0_, 1.5) / V;
+    const double m1 = a1 * std::pow(2.0 * kPi * s1 * s1, 1.5) / V;
+    return m0 + m1 / (1.0 - std::pow(b, 3.0 - alpha));
+}
 
 double Series::f_inf(double r, double* df) const {
     double v = 0.0, d = 0.0;
@@ -61,8 +84,8 @@ double Series::f_inf(double r, double* df) const {
 }
 
 double Series::f_inf0() const {
-    // sum_j a_j = 2 ln b/(sqrt(2 pi) sigma) (w0 + sum_{j>=1} b^-j)
-    return 2.0 * std::log(b) / (std::sqrt(2.0 * kPi) * sigma) * (w0 + 1.0 / (b - 1.0));
+    // sum_j a_j = pref (w0 + sum_{j>=1} b^(-alpha j))
+    return pref() * (w0 + 1.0 / (std::pow(b, (double)alpha) - 1.0));
 }
 
 double Series::near_integral(double rc) const {
@@ -102,6 +125,20 @@ double eq33_bound(int n, double b, double sigma, double lmax) {
 int choose_nterms(double b, double sigma, double lmax, double tol) {
     for (int n = 1; n <= kMaxTerms; ++n)
         if (eq33_bound(n, b, sigma, lmax) <= tol) return n;
+    return kMaxTerms;
+}
+
+double trunc_bound(int n, double b, int alpha, double sigma, double lmax) {
+    // the k-space weight a_t (2 pi s_t^2)^(3/2) exp(-s_t^2 k^2/2) of the first
+    // dropped term relative to term 0's at k = 2 pi / L (eq. 33 at alpha = 1)
+    if (alpha == 1) return eq33_bound(n, b, sigma, lmax);
+    return std::exp((3.0 - alpha) * n * std::log(b) -
+                    2.0 * (std::pow(b, 2.0 * n) - 1.0) * kPi * kPi * sigma * sigma / (lmax * lmax));
+}
+
+int choose_nterms_alpha(double b, int alpha, double sigma, double lmax, double tol) {
+    for (int n = 1; n <= kMaxTerms; ++n)
+        if (trunc_bound(n, b, alpha, sigma, lmax) <= tol) return n;
     return kMaxTerms;
 }
 
@@ -230,6 +267,50 @@ bool smallest_root(F f, double tang_tol, double* root) {
 }
 
 }  // namespace
+
+double c1_w0_of_r0_alpha(double b, int alpha, double r0) {
+    // continuity of the near part at r0 (sigma = 1): r0^alpha F(r0) = 1
+    if (alpha == 1) return c1_w0_of_r0(b, r0);
+    Series s;
+    s.b = b;
+    s.alpha = alpha;
+    double tail = 0.0;
+    for (int j = s.length() - 1; j >= 1; --j) {
+        double a, w;
+        s.term(j, &a, &w);
+        tail += a * std::exp(-r0 * r0 / (2.0 * w * w));
+    }
+    return (std::pow(r0, -(double)alpha) - tail) / (s.pref() * std::exp(-r0 * r0 / 2.0));
+}
+
+int solve_c1_alpha(double b, int alpha, double* r0, double* w0, std::string* err) {
+    if (alpha == 1) {
+        double bb, s0;
+        return solve_construction(USERIES_C1, b, &bb, r0, w0, &s0, err);
+    }
+    if (!(b > 1.0) || !std::isfinite(b)) {
+        if (err) *err = "base b must be > 1";
+        return USERIES_EINVAL;
+    }
+    // slope condition r^(alpha+1) F'(r) + alpha = 0 with w0 from continuity
+    auto resid = [b, alpha](double r) {
+        Series s;
+        s.b = b;
+        s.alpha = alpha;
+        s.w0 = c1_w0_of_r0_alpha(b, alpha, r);
+        double df;
+        s.f_inf(r, &df);
+        return std::pow(r, alpha + 1.0) * df + alpha;
+    };
+    double root;
+    if (!smallest_root(resid, 1e-12, &root)) {
+        if (err) *err = "no C1 root below r = 50";
+        return USERIES_EINVAL;
+    }
+    *r0 = root;
+    *w0 = c1_w0_of_r0_alpha(b, alpha, root);
+    return USERIES_OK;
+}
 
 double c1_w0_of_r0(double b, double r0) {
     double t, dt;
@@ -427,14 +508,16 @@ double fit_near_poly_unit(const Series& s, double rc, int degree, int nexact, do
 
 double fit_near_poly(const Series& s, double rc, int degree, int nexact, double* fcoef,
                      double* gcoef) {
-    // Every term scales with sigma: F(r; sigma) = F(r / sigma; 1) / sigma and
-    // F'(r; sigma)/r = (F'/r)(r / sigma; 1) / sigma^3.  The fit is made once
-    // per (b, w0, s0, r_c / sigma, degree, nexact) at sigma = 1 and scaled.
+    // Every term scales with sigma: F(r; sigma) = F(r / sigma; 1) / sigma^alpha
+    // and F'(r; sigma)/r = (F'/r)(r / sigma; 1) / sigma^(alpha + 2).  The fit is
+    // made once per (b, alpha, w0, s0, r_c / sigma, degree, nexact) at sigma = 1
+    // and scaled.
     struct Key {
         double b, w0, s0, u;
-        int degree, nexact;
+        int alpha, degree, nexact;
         bool operator<(const Key& o) const {
             if (b != o.b) return b < o.b;
+            if (alpha != o.alpha) return alpha < o.alpha;
             if (w0 != o.w0) return w0 < o.w0;
             if (s0 != o.s0) return s0 < o.s0;
             if (u != o.u) return u < o.u;
@@ -447,7 +530,7 @@ double fit_near_poly(const Series& s, double rc, int degree, int nexact, double*
     };
     static std::mutex mu;
     static std::map<Key, Fit> cache;
-    const Key key{s.b, s.w0, s.s0, rc / s.sigma, degree, nexact};
+    const Key key{s.b, s.w0, s.s0, rc / s.sigma, s.alpha, degree, nexact};
     Fit fit;
     bool have = false;
     {
@@ -466,10 +549,12 @@ double fit_near_poly(const Series& s, double rc, int degree, int nexact, double*
         if (cache.size() > 4096) cache.clear();
         cache[key] = fit;
     }
-    const double s1 = 1.0 / s.sigma, s3 = s1 * s1 * s1;
+    const double s1 = 1.0 / s.sigma;
+    const double sf = s.alpha == 1 ? s1 : std::pow(s.sigma, -(double)s.alpha);
+    const double sg = s.alpha == 1 ? s1 * s1 * s1 : sf * s1 * s1;
     for (int k = 0; k <= degree; ++k) {
-        fcoef[k] = fit.f[k] * s1;
-        gcoef[k] = fit.g[k] * s3;
+        fcoef[k] = fit.f[k] * sf;
+        gcoef[k] = fit.g[k] * sg;
     }
     return fit.err;
 }

@@ -655,6 +655,7 @@ int useries_server_create(useries_server_t* out, size_t hbm_budget_bytes, int ma
     S->popts.precision = precision;
     S->popts.nterms_tol = o.nterms_tol;
     S->popts.poly_degree = o.poly_degree;
+    S->popts.spectral = 0;   // the batched convolutions take dense terms only
     S->budget = hbm_budget_bytes / kAlign * kAlign;
     hipError_t e;
     if ((e = hipGetDevice(&S->device))) return set_last_error(USERIES_EHIP, hipGetErrorString(e));

@@ -21,22 +21,34 @@ constexpr int kMaxWindowCols = 256;   // x-y columns touching a spreading brick
 
 // ------------------------------------------------------------ host math
 // FP64 parameter math of the u-series (plan_math.cpp).
+// The far series of the kernel 1/r^alpha (alpha = 1: Coulomb, eqs. 11, 24,
+// 28; alpha = 6: the BSA of App. A, eq. A2, with the Gaussian scaling
+// function).
 struct Series {
     double b = 2.0, sigma = 1.0, w0 = 1.0, s0 = 1.0;
-    // amplitude and width of term j (eqs. 11, 24, 28)
+    int alpha = 1;
+    double pref() const;                        // a_j = pref w_j b^(-alpha j)
+    // amplitude and width of term j
     void term(int j, double* a, double* s) const;
-    int length() const;                         // terms with b^-j > 1e-18
+    int length() const;                         // terms with b^(-alpha j) > 1e-18
     double f_inf(double r, double* df = nullptr) const;   // all terms
     double g_inf(double r) const;               // F_inf'(r) / r, all terms
-    double f_inf0() const;                      // closed form (w0 + 1/(b-1)) 2ln b/(sqrt(2pi) sigma)
-    double near_integral(double rc) const;      // int_{|r|<rc} (1/r - F_inf) d^3r
+    double f_inf0() const;                      // closed form pref (w0 + 1/(b^alpha - 1))
+    double near_integral(double rc) const;      // int_{|r|<rc} (1/r - F_inf) d^3r (alpha = 1)
+    double kzero_sum(double V) const;           // sum_j a_j (2 pi s_j^2)^(3/2) / V (alpha > 3)
 };
 
 int solve_construction(int construction, double b, double* b_out, double* r0, double* w0,
                        double* s0, std::string* err);
+// (r0, w0) of the C1 construction for 1/r^alpha (alpha = 1: eqs. 25-26)
+int solve_c1_alpha(double b, int alpha, double* r0, double* w0, std::string* err);
 double c1_w0_of_r0(double b, double r0);       // eq. 25 at sigma = 1
+double c1_w0_of_r0_alpha(double b, int alpha, double r0);
 double eq33_bound(int n, double b, double sigma, double lmax);
+// the kernel-power form of eq. 33: b^((3 - alpha) n) exp(-2 (b^(2n) - 1) pi^2 sigma^2 / L^2)
+double trunc_bound(int n, double b, int alpha, double sigma, double lmax);
 int choose_nterms(double b, double sigma, double lmax, double tol);
+int choose_nterms_alpha(double b, int alpha, double sigma, double lmax, double tol);
 double bsa_bound(double b);
 
 // monomial coefficients in x = r^2/rc^2 on [0,1] of F_inf(r) (fcoef) and of
@@ -69,6 +81,7 @@ struct PairArgs {
     float inv_rc2;        // 1 / r_c^2
     int gz;               // grid points along z (planes of the z-plane index)
     int deg;              // polynomial degree
+    int alpha;            // kernel power: 1 (1/r) or 6 (1/r^6)
     int ne;               // leading far terms evaluated as Gaussians (0..kMaxExact)
     float c[kMaxPolyDeg + 1];   // F_inf(r) = sum_{j<ne} ea_j 2^(x ex_j) + sum c_k x^k, x = r^2/rc^2
     float c0lo;                 // c_0 - (float)c_0
@@ -89,19 +102,29 @@ struct GridArgs {
     double inv_ngrid;     // 1 / (gx gy gz)
 };
 
+constexpr int kMaxSpecRank = 17;   // Fourier modes per axis of the spectral wide terms
+
 struct ConvArgs {
     int g[3];
     int gp[3];            // padded: multiple of 16 (FP32) or 32 (BF16X3)
-    int nterms;
+    int nterms;           // terms convolved with dense circulants (the narrowest ones)
     int bf16x3;
+    // The wider terms that follow, in spectral form (spec = 1): each of their
+    // circulants is U diag(lambda_t) U^T up to modes below 1e-9 of its first
+    // one, U the n x r real Fourier basis (1, cos, sin of modes 1..K, r =
+    // 2K + 1), so together they are (U_z x U_y x U_x) diag(W) (...)^T with W the
+    // summed products of their per-axis eigenvalues (k = 0 removed).
+    int spec;
+    int rk[3];            // r per axis (x, y, z)
 };
 
 struct FinalArgs {
     int n_pair_parts;
     int n_gather_parts;   // gather blocks: 2 n_gather_parts partials (energies, then grid sums of phi)
     double f_inf0;        // self-term coefficient
-    double near_int_over_v;   // int N d^3r / V (background)
+    double near_int_over_v;   // int N d^3r / V (Coulomb background)
     double inv_ngrid;     // 1 / (gx gy gz): grid mean of phi from its sum
+    double k0_far;        // alpha > 3: sum of the far terms' k = 0 means (the grid drops them)
 };
 
 // ------------------------------------------------------------ host plan
@@ -111,10 +134,11 @@ struct FinalArgs {
 struct HostPlan {
     double box[3] = {0, 0, 0};
     double rc = 0, b = 2, sigma = 1, r0 = 1, w0 = 1, s0 = 1;
-    int construction = USERIES_C1, precision = USERIES_PLAIN_FP32;
+    int construction = USERIES_C1, precision = USERIES_PLAIN_FP32, alpha = 1;
     int nterms = 0, P = 5, deg = 8;
     int near_exact = 0;    // leading far terms the pair kernel evaluates as Gaussians
     int nterms_grid = 0;   // leading terms evaluated on the grid (the rest: k = 0 only)
+    int nterms_spec = 0;   // of those, the widest ones, in spectral form (ConvArgs::spec)
     int grid[3] = {0, 0, 0};
     double eq33 = 0, f_inf0 = 0, c1_slope = 0, poly_maxerr = 0, sigma_s[3] = {0, 0, 0};
     int ncmax[2] = {1, 1};   // bounds of the x-y column grid (chosen per evaluation)
@@ -124,7 +148,9 @@ struct HostPlan {
     GridArgs gridargs{};
     ConvArgs conv{};
     FinalArgs fin{};
-    std::vector<uint8_t> mats[3];   // device-format matrices per axis
+    std::vector<uint8_t> mats[3];   // device-format matrices per axis (dense terms)
+    std::vector<float> ubasis[3];   // spectral terms: n_a x r_a Fourier bases, row-major
+    std::vector<float> wspec;       // spectral terms: W [r_z][r_y][r_x]
 };
 
 // Record the message returned by useries_last_error() in this thread; returns code.
@@ -134,6 +160,7 @@ int set_last_error(int code, const std::string& msg);
 // error code with *err set.
 int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, double sigma,
                     int n_terms, const int grid[3], const useries_opts* opts, std::string* err);
+
 
 // The x-y column grid for n charges (about 8 charges per cluster of one
 // column cross-section and similar z extent, within the plan's bounds):
@@ -276,10 +303,18 @@ hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, cons
                        float4* fnear, double* epart, hipStream_t st);
 hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* zbin,
                          const double* qstats, float* rho, hipStream_t st);
+// device buffers of the spectral wide terms (ConvArgs::spec)
+struct SpecPtrs {
+    const float *ux = nullptr, *uy = nullptr, *uz = nullptr;   // [g_a][r_a] bases
+    const float* w = nullptr;                                  // [r_z][r_y][r_x]
+    float* c = nullptr;                                        // [g_z][r_y][r_x] plane projections
+};
+// conv_xy also projects each plane onto the spectral basis (one more block
+// per plane); conv_z adds the spectral terms' potential to its columns
 hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx,
-                          const float* ky, float* tgrid, hipStream_t st);
+                          const float* ky, float* tgrid, const SpecPtrs& sp, hipStream_t st);
 hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz, float* phi,
-                         hipStream_t st);
+                         const SpecPtrs& sp, hipStream_t st);
 // epart: 2 gather_blocks(a) doubles, the blocks' far energies then their
 // sums of phi over their own grid points
 hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm, const int* zbin,

@@ -32,13 +32,13 @@ def gpu_eval(xyz, q, box, rc, grid, **kw):
     return out
 
 
-def oracle_params(info, rc):
+def oracle_params(info, rc, alpha=1):
     return oracle.Params(b=info["b"], sigma=info["sigma"], w0=info["w0"], s0=info["s0"], rc=rc,
-                         nterms=info["n_terms"])
+                         nterms=info["n_terms"], alpha=float(alpha))
 
 
-def oracle_eval(xyz, q, box, info, rc):
-    p = oracle_params(info, rc)
+def oracle_eval(xyz, q, box, info, rc, alpha=1):
+    p = oracle_params(info, rc, alpha)
     parts, f = oracle.eval_full(np.asarray(xyz, np.float64), np.asarray(q, np.float64), box, p)
     return parts, f
 
@@ -82,7 +82,7 @@ def compare(tag, xyz, q, box, rc, grid, e_tol, f_tol, e_scale="total", **kw):
     own size, whatever the cancellation between them."""
     log("case %s: n=%d box=%s rc=%g grid=%s %s" % (tag, len(q), tuple(box), rc, tuple(grid), kw))
     gparts, gf, info = gpu_eval(xyz, q, box, rc, grid, **kw)
-    oparts, of = oracle_eval(xyz, q, box, info, rc)
+    oparts, of = oracle_eval(xyz, q, box, info, rc, kw.get("alpha", 1))
     if e_scale == "parts":
         escale = abs(oparts["near"]) + abs(oparts["far"]) + abs(oparts["self"])
     else:

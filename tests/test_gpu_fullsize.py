@@ -83,3 +83,52 @@ def test_fullsize(name, form, e_tol, f_tol):
     assert da <= 10.0 * f_tol
     # the force sum of a periodic system vanishes up to rounding
     assert np.linalg.norm(f.sum(axis=0)) <= 1e-3 * math.sqrt(len(q)) * g["force_rms"]
+
+
+CURVE = [("C1_b2", "USERIES_C1"), ("C2_b2", "USERIES_C2_B2"), ("T1_row1", "USERIES_TABLE1_ROW1"),
+         ("T1_row2", "USERIES_TABLE1_ROW2"), ("T1_row3", "USERIES_TABLE1_ROW3")]
+
+
+@pytest.mark.parametrize("name,cname", CURVE)
+@pytest.mark.parametrize("form,e_tol,f_tol", [("plain", 1e-6, 1e-5), ("bf16x3", 1e-3, 1e-3)])
+def test_fullsize_every_construction(name, cname, form, e_tol, f_tol):
+    """The water box of 26,268 charges with each series of Tables 1-2 (stored
+    oracle values from tests/golden/make_curve.py), the grid spacing at most
+    1 A and at most s_0 / 2 (80^3 for Table 1 row 3, 64^3 otherwise), in the
+    configuration the benchmark's accuracy curve times."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1911_01377_amd as U
+    path = os.path.join(GOLD, "curve_water26k.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle values for the curve")
+    gold = json.load(open(path))
+    if name not in gold["entries"]:
+        pytest.skip("no stored oracle value for %s" % name)
+    g = gold["entries"][name]
+    xyz, q, box = synth.WORKLOADS["water26k"]()
+    s0w = g["params"]["sigma"] * g["params"]["s0"]
+    gn = int(math.ceil(box[0] / min(1.0, 0.5 * s0w)))
+    log("case water26k/%s/%s: grid %d^3" % (name, form, gn))
+    prec = USERIES_BF16X3 if form == "bf16x3" else USERIES_PLAIN_FP32
+    plan = Plan(box, g["params"]["rc"], (gn, gn, gn), construction=getattr(U, cname), precision=prec)
+    info = plan.info
+    assert info["n_terms"] == g["params"]["nterms"]
+    assert abs(info["sigma"] - g["params"]["sigma"]) <= 1e-13 * g["params"]["sigma"]
+    dev = torch.device("cuda:0")
+    parts = torch.zeros(5, dtype=torch.float64, device=dev)
+    _, forces, _ = plan.eval(torch.from_numpy(xyz).to(dev), torch.from_numpy(q).to(dev),
+                             parts=parts)
+    torch.cuda.synchronize()
+    p = parts.cpu().numpy()
+    f = forces.cpu().numpy().astype(np.float64)
+    plan.close()
+    idx = np.array(gold["sample_idx"])
+    fo = np.array(g["sample_forces"])
+    de = abs(p[4] - g["parts"]["total"]) / abs(g["parts"]["total"])
+    df = math.sqrt(np.sum((f[idx] - fo) ** 2) / np.sum(fo ** 2))
+    mag = np.sqrt(np.sum(fo ** 2, axis=1))
+    da = float((np.sqrt(np.sum((f[idx] - fo) ** 2, axis=1)) / np.maximum(mag, g["force_rms"])).max())
+    log("   N=%d exact near terms %d: dE=%.2e dF(512 sampled)=%.2e max|dF_i|/max(|F_i|,rms)=%.2e"
+        % (info["n_terms"], info["near_exact"], de, df, da))
+    assert de <= e_tol and df <= f_tol and da <= 10.0 * f_tol

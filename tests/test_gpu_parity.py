@@ -356,3 +356,79 @@ def test_c1_at_other_bases():
     for b in (1.5, 3.0):
         compare("water500/C1/b%.1f" % b, xyz, q, box, min(9.0, 0.45 * L), (g, g, g), 1e-6, 1e-5,
                 construction=USERIES_C1, b=b)
+
+
+@pytest.mark.parametrize("precision,tol", FORMS)
+def test_dispersion_kernel_alpha6(precision, tol):
+    """The 1/r^6 series (App. A, C1 construction for 1/r^6 at b = 2) through
+    the same kernels: positive coefficients (no neutrality; the far terms keep
+    their k = 0 components), a water box with one coefficient per site kind
+    and random coefficients in a cube; against the oracle's 1/r^6 series with
+    the plan's parameters."""
+    f = _form(precision)
+    n_mol = 600
+    L = (n_mol / synth.WATER_DENSITY) ** (1 / 3)
+    xyz, _, box = synth.water_box(n_mol=n_mol, L=L, seed=66)
+    c = np.tile(np.array([1.0, 0.25, 0.25], np.float32), n_mol)
+    g = int(np.ceil(L))
+    _, _, _, _, info = compare("water600/r^-6/" + f, xyz, c, box, 9.0, (g, g, g), tol[0], tol[1],
+                               alpha=6, precision=precision)
+    assert info["n_terms"] >= 2
+    rng = np.random.default_rng(67)
+    xyz = rng.uniform(0, 22.0, (700, 3)).astype(np.float32)
+    c = rng.uniform(0.2, 1.5, 700).astype(np.float32)
+    compare("random700/r^-6/" + f, xyz, c, (22.0, 22.0, 22.0), 8.5, (24, 24, 24), tol[0], tol[1],
+            alpha=6, precision=precision)
+
+
+def test_dispersion_lattice_forces_vanish():
+    """Identical coefficients on a simple-cubic lattice (64 sites, spacing
+    4 A): the 1/r^6 forces vanish by symmetry and the energy matches the
+    oracle's."""
+    g = np.arange(4) * 4.0
+    xyz = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3).astype(np.float32)
+    c = np.ones(len(xyz), np.float32)
+    box = (16.0, 16.0, 16.0)
+    log("case sc64/r^-6")
+    gp, gf, info = gpu_eval(xyz, c, box, 7.9, (16, 16, 16), alpha=6)
+    op, of = oracle_eval(xyz, c, box, info, 7.9, alpha=6)
+    de = abs(gp[4] - op["total"]) / abs(op["total"])
+    # a typical pair force at the lattice spacing, for scale
+    fpair = 6.0 / 4.0 ** 7
+    log("   E_gpu=%.12g E_oracle=%.12g dE=%.2e max|F_gpu|=%.2e max|F_oracle|=%.2e (pair %.2e)"
+        % (gp[4], op["total"], de, np.max(np.abs(gf)), np.max(np.abs(of)), fpair))
+    assert de <= 1e-6
+    assert np.max(np.abs(of)) < 1e-12 * fpair
+    assert np.max(np.abs(gf)) < 1e-5 * fpair
+
+
+@pytest.mark.parametrize("precision,tol", FORMS)
+def test_spectral_wide_terms(precision, tol):
+    """The widest far terms applied together in spectral form (a low-rank form
+    of their circulants: the real Fourier modes each needs down to 1e-9 of its
+    first mode), against the oracle's exact image sums: a 30 A water box at
+    b = 2 (N = 3, the two widest spectral), the same with N = 8 terms, and
+    Table 1 row 3 (N = 15, the eight widest spectral).  The spectral and
+    dense forms of one plan agree to the truncation (1e-9) plus FP32
+    rounding."""
+    f = _form(precision)
+    xyz, q, box = synth.water_box(None, 30.0, seed=24)
+    for nt in (0, 8):
+        _, gf, _, of, info = compare("wide30/spectral/N%d/%s" % (nt, f), xyz, q, box, 9.0,
+                                     (30, 30, 30), tol[0], tol[1], n_terms=nt, spectral=1,
+                                     precision=precision)
+        assert info["n_terms_spectral"] >= 2, info
+        assert info["n_terms_grid"] - info["n_terms_spectral"] >= 1
+        gd, fd, infod = gpu_eval(xyz, q, box, 9.0, (30, 30, 30), n_terms=nt, spectral=0,
+                                 precision=precision)
+        log("   spectral %d of %d grid terms, ranks %s; vs the dense form: dF=%.2e"
+            % (info["n_terms_spectral"], info["n_terms_grid"], info["spectral_rank"],
+               rel_rms(gf, fd)))
+        assert rel_rms(gf, fd) < (2e-6 if not precision else 1e-4)
+    n_mol = 600
+    L = (n_mol / synth.WATER_DENSITY) ** (1 / 3)
+    xyz, q, box = synth.water_box(n_mol=n_mol, L=L, seed=313)
+    _, _, _, _, info = compare("water600/T1r3/spectral/" + f, xyz, q, box, 9.0, (33, 33, 33),
+                               tol[0], tol[1], construction=USERIES_TABLE1_ROW3, spectral=1,
+                               precision=precision)
+    assert info["n_terms_spectral"] >= 2, info
