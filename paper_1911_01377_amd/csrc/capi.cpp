@@ -30,8 +30,10 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(USERIES_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-constexpr const char* kKernelNames[] = {"encode", "scan",   "scatter", "colsort", "pair",
-                                        "spread", "conv_xy", "conv_z", "gather",  "finalize"};
+// the binning runs either bin_local, colbuild or encode, [scan,] scatter, colsort
+constexpr const char* kKernelNames[] = {"bin_local", "encode", "scan",    "scatter",
+                                        "colsort",   "colbuild", "pair",  "spread",
+                                        "conv_xy",   "conv_z",   "gather", "finalize"};
 constexpr int kNumKernels = sizeof(kKernelNames) / sizeof(kKernelNames[0]);
 
 template <class T>
@@ -46,6 +48,13 @@ hipError_t dalloc(T** p, size_t count) {
 namespace useries {
 int set_last_error(int code, const std::string& msg) { return fail(code, msg); }
 }  // namespace useries
+
+// ints of the per-block column prefixes of two-launch binning for up to c
+// charges (0: that binning is not used)
+static int64_t bpre_ints(const useries::HostPlan& hp, int64_t c) {
+    const int64_t nb = (c + 255) / 256;
+    return useries::bin_local_ok((int)c, hp.ncol_max) ? nb * (hp.ncol_max + 1) : 0;
+}
 
 struct useries_plan_s {
     int device = 0;
@@ -70,6 +79,8 @@ struct useries_plan_s {
     uint2* cl_z = nullptr;
     float4* fnear = nullptr;
     double *qpart = nullptr, *pair_parts = nullptr, *gather_parts = nullptr;
+    int* bpre = nullptr;
+    int64_t bpre_cap = 0;
     // timing
     bool timing = false;
     double tsum[kNumKernels] = {0};
@@ -92,6 +103,9 @@ struct useries_plan_s {
         hipFree(slots);
         hipFree(fnear);
         hipFree(qpart);
+        hipFree(bpre);
+        bpre = nullptr;
+        bpre_cap = 0;
         coord = sorted = nullptr;
         perm = slots = cl_col = nullptr;
         cl_info = nullptr;
@@ -112,10 +126,12 @@ struct useries_plan_s {
             (e = dalloc(&perm, c)) || (e = dalloc(&slots, c)) || (e = dalloc(&cl_info, clmax)) ||
             (e = dalloc(&cl_col, clmax)) || (e = dalloc(&cl_z, clmax)) ||
             (e = dalloc(&pair_parts, clmax)) || (e = dalloc(&fnear, c)) ||
-            (e = dalloc(&qpart, 2 * (size_t)((c + 255) / 256)))) {
+            (e = dalloc(&qpart, 2 * (size_t)((c + 255) / 256))) ||
+            (bpre_ints(hp, c) > 0 && (e = dalloc(&bpre, (size_t)bpre_ints(hp, c))))) {
             free_atoms();
             return fail(USERIES_ENOMEM, std::string("workspace allocation: ") + hipGetErrorString(e));
         }
+        bpre_cap = bpre_ints(hp, c);
         cap = c;
         return USERIES_OK;
     }
@@ -304,7 +320,7 @@ int plan_device(useries_plan_t p) { return p->device; }
 // Byte offsets of the per-charge workspace of n charges in one contiguous
 // buffer (each array 256-byte aligned).
 struct AtomLayout {
-    size_t coord, sorted, perm, slots, cl_info, cl_col, cl_z, pair_parts, fnear, qpart, total;
+    size_t coord, sorted, perm, slots, cl_info, cl_col, cl_z, pair_parts, fnear, qpart, bpre, total;
 };
 
 static AtomLayout atom_layout(const HostPlan& hp, int64_t n) {
@@ -327,6 +343,7 @@ static AtomLayout atom_layout(const HostPlan& hp, int64_t n) {
     L.pair_parts = take(8 * (size_t)clmax);
     L.fnear = take(16 * (size_t)c);
     L.qpart = take(16 * (size_t)((c + 255) / 256));
+    L.bpre = take(4 * (size_t)bpre_ints(hp, c));
     L.total = o;
     return L;
 }
@@ -346,6 +363,8 @@ AtomWs atom_workspace_at(useries_plan_t p, int64_t n, char* base) {
     w.pair_parts = (double*)(base + L.pair_parts);
     w.fnear = (float4*)(base + L.fnear);
     w.qpart = (double*)(base + L.qpart);
+    w.bpre_cap = bpre_ints(p->hp, std::max<int64_t>(n, 1));
+    w.bpre = w.bpre_cap > 0 ? (int*)(base + L.bpre) : nullptr;
     return w;
 }
 
@@ -374,6 +393,8 @@ int plan_eval(useries_plan_t p, int64_t n, const float* xyz, const float* q, flo
         own.pair_parts = p->pair_parts;
         own.fnear = p->fnear;
         own.qpart = p->qpart;
+        own.bpre = p->bpre;
+        own.bpre_cap = p->bpre_cap;
     }
     const AtomWs& W = ext ? *ext : own;
     HostPlan& hp = p->hp;
@@ -416,32 +437,40 @@ int plan_eval(useries_plan_t p, int64_t n, const float* xyz, const float* q, flo
     const float* kx = (const float*)p->kx;
     const float* ky = (const float*)p->ky;
     const float* kz = (const float*)p->kz;
-    USERIES_STEP(0, st, launch_encode(hp.bin, xyz, q, W.coord, p->col_count, W.qpart,
-                                      nq, st));
-    if (!scan_fused(ni, ncol))
-        USERIES_STEP(1, st, launch_scan(ncol, p->col_count, p->col_start, p->clus_start,
-                                        p->col_fill, W.qpart, nq, p->qstats, st));
-    USERIES_STEP(2, st, launch_scatter(hp.bin, W.coord, W.sorted, p->col_count, p->col_start,
-                                       p->clus_start, p->col_fill, W.slots, W.qpart, nq,
-                                       p->qstats, st));
-    USERIES_STEP(3, st, launch_colsort(ncol, hp.bin.nc[0], p->col_start, p->clus_start, W.slots,
-                                       W.coord,
-                                       W.perm, W.sorted, W.cl_info, W.cl_col, W.cl_z,
-                                       hp.grid[2], p->zbin, p->col_count, p->col_fill, st));
-    USERIES_STEP(4, st, launch_pair(hp.pair, npb, W.sorted, p->clus_start, W.cl_info, W.cl_col,
-                                    W.cl_z, p->zbin, W.fnear, W.pair_parts, st));
-    USERIES_STEP(5, st, launch_spread(hp.gridargs, W.sorted, p->zbin, p->qstats, p->rho, st));
+    if (W.bpre && bin_local_ok(ni, ncol) && (int64_t)nq * (ncol + 1) <= W.bpre_cap) {
+        USERIES_STEP(0, st, launch_bin_local(hp.bin, xyz, q, W.coord, W.slots, W.bpre, W.qpart,
+                                             st));
+        USERIES_STEP(5, st, launch_colbuild(ni, ncol, hp.bin.nc[0], hp.grid[2], npb, W.bpre,
+                                            W.coord, W.slots, W.perm, W.sorted, W.cl_info,
+                                            W.cl_col, W.cl_z, p->zbin, W.qpart, p->qstats, st));
+    } else {
+        USERIES_STEP(1, st, launch_encode(hp.bin, xyz, q, W.coord, p->col_count, W.qpart,
+                                          nq, st));
+        if (!scan_fused(ni, ncol))
+            USERIES_STEP(2, st, launch_scan(ncol, p->col_count, p->col_start, p->clus_start,
+                                            p->col_fill, W.qpart, nq, p->qstats, st));
+        USERIES_STEP(3, st, launch_scatter(hp.bin, W.coord, W.sorted, p->col_count,
+                                           p->col_start, p->clus_start, p->col_fill, W.slots,
+                                           W.qpart, nq, p->qstats, st));
+        USERIES_STEP(4, st, launch_colsort(ncol, hp.bin.nc[0], p->col_start, p->clus_start,
+                                           W.slots, W.coord, W.perm, W.sorted, W.cl_info,
+                                           W.cl_col, W.cl_z, hp.grid[2], p->zbin, p->col_count,
+                                           p->col_fill, npb, st));
+    }
+    USERIES_STEP(6, st, launch_pair(hp.pair, npb, W.sorted, W.cl_info, W.cl_col, W.cl_z,
+                                    p->zbin, W.fnear, W.pair_parts, st));
+    USERIES_STEP(7, st, launch_spread(hp.gridargs, W.sorted, p->zbin, p->qstats, p->rho, st));
     SpecPtrs sp;
     sp.ux = p->ux;
     sp.uy = p->uy;
     sp.uz = p->uz;
     sp.w = p->wspec;
     sp.c = p->cspec;
-    USERIES_STEP(6, st, launch_conv_xy(hp.conv, p->rho, kx, ky, p->tgrid, sp, st));
-    USERIES_STEP(7, st, launch_conv_z(hp.conv, p->tgrid, kz, p->phi, sp, st));
-    USERIES_STEP(8, st, launch_gather(hp.gridargs, W.sorted, W.perm, p->zbin, p->phi, W.fnear,
+    USERIES_STEP(8, st, launch_conv_xy(hp.conv, p->rho, kx, ky, p->tgrid, sp, st));
+    USERIES_STEP(9, st, launch_conv_z(hp.conv, p->tgrid, kz, p->phi, sp, st));
+    USERIES_STEP(10, st, launch_gather(hp.gridargs, W.sorted, W.perm, p->zbin, p->phi, W.fnear,
                                       forces, p->gather_parts, st));
-    USERIES_STEP(9, st, launch_finalize(hp.fin, W.pair_parts, p->gather_parts, p->qstats, energy,
+    USERIES_STEP(11, st, launch_finalize(hp.fin, W.pair_parts, p->gather_parts, p->qstats, energy,
                                         parts, st));
 #undef USERIES_STEP
     return USERIES_OK;

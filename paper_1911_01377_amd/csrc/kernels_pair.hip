@@ -159,7 +159,6 @@ __device__ __forceinline__ void pair_steps(const Poly<DEG, EXACT>& P, const uint
 
 template <int DEG, bool EXACT, int ALPHA>
 __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4* __restrict__ sorted,
-                                          const int* __restrict__ clus_start,
                                           const int2* __restrict__ cl_info,
                                           const int* __restrict__ cl_col,
                                           const uint2* __restrict__ cl_z,
@@ -176,14 +175,16 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int ia = lane >> 3, ja = lane & 7;
     const int ncx = a.nc[0], ncy = a.nc[1], gz = a.gz;
-    if (I >= clus_start[ncx * ncy]) {
+    // the cluster's records, loaded together (those of a cluster number
+    // with no charges are not used)
+    const int2 ii = cl_info[I];
+    const int C = cl_col[I];                  // cx | cy << 16
+    const uint2 zI = cl_z[I];
+    if (ii.y == 0) {
         if (tid == 0) epart[I] = 0.0;
         return;
     }
     const Poly<DEG, EXACT> P(a);
-    const int2 ii = cl_info[I];
-    const int C = cl_col[I];                  // cx | cy << 16
-    const uint2 zI = cl_z[I];
     const int cx = C & 0xffff, cy = C >> 16;
     const bool fullx = 2 * a.R[0] + 1 >= ncx, fully = 2 * a.R[1] + 1 >= ncy;
     const int nxs = fullx ? ncx : 2 * a.R[0] + 1, nys = fully ? ncy : 2 * a.R[1] + 1;
@@ -406,7 +407,6 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
 template <int DEG, bool EXACT, int ALPHA>
 __global__ void __launch_bounds__(64 * kPairWaves) k_pair(PairArgs a, int nb,
                                              const uint4* __restrict__ sorted,
-                                             const int* __restrict__ clus_start,
                                              const int2* __restrict__ cl_info,
                                              const int* __restrict__ cl_col,
                                              const uint2* __restrict__ cl_z,
@@ -415,8 +415,7 @@ __global__ void __launch_bounds__(64 * kPairWaves) k_pair(PairArgs a, int nb,
                                              double* __restrict__ epart) {
     const int item = xcd_item(blockIdx.x, nb);
     if (item < nb)
-        pair_body<DEG, EXACT, ALPHA>(a, item, sorted, clus_start, cl_info, cl_col, cl_z, zbin,
-                                     fnear, epart);
+        pair_body<DEG, EXACT, ALPHA>(a, item, sorted, cl_info, cl_col, cl_z, zbin, fnear, epart);
 }
 
 // Held to 80 registers (6 wavefronts per SIMD instead of 5; the batch walk
@@ -427,12 +426,12 @@ k_pair_batch(const BatchTable* __restrict__ tab,
                                                    const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_PAIR, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        pair_body<DEG, EXACT, 1>(d.pair, item, d.sorted, d.clus_start, d.cl_info, d.cl_col, d.cl_z,
-                                 d.zbin, d.fnear, d.pair_parts);
+        pair_body<DEG, EXACT, 1>(d.pair, item, d.sorted, d.cl_info, d.cl_col, d.cl_z, d.zbin,
+                                 d.fnear, d.pair_parts);
     });
 }
 
-hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, const int* clus_start,
+hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted,
                        const int2* cl_info, const int* cl_col, const uint2* cl_z, const int* zbin,
                        float4* fnear, double* epart, hipStream_t st) {
     if (nblocks <= 0) return hipSuccess;
@@ -441,8 +440,8 @@ hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, cons
     if (a.alpha != 1 && a.alpha != 6) return hipErrorInvalidValue;
     switch (a.deg) {
 #define USERIES_PAIR_LAUNCH(D, E, A)                                                          \
-    hipLaunchKernelGGL((k_pair<D, E, A>), grid, block, 0, st, a, nblocks, sorted, clus_start, \
-                       cl_info, cl_col, cl_z, zbin, fnear, epart)
+    hipLaunchKernelGGL((k_pair<D, E, A>), grid, block, 0, st, a, nblocks, sorted, cl_info,    \
+                       cl_col, cl_z, zbin, fnear, epart)
 #define USERIES_PAIR_DEG(D)                                                                   \
     case D:                                                                                   \
         if (a.alpha == 6) {                                                                   \

@@ -90,7 +90,7 @@ private:
 struct Layout {
     size_t q, mat[3], col_count, xyz, forces, energies, up_bytes, prefix, coord, sorted, perm,
         slots, cl_info, cl_col, cl_z, fnear, qpart, pair_parts, gather_parts, qstats, col_start,
-        col_fill, clus_start, zbin, rho, tgrid, phi, total;
+        col_fill, clus_start, bpre, zbin, rho, tgrid, phi, total;
 };
 
 Layout make_layout(const HostPlan& hp, int n, int n_evals) {
@@ -128,6 +128,9 @@ Layout make_layout(const HostPlan& hp, int n, int n_evals) {
     L.col_start = take(4 * (ncm + 1));
     L.col_fill = take(4 * ncm);
     L.clus_start = take(4 * (ncm + 1));
+    // two-launch binning's per-block column prefixes (the columns of n charges)
+    const int ncol = hp.bin.nc[0] * hp.bin.nc[1];
+    L.bpre = take(bin_local_ok(n, ncol) ? 4 * ((c + 255) / 256) * (size_t)(ncol + 1) : 0);
     L.zbin = take(4 * ncm * (size_t)(hp.grid[2] + 1));
     L.rho = take(4 * ng);
     L.tgrid = take(4 * ng * (size_t)hp.conv.nterms);
@@ -142,6 +145,7 @@ struct Req {
     HostPlan hp;
     Layout lay{};
     int items[BK_COUNT] = {0};
+    bool local = false;                      // two-launch binning
     size_t lds = 0, lds_z = 0, lds_g = 0;   // dynamic LDS of conv_xy, conv_z and gather
     int P = 0;                               // stencil half width
     // shared with API threads (under the server mutex)
@@ -195,7 +199,7 @@ struct useries_server_s {
     int grid[BK_COUNT] = {0};
     int lds_limit = 0;
     // by the dynamic LDS sizes and the stencil half width
-    std::map<std::tuple<size_t, size_t, size_t, int, bool>, hipGraphExec_t> graphs;
+    std::map<std::tuple<size_t, size_t, size_t, int, bool, int>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_objs;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
@@ -244,14 +248,22 @@ struct useries_server_s {
 
     // the kernels of one step, in order, on the server stream
     // P: the stencil half width shared by the step's boxes, 0 if they differ;
-    // exact: some box evaluates leading far terms as Gaussians in its near part
-    hipError_t enqueue_kernels(size_t lds, size_t lds_z, size_t lds_g, int P, bool exact) {
+    // exact: some box evaluates leading far terms as Gaussians in its near part;
+    // bins: bit 0 some box bins in two launches, bit 1 some box in four
+    hipError_t enqueue_kernels(size_t lds, size_t lds_z, size_t lds_g, int P, bool exact,
+                               int bins) {
         const bool bf = precision == USERIES_BF16X3;
         hipError_t e;
-        if ((e = launch_encode_batch(d_table, d_desc, grid[BK_ENCODE], st))) return e;
-        if ((e = launch_scan_batch(d_table, d_desc, grid[BK_SCAN], st))) return e;
-        if ((e = launch_scatter_batch(d_table, d_desc, grid[BK_SCATTER], st))) return e;
-        if ((e = launch_colsort_batch(d_table, d_desc, grid[BK_COLSORT], st))) return e;
+        if ((bins & 1) && (e = launch_bin_local_batch(d_table, d_desc, grid[BK_BINLOCAL], st)))
+            return e;
+        if (bins & 2) {
+            if ((e = launch_encode_batch(d_table, d_desc, grid[BK_ENCODE], st))) return e;
+            if ((e = launch_scan_batch(d_table, d_desc, grid[BK_SCAN], st))) return e;
+            if ((e = launch_scatter_batch(d_table, d_desc, grid[BK_SCATTER], st))) return e;
+            if ((e = launch_colsort_batch(d_table, d_desc, grid[BK_COLSORT], st))) return e;
+        }
+        if ((bins & 1) && (e = launch_colbuild_batch(d_table, d_desc, grid[BK_COLBUILD], st)))
+            return e;
         if ((e = launch_pair_batch(d_table, d_desc, popts.poly_degree, exact, grid[BK_PAIR], st))) return e;
         if ((e = launch_spread_batch(d_table, d_desc, P, grid[BK_SPREAD], st))) return e;
         if ((e = launch_conv_xy_batch(d_table, d_desc, bf, lds, grid[BK_CONV_XY], st))) return e;
@@ -261,9 +273,10 @@ struct useries_server_s {
         return launch_displace_batch(d_table, d_desc, grid[BK_DISPLACE], st);
     }
 
-    hipError_t graph_for(size_t lds, size_t lds_z, size_t lds_g, int P, bool exact,
+    hipError_t graph_for(size_t lds, size_t lds_z, size_t lds_g, int P, bool exact, int bins,
                          hipGraphExec_t* out) {
-        const std::tuple<size_t, size_t, size_t, int, bool> key(lds, lds_z, lds_g, P, exact);
+        const std::tuple<size_t, size_t, size_t, int, bool, int> key(lds, lds_z, lds_g, P, exact,
+                                                                     bins);
         auto it = graphs.find(key);
         if (it != graphs.end()) {
             *out = it->second;
@@ -271,7 +284,7 @@ struct useries_server_s {
         }
         hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e) return e;
-        const hipError_t el = enqueue_kernels(lds, lds_z, lds_g, P, exact);
+        const hipError_t el = enqueue_kernels(lds, lds_z, lds_g, P, exact, bins);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(st, &g);
         if (el) {
@@ -348,6 +361,7 @@ struct useries_server_s {
         d.col_start = (int*)(base + L.col_start);
         d.col_fill = (int*)(base + L.col_fill);
         d.clus_start = (int*)(base + L.clus_start);
+        d.bpre = R->local ? (int*)(base + L.bpre) : nullptr;
         d.zbin = (int*)(base + L.zbin);
         d.rho = (float*)(base + L.rho);
         d.tgrid = (float*)(base + L.tgrid);
@@ -414,9 +428,11 @@ struct useries_server_s {
         size_t lds = 0, lds_z = 0, lds_g = 0;
         int P = -1;
         bool exact = false;
+        int bins = 0;
         for (int i = 0; i < nb; ++i) {
             Req* R = active[i];
             exact = exact || R->hp.near_exact > 0;
+            bins |= R->local ? 1 : 2;
             T.slot[i] = R->slot;
             T.step[i] = R->step;
             for (int k = 0; k < BK_COUNT; ++k) {
@@ -436,9 +452,9 @@ struct useries_server_s {
             return e;
         if (o.use_graph) {
             hipGraphExec_t ex = nullptr;
-            if ((e = graph_for(lds, lds_z, lds_g, P, exact, &ex))) return e;
+            if ((e = graph_for(lds, lds_z, lds_g, P, exact, bins, &ex))) return e;
             if ((e = hipGraphLaunch(ex, st))) return e;
-        } else if ((e = enqueue_kernels(lds, lds_z, lds_g, P, exact))) {
+        } else if ((e = enqueue_kernels(lds, lds_z, lds_g, P, exact, bins))) {
             return e;
         }
         if ((e = hipEventRecord(ring_ev[r], st))) return e;
@@ -664,6 +680,8 @@ int useries_server_create(useries_server_t* out, size_t hbm_budget_bytes, int ma
     hipDeviceGetAttribute(&S->lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, S->device);
     cu = std::max(cu, 1);
     // persistent grids: a few resident blocks per compute unit for each kernel
+    S->grid[BK_BINLOCAL] = 4 * cu;
+    S->grid[BK_COLBUILD] = 2 * cu;
     S->grid[BK_ENCODE] = 4 * cu;
     S->grid[BK_SCAN] = max_slots;
     S->grid[BK_SCATTER] = 4 * cu;
@@ -723,10 +741,17 @@ int useries_submit(useries_server_t S, const useries_request* req, uint64_t* tic
         return set_last_error(USERIES_ENOMEM, "request workspace exceeds the server's budget");
     const int nq = (n + 255) / 256;
     const int kB = 8;   // spreading brick edge
-    R->items[BK_ENCODE] = nq;
-    R->items[BK_SCAN] = 1;
-    R->items[BK_SCATTER] = nq;
-    R->items[BK_COLSORT] = hp.bin.nc[0] * hp.bin.nc[1];
+    const int ncol = hp.bin.nc[0] * hp.bin.nc[1];
+    R->local = bin_local_ok(n, ncol);
+    if (R->local) {
+        R->items[BK_BINLOCAL] = nq;
+        R->items[BK_COLBUILD] = ncol;
+    } else {
+        R->items[BK_ENCODE] = nq;
+        R->items[BK_SCAN] = 1;
+        R->items[BK_SCATTER] = nq;
+        R->items[BK_COLSORT] = ncol;
+    }
     R->items[BK_PAIR] = hp.fin.n_pair_parts;
     R->items[BK_SPREAD] = ((hp.grid[0] + kB - 1) / kB) * ((hp.grid[1] + kB - 1) / kB) *
                           ((hp.grid[2] + kB - 1) / kB);

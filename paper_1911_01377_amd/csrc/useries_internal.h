@@ -187,8 +187,8 @@ int gather_blocks(const GridArgs& a);
 // serves every batch composition.
 constexpr int kMaxBatch = 64;
 enum BatchKernel {
-    BK_ENCODE, BK_SCAN, BK_SCATTER, BK_COLSORT, BK_PAIR, BK_SPREAD, BK_CONV_XY, BK_CONV_Z,
-    BK_GATHER, BK_FINAL, BK_DISPLACE, BK_COUNT
+    BK_BINLOCAL, BK_ENCODE, BK_SCAN, BK_SCATTER, BK_COLSORT, BK_COLBUILD, BK_PAIR, BK_SPREAD,
+    BK_CONV_XY, BK_CONV_Z, BK_GATHER, BK_FINAL, BK_DISPLACE, BK_COUNT
 };
 
 // One cell's arguments and device buffers (resident while its request runs)
@@ -215,6 +215,7 @@ struct BoxDesc {
     float4* fnear;
     double *qpart, *pair_parts, *gather_parts, *qstats;
     int *col_count, *col_start, *col_fill, *clus_start;
+    int* bpre;                 // two-launch binning's block prefixes (NULL: four launches)
     int* zbin;                 // [ncol][g_z + 1]: first charge of each grid z-plane per column
     float *rho, *tgrid, *phi;
     const float *kx, *ky, *kz;
@@ -232,6 +233,10 @@ hipError_t launch_encode_batch(const BatchTable* tab, const BoxDesc* desc, int g
 hipError_t launch_scan_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
 hipError_t launch_scatter_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
 hipError_t launch_colsort_batch(const BatchTable* tab, const BoxDesc* desc, int grid, hipStream_t st);
+hipError_t launch_bin_local_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
+                                  hipStream_t st);
+hipError_t launch_colbuild_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
+                                 hipStream_t st);
 // exact: some box of the batch evaluates leading far terms as Gaussians (ne > 0)
 hipError_t launch_pair_batch(const BatchTable* tab, const BoxDesc* desc, int deg, bool exact,
                              int grid, hipStream_t st);
@@ -264,6 +269,8 @@ struct AtomWs {
     double* pair_parts = nullptr;
     float4* fnear = nullptr;
     double* qpart = nullptr;
+    int* bpre = nullptr;       // per-block column prefixes of two-launch binning
+    int64_t bpre_cap = 0;      // ints available there (0: four-launch binning only)
 };
 
 // The evaluation sequence of useries_eval / useries_eval_parts.  ws == NULL:
@@ -293,12 +300,28 @@ hipError_t launch_scatter(const BinArgs& a, const uint4* coord, uint4* sorted, c
                           int* col_start, int* clus_start, int* col_fill, int* slots,
                           const double* qpart, int nqpart, double* qstats, hipStream_t st);
 // also clears col_count and col_fill of the ncol columns
-// cl_col holds each cluster's column as cx | cy << 16 (ncx columns along x)
+// cl_col holds each cluster's column as cx | cy << 16 (ncx columns along x);
+// cluster numbers from the last cluster to npb get a count of 0
 hipError_t launch_colsort(int ncol, int ncx, const int* col_start, const int* clus_start,
                           const int* slots, const uint4* coord, int* perm, uint4* sorted,
                           int2* cl_info, int* cl_col, uint2* cl_z, int gz, int* zbin,
-                          int* col_count, int* col_fill, hipStream_t st);
-hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted, const int* clus_start,
+                          int* col_count, int* col_fill, int npb, hipStream_t st);
+// Two-launch binning (in place of encode, scan, scatter, colsort) for n > 0
+// charges when bin_local_ok(n, ncol); bpre holds ceil(n / 256) (ncol + 1) ints.
+// coord and slots hold the records and input indices grouped by column per
+// block of 256 charges; the outputs are those of colsort, except that column
+// c's clusters are numbered from floor(lo_c / 8) + c (lo_c: its first sorted
+// charge) and every other number below npb has a count of 0.
+bool bin_local_ok(int n, int ncol);
+hipError_t launch_bin_local(const BinArgs& a, const float* xyz, const float* q, uint4* coord,
+                            int* slots, int* bpre, double* qpart, hipStream_t st);
+hipError_t launch_colbuild(int n, int ncol, int ncx, int gz, int npb, const int* bpre,
+                           const uint4* coord, const int* slots, int* perm, uint4* sorted,
+                           int2* cl_info, int* cl_col, uint2* cl_z, int* zbin,
+                           const double* qpart, double* qstats, hipStream_t st);
+// one block per cluster number below nblocks (those with a count of 0 only
+// write a zero energy part)
+hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted,
                        const int2* cl_info, const int* cl_col, const uint2* cl_z, const int* zbin,
                        float4* fnear, double* epart, hipStream_t st);
 hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* zbin,
