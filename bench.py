@@ -480,7 +480,11 @@ def main():
     gp = [(g + pad - 1) // pad * pad for g in grid]
     nprod = 3 if bf else 1
     mfma_peak = PEAK_BF16_TFLOPS if bf else PEAK_FP32_TFLOPS
+    nb256 = (n + 255) // 256
+    ncol_used = info["ncell"][0] * info["ncell"][1] if "ncell" in info else 0
     alg_bytes = {
+        "bin_local": n * (12 + 4) + n * (16 + 4) + 4 * nb256 * (ncol_used + 1),
+        "colbuild": n * (16 + 4) + n * (4 + 16) + 8 * nb256 * ncol_used,
         "encode": n * (12 + 4) + n * (16 + 4),
         "scan": 0,
         "scatter": n * (4 + 4),

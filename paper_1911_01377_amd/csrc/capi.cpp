@@ -30,10 +30,11 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(USERIES_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// the binning runs either bin_local, colbuild or encode, [scan,] scatter, colsort
+// the binning runs either bin_local, colbuild or encode, [scan,] scatter,
+// colsort; gather's launch also forms the energy total
 constexpr const char* kKernelNames[] = {"bin_local", "encode", "scan",    "scatter",
                                         "colsort",   "colbuild", "pair",  "spread",
-                                        "conv_xy",   "conv_z",   "gather", "finalize"};
+                                        "conv_xy",   "conv_z",   "gather"};
 constexpr int kNumKernels = sizeof(kKernelNames) / sizeof(kKernelNames[0]);
 
 template <class T>
@@ -78,7 +79,7 @@ struct useries_plan_s {
     int* cl_col = nullptr;
     uint2* cl_z = nullptr;
     float4* fnear = nullptr;
-    double *qpart = nullptr, *pair_parts = nullptr, *gather_parts = nullptr;
+    double *qpart = nullptr, *pair_parts = nullptr, *far_parts = nullptr;
     int* bpre = nullptr;
     int64_t bpre_cap = 0;
     // timing
@@ -178,7 +179,7 @@ struct useries_plan_s {
         hipFree(clus_start);
         hipFree(zbin);
         hipFree(qstats);
-        hipFree(gather_parts);
+        hipFree(far_parts);
         hipFree(parts_tmp);
         hipFree(rho);
         hipFree(tgrid);
@@ -287,7 +288,7 @@ int useries_plan(useries_plan_t* out, const double box[3], double r_c, double b,
         (e = dalloc(&p->clus_start, hp.ncol_max + 1)) ||
         (e = dalloc(&p->zbin, (size_t)hp.ncol_max * (hp.grid[2] + 1))) ||
         (e = dalloc(&p->qstats, 2)) ||
-        (e = dalloc(&p->gather_parts, 2 * (size_t)gather_blocks(hp.gridargs))) ||
+        (e = dalloc(&p->far_parts, (size_t)far_parts(hp.conv))) ||
         (e = dalloc(&p->parts_tmp, 5)) || (e = dalloc(&p->rho, ng)) ||
         (e = dalloc(&p->tgrid, ng * hp.conv.nterms)) || (e = dalloc(&p->phi, ng))) {
         delete p;
@@ -467,11 +468,11 @@ int plan_eval(useries_plan_t p, int64_t n, const float* xyz, const float* q, flo
     sp.w = p->wspec;
     sp.c = p->cspec;
     USERIES_STEP(8, st, launch_conv_xy(hp.conv, p->rho, kx, ky, p->tgrid, sp, st));
-    USERIES_STEP(9, st, launch_conv_z(hp.conv, p->tgrid, kz, p->phi, sp, st));
+    USERIES_STEP(9, st, launch_conv_z(hp.conv, p->tgrid, kz, p->phi, p->rho, p->far_parts, sp,
+                                      st));
     USERIES_STEP(10, st, launch_gather(hp.gridargs, W.sorted, W.perm, p->zbin, p->phi, W.fnear,
-                                      forces, p->gather_parts, st));
-    USERIES_STEP(11, st, launch_finalize(hp.fin, W.pair_parts, p->gather_parts, p->qstats, energy,
-                                        parts, st));
+                                       forces, hp.fin, W.pair_parts, p->far_parts, p->qstats,
+                                       energy, parts, st));
 #undef USERIES_STEP
     return USERIES_OK;
 }

@@ -212,6 +212,31 @@ __device__ __forceinline__ f32x4 conv_z_reduce(f32x4 acc, float* smem, bool act,
     return acc;
 }
 
+// Output of a conv_z wavefront of group 0: phi at rows tz 16 + 4 lk + r of
+// columns c0 + li (the spectral part ps added), written to the grid, and the
+// wavefront's share of the far energy, sum rho phi over those points in FP64
+// (products of FP32 values, exact in FP64), to fpart[bid tz_n + tz].
+__device__ __forceinline__ void conv_z_store(const ConvArgs& a, int bid, int tz, int li, int lk,
+                                             int c0, f32x4 acc, const float* ps,
+                                             const float* __restrict__ rho,
+                                             float* __restrict__ phi, double* __restrict__ fpart) {
+    const int g2 = a.g[2], ncol = a.g[0] * a.g[1];
+    const int col = c0 + li;
+    double e = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int zz = tz * 16 + 4 * lk + r;
+        if (zz < g2 && col < ncol) {
+            const size_t o = (size_t)zz * ncol + col;
+            const float v = ps ? acc[r] + ps[li * g2 + zz] : acc[r];
+            phi[o] = v;
+            e = fma((double)rho[o], (double)v, e);
+        }
+    }
+    e = wave_sum_d(e);
+    if (fpart && threadIdx.x % 64 == 0) fpart[bid * (a.gp[2] / 16) + tz] = e;
+}
+
 // phi[:, c] = sum_t Kz_t T_t[:, c] for the block's 16 grid columns c.  The
 // columns of a chunk of terms are staged transposed ([t][col][z']); the
 // wavefronts form G groups, in a group wavefront w owns row tile w mod n_tiles
@@ -221,6 +246,8 @@ __device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid, floa
                                                 const float* __restrict__ tgrid,
                                                 const float* __restrict__ kz,
                                                 float* __restrict__ phi,
+                                                const float* __restrict__ rho,
+                                                double* __restrict__ fpart,
                                                 const float* ps = nullptr) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int li = l & 15, lk = l >> 4;
@@ -273,12 +300,7 @@ __device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid, floa
     }
     if (G > 1) acc = conv_z_reduce(acc, smem, act, grp, G, tz, tz_n, l);
     if (!act || grp != 0) return;
-    const int col = cb + li;
-    for (int r = 0; r < 4; ++r) {
-        const int zz = tz * 16 + 4 * lk + r;
-        if (zz < g2 && col < ncol)
-            phi[(size_t)zz * ncol + col] = ps ? acc[r] + ps[li * g2 + zz] : acc[r];
-    }
+    conv_z_store(a, bid, tz, li, lk, cb, acc, ps, rho, phi, fpart);
 }
 
 // ------------------------------------------------------------------ BF16X3
@@ -409,6 +431,8 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
                                                  const float* __restrict__ tgrid,
                                                  const unsigned short* __restrict__ kz,
                                                  float* __restrict__ phi,
+                                                 const float* __restrict__ rho,
+                                                 double* __restrict__ fpart,
                                                  const float* ps = nullptr) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int li = l & 15, lk = l >> 4;
@@ -477,12 +501,7 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
     }
     if (G > 1) acc = conv_z_reduce(acc, smem, act, grp, G, tz, tz_n, l);
     if (!act || grp != 0) return;
-    const int col = c0 + li;
-    for (int r = 0; r < 4; ++r) {
-        const int zz = tz * 16 + 4 * lk + r;
-        if (zz < g2 && col < ncol)
-            phi[(size_t)zz * ncol + col] = ps ? acc[r] + ps[li * g2 + zz] : acc[r];
-    }
+    conv_z_store(a, bid, tz, li, lk, c0, acc, ps, rho, phi, fpart);
 }
 
 // ------------------------------------------------------------------ spectral wide terms
@@ -652,13 +671,15 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_z_f32(ConvArgs a, int nb,
                                                              const float* __restrict__ tgrid,
                                                              const float* __restrict__ kz,
                                                              float* __restrict__ phi,
+                                                             const float* __restrict__ rho,
+                                                             double* __restrict__ fpart,
                                                              const float* __restrict__ g,
                                                              SpecPtrs sp, int spec_off) {
     extern __shared__ float dyn_lds[];
     const int item = xcd_item(blockIdx.x, nb);
     if (item >= nb) return;
     const float* ps = a.spec ? spec_z_part(a, item, dyn_lds + spec_off, g, sp) : nullptr;
-    conv_z_f32_body(a, item, dyn_lds, tgrid, kz, phi, ps);
+    conv_z_f32_body(a, item, dyn_lds, tgrid, kz, phi, rho, fpart, ps);
 }
 
 __global__ void __launch_bounds__(kConvThreads) k_conv_xy_bf16(ConvArgs a, const float* __restrict__ rho,
@@ -677,13 +698,15 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_z_bf16(ConvArgs a, int nb
                                                               const float* __restrict__ tgrid,
                                                               const unsigned short* __restrict__ kz,
                                                               float* __restrict__ phi,
+                                                              const float* __restrict__ rho,
+                                                              double* __restrict__ fpart,
                                                               const float* __restrict__ g,
                                                               SpecPtrs sp, int spec_off) {
     extern __shared__ float dyn_lds[];
     const int item = xcd_item(blockIdx.x, nb);
     if (item >= nb) return;
     const float* ps = a.spec ? spec_z_part(a, item, dyn_lds + spec_off, g, sp) : nullptr;
-    conv_z_bf16_body(a, item, dyn_lds, tgrid, kz, phi, ps);
+    conv_z_bf16_body(a, item, dyn_lds, tgrid, kz, phi, rho, fpart, ps);
 }
 
 // batched: item = t * g_z + z (conv_xy), 16-column group (conv_z)
@@ -712,9 +735,10 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_z_batch(const BatchTable*
         const BoxDesc& d = desc[tab->slot[i]];
         if constexpr (BF16 != 0)
             conv_z_bf16_body(d.conv, item, dyn_lds, d.tgrid,
-                             reinterpret_cast<const unsigned short*>(d.kz), d.phi);
+                             reinterpret_cast<const unsigned short*>(d.kz), d.phi, d.rho,
+                             d.far_parts);
         else
-            conv_z_f32_body(d.conv, item, dyn_lds, d.tgrid, d.kz, d.phi);
+            conv_z_f32_body(d.conv, item, dyn_lds, d.tgrid, d.kz, d.phi, d.rho, d.far_parts);
     });
 }
 
@@ -749,6 +773,8 @@ size_t conv_z_lds_bytes(const ConvArgs& a) {
 
 int conv_z_blocks(const ConvArgs& a) { return (a.g[0] * a.g[1] + 15) / 16; }
 
+int far_parts(const ConvArgs& a) { return conv_z_blocks(a) * (a.gp[2] / 16); }
+
 hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx, const float* ky,
                           float* tgrid, const SpecPtrs& sp, hipStream_t st) {
     const size_t lds = conv_xy_lds_bytes(a);
@@ -764,7 +790,7 @@ hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx, 
 }
 
 hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz, float* phi,
-                         const SpecPtrs& sp, hipStream_t st) {
+                         const float* rho, double* fpart, const SpecPtrs& sp, hipStream_t st) {
     const int nb = conv_z_blocks(a);
     // the spectral core G goes to the plane-projection buffer's tail
     float* g = a.spec ? sp.c + (size_t)a.g[2] * a.rk[1] * a.rk[0] : nullptr;
@@ -777,10 +803,11 @@ hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz,
     if (a.bf16x3)
         hipLaunchKernelGGL(k_conv_z_bf16, dim3(xcd_blocks(nb)), dim3(kConvThreads),
                            conv_z_lds_bytes(a), st, a, nb, tgrid,
-                           reinterpret_cast<const unsigned short*>(kz), phi, g, sp, off);
+                           reinterpret_cast<const unsigned short*>(kz), phi, rho, fpart, g, sp,
+                           off);
     else
         hipLaunchKernelGGL(k_conv_z_f32, dim3(xcd_blocks(nb)), dim3(kConvThreads),
-                           conv_z_lds_bytes(a), st, a, nb, tgrid, kz, phi, g, sp, off);
+                           conv_z_lds_bytes(a), st, a, nb, tgrid, kz, phi, rho, fpart, g, sp, off);
     return hipGetLastError();
 }
 

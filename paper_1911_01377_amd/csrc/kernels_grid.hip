@@ -17,11 +17,12 @@
 //   a fixed order.  No atomics.
 // gather: one block per brick with the potential on the brick and its halo in
 //   LDS; each charge is evaluated by the block whose brick holds its stencil
-//   anchor, 16 lanes per charge.
+//   anchor, 16 lanes per charge.  One more block forms the energy total.
 #include <algorithm>
 
 #include "useries_internal.h"
 #include "device_common.h"
+#include "energy_total.h"
 
 namespace useries {
 
@@ -278,7 +279,7 @@ __host__ __device__ inline int gather_brick(int P) { return P <= 5 ? 8 : 4; }
 // Dynamic LDS of a gather block for stencil half width P (byte offsets): the
 // halo of edge brick + 2P - 1 and the per-owner weights are sized by P.
 struct GatherLds {
-    int own, ownf, ownp, sphi, sw, rowtab, pbeg, poff, wtot, se, total;
+    int own, ownf, ownp, sphi, sw, rowtab, pbeg, poff, wtot, total;
 };
 __host__ __device__ inline GatherLds gather_lds(int P) {
     const int E = gather_brick(P) + 2 * P - 1;
@@ -298,7 +299,6 @@ __host__ __device__ inline GatherLds gather_lds(int P) {
     L.pbeg = take(4 * kGatherMaxPieces);
     L.poff = take(4 * (kGatherMaxPieces + 1));
     L.wtot = take(4 * kGatherWaves);
-    L.se = take(16 * kGatherWaves);
     L.total = o;
     return L;
 }
@@ -312,9 +312,7 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                                             const int* __restrict__ zbin,
                                             const float* __restrict__ phi,
                                             const float4* __restrict__ fnear,
-                                            float* __restrict__ forces,
-                                            double* __restrict__ epart,
-                                            double* __restrict__ phisum, char* lds) {
+                                            float* __restrict__ forces, char* lds) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, l16 = lane & 15;
     const int P = PT > 0 ? PT : a.P, P2 = 2 * P, GB = gather_brick(P);
@@ -329,7 +327,6 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
     int* pbeg = reinterpret_cast<int*>(lds + LL.pbeg);
     int* poff = reinterpret_cast<int*>(lds + LL.poff);
     int* wtot = reinterpret_cast<int*>(lds + LL.wtot);
-    double* se = reinterpret_cast<double*>(lds + LL.se);
     const int nbx = (a.g[0] + GB - 1) / GB, nby = (a.g[1] + GB - 1) / GB;
     const int X0 = (bid % nbx) * GB, Y0 = ((bid / nbx) % nby) * GB, Z0 = (bid / (nbx * nby)) * GB;
     const int B0 = min(GB, a.g[0] - X0), B1 = min(GB, a.g[1] - Y0), B2 = min(GB, a.g[2] - Z0);
@@ -337,16 +334,9 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
     // potential on the brick and halo: local (hx, hy, hz) = global (X0 - P + 1 + hx, ...)
     const float inv0 = 1.0f / (float)E0, inv1 = 1.0f / (float)E1;
     const int nh = E0 * E1 * E2;
-    // sum of the potential over the brick's own points (each grid point lies
-    // in exactly one brick): its total over the blocks is the grid's k = 0
-    // component, which the far energy must not contain.  A thread adds at
-    // most a handful of points in FP32; the sums over threads and blocks are
-    // FP64.
-    float phs = 0.0f;
     // the loads of a pass are issued together, then stored
     for (int base = tid; base < nh; base += kGatherThreads * kGatherBatch) {
         float v[kGatherBatch];
-        bool inb[kGatherBatch];
 #pragma unroll
         for (int u = 0; u < kGatherBatch; ++u) {
             const int idx = base + kGatherThreads * u;
@@ -356,14 +346,11 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
             const int gy = wrap1(Y0 - P + 1 + hy, a.g[1]);
             const int gz = wrap1(Z0 - P + 1 + hz, a.g[2]);
             v[u] = idx < nh ? phi[((size_t)gz * a.g[1] + gy) * a.g[0] + gx] : 0.0f;
-            inb[u] = idx < nh && (unsigned)(hx - (P - 1)) < (unsigned)B0 &&
-                     (unsigned)(hy - (P - 1)) < (unsigned)B1 && (unsigned)(hz - (P - 1)) < (unsigned)B2;
         }
 #pragma unroll
         for (int u = 0; u < kGatherBatch; ++u) {
             const int idx = base + kGatherThreads * u;
             if (idx < nh) sphi[idx] = v[u];
-            if (inb[u]) phs += v[u];
         }
     }
     // stencil rows (ky, kz) of a charge and their offsets in the halo, once per block
@@ -395,7 +382,6 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
         __syncthreads();
     }
     const int total = poff[np];
-    double e_wave = 0.0;
     for (int base = 0; base < total; base += kGatherThreads) {
         const int t = base + tid;
         bool mine = false;
@@ -458,7 +444,7 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                 }
             }
             wave_sync();
-            float pe = 0.0f, px = 0.0f, py = 0.0f, pz = 0.0f;
+            float px = 0.0f, py = 0.0f, pz = 0.0f;
             if (valid) {
                 const float* W = swb + (wave * 4 + g) * 6 * P2;   // [6][2P]
                 // stencil point k of the charge is halo point (gi - brick origin) + k
@@ -478,14 +464,11 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                         }
                     }
                     const float wy = W[P2 + ky], wz = W[2 * P2 + kz];
-                    const float wyz = wy * wz;
-                    pe = fmaf(wyz, sx, pe);
-                    px = fmaf(wyz, dsx, px);
+                    px = fmaf(wy * wz, dsx, px);
                     py = fmaf(W[4 * P2 + ky] * wz, sx, py);
                     pz = fmaf(wy * W[5 * P2 + kz], sx, pz);
                 }
             }
-            pe = row_sum16(pe);
             px = row_sum16(px);
             py = row_sum16(py);
             pz = row_sum16(pz);
@@ -496,30 +479,14 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                 forces[3 * oi + 1] = fn.y - qi * py;
                 forces[3 * oi + 2] = fn.z - qi * pz;
             }
-            // the four charges' energies, in a fixed order
-            const double ei = (valid && l16 == 0) ? 0.5 * (double)qi * (double)pe : 0.0;
-            e_wave += (read_lane(ei, 0) + read_lane(ei, 16)) + (read_lane(ei, 32) + read_lane(ei, 48));
             wave_sync();
         }
         __syncthreads();
     }
-    const double phw = wave_sum_d((double)phs);
-    if (lane == 0) {
-        se[2 * wave] = e_wave;
-        se[2 * wave + 1] = phw;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double es = 0.0, ps = 0.0;
-        for (int w = 0; w < kGatherWaves; ++w) {
-            es += se[2 * w];
-            ps += se[2 * w + 1];
-        }
-        epart[bid] = es;
-        phisum[bid] = ps;
-    }
 }
 
+// Block xcd_blocks(nb) (one past the bricks' blocks) forms the energy total:
+// it reads only what earlier launches wrote, so it runs beside the bricks.
 template <int PT>
 __global__ void __launch_bounds__(kGatherThreads) k_gather(GridArgs a, int nb,
                                                 const uint4* __restrict__ sorted,
@@ -527,12 +494,20 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather(GridArgs a, int nb,
                                                 const int* __restrict__ zbin,
                                                 const float* __restrict__ phi,
                                                 const float4* __restrict__ fnear,
-                                                float* __restrict__ forces,
-                                                double* __restrict__ epart) {
+                                                float* __restrict__ forces, FinalArgs fa,
+                                                const double* __restrict__ pair_parts,
+                                                const double* __restrict__ far_parts,
+                                                const double* __restrict__ qstats,
+                                                double* __restrict__ energy,
+                                                double* __restrict__ parts) {
     extern __shared__ char dyn[];
+    if ((int)blockIdx.x == xcd_blocks(nb)) {
+        energy_total<kGatherThreads>(fa, pair_parts, far_parts, qstats, energy, parts,
+                                     reinterpret_cast<double*>(dyn));
+        return;
+    }
     const int item = xcd_item(blockIdx.x, nb);
-    if (item < nb)
-        gather_body<PT>(a, item, sorted, perm, zbin, phi, fnear, forces, epart, epart + nb, dyn);
+    if (item < nb) gather_body<PT>(a, item, sorted, perm, zbin, phi, fnear, forces, dyn);
 }
 
 // PT > 0 only when every box of the batch has stencil half width PT
@@ -542,8 +517,13 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather_batch(const BatchTabl
     extern __shared__ char dyn[];
     batch_for(tab, BK_GATHER, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        gather_body<PT>(d.grid, item, d.sorted, d.perm, d.zbin, d.phi, d.fnear, d.forces,
-                        d.gather_parts, d.gather_parts + d.ngb, dyn);
+        if (item == d.ngb)   // the box's energy total, after its bricks
+            energy_total<kGatherThreads>(d.fin, d.pair_parts, d.far_parts, d.qstats,
+                                         d.energies + tab->step[i], nullptr,
+                                         reinterpret_cast<double*>(dyn));
+        else
+            gather_body<PT>(d.grid, item, d.sorted, d.perm, d.zbin, d.phi, d.fnear, d.forces,
+                            dyn);
     });
 }
 
@@ -567,21 +547,23 @@ int gather_blocks(const GridArgs& a) {
 }
 
 hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm, const int* zbin,
-                         const float* phi, const float4* fnear, float* forces, double* epart,
-                         hipStream_t st) {
+                         const float* phi, const float4* fnear, float* forces,
+                         const FinalArgs& fa, const double* pair_parts, const double* far_parts,
+                         const double* qstats, double* energy, double* parts, hipStream_t st) {
     const int nb = gather_blocks(a);
-    const dim3 grid(xcd_blocks(nb)), block(kGatherThreads);
+    const dim3 grid(xcd_blocks(nb) + 1), block(kGatherThreads);
     const size_t lds = gather_lds(a.P).total;
     // the default stencils of the two forms (P = 3, 5) have their own code
+#define USERIES_GATHER_LAUNCH(PT)                                                            \
+    hipLaunchKernelGGL(k_gather<PT>, grid, block, lds, st, a, nb, sorted, perm, zbin, phi,   \
+                       fnear, forces, fa, pair_parts, far_parts, qstats, energy, parts)
     if (a.P == 3)
-        hipLaunchKernelGGL(k_gather<3>, grid, block, lds, st, a, nb, sorted, perm, zbin, phi, fnear,
-                           forces, epart);
+        USERIES_GATHER_LAUNCH(3);
     else if (a.P == 5)
-        hipLaunchKernelGGL(k_gather<5>, grid, block, lds, st, a, nb, sorted, perm, zbin, phi, fnear,
-                           forces, epart);
+        USERIES_GATHER_LAUNCH(5);
     else
-        hipLaunchKernelGGL(k_gather<0>, grid, block, lds, st, a, nb, sorted, perm, zbin, phi, fnear,
-                           forces, epart);
+        USERIES_GATHER_LAUNCH(0);
+#undef USERIES_GATHER_LAUNCH
     return hipGetLastError();
 }
 

@@ -350,7 +350,6 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     // grid removes, are added back for the net "charge" Q = sum c_i
     p.fin.near_int_over_v = alpha == 1 ? s.near_integral(r_c) / V : 0.0;
     p.fin.k0_far = alpha == 1 ? 0.0 : s.kzero_sum(V);
-    p.fin.inv_ngrid = ga.inv_ngrid;
     return USERIES_OK;
 }
 
@@ -367,7 +366,7 @@ void choose_columns(HostPlan* hp, int n) {
     p.bin.n = p.pair.n = p.gridargs.n = n;
     const int ncol = p.bin.nc[0] * p.bin.nc[1];
     p.fin.n_pair_parts = pair_blocks(n, ncol);
-    p.fin.n_gather_parts = gather_blocks(p.gridargs);
+    p.fin.n_far_parts = far_parts(p.conv);
 }
 
 }  // namespace useries

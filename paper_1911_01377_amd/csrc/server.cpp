@@ -89,7 +89,7 @@ private:
 // forces, energies: one copy); the slot's pinned staging mirrors that prefix.
 struct Layout {
     size_t q, mat[3], col_count, xyz, forces, energies, up_bytes, prefix, coord, sorted, perm,
-        slots, cl_info, cl_col, cl_z, fnear, qpart, pair_parts, gather_parts, qstats, col_start,
+        slots, cl_info, cl_col, cl_z, fnear, qpart, pair_parts, far_parts, qstats, col_start,
         col_fill, clus_start, bpre, zbin, rho, tgrid, phi, total;
 };
 
@@ -123,7 +123,7 @@ Layout make_layout(const HostPlan& hp, int n, int n_evals) {
     L.fnear = take(16 * c);
     L.qpart = take(16 * ((c + 255) / 256));
     L.pair_parts = take(8 * clmax);
-    L.gather_parts = take(16 * (size_t)gather_blocks(hp.gridargs));   // energies, phi sums
+    L.far_parts = take(8 * (size_t)far_parts(hp.conv));
     L.qstats = take(16);
     L.col_start = take(4 * (ncm + 1));
     L.col_fill = take(4 * ncm);
@@ -269,7 +269,6 @@ struct useries_server_s {
         if ((e = launch_conv_xy_batch(d_table, d_desc, bf, lds, grid[BK_CONV_XY], st))) return e;
         if ((e = launch_conv_z_batch(d_table, d_desc, bf, lds_z, grid[BK_CONV_Z], st))) return e;
         if ((e = launch_gather_batch(d_table, d_desc, P, lds_g, grid[BK_GATHER], st))) return e;
-        if ((e = launch_finalize_batch(d_table, d_desc, grid[BK_FINAL], st))) return e;
         return launch_displace_batch(d_table, d_desc, grid[BK_DISPLACE], st);
     }
 
@@ -336,7 +335,7 @@ struct useries_server_s {
         d.ncol = hp.bin.nc[0] * hp.bin.nc[1];
         d.nq = (n + 255) / 256;
         d.npb = hp.fin.n_pair_parts;
-        d.ngb = hp.fin.n_gather_parts;
+        d.ngb = gather_blocks(hp.gridargs);
         d.n_evals = R->r.n_evals;
         d.disp_sigma = (float)R->r.disp_sigma;
         d.key[0] = (uint32_t)R->r.seed;
@@ -355,7 +354,7 @@ struct useries_server_s {
         d.fnear = (float4*)(base + L.fnear);
         d.qpart = (double*)(base + L.qpart);
         d.pair_parts = (double*)(base + L.pair_parts);
-        d.gather_parts = (double*)(base + L.gather_parts);
+        d.far_parts = (double*)(base + L.far_parts);
         d.qstats = (double*)(base + L.qstats);
         d.col_count = (int*)(base + L.col_count);
         d.col_start = (int*)(base + L.col_start);
@@ -691,7 +690,6 @@ int useries_server_create(useries_server_t* out, size_t hbm_budget_bytes, int ma
     S->grid[BK_CONV_XY] = 2 * cu;
     S->grid[BK_CONV_Z] = 4 * cu;
     S->grid[BK_GATHER] = 4 * cu;
-    S->grid[BK_FINAL] = max_slots;
     S->grid[BK_DISPLACE] = 2 * cu;
     S->ring_stride = align_up(sizeof(BatchTable)) + align_up(sizeof(BoxDesc) * max_slots);
     S->h_desc = new BoxDesc[max_slots]();
@@ -757,8 +755,7 @@ int useries_submit(useries_server_t S, const useries_request* req, uint64_t* tic
                           ((hp.grid[2] + kB - 1) / kB);
     R->items[BK_CONV_XY] = hp.grid[2] * hp.conv.nterms;
     R->items[BK_CONV_Z] = conv_z_blocks(hp.conv);
-    R->items[BK_GATHER] = hp.fin.n_gather_parts;
-    R->items[BK_FINAL] = 1;
+    R->items[BK_GATHER] = gather_blocks(hp.gridargs) + 1;   // the bricks, then the energy total
     R->items[BK_DISPLACE] = nq;
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->broken) return set_last_error(USERIES_EHIP, S->broken_msg);

@@ -120,10 +120,9 @@ struct ConvArgs {
 
 struct FinalArgs {
     int n_pair_parts;
-    int n_gather_parts;   // gather blocks: 2 n_gather_parts partials (energies, then grid sums of phi)
+    int n_far_parts;      // far-energy partials: one per z tile of each conv_z column block
     double f_inf0;        // self-term coefficient
     double near_int_over_v;   // int N d^3r / V (Coulomb background)
-    double inv_ngrid;     // 1 / (gx gy gz): grid mean of phi from its sum
     double k0_far;        // alpha > 3: sum of the far terms' k = 0 means (the grid drops them)
 };
 
@@ -172,6 +171,8 @@ size_t conv_xy_lds_bytes(const ConvArgs& a);
 size_t conv_z_lds_bytes(const ConvArgs& a);
 // blocks of the conv_z kernel (grid columns per block depend on the form and n_z)
 int conv_z_blocks(const ConvArgs& a);
+// far-energy partials written by conv_z (one per 16-row z tile of each block)
+int far_parts(const ConvArgs& a);
 
 // Blocks of the pair kernel for n charges (an upper bound of the clusters)
 // and of the gather kernel (its bricks)
@@ -188,7 +189,7 @@ int gather_blocks(const GridArgs& a);
 constexpr int kMaxBatch = 64;
 enum BatchKernel {
     BK_BINLOCAL, BK_ENCODE, BK_SCAN, BK_SCATTER, BK_COLSORT, BK_COLBUILD, BK_PAIR, BK_SPREAD,
-    BK_CONV_XY, BK_CONV_Z, BK_GATHER, BK_FINAL, BK_DISPLACE, BK_COUNT
+    BK_CONV_XY, BK_CONV_Z, BK_GATHER, BK_DISPLACE, BK_COUNT
 };
 
 // One cell's arguments and device buffers (resident while its request runs)
@@ -198,7 +199,7 @@ struct BoxDesc {
     GridArgs grid;
     ConvArgs conv;
     FinalArgs fin;
-    int ncol, nq, npb, ngb;
+    int ncol, nq, npb, ngb;   // columns, blocks of 256 charges, pair blocks, gather bricks
     int n_evals;
     float disp_sigma;          // displacement per coordinate between evaluations (A)
     uint32_t key[2];           // Philox key of the request
@@ -213,7 +214,7 @@ struct BoxDesc {
     int2* cl_info;
     uint2* cl_z;
     float4* fnear;
-    double *qpart, *pair_parts, *gather_parts, *qstats;
+    double *qpart, *pair_parts, *far_parts, *qstats;
     int *col_count, *col_start, *col_fill, *clus_start;
     int* bpre;                 // two-launch binning's block prefixes (NULL: four launches)
     int* zbin;                 // [ncol][g_z + 1]: first charge of each grid z-plane per column
@@ -248,13 +249,12 @@ hipError_t launch_conv_xy_batch(const BatchTable* tab, const BoxDesc* desc, int 
                                 size_t lds, int grid, hipStream_t st);
 hipError_t launch_conv_z_batch(const BatchTable* tab, const BoxDesc* desc, int bf16x3, size_t lds,
                                int grid, hipStream_t st);
-// lds >= gather_lds_bytes(P) of every box in the batch
+// lds >= gather_lds_bytes(P) of every box in the batch; a box's items are
+// its bricks and then one that writes its energy total to energies[step]
 hipError_t launch_gather_batch(const BatchTable* tab, const BoxDesc* desc, int P, size_t lds,
                                int grid, hipStream_t st);
 // dynamic LDS of one gather block for stencil half width P
 size_t gather_lds_bytes(int P);
-hipError_t launch_finalize_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
-                                 hipStream_t st);
 hipError_t launch_displace_batch(const BatchTable* tab, const BoxDesc* desc, int grid,
                                  hipStream_t st);
 
@@ -336,15 +336,15 @@ struct SpecPtrs {
 // per plane); conv_z adds the spectral terms' potential to its columns
 hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx,
                           const float* ky, float* tgrid, const SpecPtrs& sp, hipStream_t st);
+// fpart: far_parts(a) doubles, the sums of rho phi over each z tile's grid
+// points (FP64), for the far energy 1/2 sum_g rho_g phi_g
 hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz, float* phi,
-                         const SpecPtrs& sp, hipStream_t st);
-// epart: 2 gather_blocks(a) doubles, the blocks' far energies then their
-// sums of phi over their own grid points
+                         const float* rho, double* fpart, const SpecPtrs& sp, hipStream_t st);
+// forces in input order; one more block than the bricks forms the energy
+// total from the pair and far partials and the charge sums (energy, parts)
 hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm, const int* zbin,
-                         const float* phi, const float4* fnear, float* forces, double* epart,
-                         hipStream_t st);
-hipError_t launch_finalize(const FinalArgs& a, const double* pair_parts,
-                           const double* gather_parts, const double* qstats, double* energy,
-                           double* parts, hipStream_t st);
+                         const float* phi, const float4* fnear, float* forces,
+                         const FinalArgs& fa, const double* pair_parts, const double* far_parts,
+                         const double* qstats, double* energy, double* parts, hipStream_t st);
 
 }  // namespace useries
