@@ -30,8 +30,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kStageBatch = 16;   // global loads issued together per thread when staging
-constexpr int kStageBatchZ = 8;   // the same for BF16 conv_z (its Kz fragment is live meanwhile)
 
 __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -59,6 +57,33 @@ __device__ __forceinline__ f32x4 mfma3(u16x8 ah, u16x8 al, u16x8 bh, u16x8 bl, f
     c = mfma32(al, bh, c);
     c = mfma32(ah, bl, c);
     return mfma32(ah, bh, c);
+}
+
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+
+// Staging works on runs of 8 consecutive values of a row (an "octet"): one
+// split and one 16-byte LDS store per run.  row[x0 .. x0 + 7], 0 at and past
+// n (two 16-byte loads when the run is inside the row and aligned).
+__device__ __forceinline__ void load8(const float* __restrict__ row, int x0, int n, float v[8]) {
+    if (x0 + 8 <= n && (reinterpret_cast<uintptr_t>(row + x0) & 15) == 0) {
+        const float4 a = *reinterpret_cast<const float4*>(row + x0);
+        const float4 b = *reinterpret_cast<const float4*>(row + x0 + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = x0 + u < n ? row[x0 + u] : 0.0f;
+    }
+}
+
+__device__ __forceinline__ void split8(const float v[8], u16x8* hi, u16x8* lo) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        unsigned short h, l;
+        split(v[u], &h, &l);
+        (*hi)[u] = h;
+        (*lo)[u] = l;
+    }
 }
 
 }  // namespace
@@ -130,21 +155,29 @@ __device__ __forceinline__ void conv_xy_f32_body(const ConvArgs& a, int z, int t
     if (act1) load_frag32(bx, kx + (size_t)p0 * p0 * t, p0, tx, li, lk);
     if (act2) load_frag32(ay, ky + (size_t)p1 * p1 * t, p1, ty, li, lk);
     const float* src = rho + (size_t)z * g1 * g0;
-    const float ip0 = 1.0f / (float)p0;
-    // the loads of a pass are issued together, then stored
-    for (int base = threadIdx.x; base < p1 * p0; base += kConvThreads * kStageBatch) {
-        float v[kStageBatch];
+    // octets of the padded plane, two per thread per pass (loads first)
+    const int no = p1 * (p0 / 8);
+    const float iq = 1.0f / (float)(p0 / 8);
+    for (int o0 = threadIdx.x; o0 < no; o0 += 2 * kConvThreads) {
+        float v[2][8];
 #pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-            const int idx = base + kConvThreads * u;
-            const int y = small_div(idx, ip0), x = idx - y * p0;
-            v[u] = (idx < p1 * p0 && y < g1 && x < g0) ? src[y * g0 + x] : 0.0f;
+        for (int u = 0; u < 2; ++u) {
+            const int o = o0 + u * kConvThreads;
+            const int y = small_div(o, iq), x0 = 8 * (o - y * (p0 / 8));
+            if (o < no && y < g1) load8(src + (size_t)y * g0, x0, g0, v[u]);
+            else
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[u][e] = 0.0f;
         }
 #pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-            const int idx = base + kConvThreads * u;
-            const int y = small_div(idx, ip0), x = idx - y * p0;
-            if (idx < p1 * p0) rp[y * ld + x] = v[u];
+        for (int u = 0; u < 2; ++u) {
+            const int o = o0 + u * kConvThreads;
+            const int y = small_div(o, iq), x0 = 8 * (o - y * (p0 / 8));
+            if (o < no) {
+                float* d = rp + y * ld + x0;
+                *reinterpret_cast<float4*>(d) = make_float4(v[u][0], v[u][1], v[u][2], v[u][3]);
+                *reinterpret_cast<float4*>(d + 4) = make_float4(v[u][4], v[u][5], v[u][6], v[u][7]);
+            }
         }
     }
     __syncthreads();
@@ -259,32 +292,30 @@ __device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid, floa
     const int tz = w % tz_n, grp = w / tz_n;
     const size_t mz = (size_t)p2 * p2;
     const int tc = conv_z_chunk(a);
-    const float ip2 = 1.0f / (float)p2;
+    const float iq8 = 1.0f / (float)(p2 / 8);
     f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int t0 = 0; t0 < a.nterms; t0 += tc) {
         const int nt = (a.nterms - t0 < tc) ? a.nterms - t0 : tc;
         Frag32 cur, nxt;
         if (act && grp < nt) load_frag32(cur, kz + mz * (t0 + grp), p2, tz, li, lk);
         if (t0 > 0) __syncthreads();     // the previous chunk's columns are consumed
-        const int nst = nt * 16 * p2;
-        for (int base = threadIdx.x; base < nst; base += kConvThreads * kStageBatchZ) {
-            float v[kStageBatchZ];
+        // octets (t, column c, z' = 8 zb .. 8 zb + 7): 8 loads down the
+        // column (each coalesced over the 16 columns), two 16-byte stores
+        const int no = nt * 16 * (p2 / 8);
+        for (int o = threadIdx.x; o < no; o += kConvThreads) {
+            const int c = o & 15, q8 = o >> 4;
+            const int t = small_div(q8, iq8), zb = q8 - t * (p2 / 8);
+            float v[8];
 #pragma unroll
-            for (int u = 0; u < kStageBatchZ; ++u) {
-                const int r = base + kConvThreads * u;
-                const int q = r >> 4, c = r & 15;          // q = t p2 + z'
-                const int t = small_div(q, ip2), zp = q - t * p2;
-                v[u] = (r < nst && zp < g2 && cb + c < ncol)
+            for (int u = 0; u < 8; ++u) {
+                const int zp = 8 * zb + u;
+                v[u] = (zp < g2 && cb + c < ncol)
                            ? tgrid[((size_t)(t0 + t) * g2 + zp) * ncol + cb + c]
                            : 0.0f;
             }
-#pragma unroll
-            for (int u = 0; u < kStageBatchZ; ++u) {
-                const int r = base + kConvThreads * u;
-                const int q = r >> 4, c = r & 15;
-                const int t = small_div(q, ip2), zp = q - t * p2;
-                if (r < nst) smem[(t * 16 + c) * ld + zp] = v[u];
-            }
+            float* d = smem + (t * 16 + c) * ld + 8 * zb;
+            *reinterpret_cast<float4*>(d) = make_float4(v[0], v[1], v[2], v[3]);
+            *reinterpret_cast<float4*>(d + 4) = make_float4(v[4], v[5], v[6], v[7]);
         }
         __syncthreads();
         if (act)
@@ -352,25 +383,29 @@ __device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int 
     if (act1) load_frag(bx, kx + 2 * mx * t, kx + 2 * mx * t + mx, p0, tx, li, lk);
     if (act2) load_frag(ay, ky + 2 * my * t, ky + 2 * my * t + my, p1, ty, li, lk);
     const float* src = rho + (size_t)z * g1 * g0;
-    const float ip0 = 1.0f / (float)p0;
-    // the loads of a pass are issued together, then split and stored
-    for (int base = threadIdx.x; base < p1 * p0; base += kConvThreads * kStageBatch) {
-        float v[kStageBatch];
+    // octets of the padded plane, two per thread per pass (loads first)
+    const int no = p1 * (p0 / 8);
+    const float iq = 1.0f / (float)(p0 / 8);
+    for (int o0 = threadIdx.x; o0 < no; o0 += 2 * kConvThreads) {
+        float v[2][8];
 #pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-            const int idx = base + kConvThreads * u;
-            const int y = small_div(idx, ip0), x = idx - y * p0;
-            v[u] = (idx < p1 * p0 && y < g1 && x < g0) ? src[y * g0 + x] : 0.0f;
+        for (int u = 0; u < 2; ++u) {
+            const int o = o0 + u * kConvThreads;
+            const int y = small_div(o, iq), x0 = 8 * (o - y * (p0 / 8));
+            if (o < no && y < g1) load8(src + (size_t)y * g0, x0, g0, v[u]);
+            else
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[u][e] = 0.0f;
         }
 #pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) {
-            const int idx = base + kConvThreads * u;
-            const int y = small_div(idx, ip0), x = idx - y * p0;
-            if (idx < p1 * p0) {
-                unsigned short h, lo;
-                split(v[u], &h, &lo);
-                ph[y * ldb + x] = h;
-                pl[y * ldb + x] = lo;
+        for (int u = 0; u < 2; ++u) {
+            const int o = o0 + u * kConvThreads;
+            const int y = small_div(o, iq), x0 = 8 * (o - y * (p0 / 8));
+            if (o < no) {
+                u16x8 h, lo;
+                split8(v[u], &h, &lo);
+                *reinterpret_cast<u16x8*>(ph + y * ldb + x0) = h;
+                *reinterpret_cast<u16x8*>(pl + y * ldb + x0) = lo;
             }
         }
     }
@@ -388,14 +423,17 @@ __device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int 
                     acc = mfma3(ah, al, bx.h[ks], bx.l[ks], acc);
                 }
             }
+            u16x4 h4, l4;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 unsigned short h, lo;
                 split(acc[r], &h, &lo);
-                const int o = (tx * 16 + li) * ldb + s * 16 + 4 * lk + r;
-                uh[o] = h;
-                ul[o] = lo;
+                h4[r] = h;
+                l4[r] = lo;
             }
+            const int o = (tx * 16 + li) * ldb + s * 16 + 4 * lk;
+            *reinterpret_cast<u16x4*>(uh + o) = h4;
+            *reinterpret_cast<u16x4*>(ul + o) = l4;
         }
     __syncthreads();
     // T = Ky U: tiles (row tile ty, column strip c); B[k][j] = U^T[x][y']
@@ -444,7 +482,7 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
     const int tz = w % tz_n, grp = w / tz_n;
     const size_t mz = (size_t)p2 * p2;
     const int tc = conv_z_chunk(a);
-    const float ip2 = 1.0f / (float)p2;
+    const float iq8 = 1.0f / (float)(p2 / 8);
     unsigned short* th = reinterpret_cast<unsigned short*>(smem);   // [t][16][ld] hi
     unsigned short* tl = th + (size_t)tc * 16 * ld;                 // lo
     f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -454,31 +492,25 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
         if (act && grp < nt)
             load_frag(cur, kz + 2 * mz * (t0 + grp), kz + 2 * mz * (t0 + grp) + mz, p2, tz, li, lk);
         if (t0 > 0) __syncthreads();     // the previous chunk's columns are consumed
-        // the loads of a pass are issued together, then split and stored
-        const int nst = nt * 16 * p2;
-        for (int base = threadIdx.x; base < nst; base += kConvThreads * kStageBatchZ) {
-            float v[kStageBatchZ];
+        // octets (t, column c, z' = 8 zb .. 8 zb + 7): 8 loads down the
+        // column (each coalesced over the 16 columns), one split, two
+        // 16-byte stores
+        const int no = nt * 16 * (p2 / 8);
+        for (int o = threadIdx.x; o < no; o += kConvThreads) {
+            const int c = o & 15, q8 = o >> 4;
+            const int t = small_div(q8, iq8), zb = q8 - t * (p2 / 8);
+            float v[8];
 #pragma unroll
-            for (int u = 0; u < kStageBatchZ; ++u) {
-                const int r = base + kConvThreads * u;
-                const int q = r >> 4, c = r & 15;          // q = t p2 + z'
-                const int t = small_div(q, ip2), zp = q - t * p2;
-                v[u] = (r < nst && zp < g2 && c0 + c < ncol)
+            for (int u = 0; u < 8; ++u) {
+                const int zp = 8 * zb + u;
+                v[u] = (zp < g2 && c0 + c < ncol)
                            ? tgrid[((size_t)(t0 + t) * g2 + zp) * ncol + c0 + c]
                            : 0.0f;
             }
-#pragma unroll
-            for (int u = 0; u < kStageBatchZ; ++u) {
-                const int r = base + kConvThreads * u;
-                const int q = r >> 4, c = r & 15;
-                const int t = small_div(q, ip2), zp = q - t * p2;
-                if (r < nst) {
-                    unsigned short h, lo;
-                    split(v[u], &h, &lo);
-                    th[(t * 16 + c) * ld + zp] = h;
-                    tl[(t * 16 + c) * ld + zp] = lo;
-                }
-            }
+            u16x8 h, lo;
+            split8(v, &h, &lo);
+            *reinterpret_cast<u16x8*>(th + (t * 16 + c) * ld + 8 * zb) = h;
+            *reinterpret_cast<u16x8*>(tl + (t * 16 + c) * ld + 8 * zb) = lo;
         }
         __syncthreads();
         if (act)
