@@ -101,6 +101,19 @@ def test_tall_box_long_columns():
     assert len(q) / (info["ncell"][0] * info["ncell"][1]) > 256
 
 
+def test_one_dense_column_global_ranking():
+    """2,000 random charges in a 3 x 3 A wire along z of a 20 x 20 x 64 A cell:
+    the 4 x 4 columns are 5 A wide, so one column holds every charge, more
+    than the 1,024 that the column sort ranks in LDS (it ranks them from
+    global memory), and the other fifteen are empty."""
+    xyz, q, _ = synth.random_box(2000, (3.0, 3.0, 64.0), seed=43)
+    xyz = (xyz + np.array([0.5, 0.5, 0.0], np.float32)).astype(np.float32)
+    box = (20.0, 20.0, 64.0)
+    _, _, _, _, info = compare("wire2000/plain", xyz, q, box, 9.0, (20, 20, 64), 1e-6, 1e-5,
+                               e_scale="parts")
+    assert tuple(info["ncell"][:2]) == (4, 4), info["ncell"]
+
+
 def test_many_columns_global_binning():
     """A flat 256 x 256 x 19 A cell of 200,000 random charges: 69 x 69
     columns, more than the 4096 whose counts the binning kernels keep in LDS,
