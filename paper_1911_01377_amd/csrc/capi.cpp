@@ -51,10 +51,12 @@ int set_last_error(int code, const std::string& msg) { return fail(code, msg); }
 }  // namespace useries
 
 // ints of the per-block column prefixes of two-launch binning for up to c
-// charges (0: that binning is not used)
+// charges (0: that binning is not used): fewer charges take no more blocks
+// and no more columns
 static int64_t bpre_ints(const useries::HostPlan& hp, int64_t c) {
     const int64_t nb = (c + 255) / 256;
-    return useries::bin_local_ok((int)c, hp.ncol_max) ? nb * (hp.ncol_max + 1) : 0;
+    const int ncol = useries::columns_per_axis(hp, (int)c, 0) * useries::columns_per_axis(hp, (int)c, 1);
+    return useries::bin_local_ok((int)c, ncol) ? nb * (ncol + 1) : 0;
 }
 
 struct useries_plan_s {

@@ -353,12 +353,16 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     return USERIES_OK;
 }
 
-void choose_columns(HostPlan* hp, int n) {
-    HostPlan& p = *hp;
+int columns_per_axis(const HostPlan& p, int n, int a) {
     const double V = p.box[0] * p.box[1] * p.box[2];
     const double w = n > 0 ? std::cbrt(8.0 * V / n) : 1e300;
+    return std::max(1, std::min(p.ncmax[a], (int)std::floor(p.box[a] / w)));
+}
+
+void choose_columns(HostPlan* hp, int n) {
+    HostPlan& p = *hp;
     for (int a = 0; a < 2; ++a) {
-        const int nc = std::max(1, std::min(p.ncmax[a], (int)std::floor(p.box[a] / w)));
+        const int nc = columns_per_axis(p, n, a);
         p.bin.nc[a] = p.pair.nc[a] = p.gridargs.nc[a] = nc;
         p.pair.cw[a] = (float)(p.box[a] / nc);
         p.pair.R[a] = (int)std::ceil(p.rc * nc / p.box[a]);

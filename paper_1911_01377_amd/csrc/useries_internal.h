@@ -165,6 +165,9 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
 // column cross-section and similar z extent, within the plan's bounds):
 // sets nc, R, cw and n in the kernel arguments.
 void choose_columns(HostPlan* hp, int n);
+// the columns along x-y axis a that choose_columns takes for n charges (never
+// fewer for more charges)
+int columns_per_axis(const HostPlan& p, int n, int a);
 
 // dynamic LDS bytes of the conv_xy and conv_z kernels for a grid shape
 size_t conv_xy_lds_bytes(const ConvArgs& a);
