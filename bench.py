@@ -496,7 +496,6 @@ def main():
         "conv_xy": 4 * G + 4 * nt * G,
         "conv_z": 4 * nt * G + 4 * G,
         "gather": 4 * G + n * (16 + 16 + 4) + n * 12,
-        "finalize": 0,
     }
     issued = {
         "conv_xy": nprod * nt * grid[2] * 2.0 * (gp[1] * gp[0] * gp[0] + gp[1] * gp[1] * gp[0]),

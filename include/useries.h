@@ -244,8 +244,11 @@ int useries_destroy(useries_plan_t plan);
 /*
  * Per-kernel timing.  When enabled, each evaluation records HIP events
  * around each kernel on the evaluation stream; useries_timing_read (after the
- * stream has been synchronised) returns, for kernel k in launch order, its
- * name, the summed duration in ms and the number of launches timed.
+ * stream has been synchronised) returns, for kernel k of the sequence
+ * (bin_local, encode, scan, scatter, colsort, colbuild, pair, spread, conv_xy,
+ * conv_z, gather: the binning runs either bin_local and colbuild or the four
+ * kernels between them), its name, the summed duration in ms and the number
+ * of launches timed (0 for kernels not run).
  * Enabling resets the sums.  Returns USERIES_ENOTFOUND when k is out of range.
  */
 int useries_timing_enable(useries_plan_t plan, int enable);

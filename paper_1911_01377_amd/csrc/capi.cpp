@@ -1,8 +1,9 @@
 // C ABI of the library: plan construction (host FP64 math + one upload),
 // device workspace, and the evaluation sequence
-//   encode -> [scan, only for very many columns] -> scatter -> colsort -> pair (near part)
-//   -> spread -> conv_xy -> conv_z -> gather (far part, + near forces)
-//   -> finalize (FP64 energy).
+//   bin_local -> colbuild (or, for very large inputs, encode -> [scan] -> scatter
+//   -> colsort) -> pair (near part) -> spread -> conv_xy -> conv_z (far part,
+//   far-energy partials) -> gather (far forces + near forces; one extra block
+//   forms the FP64 energy total).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
