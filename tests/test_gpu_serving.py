@@ -78,6 +78,37 @@ def test_single_evaluation_equals_plan(form, prec, e_tol, f_tol):
     assert np.array_equal(res["forces"], f)
 
 
+def test_step_with_both_binning_sequences():
+    """A flat 256 x 256 x 19 A cell of 200,000 random charges (69 x 69
+    columns: more than the two-launch binning takes, so it bins in four
+    launches) and a small water box (two-launch binning) admitted into the
+    same steps: the step launches both sequences, each box's kernels take
+    only their own, and each result equals the plan's evaluation bitwise."""
+    need_gpu()
+    big_xyz, big_q, big_box = synth.random_box(200000, (256.0, 256.0, 19.0), seed=31)
+    cells = [(big_xyz, big_q, big_box, 9.0, (128, 128, 20)), small_water(216, 11)]
+    log("case mixed-binning: sizes %s" % [len(c[1]) for c in cells])
+    srv = Server(1 << 30, max_slots=4, precision=USERIES_BF16X3)
+    res = run_all(srv, cells, 1, 0.0, [5, 6])
+    st = srv.stats()
+    srv.close()
+    assert st["max_batch"] == 2, st
+    dev = torch.device("cuda:0")
+    for (xyz, q, box, rc, grid), r in zip(cells, res):
+        plan = Plan(box, rc, grid, precision=USERIES_BF16X3)
+        e, f, _ = plan.eval(torch.from_numpy(xyz).to(dev), torch.from_numpy(q).to(dev))
+        torch.cuda.synchronize()
+        e, f = float(e.cpu()[0]), f.cpu().numpy()
+        ncell = N.useries_plan_info(plan.handle)["ncell"]   # the columns of this evaluation
+        plan.close()
+        log("   n=%d columns %s: E_server=%.15g E_plan=%.15g max|dF|=%.3e"
+            % (len(q), ncell, r["energies"][0], e, float(np.max(np.abs(r["forces"] - f)))))
+        assert r["energies"][0] == e
+        assert np.array_equal(r["forces"], f)
+        if len(q) == 200000:
+            assert ncell[0] * ncell[1] > 4096, ncell
+
+
 @pytest.mark.parametrize("form,prec,e_tol,f_tol", FORMS)
 def test_alone_equals_mix(form, prec, e_tol, f_tol):
     need_gpu()
