@@ -409,7 +409,10 @@ def test_series_error_matches_eqA3(alpha, b):
     j < 0 terms and the C1 weight of term 0 are below 1e-13 there, and the
     terms beyond the series length below 1e-13 of r^-alpha), so
     r^alpha F_inf(r) - 1 must follow the explicit error formula A3.  This
-    pins the amplitude ln b / phi~(alpha) and the weights b^(-alpha j)."""
+    pins the amplitude ln b / phi~(alpha) and the weights b^(-alpha j).
+    (At alpha = 12 no range of r meets both conditions: where term 0's weight
+    has died out, r^-12 is so small that the terms past the series length
+    reach 1e-10 of it; the lattice sums pin that series instead.)"""
     p = O.Params(b=b, sigma=1.0, w0=0.9, s0=1.0, rc=1.0, nterms=0, alpha=alpha)
     worst = 0.0
     for r in np.linspace(10.0, 20.0, 21):
@@ -419,20 +422,22 @@ def test_series_error_matches_eqA3(alpha, b):
     assert worst < 1e-12, worst
 
 
-@pytest.mark.parametrize("b", [2.0, 1.5, 1.15])
-def test_alpha6_c1_construction(b):
-    """The C1 construction for 1/r^6: the near part 1/r^6 - F_inf vanishes at
-    r_c with zero slope, and inside r_c near + far is exactly 1/r^6."""
-    r0, w0 = O.solve_c1a(b, 6.0)
+@pytest.mark.parametrize("alpha,b", [(6.0, 2.0), (6.0, 1.5), (6.0, 1.15), (12.0, 2.0),
+                                     (12.0, 1.5)])
+def test_alpha_c1_construction(alpha, b):
+    """The C1 construction for 1/r^alpha: the near part 1/r^alpha - F_inf
+    vanishes at r_c with zero slope, and inside r_c near + far is exactly
+    1/r^alpha."""
+    r0, w0 = O.solve_c1a(b, alpha)
     sigma = 1.3
-    p = O.Params(b=b, sigma=sigma, w0=w0, s0=1.0, rc=r0 * sigma, nterms=0, alpha=6.0)
+    p = O.Params(b=b, sigma=sigma, w0=w0, s0=1.0, rc=r0 * sigma, nterms=0, alpha=alpha)
     rc = r0 * sigma
     nk = O.near_kernel(p, rc * (1 - 1e-12))
-    scale = rc ** -6
+    scale = rc ** -alpha
     assert abs(nk[0]) < 1e-9 * scale
-    assert abs(nk[1]) < 1e-8 * scale / rc
+    assert abs(nk[1]) < 1e-8 * alpha / 6.0 * scale / rc
     for r in (0.3, 1.0, 0.9 * rc):
-        assert rel(O.near_kernel(p, r)[0] + O.far_inf(p, r)[0], r ** -6) < 1e-13
+        assert rel(O.near_kernel(p, r)[0] + O.far_inf(p, r)[0], r ** -alpha) < 1e-13
 
 
 def _lattice(kind, ncell, a):
@@ -444,28 +449,30 @@ def _lattice(kind, ncell, a):
     return np.array(pts, float)
 
 
+@pytest.mark.parametrize("alpha", [6, 12])
 @pytest.mark.parametrize("kind,ncell,a,dnn", [("sc", 3, 4.0, 4.0),
                                               ("fcc", 2, 6.0, 6.0 / math.sqrt(2))])
-def test_alpha6_lattice_sums(kind, ncell, a, dnn):
-    """1/r^6 lattice sums: identical coefficients c = 1 on a simple-cubic or
-    face-centred-cubic lattice in a periodic cell of edge 12 A have energy
-    1/2 A6 / d^6 per site (A6 the textbook lattice sum, d the nearest-neighbour
-    distance).  With b = 1.15 the BSA error is below 1e-10, so the u-series
-    (near pairs inside r_c = 5.9 A, far Gaussians with their k = 0 parts, the
-    dropped terms' k = 0 parts, minus the self term) must give it.  No
-    neutralisation: the lattice sum of 1/r^6 converges absolutely."""
+def test_alpha_lattice_sums(kind, ncell, a, dnn, alpha):
+    """1/r^alpha lattice sums (alpha = 6, 12): identical coefficients c = 1 on
+    a simple-cubic or face-centred-cubic lattice in a periodic cell of edge
+    12 A have energy 1/2 A_alpha / d^alpha per site (A_alpha the textbook
+    lattice sum, d the nearest-neighbour distance).  With b = 1.15 the BSA
+    error is below 1e-10, so the u-series (near pairs inside r_c = 5.9 A, far
+    Gaussians with their k = 0 parts, the dropped terms' k = 0 parts, minus
+    the self term) must give it.  No neutralisation: these lattice sums
+    converge absolutely."""
     xyz = _lattice(kind, ncell, a)
     L = ncell * a
-    r0, w0 = O.solve_c1a(1.15, 6.0)
+    r0, w0 = O.solve_c1a(1.15, float(alpha))
     rc = 5.9
     sigma = rc / r0
     n = 1
-    while O.trunc_bound(n, 1.15, 6.0, sigma, L) > 1e-16:
+    while O.trunc_bound(n, 1.15, float(alpha), sigma, L) > 1e-16:
         n += 1
-    p = O.Params(b=1.15, sigma=sigma, w0=w0, s0=1.0, rc=rc, nterms=n, alpha=6.0)
+    p = O.Params(b=1.15, sigma=sigma, w0=w0, s0=1.0, rc=rc, nterms=n, alpha=float(alpha))
     q = np.ones(len(xyz))
     parts, f = O.eval_full(xyz, q, (L, L, L), p)
-    want = 0.5 * float(LC["lj_lattice_sum_a6"][kind]) / dnn ** 6 * len(xyz)
+    want = (0.5 * float(LC["lj_lattice_sum_a%d" % alpha][kind]) / dnn ** alpha * len(xyz))
     assert rel(parts["total"], want) < 1e-10, (parts, want)
     assert parts["bg"] == 0.0
     assert np.max(np.abs(f)) < 1e-10 * abs(want)       # forces vanish by symmetry
