@@ -96,19 +96,22 @@ enum {
  *                    useries_plan fails with USERIES_EINVAL.
  *   max_atoms        workspace capacity in charges; <= 0 grows on demand
  *                    (a growth reallocates and synchronises the device).
- *   alpha            kernel power: 1 (Coulomb 1/r, the default) or 6 (1/r^6,
- *                    e.g. London dispersion; App. A).  With 6 the series is
- *                    the BSA of eq. A2 with a Gaussian scaling function
- *                    (a_j = ln b w_j b^(-6j) / (phi~(6) sigma^6), phi~(6) = 8),
- *                    the construction must be USERIES_C1 (solved for 1/r^6 at
- *                    any b > 1: continuity and zero slope at r_c), the
- *                    "charges" are the coefficients c_i of
- *                    E = 1/2 sum'_{i,j,images} c_i c_j / r^6 (no neutrality: the
- *                    lattice sum converges absolutely, and every far term's
- *                    k = 0 component is kept), and n_terms <= 0 takes the
- *                    smallest N with b^(-3N) exp(-2 (b^(2N) - 1) pi^2 sigma^2
- *                    / L^2) <= nterms_tol (eq. 33's form for 1/r^6).  The
- *                    Table 1 and 2 presets are Coulomb series.
+ *   alpha            kernel power: 1 (Coulomb 1/r, the default), 6 (1/r^6,
+ *                    e.g. London dispersion) or 12 (1/r^12, the repulsive
+ *                    Lennard-Jones power); App. A.  With alpha > 1 the series
+ *                    is the BSA of eq. A2 with a Gaussian scaling function
+ *                    (a_j = ln b w_j b^(-alpha j) / (phi~(alpha) sigma^alpha),
+ *                    phi~(alpha) = 2^(alpha/2 - 1) Gamma(alpha/2): 8 for 6,
+ *                    3840 for 12), the construction must be USERIES_C1
+ *                    (solved for 1/r^alpha at any b > 1: continuity and zero
+ *                    slope at r_c), the "charges" are the coefficients c_i of
+ *                    E = 1/2 sum'_{i,j,images} c_i c_j / r^alpha (no
+ *                    neutrality: the lattice sum converges absolutely, and
+ *                    every far term's k = 0 component is kept), and n_terms
+ *                    <= 0 takes the smallest N with b^((3 - alpha) N)
+ *                    exp(-2 (b^(2N) - 1) pi^2 sigma^2 / L^2) <= nterms_tol
+ *                    (eq. 33's form for 1/r^alpha).  The Table 1 and 2
+ *                    presets are Coulomb series.
  *   spectral         apply the widest far terms together in spectral form
  *                    (a low-rank form of their circulants: the real Fourier
  *                    modes each needs down to 1e-9 of its first mode, at most

@@ -3,7 +3,8 @@
 //   force   q_i q_j (1/r^3 + F'(r)/r) (r_i - r_j)  on charge i,
 // where F is the infinite far series (eq. 24), represented inside the cutoff
 // by a polynomial in x = r^2/r_c^2 fitted on the host in FP64.  For the
-// kernel 1/r^6 (App. A) the same with 1/r^6 - F(r) and 6/r^8 + F'(r)/r.
+// kernels 1/r^6 and 1/r^12 (App. A) the same with 1/r^alpha - F(r) and
+// alpha/r^(alpha + 2) + F'(r)/r.
 //
 // Layout: cluster-pair tiles.  Charges are binned into x-y columns, sorted
 // by z, and cut into clusters of up to 8 (see kernels_bin.hip).  One block of
@@ -96,6 +97,22 @@ __device__ __forceinline__ StencilCol stencil_col(int k, int ci, int R, int nc, 
 
 }  // namespace
 
+// Scale terms of the 1/r^6 and 1/r^12 kernels.  A power p of 1/r carries p
+// times the relative error of the unit scale, and an FP32 scale is off by up
+// to 2^-24: a bias of a few 1e-7 in every pair at p = 12.  These kernels take
+// the scale as an FP32 pair (hi + lo) instead: per axis for components in A,
+// and (1/u)^2 for distances in fixed-point units.
+struct PowScale {
+    float lo[3];          // scale_lo per axis (components scaled to A)
+    float is2h, is2l;     // (1/u)^2 = is2h + is2l (distances kept in units)
+};
+
+// 1/r2 to about half an ulp: the hardware reciprocal and one Newton step
+__device__ __forceinline__ float recip_nr(float r2) {
+    const float y = __builtin_amdgcn_rcpf(r2);
+    return fmaf(y, fmaf(-r2, y, 1.0f), y);
+}
+
 // nsteps steps of 8 staged j-charges (st8[s * 8 + ja]) against i-charge ci.
 // CUBIC: distances in fixed-point units (one scale for all axes), qw = q_i u,
 // rc2/irc2 in those units and is = 1/u; otherwise distances in A, qw = q_i.
@@ -103,24 +120,29 @@ template <int DEG, bool CUBIC, bool EXACT, int ALPHA>
 __device__ __forceinline__ void pair_steps(const Poly<DEG, EXACT>& P, const uint4* st8, int ja,
                                            int nsteps,
                                            uint4 ci, float qw, float sx, float sy, float sz,
-                                           float rc2, float irc2, float is, float ctop, float dtop,
+                                           float rc2, float irc2, float is, const PowScale& ps,
+                                           float ctop, float dtop,
                                            float& fx, float& fy, float& fz, float& ec) {
     for (int s = 0; s < nsteps; ++s) {
         const uint4 cj = st8[s * 8 + ja];
         float dx = (float)(int)(ci.x - cj.x), dy = (float)(int)(ci.y - cj.y),
               dz = (float)(int)(ci.z - cj.z);
         if (!CUBIC) {
-            dx *= sx;
-            dy *= sy;
-            dz *= sz;
+            if (ALPHA == 1) {
+                dx *= sx;
+                dy *= sy;
+                dz *= sz;
+            } else {
+                dx = fmaf(dx, sx, dx * ps.lo[0]);
+                dy = fmaf(dy, sy, dy * ps.lo[1]);
+                dz = fmaf(dz, sz, dz * ps.lo[2]);
+            }
         }
         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
         // a charge of 0 (padding) contributes exactly 0; r2 is then still
         // >= (L / 2^32)^2 (>= 1 in fixed-point units) or 0, never subnormal
         if (r2 < rc2 && r2 > 0.0f) {
             const float qq = qw * __uint_as_float(cj.w);
-            const float rsq = __builtin_amdgcn_rsqf(r2);
-            const float rinv = CUBIC ? rsq * is : rsq;   // 1/r in 1/A
             const float x = r2 * irc2;
             float Pp = fmaf(ctop, x, P.c[DEG - 1]);
 #pragma unroll
@@ -141,14 +163,18 @@ __device__ __forceinline__ void pair_steps(const Poly<DEG, EXACT>& P, const uint
                 }
             }
             float fs;
-            if (ALPHA == 6) {
-                const float i2 = rinv * rinv;
-                const float i6 = i2 * i2 * i2;
-                ec = fmaf(qq, ((i6 - P.c[0]) - Flo) - Fe, ec);
-                fs = qq * fmaf(6.0f * i6, i2, G);
-            } else {
+            if (ALPHA == 1) {
+                const float rsq = __builtin_amdgcn_rsqf(r2);
+                const float rinv = CUBIC ? rsq * is : rsq;   // 1/r in 1/A
                 ec = fmaf(qq, ((rinv - P.c[0]) - Flo) - Fe, ec);
                 fs = qq * fmaf(rinv * rinv, rinv, G);
+            } else {
+                float i2 = recip_nr(r2);                     // 1/r^2 in 1/A^2
+                if (CUBIC) i2 = fmaf(i2, ps.is2h, i2 * ps.is2l);
+                const float i6 = i2 * i2 * i2;
+                const float ip = ALPHA == 12 ? i6 * i6 : i6;
+                ec = fmaf(qq, ((ip - P.c[0]) - Flo) - Fe, ec);
+                fs = qq * fmaf((float)ALPHA * ip, i2, G);
             }
             fx = fmaf(fs, dx, fx);
             fy = fmaf(fs, dy, fy);
@@ -307,6 +333,16 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     const float rc2w = cubic ? a.rc2 * isx * isx : a.rc2;
     const float irc2w = cubic ? a.inv_rc2 * sx * sx : a.inv_rc2;
     const float qw = cubic ? qi * sx : qi;
+    PowScale ps = {};
+    if (ALPHA != 1) {
+        const double is2 = 1.0 / (((double)sx + (double)a.scale_lo[0]) *
+                                  ((double)sx + (double)a.scale_lo[0]));
+        ps.lo[0] = a.scale_lo[0];
+        ps.lo[1] = a.scale_lo[1];
+        ps.lo[2] = a.scale_lo[2];
+        ps.is2h = (float)is2;
+        ps.is2l = (float)(is2 - (double)ps.is2h);
+    }
     const float ctop = to_vgpr(P.c[DEG]), dtop = to_vgpr(P.d[DEG]);
 
     // bounding box of the i-cluster (fixed point, offsets from its first
@@ -374,11 +410,11 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         float ec = 0.0f;
         if (cubic)
             pair_steps<DEG, true, EXACT, ALPHA>(P, stage[w], ja, nsteps, ci, qw, sx, sx, sx, rc2w, irc2w,
-                                                isx,
+                                                isx, ps,
                                   ctop, dtop, fx, fy, fz, ec);
         else
             pair_steps<DEG, false, EXACT, ALPHA>(P, stage[w], ja, nsteps, ci, qw, sx, sy, sz, rc2w, irc2w,
-                                                 1.0f,
+                                                 1.0f, ps,
                                    ctop, dtop, fx, fy, fz, ec);
         e += (double)ec;
         wave_sync();
@@ -437,7 +473,7 @@ hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted,
     if (nblocks <= 0) return hipSuccess;
     const dim3 grid(xcd_blocks(nblocks)), block(64 * kPairWaves);
     const bool exact = a.ne > 0;
-    if (a.alpha != 1 && a.alpha != 6) return hipErrorInvalidValue;
+    if (a.alpha != 1 && a.alpha != 6 && a.alpha != 12) return hipErrorInvalidValue;
     switch (a.deg) {
 #define USERIES_PAIR_LAUNCH(D, E, A)                                                          \
     hipLaunchKernelGGL((k_pair<D, E, A>), grid, block, 0, st, a, nblocks, sorted, cl_info,    \
@@ -447,6 +483,9 @@ hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted,
         if (a.alpha == 6) {                                                                   \
             if (exact) USERIES_PAIR_LAUNCH(D, true, 6);                                       \
             else USERIES_PAIR_LAUNCH(D, false, 6);                                            \
+        } else if (a.alpha == 12) {                                                           \
+            if (exact) USERIES_PAIR_LAUNCH(D, true, 12);                                      \
+            else USERIES_PAIR_LAUNCH(D, false, 12);                                           \
         } else if (exact) {                                                                   \
             USERIES_PAIR_LAUNCH(D, true, 1);                                                  \
         } else {                                                                              \

@@ -61,7 +61,8 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
         return fail(err, USERIES_EINVAL, "need 0 < r_c < min(L)/2");
     if (n_terms > kMaxTerms) return fail(err, USERIES_EINVAL, "n_terms > 32");
     const int alpha = o.alpha > 0 ? o.alpha : 1;
-    if (alpha != 1 && alpha != 6) return fail(err, USERIES_EINVAL, "alpha must be 1 or 6");
+    if (alpha != 1 && alpha != 6 && alpha != 12)
+        return fail(err, USERIES_EINVAL, "alpha must be 1, 6 or 12");
     if (alpha != 1 && o.construction != USERIES_C1)
         return fail(err, USERIES_EINVAL, "1/r^6 supports the C1 construction only");
 
@@ -176,6 +177,7 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     for (int a = 0; a < 3; ++a) {
         p.bin.inv_box[a] = 1.0 / box[a];
         pa.scale[a] = (float)(box[a] / 4294967296.0);
+        pa.scale_lo[a] = (float)(box[a] / 4294967296.0 - (double)pa.scale[a]);
     }
     pa.zinv = (float)(4294967296.0 / box[2]);
 

@@ -75,13 +75,14 @@ struct PairArgs {
     int nc[2];            // x-y columns per axis
     int R[2];             // columns within reach of r_c per axis: ceil(r_c / cw)
     float scale[3];       // L / 2^32: fixed-point units to A
+    float scale_lo[3];    // L / 2^32 - scale: the FP32 rounding of the scale
     float cw[2];          // column widths L / nc
     float zinv;           // 2^32 / L_z: A to fixed-point units along z
     float rc2;            // r_c^2
     float inv_rc2;        // 1 / r_c^2
     int gz;               // grid points along z (planes of the z-plane index)
     int deg;              // polynomial degree
-    int alpha;            // kernel power: 1 (1/r) or 6 (1/r^6)
+    int alpha;            // kernel power: 1 (1/r), 6 (1/r^6) or 12 (1/r^12)
     int ne;               // leading far terms evaluated as Gaussians (0..kMaxExact)
     float c[kMaxPolyDeg + 1];   // F_inf(r) = sum_{j<ne} ea_j 2^(x ex_j) + sum c_k x^k, x = r^2/rc^2
     float c0lo;                 // c_0 - (float)c_0

@@ -394,6 +394,49 @@ def test_dispersion_kernel_alpha6(precision, tol):
             alpha=6, precision=precision)
 
 
+@pytest.mark.parametrize("precision,tol", FORMS)
+def test_repulsion_kernel_alpha12(precision, tol):
+    """The 1/r^12 series (App. A, C1 construction for 1/r^12 at b = 2,
+    mellin factor 3840) through the same kernels: a water box with one
+    coefficient per site kind (close intramolecular pairs dominate) and random
+    positive coefficients in a cube; against the oracle's 1/r^12 series with
+    the plan's parameters."""
+    f = _form(precision)
+    n_mol = 600
+    L = (n_mol / synth.WATER_DENSITY) ** (1 / 3)
+    xyz, _, box = synth.water_box(n_mol=n_mol, L=L, seed=68)
+    c = np.tile(np.array([1.0, 0.1, 0.1], np.float32), n_mol)
+    g = int(np.ceil(L))
+    _, _, _, _, info = compare("water600/r^-12/" + f, xyz, c, box, 9.0, (g, g, g), tol[0], tol[1],
+                               alpha=12, precision=precision)
+    assert info["n_terms"] >= 1
+    rng = np.random.default_rng(69)
+    xyz = rng.uniform(0, 22.0, (700, 3)).astype(np.float32)
+    c = rng.uniform(0.2, 1.5, 700).astype(np.float32)
+    compare("random700/r^-12/" + f, xyz, c, (22.0, 22.0, 22.0), 8.5, (24, 24, 24), tol[0], tol[1],
+            alpha=12, precision=precision)
+
+
+def test_repulsion_lattice_forces_vanish():
+    """Identical coefficients on a simple-cubic lattice (64 sites, spacing
+    2 A): the 1/r^12 forces vanish by symmetry and the energy matches the
+    oracle's."""
+    g = np.arange(8) * 2.0
+    xyz = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3).astype(np.float32)
+    c = np.ones(len(xyz), np.float32)
+    box = (16.0, 16.0, 16.0)
+    log("case sc512/r^-12")
+    gp, gf, info = gpu_eval(xyz, c, box, 7.9, (16, 16, 16), alpha=12)
+    op, of = oracle_eval(xyz, c, box, info, 7.9, alpha=12)
+    de = abs(gp[4] - op["total"]) / abs(op["total"])
+    fpair = 12.0 / 2.0 ** 13
+    log("   E_gpu=%.12g E_oracle=%.12g dE=%.2e max|F_gpu|=%.2e max|F_oracle|=%.2e (pair %.2e)"
+        % (gp[4], op["total"], de, np.max(np.abs(gf)), np.max(np.abs(of)), fpair))
+    assert de <= 1e-6
+    assert np.max(np.abs(of)) < 1e-12 * fpair
+    assert np.max(np.abs(gf)) < 1e-5 * fpair
+
+
 def test_dispersion_lattice_forces_vanish():
     """Identical coefficients on a simple-cubic lattice (64 sites, spacing
     4 A): the 1/r^6 forces vanish by symmetry and the energy matches the
