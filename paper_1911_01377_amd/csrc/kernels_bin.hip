@@ -561,9 +561,26 @@ __device__ __forceinline__ void bin_local_body(const BinArgs& a, int b, const fl
 // gathered (list position k lies in the segment b with segoff[b] <= k <
 // segoff[b + 1]), sorted by (z, input index) -- up to 256 by counting ranks,
 // up to kSortCap by a bitonic sort in LDS, beyond by ranking from global
-// memory -- and written with the column's z-plane index and clusters.  Block
-// 0 also reduces the charge sums in a fixed order.
+// memory -- and written with the column's z-plane index and clusters.
+// reduce_q: this block also reduces the charge sums (qstats_reduce).
+__device__ __forceinline__ void qstats_reduce(int nb, const double* __restrict__ qpart,
+                                              double* __restrict__ qstats) {
+    const int lane = threadIdx.x & 63;
+    double qa = 0.0, qb = 0.0;
+    for (int k = lane; k < nb; k += 64) {
+        qa += qpart[2 * k];
+        qb += qpart[2 * k + 1];
+    }
+    qa = wave_sum_d(qa);
+    qb = wave_sum_d(qb);
+    if (lane == 0) {
+        qstats[0] = qa;
+        qstats[1] = qb;
+    }
+}
+
 __device__ __forceinline__ void colbuild_body(int col, int nb, int ncol, int ncx, int gz, int npb,
+                                              bool reduce_q,
                                               const int* __restrict__ bpre,
                                               const uint4* __restrict__ coord,
                                               const int* __restrict__ slots,
@@ -619,19 +636,7 @@ __device__ __forceinline__ void colbuild_body(int col, int nb, int ncol, int ncx
         }
     }
     if (t == 0) segoff[nb] = cnt;
-    if (col == 0 && wv == 1) {
-        double qa = 0.0, qb = 0.0;
-        for (int k = lane; k < nb; k += 64) {
-            qa += qpart[2 * k];
-            qb += qpart[2 * k + 1];
-        }
-        qa = wave_sum_d(qa);
-        qb = wave_sum_d(qb);
-        if (lane == 0) {
-            qstats[0] = qa;
-            qstats[1] = qb;
-        }
-    }
+    if (reduce_q && wv == 1) qstats_reduce(nb, qpart, qstats);
 
     // cluster numbers: this column's from floor(lo / 8) + col, the next
     // column's from floor((lo + cnt) / 8) + col + 1 (the last column's run to
@@ -787,8 +792,13 @@ __global__ void __launch_bounds__(256) k_colbuild(int nb, int ncol, int ncx, int
                                                   int* __restrict__ zbin,
                                                   const double* __restrict__ qpart,
                                                   double* __restrict__ qstats) {
-    colbuild_body(blockIdx.x, nb, ncol, ncx, gz, npb, bpre, coord, slots, perm, sorted, cl_info,
-                  cl_col, cl_z, zbin, qpart, qstats);
+    // block ncol (one past the columns) reduces the charge sums, beside the columns
+    if (blockIdx.x == ncol) {
+        if (threadIdx.x < 64) qstats_reduce(nb, qpart, qstats);
+        return;
+    }
+    colbuild_body(blockIdx.x, nb, ncol, ncx, gz, npb, false, bpre, coord, slots, perm, sorted,
+                  cl_info, cl_col, cl_z, zbin, qpart, qstats);
 }
 
 __global__ void __launch_bounds__(256) k_bin_local_batch(const BatchTable* __restrict__ tab,
@@ -803,9 +813,9 @@ __global__ void __launch_bounds__(256) k_colbuild_batch(const BatchTable* __rest
                                                         const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_COLBUILD, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        colbuild_body(item, d.nq, d.ncol, d.bin.nc[0], d.grid.g[2], d.npb, d.bpre, d.coord,
-                      d.slots, d.perm, d.sorted, d.cl_info, d.cl_col, d.cl_z, d.zbin, d.qpart,
-                      d.qstats);
+        colbuild_body(item, d.nq, d.ncol, d.bin.nc[0], d.grid.g[2], d.npb, item == 0, d.bpre,
+                      d.coord, d.slots, d.perm, d.sorted, d.cl_info, d.cl_col, d.cl_z, d.zbin,
+                      d.qpart, d.qstats);
     });
 }
 
@@ -835,7 +845,7 @@ hipError_t launch_colbuild(int n, int ncol, int ncx, int gz, int npb, const int*
                            int2* cl_info, int* cl_col, uint2* cl_z, int* zbin,
                            const double* qpart, double* qstats, hipStream_t st) {
     const int nb = (n + 255) / 256;
-    hipLaunchKernelGGL(k_colbuild, dim3(ncol), dim3(256), 0, st, nb, ncol, ncx, gz, npb, bpre,
+    hipLaunchKernelGGL(k_colbuild, dim3(ncol + 1), dim3(256), 0, st, nb, ncol, ncx, gz, npb, bpre,
                        coord, slots, perm, sorted, cl_info, cl_col, cl_z, zbin, qpart, qstats);
     return hipGetLastError();
 }

@@ -249,9 +249,23 @@ __device__ __forceinline__ f32x4 conv_z_reduce(f32x4 acc, float* smem, bool act,
 // columns c0 + li (the spectral part ps added), written to the grid, and the
 // wavefront's share of the far energy, sum rho phi over those points in FP64
 // (products of FP32 values, exact in FP64), to fpart[bid tz_n + tz].
+// rho at the points a wavefront of group 0 writes, loaded when the block
+// starts (off the end of the block's dependency chain)
+__device__ __forceinline__ f32x4 conv_z_rho(const ConvArgs& a, int tz, int li, int lk, int c0,
+                                            const float* __restrict__ rho) {
+    const int g2 = a.g[2], ncol = a.g[0] * a.g[1];
+    const int col = c0 + li;
+    f32x4 v = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int zz = tz * 16 + 4 * lk + r;
+        if (zz < g2 && col < ncol) v[r] = rho[(size_t)zz * ncol + col];
+    }
+    return v;
+}
+
 __device__ __forceinline__ void conv_z_store(const ConvArgs& a, int bid, int tz, int li, int lk,
-                                             int c0, f32x4 acc, const float* ps,
-                                             const float* __restrict__ rho,
+                                             int c0, f32x4 acc, const float* ps, f32x4 rv,
                                              float* __restrict__ phi, double* __restrict__ fpart) {
     const int g2 = a.g[2], ncol = a.g[0] * a.g[1];
     const int col = c0 + li;
@@ -263,7 +277,7 @@ __device__ __forceinline__ void conv_z_store(const ConvArgs& a, int bid, int tz,
             const size_t o = (size_t)zz * ncol + col;
             const float v = ps ? acc[r] + ps[li * g2 + zz] : acc[r];
             phi[o] = v;
-            e = fma((double)rho[o], (double)v, e);
+            e = fma((double)rv[r], (double)v, e);
         }
     }
     e = wave_sum_d(e);
@@ -293,6 +307,8 @@ __device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid, floa
     const size_t mz = (size_t)p2 * p2;
     const int tc = conv_z_chunk(a);
     const float iq8 = 1.0f / (float)(p2 / 8);
+    const f32x4 rv = (act && grp == 0) ? conv_z_rho(a, tz, li, lk, cb, rho)
+                                       : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int t0 = 0; t0 < a.nterms; t0 += tc) {
         const int nt = (a.nterms - t0 < tc) ? a.nterms - t0 : tc;
@@ -331,7 +347,7 @@ __device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid, floa
     }
     if (G > 1) acc = conv_z_reduce(acc, smem, act, grp, G, tz, tz_n, l);
     if (!act || grp != 0) return;
-    conv_z_store(a, bid, tz, li, lk, cb, acc, ps, rho, phi, fpart);
+    conv_z_store(a, bid, tz, li, lk, cb, acc, ps, rv, phi, fpart);
 }
 
 // ------------------------------------------------------------------ BF16X3
@@ -485,6 +501,8 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
     const float iq8 = 1.0f / (float)(p2 / 8);
     unsigned short* th = reinterpret_cast<unsigned short*>(smem);   // [t][16][ld] hi
     unsigned short* tl = th + (size_t)tc * 16 * ld;                 // lo
+    const f32x4 rv = (act && grp == 0) ? conv_z_rho(a, tz, li, lk, c0, rho)
+                                       : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int t0 = 0; t0 < a.nterms; t0 += tc) {
         const int nt = (a.nterms - t0 < tc) ? a.nterms - t0 : tc;
@@ -533,7 +551,7 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
     }
     if (G > 1) acc = conv_z_reduce(acc, smem, act, grp, G, tz, tz_n, l);
     if (!act || grp != 0) return;
-    conv_z_store(a, bid, tz, li, lk, c0, acc, ps, rho, phi, fpart);
+    conv_z_store(a, bid, tz, li, lk, c0, acc, ps, rv, phi, fpart);
 }
 
 // ------------------------------------------------------------------ spectral wide terms

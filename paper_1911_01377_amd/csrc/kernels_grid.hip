@@ -84,6 +84,8 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
     __shared__ int wtot[kSpreadWaves];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int ty = lane & 7, tz = lane >> 3;
+    // the grid mean of the charge (removed at the end), loaded first
+    const float mean = (float)(qstats[0] * a.inv_ngrid);
     const int nbx = (a.g[0] + kBrick - 1) / kBrick, nby = (a.g[1] + kBrick - 1) / kBrick;
     const int X0 = (bid % nbx) * kBrick, Y0 = ((bid / nbx) % nby) * kBrick,
               Z0 = (bid / (nbx * nby)) * kBrick;
@@ -231,7 +233,6 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
         for (int v = 0; v < kSpreadWaves - 1; ++v)
 #pragma unroll
             for (int b = 0; b < kBrick; ++b) acc[b] += red[v][b][lane];
-        const float mean = (float)(qstats[0] * a.inv_ngrid);
         if (ty < B1 && tz < B2) {
             float* out = rho + ((size_t)(Z0 + tz) * a.g[1] + (Y0 + ty)) * a.g[0] + X0;
 #pragma unroll
