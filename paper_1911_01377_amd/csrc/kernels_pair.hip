@@ -48,32 +48,32 @@ __device__ __forceinline__ float to_vgpr(float s) {
 }
 
 // Polynomial coefficients held in registers (compile-time degree, fully
-// unrolled): F = c0 + x P(x) with c0 carried as hi + lo, and G = F'(r)/r,
-// each fitted separately in FP64 on the host.  EXACT: the ne (<= kMaxExact)
+// unrolled): F = c0 + x P(x) and G = F'(r)/r, each fitted separately in
+// FP64 on the host and rounded to FP32.  EXACT: the ne (<= kMaxExact)
 // narrowest far terms are not in the polynomials but evaluated as
 // Gaussians, a_j 2^(x ex_j) in F and -a_j/s_j^2 2^(x ex_j) in G (small b puts
 // them deep inside r_c, where no polynomial of modest degree follows them).
 template <int DEG, bool EXACT>
 struct Poly {
     float c[DEG + 1];
-    float c0lo;
     float d[DEG + 1];
     int ne;
     float ex[EXACT ? kMaxExact : 1], ea[EXACT ? kMaxExact : 1], eg[EXACT ? kMaxExact : 1];
-    __device__ __forceinline__ explicit Poly(const PairArgs& a) {
+    // units: the coefficients for distances in fixed-point units u (F u and
+    // G u^3, the 1/r kernel in cubic cells)
+    __device__ __forceinline__ Poly(const PairArgs& a, bool units) {
 #pragma unroll
         for (int m = 0; m <= DEG; ++m) {
-            c[m] = a.c[m];
-            d[m] = a.d[m];
+            c[m] = units ? a.cu[m] : a.c[m];
+            d[m] = units ? a.du[m] : a.d[m];
         }
-        c0lo = a.c0lo;
         ne = a.ne;
         if (EXACT) {
 #pragma unroll
             for (int j = 0; j < kMaxExact; ++j) {
                 ex[j] = a.ex[j];
-                ea[j] = a.ea[j];
-                eg[j] = a.eg[j];
+                ea[j] = units ? a.eau[j] : a.ea[j];
+                eg[j] = units ? a.egu[j] : a.eg[j];
             }
         }
     }
@@ -113,14 +113,17 @@ __device__ __forceinline__ float recip_nr(float r2) {
     return fmaf(y, fmaf(-r2, y, 1.0f), y);
 }
 
-// nsteps steps of 8 staged j-charges (st8[s * 8 + ja]) against i-charge ci.
-// CUBIC: distances in fixed-point units (one scale for all axes), qw = q_i u,
-// rc2/irc2 in those units and is = 1/u; otherwise distances in A, qw = q_i.
+// nsteps steps of 8 staged j-charges (st8[s * 8 + ja]) against i-charge ci,
+// accumulating sum_j q_j (...) (q_i is applied once, at the end).  CUBIC:
+// distance components in fixed-point units u (one scale for all axes), rc2
+// and irc2 in those units; for 1/r the polynomials P are those for units
+// too (1/r, F in 1/u, G in 1/u^3), for the powers 1/r^2 is taken back to A.
+// Otherwise components in A.
 template <int DEG, bool CUBIC, bool EXACT, int ALPHA>
 __device__ __forceinline__ void pair_steps(const Poly<DEG, EXACT>& P, const uint4* st8, int ja,
                                            int nsteps,
-                                           uint4 ci, float qw, float sx, float sy, float sz,
-                                           float rc2, float irc2, float is, const PowScale& ps,
+                                           uint4 ci, float sx, float sy, float sz,
+                                           float rc2, float irc2, const PowScale& ps,
                                            float ctop, float dtop,
                                            float& fx, float& fy, float& fz, float& ec) {
     for (int s = 0; s < nsteps; ++s) {
@@ -142,12 +145,12 @@ __device__ __forceinline__ void pair_steps(const Poly<DEG, EXACT>& P, const uint
         // a charge of 0 (padding) contributes exactly 0; r2 is then still
         // >= (L / 2^32)^2 (>= 1 in fixed-point units) or 0, never subnormal
         if (r2 < rc2 && r2 > 0.0f) {
-            const float qq = qw * __uint_as_float(cj.w);
+            const float qj = __uint_as_float(cj.w);
             const float x = r2 * irc2;
             float Pp = fmaf(ctop, x, P.c[DEG - 1]);
 #pragma unroll
             for (int m = DEG - 2; m >= 1; --m) Pp = fmaf(Pp, x, P.c[m]);
-            const float Flo = fmaf(Pp, x, P.c0lo);
+            const float Flo = fmaf(Pp, x, P.c[0]);
             float G = fmaf(dtop, x, P.d[DEG - 1]);
 #pragma unroll
             for (int m = DEG - 2; m >= 0; --m) G = fmaf(G, x, P.d[m]);
@@ -164,17 +167,16 @@ __device__ __forceinline__ void pair_steps(const Poly<DEG, EXACT>& P, const uint
             }
             float fs;
             if (ALPHA == 1) {
-                const float rsq = __builtin_amdgcn_rsqf(r2);
-                const float rinv = CUBIC ? rsq * is : rsq;   // 1/r in 1/A
-                ec = fmaf(qq, ((rinv - P.c[0]) - Flo) - Fe, ec);
-                fs = qq * fmaf(rinv * rinv, rinv, G);
+                const float rinv = __builtin_amdgcn_rsqf(r2);
+                ec = fmaf(qj, (rinv - Flo) - Fe, ec);
+                fs = qj * fmaf(rinv * rinv, rinv, G);
             } else {
                 float i2 = recip_nr(r2);                     // 1/r^2 in 1/A^2
                 if (CUBIC) i2 = fmaf(i2, ps.is2h, i2 * ps.is2l);
                 const float i6 = i2 * i2 * i2;
                 const float ip = ALPHA == 12 ? i6 * i6 : i6;
-                ec = fmaf(qq, ((ip - P.c[0]) - Flo) - Fe, ec);
-                fs = qq * fmaf((float)ALPHA * ip, i2, G);
+                ec = fmaf(qj, (ip - Flo) - Fe, ec);
+                fs = qj * fmaf((float)ALPHA * ip, i2, G);
             }
             fx = fmaf(fs, dx, fx);
             fy = fmaf(fs, dy, fy);
@@ -210,7 +212,6 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         if (tid == 0) epart[I] = 0.0;
         return;
     }
-    const Poly<DEG, EXACT> P(a);
     const int cx = C & 0xffff, cy = C >> 16;
     const bool fullx = 2 * a.R[0] + 1 >= ncx, fully = 2 * a.R[1] + 1 >= ncy;
     const int nxs = fullx ? ncx : 2 * a.R[0] + 1, nys = fully ? ncy : 2 * a.R[1] + 1;
@@ -325,14 +326,20 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     const uint4 ci = ivalid ? sorted[ii.x + ia] : make_uint4(0, 0, 0, 0);   // q = 0 if invalid
     const float qi = __uint_as_float(ci.w);
     const float sx = a.scale[0], sy = a.scale[1], sz = a.scale[2];
-    // cubic cells: distances stay in fixed-point units u = L / 2^32 (the
-    // scale folded into r_c^2, x = r^2 / r_c^2, 1/r, and the charge of the
-    // force); otherwise each component is scaled to A
+    // cubic cells: distance components stay in fixed-point units u = L / 2^32
+    // (the scale folded into r_c^2, x = r^2 / r_c^2, for 1/r into the
+    // polynomials, and into the factors applied at the end); otherwise each
+    // component is scaled to A
     const bool cubic = sx == sy && sx == sz;
+    const bool units = cubic && ALPHA == 1;
     const float isx = 1.0f / sx;
     const float rc2w = cubic ? a.rc2 * isx * isx : a.rc2;
     const float irc2w = cubic ? a.inv_rc2 * sx * sx : a.inv_rc2;
-    const float qw = cubic ? qi * sx : qi;
+    // q_i and the scale of the sums over j: force sum_j q_j (1/r^3 + G) d in
+    // 1/u^2 (units), A / u (cubic powers) or A; energy in 1/u or 1/A
+    const float ffac = units ? qi * (isx * isx) : (cubic ? qi * sx : qi);
+    const double efac = units ? (double)qi / (double)sx : (double)qi;
+    const Poly<DEG, EXACT> P(a, false), Pu(a, ALPHA == 1);
     PowScale ps = {};
     if (ALPHA != 1) {
         const double is2 = 1.0 / (((double)sx + (double)a.scale_lo[0]) *
@@ -343,7 +350,8 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         ps.is2h = (float)is2;
         ps.is2l = (float)(is2 - (double)ps.is2h);
     }
-    const float ctop = to_vgpr(P.c[DEG]), dtop = to_vgpr(P.d[DEG]);
+    const float ctop = to_vgpr(cubic ? Pu.c[DEG] : P.c[DEG]);
+    const float dtop = to_vgpr(cubic ? Pu.d[DEG] : P.d[DEG]);
 
     // bounding box of the i-cluster (fixed point, offsets from its first
     // charge), as a centre and half extents.  Per axis the periodic distance
@@ -409,22 +417,19 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         const int nsteps = (kept + 7) >> 3;
         float ec = 0.0f;
         if (cubic)
-            pair_steps<DEG, true, EXACT, ALPHA>(P, stage[w], ja, nsteps, ci, qw, sx, sx, sx, rc2w, irc2w,
-                                                isx, ps,
-                                  ctop, dtop, fx, fy, fz, ec);
+            pair_steps<DEG, true, EXACT, ALPHA>(Pu, stage[w], ja, nsteps, ci, sx, sx, sx, rc2w,
+                                                irc2w, ps, ctop, dtop, fx, fy, fz, ec);
         else
-            pair_steps<DEG, false, EXACT, ALPHA>(P, stage[w], ja, nsteps, ci, qw, sx, sy, sz, rc2w, irc2w,
-                                                 1.0f, ps,
-                                   ctop, dtop, fx, fy, fz, ec);
+            pair_steps<DEG, false, EXACT, ALPHA>(P, stage[w], ja, nsteps, ci, sx, sy, sz, rc2w,
+                                                 irc2w, ps, ctop, dtop, fx, fy, fz, ec);
         e += (double)ec;
         wave_sync();
     }
     // force on i-charge a: sum over its 8 lanes, then over the wavefronts
-    fx = sum8(fx);
-    fy = sum8(fy);
-    fz = sum8(fz);
-    // the cubic path summed (q_i u) q_j (...): back to q_i q_j
-    const double es = wave_sum_d(e) * (cubic ? 1.0 / (double)sx : 1.0);
+    fx = ffac * sum8(fx);
+    fy = ffac * sum8(fy);
+    fz = ffac * sum8(fz);
+    const double es = wave_sum_d(e * efac);
     if (w == 1) {
         if (ja == 0) fother[ia] = make_float4(fx, fy, fz, 0.0f);
         if (lane == 0) eother = es;

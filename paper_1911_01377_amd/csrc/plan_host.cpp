@@ -146,15 +146,21 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
     pa.deg = deg;
     pa.alpha = alpha;
     pa.ne = ne;
-    for (int k = 0; k <= deg; ++k) pa.c[k] = (float)coef[k];
-    pa.c0lo = (float)(coef[0] - (double)pa.c[0]);
-    for (int k = 0; k <= deg; ++k) pa.d[k] = (float)gcoef[k];
+    const double u = (double)(float)(box[0] / 4294967296.0), u3 = u * u * u;
+    for (int k = 0; k <= deg; ++k) {
+        pa.c[k] = (float)coef[k];
+        pa.d[k] = (float)gcoef[k];
+        pa.cu[k] = (float)(coef[k] * u);
+        pa.du[k] = (float)(gcoef[k] * u3);
+    }
     for (int j = 0; j < kMaxExact; ++j) {
         double aj = 0.0, sj = 1.0;
         if (j < ne) s.term(j, &aj, &sj);
         pa.ex[j] = (float)(-1.4426950408889634 * r_c * r_c / (2.0 * sj * sj));
         pa.ea[j] = (float)aj;
         pa.eg[j] = (float)(-aj / (sj * sj));
+        pa.eau[j] = (float)(aj * u);
+        pa.egu[j] = (float)(-aj / (sj * sj) * u3);
     }
     pa.gz = grid[2];
     pa.rc2 = (float)(r_c * r_c);

@@ -85,11 +85,14 @@ struct PairArgs {
     int alpha;            // kernel power: 1 (1/r), 6 (1/r^6) or 12 (1/r^12)
     int ne;               // leading far terms evaluated as Gaussians (0..kMaxExact)
     float c[kMaxPolyDeg + 1];   // F_inf(r) = sum_{j<ne} ea_j 2^(x ex_j) + sum c_k x^k, x = r^2/rc^2
-    float c0lo;                 // c_0 - (float)c_0
     float d[kMaxPolyDeg + 1];   // F_inf'(r)/r = sum_{j<ne} eg_j 2^(x ex_j) + sum d_k x^k
     float ex[kMaxExact];        // -log2(e) rc^2 / (2 s_j^2)
     float ea[kMaxExact];        // a_j
     float eg[kMaxExact];        // -a_j / s_j^2
+    // the same for distances in fixed-point units u = scale[0] (cubic cells,
+    // the 1/r kernel): F u and (F'/r) u^3
+    float cu[kMaxPolyDeg + 1], du[kMaxPolyDeg + 1];
+    float eau[kMaxExact], egu[kMaxExact];
 };
 
 struct GridArgs {
