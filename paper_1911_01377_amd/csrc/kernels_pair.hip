@@ -119,15 +119,20 @@ __device__ __forceinline__ float recip_nr(float r2) {
 // and irc2 in those units; for 1/r the polynomials P are those for units
 // too (1/r, F in 1/u, G in 1/u^3), for the powers 1/r^2 is taken back to A.
 // Otherwise components in A.
-template <int DEG, bool CUBIC, bool EXACT, int ALPHA>
+template <int DEG, bool CUBIC, bool EXACT, int ALPHA, bool PIPE>
 __device__ __forceinline__ void pair_steps(const Poly<DEG, EXACT>& P, const uint4* st8, int ja,
                                            int nsteps,
                                            uint4 ci, float sx, float sy, float sz,
                                            float rc2, float irc2, const PowScale& ps,
                                            float ctop, float dtop,
                                            float& fx, float& fy, float& fz, float& ec) {
+    // PIPE: the next step's j-charge is read while this step computes (the
+    // stage has 8 spare slots, so the read past the last step stays in
+    // bounds); it costs four registers
+    uint4 cn = st8[ja];
     for (int s = 0; s < nsteps; ++s) {
-        const uint4 cj = st8[s * 8 + ja];
+        const uint4 cj = PIPE ? cn : st8[s * 8 + ja];
+        if (PIPE) cn = st8[(s + 1) * 8 + ja];
         float dx = (float)(int)(ci.x - cj.x), dy = (float)(int)(ci.y - cj.y),
               dz = (float)(int)(ci.z - cj.z);
         if (!CUBIC) {
@@ -185,7 +190,7 @@ __device__ __forceinline__ void pair_steps(const Poly<DEG, EXACT>& P, const uint
     }
 }
 
-template <int DEG, bool EXACT, int ALPHA>
+template <int DEG, bool EXACT, int ALPHA, bool PIPE>
 __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4* __restrict__ sorted,
                                           const int2* __restrict__ cl_info,
                                           const int* __restrict__ cl_col,
@@ -193,7 +198,7 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
                                           const int* __restrict__ zbin,
                                           float4* __restrict__ fnear,
                                           double* __restrict__ epart) {
-    __shared__ uint4 stage[kPairWaves][kChunkCharges];
+    __shared__ uint4 stage[kPairWaves][kChunkCharges + 8];
     __shared__ int rbeg[2 * kMaxStencilCols];       // first sorted charge of each non-empty range
     __shared__ int roff[2 * kMaxStencilCols + 1];   // prefix sums of the range lengths
     __shared__ int wtot[kPairWaves][2];
@@ -417,10 +422,10 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         const int nsteps = (kept + 7) >> 3;
         float ec = 0.0f;
         if (cubic)
-            pair_steps<DEG, true, EXACT, ALPHA>(Pu, stage[w], ja, nsteps, ci, sx, sx, sx, rc2w,
+            pair_steps<DEG, true, EXACT, ALPHA, PIPE>(Pu, stage[w], ja, nsteps, ci, sx, sx, sx, rc2w,
                                                 irc2w, ps, ctop, dtop, fx, fy, fz, ec);
         else
-            pair_steps<DEG, false, EXACT, ALPHA>(P, stage[w], ja, nsteps, ci, sx, sy, sz, rc2w,
+            pair_steps<DEG, false, EXACT, ALPHA, PIPE>(P, stage[w], ja, nsteps, ci, sx, sy, sz, rc2w,
                                                  irc2w, ps, ctop, dtop, fx, fy, fz, ec);
         e += (double)ec;
         wave_sync();
@@ -445,29 +450,29 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     }
 }
 
+// Held to 72 registers without exact Gaussians (7 wavefronts per SIMD, no
+// spill), 80 with them.
 template <int DEG, bool EXACT, int ALPHA>
-__global__ void __launch_bounds__(64 * kPairWaves) k_pair(PairArgs a, int nb,
-                                             const uint4* __restrict__ sorted,
-                                             const int2* __restrict__ cl_info,
-                                             const int* __restrict__ cl_col,
-                                             const uint2* __restrict__ cl_z,
-                                             const int* __restrict__ zbin,
-                                             float4* __restrict__ fnear,
-                                             double* __restrict__ epart) {
+__global__ void __launch_bounds__(64 * kPairWaves)
+__attribute__((amdgpu_waves_per_eu(EXACT ? 6 : 7)))
+k_pair(PairArgs a, int nb, const uint4* __restrict__ sorted, const int2* __restrict__ cl_info,
+       const int* __restrict__ cl_col, const uint2* __restrict__ cl_z,
+       const int* __restrict__ zbin, float4* __restrict__ fnear, double* __restrict__ epart) {
     const int item = xcd_item(blockIdx.x, nb);
     if (item < nb)
-        pair_body<DEG, EXACT, ALPHA>(a, item, sorted, cl_info, cl_col, cl_z, zbin, fnear, epart);
+        pair_body<DEG, EXACT, ALPHA, true>(a, item, sorted, cl_info, cl_col, cl_z, zbin, fnear, epart);
 }
 
-// Held to 80 registers (6 wavefronts per SIMD instead of 5; the batch walk
-// costs 8-12 bytes of spill per lane): about 2% more batched evaluations/s.
+// Held to 80 registers (6 wavefronts per SIMD instead of 5; the variant with
+// exact Gaussians then spills about 24 bytes per lane), without the step
+// pipelining (its four registers would spill here).
 template <int DEG, bool EXACT>
 __global__ void __launch_bounds__(64 * kPairWaves) __attribute__((amdgpu_waves_per_eu(6)))
 k_pair_batch(const BatchTable* __restrict__ tab,
                                                    const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_PAIR, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        pair_body<DEG, EXACT, 1>(d.pair, item, d.sorted, d.cl_info, d.cl_col, d.cl_z, d.zbin,
+        pair_body<DEG, EXACT, 1, false>(d.pair, item, d.sorted, d.cl_info, d.cl_col, d.cl_z, d.zbin,
                                  d.fnear, d.pair_parts);
     });
 }
