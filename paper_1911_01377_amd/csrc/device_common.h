@@ -39,9 +39,10 @@ __device__ __forceinline__ int wrap1(int v, int n) {
     return v >= n ? v - n : v;
 }
 
-// floor(v / d) for v >= 0, d >= 1 and v d < 2^22, from a float reciprocal:
-// (v + 1/2)/d lies at least 1/(2d) from an integer, and the float error of
-// the product, below (v/d) 2^-23, is smaller than that
+// floor(v / d) for v >= 0, d >= 1 and v < 2^20, from a float reciprocal
+// within 1 ulp (the hardware reciprocal, or a division): (v + 1/2)/d lies at
+// least 1/(2d) from an integer, and the float error of the product, below
+// (v/d) 2^-21, is smaller than that
 __device__ __forceinline__ int small_div(int v, float inv_d) {
     return (int)(((float)v + 0.5f) * inv_d);
 }

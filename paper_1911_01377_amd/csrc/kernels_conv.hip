@@ -157,7 +157,7 @@ __device__ __forceinline__ void conv_xy_f32_body(const ConvArgs& a, int z, int t
     const float* src = rho + (size_t)z * g1 * g0;
     // octets of the padded plane, two per thread per pass (loads first)
     const int no = p1 * (p0 / 8);
-    const float iq = 1.0f / (float)(p0 / 8);
+    const float iq = __builtin_amdgcn_rcpf((float)(p0 / 8));   // small_div: ample margin
     for (int o0 = threadIdx.x; o0 < no; o0 += 2 * kConvThreads) {
         float v[2][8];
 #pragma unroll
@@ -306,7 +306,7 @@ __device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid, floa
     const int tz = w % tz_n, grp = w / tz_n;
     const size_t mz = (size_t)p2 * p2;
     const int tc = conv_z_chunk(a);
-    const float iq8 = 1.0f / (float)(p2 / 8);
+    const float iq8 = __builtin_amdgcn_rcpf((float)(p2 / 8));   // small_div: ample margin
     const f32x4 rv = (act && grp == 0) ? conv_z_rho(a, tz, li, lk, cb, rho)
                                        : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -401,7 +401,7 @@ __device__ __forceinline__ void conv_xy_bf16_body(const ConvArgs& a, int z, int 
     const float* src = rho + (size_t)z * g1 * g0;
     // octets of the padded plane, two per thread per pass (loads first)
     const int no = p1 * (p0 / 8);
-    const float iq = 1.0f / (float)(p0 / 8);
+    const float iq = __builtin_amdgcn_rcpf((float)(p0 / 8));   // small_div: ample margin
     for (int o0 = threadIdx.x; o0 < no; o0 += 2 * kConvThreads) {
         float v[2][8];
 #pragma unroll
@@ -498,7 +498,7 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
     const int tz = w % tz_n, grp = w / tz_n;
     const size_t mz = (size_t)p2 * p2;
     const int tc = conv_z_chunk(a);
-    const float iq8 = 1.0f / (float)(p2 / 8);
+    const float iq8 = __builtin_amdgcn_rcpf((float)(p2 / 8));   // small_div: ample margin
     unsigned short* th = reinterpret_cast<unsigned short*>(smem);   // [t][16][ld] hi
     unsigned short* tl = th + (size_t)tc * 16 * ld;                 // lo
     const f32x4 rv = (act && grp == 0) ? conv_z_rho(a, tz, li, lk, c0, rho)

@@ -333,7 +333,8 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
     const int B0 = min(GB, a.g[0] - X0), B1 = min(GB, a.g[1] - Y0), B2 = min(GB, a.g[2] - Z0);
     const int E0 = B0 + P2 - 1, E1 = B1 + P2 - 1, E2 = B2 + P2 - 1;
     // potential on the brick and halo: local (hx, hy, hz) = global (X0 - P + 1 + hx, ...)
-    const float inv0 = 1.0f / (float)E0, inv1 = 1.0f / (float)E1;
+    // approximate reciprocals: (idx + 1/2) / E stays 1 / (2E) from an integer
+    const float inv0 = __builtin_amdgcn_rcpf((float)E0), inv1 = __builtin_amdgcn_rcpf((float)E1);
     const int nh = E0 * E1 * E2;
     // the loads of a pass are issued together, then stored
     for (int base = tid; base < nh; base += kGatherThreads * kGatherBatch) {

@@ -226,7 +226,9 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     // second only where the z window wraps)
     int rb0 = 0, n0 = 0, rb1 = 0, n1 = 0;
     if (tid < NC) {
-        const int ky = small_div(tid, 1.0f / (float)nxs);   // tid < 128, nxs <= 128
+        // tid < 128, nxs <= 128: (tid + 1/2) / nxs stays 1/256 from an integer,
+        // far beyond the reciprocal's error
+        const int ky = small_div(tid, __builtin_amdgcn_rcpf((float)nxs));
         const StencilCol sx = stencil_col(tid - ky * nxs, cx, a.R[0], ncx, fullx);
         const StencilCol sy = stencil_col(ky, cy, a.R[1], ncy, fully);
         const int colx = sx.col, coly = sy.col, dx = sx.d, dy = sy.d;
@@ -337,23 +339,21 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     // component is scaled to A
     const bool cubic = sx == sy && sx == sz;
     const bool units = cubic && ALPHA == 1;
-    const float isx = 1.0f / sx;
+    const float isx = a.inv_scale;
     const float rc2w = cubic ? a.rc2 * isx * isx : a.rc2;
     const float irc2w = cubic ? a.inv_rc2 * sx * sx : a.inv_rc2;
     // q_i and the scale of the sums over j: force sum_j q_j (1/r^3 + G) d in
     // 1/u^2 (units), A / u (cubic powers) or A; energy in 1/u or 1/A
     const float ffac = units ? qi * (isx * isx) : (cubic ? qi * sx : qi);
-    const double efac = units ? (double)qi / (double)sx : (double)qi;
+    const double efac = units ? (double)qi * a.inv_scale_d : (double)qi;
     const Poly<DEG, EXACT> P(a, false), Pu(a, ALPHA == 1);
     PowScale ps = {};
     if (ALPHA != 1) {
-        const double is2 = 1.0 / (((double)sx + (double)a.scale_lo[0]) *
-                                  ((double)sx + (double)a.scale_lo[0]));
         ps.lo[0] = a.scale_lo[0];
         ps.lo[1] = a.scale_lo[1];
         ps.lo[2] = a.scale_lo[2];
-        ps.is2h = (float)is2;
-        ps.is2l = (float)(is2 - (double)ps.is2h);
+        ps.is2h = a.is2h;
+        ps.is2l = a.is2l;
     }
     const float ctop = to_vgpr(cubic ? Pu.c[DEG] : P.c[DEG]);
     const float dtop = to_vgpr(cubic ? Pu.d[DEG] : P.d[DEG]);
@@ -390,8 +390,7 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     const float hx = (float)((bh[0] - bl[0]) / 2 + 1) * sx;
     const float hy = (float)((bh[1] - bl[1]) / 2 + 1) * sy;
     const float hz = (float)((bh[2] - bl[2]) / 2 + 1) * sz;
-    const float rcm = sqrtf(a.rc2) + 1e-3f;
-    const float rcm2 = rcm * rcm;
+    const float rcm2 = a.rcm2;
     auto near_box = [&](const uint4& cj) {
         const float ex = fmaxf(0.0f, fabsf((float)(int)(cj.x - cenx) * sx) - hx);
         const float ey = fmaxf(0.0f, fabsf((float)(int)(cj.y - ceny) * sy) - hy);

@@ -186,6 +186,16 @@ int build_host_plan(HostPlan* hp, const double box[3], double r_c, double b, dou
         pa.scale_lo[a] = (float)(box[a] / 4294967296.0 - (double)pa.scale[a]);
     }
     pa.zinv = (float)(4294967296.0 / box[2]);
+    pa.inv_scale = 1.0f / pa.scale[0];
+    pa.inv_scale_d = 1.0 / (double)pa.scale[0];
+    {
+        const double ux = (double)pa.scale[0] + (double)pa.scale_lo[0];
+        const double is2 = 1.0 / (ux * ux);
+        pa.is2h = (float)is2;
+        pa.is2l = (float)(is2 - (double)pa.is2h);
+        const float rcm = std::sqrt(pa.rc2) + 1e-3f;
+        pa.rcm2 = rcm * rcm;
+    }
 
     // far part.  A term so wide that every non-zero Fourier mode of its
     // periodised Gaussian lies below 2^-60 of the k = 0 mode equals, to double

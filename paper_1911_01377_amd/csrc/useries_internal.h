@@ -76,6 +76,10 @@ struct PairArgs {
     int R[2];             // columns within reach of r_c per axis: ceil(r_c / cw)
     float scale[3];       // L / 2^32: fixed-point units to A
     float scale_lo[3];    // L / 2^32 - scale: the FP32 rounding of the scale
+    float inv_scale;      // 1 / scale[0] (FP32)
+    double inv_scale_d;   // 1 / scale[0] (FP64)
+    float is2h, is2l;     // (1 / (scale[0] + scale_lo[0]))^2 as FP32 hi + lo
+    float rcm2;           // (r_c + 1e-3)^2: the bounding-box test's reach
     float cw[2];          // column widths L / nc
     float zinv;           // 2^32 / L_z: A to fixed-point units along z
     float rc2;            // r_c^2
