@@ -76,7 +76,8 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
                                             const double* __restrict__ qstats,
                                             float* __restrict__ rho) {
     __shared__ float sw[kSpreadChunk][3 * kBrick];
-    static_assert((kSpreadWaves - 1) * kBrick * 64 <= kSpreadChunk * 3 * kBrick, "red fits in sw");
+    static_assert(kSpreadWaves * kBrick * 64 <= kSpreadChunk * 3 * kBrick, "red fits in sw");
+    static_assert(kSpreadWaves == kBrick, "one wavefront per x plane in the final sum");
     // the wavefronts' partial bricks, summed after the last chunk (reuses sw)
     float (*red)[kBrick][64] = reinterpret_cast<float (*)[kBrick][64]>(&sw[0][0]);
     __shared__ int pbeg[2 * kMaxWindowCols];       // first charge of each column piece
@@ -224,22 +225,16 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
         __syncthreads();
     }
 
-    // fixed-order sum of the wavefronts' partial bricks
-    if (w > 0)
+    // fixed-order sum of the wavefronts' partial bricks: all partials to LDS,
+    // then wavefront w sums x plane w over them in wavefront order
 #pragma unroll
-        for (int b = 0; b < kBrick; ++b) red[w - 1][b][lane] = acc[b];
+    for (int b = 0; b < kBrick; ++b) red[w][b][lane] = acc[b];
     __syncthreads();
-    if (w == 0) {
-        for (int v = 0; v < kSpreadWaves - 1; ++v)
+    float v = red[0][w][lane];
 #pragma unroll
-            for (int b = 0; b < kBrick; ++b) acc[b] += red[v][b][lane];
-        if (ty < B1 && tz < B2) {
-            float* out = rho + ((size_t)(Z0 + tz) * a.g[1] + (Y0 + ty)) * a.g[0] + X0;
-#pragma unroll
-            for (int b = 0; b < kBrick; ++b)
-                if (b < B0) out[b] = acc[b] - mean;
-        }
-    }
+    for (int u = 1; u < kSpreadWaves; ++u) v += red[u][w][lane];
+    if (w < B0 && ty < B1 && tz < B2)
+        rho[((size_t)(Z0 + tz) * a.g[1] + (Y0 + ty)) * a.g[0] + X0 + w] = v - mean;
 }
 
 template <int PT>
