@@ -750,15 +750,27 @@ __device__ __forceinline__ void colbuild_body(int col, int nb, int ncol, int ncx
     }
     __syncthreads();
     const bool in_lds = cnt <= kSortCap;
-    // z-plane index: zrow[z] = first charge whose grid z index is >= z
-    for (int z = t; z <= gz; z += 256) {
-        int l = 0, hh = cnt;
-        while (l < hh) {
-            const int mid = (l + hh) >> 1;
-            const uint32_t zz = in_lds ? skz[mid] : sorted[lo + mid].z;
-            if (cell_coord(zz, gz) < z) l = mid + 1; else hh = mid;
+    // z-plane index: zrow[z] = first charge whose grid z index is >= z.  From
+    // the LDS copy, sorted charge k writes the planes after its predecessor's
+    // grid z index up to its own (the last charge also those up to gz);
+    // otherwise a search per plane
+    if (in_lds) {
+        for (int k = t; k < cnt; k += 256) {
+            const int zk = cell_coord(skz[k], gz);
+            const int zp = k > 0 ? cell_coord(skz[k - 1], gz) : -1;
+            for (int z = zp + 1; z <= zk; ++z) zrow[z] = lo + k;
+            if (k == cnt - 1)
+                for (int z = zk + 1; z <= gz; ++z) zrow[z] = lo + cnt;
         }
-        zrow[z] = lo + l;
+    } else {
+        for (int z = t; z <= gz; z += 256) {
+            int l = 0, hh = cnt;
+            while (l < hh) {
+                const int mid = (l + hh) >> 1;
+                if (cell_coord(sorted[lo + mid].z, gz) < z) l = mid + 1; else hh = mid;
+            }
+            zrow[z] = lo + l;
+        }
     }
     const int cyx = (col % ncx) | ((col / ncx) << 16);
     for (int k = t; k < nclus; k += 256) {

@@ -17,8 +17,9 @@
 // (lane / 8, lane % 8) holds i-charge a and j-charge b of the step, so every
 // lane evaluates one pair per step and no lane waits on another's branch.
 // The two wavefronts take alternate chunks of 256 candidates, each loading
-// its chunk one chunk ahead (4 consecutive candidates per lane, so a lane
-// searches the range list once per chunk) and staging in LDS only the
+// its chunk one chunk ahead (4 consecutive candidates per lane; the range
+// of a lane's first one from a per-cluster table of candidate groups, or a
+// search when the candidates are many) and staging in LDS only the
 // candidates within r_c of the i-cluster's bounding box (about 58% of them
 // in water), so the steps skip most pairs that cannot be in range.  The force on
 // charge a is summed over its 8 lanes by shuffles, then over the two
@@ -38,6 +39,10 @@ constexpr int kPairWaves = 2;         // wavefronts per i-cluster
 constexpr int kChunk = 32;            // steps of 8 j-charges staged per pass (4 KB of LDS)
 constexpr int kChunkCharges = 8 * kChunk;
 constexpr int kPerLane = kChunkCharges / 64;   // consecutive candidates loaded per lane
+// groups of kPerLane candidates with a range table entry; the block's LDS
+// (about 11 KB with it) must stay within 160 KB / 14 blocks, or the kernel
+// loses its 7th wavefront per SIMD (a 1024-entry table did: 2.3 us slower)
+constexpr int kPairTab = 512;
 
 // a loop-invariant value held in a vector register (lets a polynomial step
 // take its two coefficients from one scalar and one vector operand)
@@ -201,6 +206,8 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     __shared__ uint4 stage[kPairWaves][kChunkCharges + 8];
     __shared__ int rbeg[2 * kMaxStencilCols];       // first sorted charge of each non-empty range
     __shared__ int roff[2 * kMaxStencilCols + 1];   // prefix sums of the range lengths
+    __shared__ unsigned char rtab[kPairTab];         // range of candidate kPerLane g
+    static_assert(2 * kMaxStencilCols <= 256, "range indices fit in a byte");
     __shared__ int wtot[kPairWaves][2];
     __shared__ float4 fother[8];
     __shared__ double eother;
@@ -297,6 +304,16 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     if (tid == 0) roff[nr] = tot;
     __syncthreads();
     const int total = __builtin_amdgcn_readfirstlane(tot);   // uniform: loop bounds in SGPRs
+    // the range of each lane's first candidate in a chunk from a table when
+    // the candidates are few enough (one LDS read instead of a search)
+    const bool tabbed = total <= kPerLane * kPairTab;
+    if (tabbed) {
+        for (int r = tid; r < nr; r += 64 * kPairWaves) {
+            const int g1 = (roff[r + 1] + kPerLane - 1) / kPerLane;
+            for (int g = (roff[r] + kPerLane - 1) / kPerLane; g < g1; ++g) rtab[g] = (unsigned char)r;
+        }
+        __syncthreads();
+    }
 
     // candidates p0 .. p0 + 3 of a chunk (p0 = chunk start + 4 lane), loaded by
     // this lane: one search for the range of p0, then at most one range
@@ -305,12 +322,16 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         const int p0 = c * kChunkCharges + kPerLane * lane;
         int r = 0;
         if (p0 < total) {
-            int lo = 0, hi = nr;                 // range r with roff[r] <= p0 < roff[r + 1]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (roff[mid] <= p0) lo = mid; else hi = mid;
+            if (tabbed) {
+                r = rtab[p0 / kPerLane];
+            } else {
+                int lo = 0, hi = nr;             // range r with roff[r] <= p0 < roff[r + 1]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (roff[mid] <= p0) lo = mid; else hi = mid;
+                }
+                r = lo;
             }
-            r = lo;
         }
         int end = roff[r + 1];
         int b = rbeg[r] - roff[r];
