@@ -47,6 +47,12 @@ __device__ __forceinline__ int small_div(int v, float inv_d) {
     return (int)(((float)v + 0.5f) * inv_d);
 }
 
+// number of set bits of m in the lanes below this one
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Order LDS traffic between the lanes of one wavefront (the LDS of a
 // wavefront-private region needs no block barrier).
 __device__ __forceinline__ void wave_sync() {

@@ -431,9 +431,11 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
 #pragma unroll
         for (int u = 0; u < kPerLane; ++u) {
             const int p = c * kChunkCharges + kPerLane * lane + u;
-            const bool keep = p < total && near_box(pre[u]);
+            // both tests evaluated (no branch): a candidate past the end is
+            // the zero record fetch left, tested and dropped
+            const bool keep = (p < total) & near_box(pre[u]);
             const uint64_t m = __ballot(keep);
-            if (keep) stage[w][kept + __popcll(m & ((1ull << lane) - 1ull))] = pre[u];
+            if (keep) stage[w][kept + lanes_below(m)] = pre[u];
             kept += __popcll(m);
         }
         if (lane < ((kept + 7) & ~7) - kept) stage[w][kept + lane] = make_uint4(0, 0, 0, 0);
