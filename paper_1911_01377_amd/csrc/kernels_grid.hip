@@ -75,16 +75,18 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
                                             const int* __restrict__ zbin,
                                             const double* __restrict__ qstats,
                                             float* __restrict__ rho) {
-    __shared__ float sw[kSpreadChunk][3 * kBrick];
+    __shared__ __align__(16) float sw[kSpreadChunk][3 * kBrick];   // rows of 96 B (16-byte stores)
     static_assert(kSpreadWaves * kBrick * 64 <= kSpreadChunk * 3 * kBrick, "red fits in sw");
-    static_assert(kSpreadWaves == kBrick, "one wavefront per x plane in the final sum");
+    static_assert(kSpreadWaves == kBrick && kBrick == 8, "one wavefront per x plane; 8-wide rows");
     // the wavefronts' partial bricks, summed after the last chunk (reuses sw)
     float (*red)[kBrick][64] = reinterpret_cast<float (*)[kBrick][64]>(&sw[0][0]);
     __shared__ int pbeg[2 * kMaxWindowCols];       // first charge of each column piece
     __shared__ int poff[2 * kMaxWindowCols + 1];   // prefix sums of the piece lengths
     __shared__ int wtot[kSpreadWaves];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int ty = lane & 7, tz = lane >> 3;
+    // lane's 2 x 2 x 2 points of the brick: x 2cx + dx, y 2cy + dy, z 2cz + dz;
+    // its partial sums acc[dx + 2 dy + 4 dz]
+    const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
     // the grid mean of the charge (removed at the end), loaded first
     const float mean = (float)(qstats[0] * a.inv_ngrid);
     const int nbx = (a.g[0] + kBrick - 1) / kBrick, nby = (a.g[1] + kBrick - 1) / kBrick;
@@ -217,24 +219,49 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
             }
         }
         __syncthreads();
-        for (int sidx = w; sidx < nst; sidx += kSpreadWaves) {
-            const float c = sw[sidx][kBrick + ty] * sw[sidx][2 * kBrick + tz];
+        // the staged charges of this wavefront, two at a time with their LDS
+        // reads issued together; per charge three 8-byte reads (the lane's two
+        // weights of each axis), four y z products and eight FMAs, in staged
+        // order
+        auto add = [&](const float2 X, const float2 Y, const float2 Z) {
+            const float yz[4] = {Y.x * Z.x, Y.y * Z.x, Y.x * Z.y, Y.y * Z.y};
 #pragma unroll
-            for (int b = 0; b < kBrick; ++b) acc[b] = fmaf(c, sw[sidx][b], acc[b]);
+            for (int k = 0; k < 8; ++k) acc[k] = fmaf(k & 1 ? X.y : X.x, yz[k >> 1], acc[k]);
+        };
+        auto wts = [&](int sidx, float2& X, float2& Y, float2& Z) {
+            const float* row = sw[sidx];
+            X = *reinterpret_cast<const float2*>(row + 2 * cx);
+            Y = *reinterpret_cast<const float2*>(row + kBrick + 2 * cy);
+            Z = *reinterpret_cast<const float2*>(row + 2 * kBrick + 2 * cz);
+        };
+        int sidx = w;
+        for (; sidx + kSpreadWaves < nst; sidx += 2 * kSpreadWaves) {
+            float2 X0w, Y0w, Z0w, X1w, Y1w, Z1w;
+            wts(sidx, X0w, Y0w, Z0w);
+            wts(sidx + kSpreadWaves, X1w, Y1w, Z1w);
+            add(X0w, Y0w, Z0w);
+            add(X1w, Y1w, Z1w);
+        }
+        if (sidx < nst) {
+            float2 Xw, Yw, Zw;
+            wts(sidx, Xw, Yw, Zw);
+            add(Xw, Yw, Zw);
         }
         __syncthreads();
     }
 
     // fixed-order sum of the wavefronts' partial bricks: all partials to LDS,
-    // then wavefront w sums x plane w over them in wavefront order
+    // then wavefront w sums partial w of every lane over them in wavefront
+    // order
 #pragma unroll
-    for (int b = 0; b < kBrick; ++b) red[w][b][lane] = acc[b];
+    for (int k = 0; k < kBrick; ++k) red[w][k][lane] = acc[k];
     __syncthreads();
     float v = red[0][w][lane];
 #pragma unroll
     for (int u = 1; u < kSpreadWaves; ++u) v += red[u][w][lane];
-    if (w < B0 && ty < B1 && tz < B2)
-        rho[((size_t)(Z0 + tz) * a.g[1] + (Y0 + ty)) * a.g[0] + X0 + w] = v - mean;
+    const int px = 2 * cx + (w & 1), py = 2 * cy + ((w >> 1) & 1), pz = 2 * cz + (w >> 2);
+    if (px < B0 && py < B1 && pz < B2)
+        rho[((size_t)(Z0 + pz) * a.g[1] + (Y0 + py)) * a.g[0] + X0 + px] = v - mean;
 }
 
 template <int PT>
