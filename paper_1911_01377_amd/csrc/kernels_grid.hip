@@ -17,7 +17,7 @@
 //   a fixed order.  No atomics.
 // gather: one block per brick with the potential on the brick and its halo in
 //   LDS; each charge is evaluated by the block whose brick holds its stencil
-//   anchor, 16 lanes per charge.  One more block forms the energy total.
+//   anchor, 8 or 16 lanes per charge.  One more block forms the energy total.
 #include <algorithm>
 
 #include "useries_internal.h"
@@ -290,12 +290,14 @@ __global__ void __launch_bounds__(64 * kSpreadWaves) k_spread_batch(
 // whose stencil anchor (grid cell) lies in the brick: per overlapping column
 // the z-plane index gives one contiguous range; candidates are loaded one per
 // thread and the owners compacted in thread order.  A wavefront evaluates
-// four owners at a time, 16 lanes each: a lane owns stencil rows (y, z) and
-// reads the 2P x points of each from LDS; the 16-lane groups then reduce.
+// eight owners at a time with 8 lanes each (stencils of up to 8 points per
+// axis, compiled for that width) or four with 16: a lane owns stencil rows
+// (y, z) and reads the 2P x points of each from LDS; the groups then reduce.
 constexpr int kGatherMaxPieces = 256;     // columns overlapping a brick
 constexpr int kGatherWaves = 8;           // wavefronts per brick
 constexpr int kGatherThreads = 64 * kGatherWaves;
 constexpr int kGatherBatch = 8;           // halo loads issued together per thread
+constexpr int kGatherOwners = 8;          // owners per wavefront pass, at most
 
 __host__ __device__ inline int gather_brick(int P) { return P <= 5 ? 8 : 4; }
 
@@ -317,7 +319,7 @@ __host__ __device__ inline GatherLds gather_lds(int P) {
     L.ownf = take(16 * kGatherThreads);                // owners' near forces
     L.ownp = take(4 * kGatherThreads);                 // owners' input indices
     L.sphi = take(4 * E * E * E);                      // potential on brick + halo
-    L.sw = take(4 * kGatherWaves * 4 * 6 * 2 * P);     // weights, derivatives [wave][owner][6][2P]
+    L.sw = take(4 * kGatherWaves * kGatherOwners * 6 * 2 * P);   // weights, derivatives [wave][owner][6][2P]
     L.rowtab = take(8 * 4 * P * P);                    // stencil rows {offset, ky | kz << 16}
     L.pbeg = take(4 * kGatherMaxPieces);
     L.poff = take(4 * (kGatherMaxPieces + 1));
@@ -337,7 +339,10 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                                             const float4* __restrict__ fnear,
                                             float* __restrict__ forces, char* lds) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int g = lane >> 4, l16 = lane & 15;
+    // LPO lanes per owner charge (8 for a compile-time stencil of at most 8
+    // points per axis, else 16), OPW owners per wavefront pass
+    constexpr int LPO = (PT > 0 && 2 * PT <= 8) ? 8 : 16, OPW = 64 / LPO;
+    const int g = lane / LPO, lg = lane % LPO;
     const int P = PT > 0 ? PT : a.P, P2 = 2 * P, GB = gather_brick(P);
     constexpr int KMAX = PT > 0 ? 2 * PT : 2 * kMaxStencilHalf;   // x points per stencil row
     const GatherLds LL = gather_lds(P);
@@ -443,8 +448,9 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
             ownp[slot] = pj;
         }
         __syncthreads();
-        // four owners per wavefront pass, groups dealt round-robin to the wavefronts
-        for (int o0 = wave * 4; o0 < nown; o0 += 4 * kGatherWaves) {
+        // OPW owners per wavefront pass, groups dealt round-robin to the wavefronts
+        static_assert(OPW <= kGatherOwners, "weights sized for kGatherOwners per wavefront");
+        for (int o0 = wave * OPW; o0 < nown; o0 += OPW * kGatherWaves) {
             const int o = o0 + g;
             const bool valid = o < nown;
             int gi[3] = {0, 0, 0};
@@ -456,25 +462,25 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                 grid_coord(cc.y, a.g[1], &gi[1], &f[1]);
                 grid_coord(cc.z, a.g[2], &gi[2], &f[2]);
                 qi = __uint_as_float(cc.w);
-                // lane l16 < 2P: weights and derivatives of stencil point l16, all axes
-                if (l16 < P2) {
+                // lane lg < 2P: weights and derivatives of stencil point lg, all axes
+                if (lg < P2) {
 #pragma unroll
                     for (int ax = 0; ax < 3; ++ax) {
-                        const float tt = (float)(l16 - P + 1) - f[ax];
+                        const float tt = (float)(lg - P + 1) - f[ax];
                         const float w = a.cw[ax] * __expf(-tt * tt * a.hs[ax]);
-                        swb[((wave * 4 + g) * 6 + ax) * P2 + l16] = w;
-                        swb[((wave * 4 + g) * 6 + 3 + ax) * P2 + l16] = w * tt * a.dws[ax];
+                        swb[((wave * kGatherOwners + g) * 6 + ax) * P2 + lg] = w;
+                        swb[((wave * kGatherOwners + g) * 6 + 3 + ax) * P2 + lg] = w * tt * a.dws[ax];
                     }
                 }
             }
             wave_sync();
             float px = 0.0f, py = 0.0f, pz = 0.0f;
             if (valid) {
-                const float* W = swb + (wave * 4 + g) * 6 * P2;   // [6][2P]
+                const float* W = swb + (wave * kGatherOwners + g) * 6 * P2;   // [6][2P]
                 // stencil point k of the charge is halo point (gi - brick origin) + k
                 const int lx = gi[0] - X0, ly = gi[1] - Y0, lz = gi[2] - Z0;
                 const float* obase = sphi + (lz * E1 + ly) * E0 + lx;
-                for (int r = l16; r < P2 * P2; r += 16) {
+                for (int r = lg; r < P2 * P2; r += LPO) {
                     const int2 rt = rowtab[r];
                     const int ky = rt.y & 0xffff, kz = rt.y >> 16;
                     const float* rowp = obase + rt.x;
@@ -493,10 +499,10 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
                     pz = fmaf(wy * W[5 * P2 + kz], sx, pz);
                 }
             }
-            px = row_sum16(px);
-            py = row_sum16(py);
-            pz = row_sum16(pz);
-            if (valid && l16 == 0) {
+            px = LPO == 8 ? sum8(px) : row_sum16(px);
+            py = LPO == 8 ? sum8(py) : row_sum16(py);
+            pz = LPO == 8 ? sum8(pz) : row_sum16(pz);
+            if (valid && lg == 0) {
                 const float4 fn = ownf[o];    // near force from the pair kernel
                 const int oi = ownp[o];
                 forces[3 * oi + 0] = fn.x - qi * px;
