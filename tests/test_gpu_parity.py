@@ -151,6 +151,18 @@ def _form(precision):
 
 
 @pytest.mark.parametrize("precision,tol", FORMS)
+def test_many_candidates_per_cluster(precision, tol):
+    """3,000 random charges in a 20 A cube (0.375 per A^3) with r_c = 9.5 A:
+    every cluster has 2,400 to 3,000 candidates (a host count with the
+    kernel's column and z-window rules), more than the 2,048 whose ranges
+    the pair kernel looks up in its table, so every block takes the range
+    search instead."""
+    xyz, q, box = synth.random_box(3000, (20.0, 20.0, 20.0), seed=47)
+    compare("dense3000/" + _form(precision), xyz, q, box, 9.5, (20, 20, 20), tol[0], tol[1],
+            e_scale="parts", precision=precision)
+
+
+@pytest.mark.parametrize("precision,tol", FORMS)
 def test_terms_staged_in_chunks(precision, tol):
     """N = 4 on grids of 128 z points: a z-convolution block stages the columns
     of at most 2 terms at once (20 KiB of LDS), so it runs over two chunks of
