@@ -82,7 +82,7 @@ struct useries_plan_s {
     int* cl_col = nullptr;
     uint2* cl_z = nullptr;
     float4* fnear = nullptr;
-    double *pair_parts = nullptr, *far_parts = nullptr;
+    double *qpart = nullptr, *pair_parts = nullptr, *far_parts = nullptr;
     int* bpre = nullptr;
     int64_t bpre_cap = 0;
     // timing
@@ -106,6 +106,7 @@ struct useries_plan_s {
         hipFree(perm);
         hipFree(slots);
         hipFree(fnear);
+        hipFree(qpart);
         hipFree(bpre);
         bpre = nullptr;
         bpre_cap = 0;
@@ -115,6 +116,7 @@ struct useries_plan_s {
         cl_z = nullptr;
         pair_parts = nullptr;
         fnear = nullptr;
+        qpart = nullptr;
         cap = 0;
     }
 
@@ -128,6 +130,7 @@ struct useries_plan_s {
             (e = dalloc(&perm, c)) || (e = dalloc(&slots, c)) || (e = dalloc(&cl_info, clmax)) ||
             (e = dalloc(&cl_col, clmax)) || (e = dalloc(&cl_z, clmax)) ||
             (e = dalloc(&pair_parts, clmax)) || (e = dalloc(&fnear, c)) ||
+            (e = dalloc(&qpart, 2 * (size_t)((c + 255) / 256))) ||
             (bpre_ints(hp, c) > 0 && (e = dalloc(&bpre, (size_t)bpre_ints(hp, c))))) {
             free_atoms();
             return fail(USERIES_ENOMEM, std::string("workspace allocation: ") + hipGetErrorString(e));
@@ -321,7 +324,7 @@ int plan_device(useries_plan_t p) { return p->device; }
 // Byte offsets of the per-charge workspace of n charges in one contiguous
 // buffer (each array 256-byte aligned).
 struct AtomLayout {
-    size_t coord, sorted, perm, slots, cl_info, cl_col, cl_z, pair_parts, fnear, bpre, total;
+    size_t coord, sorted, perm, slots, cl_info, cl_col, cl_z, pair_parts, fnear, qpart, bpre, total;
 };
 
 static AtomLayout atom_layout(const HostPlan& hp, int64_t n) {
@@ -343,6 +346,7 @@ static AtomLayout atom_layout(const HostPlan& hp, int64_t n) {
     L.cl_z = take(8 * (size_t)clmax);
     L.pair_parts = take(8 * (size_t)clmax);
     L.fnear = take(16 * (size_t)c);
+    L.qpart = take(16 * (size_t)((c + 255) / 256));
     L.bpre = take(4 * (size_t)bpre_ints(hp, c));
     L.total = o;
     return L;
@@ -362,6 +366,7 @@ AtomWs atom_workspace_at(useries_plan_t p, int64_t n, char* base) {
     w.cl_z = (uint2*)(base + L.cl_z);
     w.pair_parts = (double*)(base + L.pair_parts);
     w.fnear = (float4*)(base + L.fnear);
+    w.qpart = (double*)(base + L.qpart);
     w.bpre_cap = bpre_ints(p->hp, std::max<int64_t>(n, 1));
     w.bpre = w.bpre_cap > 0 ? (int*)(base + L.bpre) : nullptr;
     return w;
@@ -391,6 +396,7 @@ int plan_eval(useries_plan_t p, int64_t n, const float* xyz, const float* q, flo
         own.cl_z = p->cl_z;
         own.pair_parts = p->pair_parts;
         own.fnear = p->fnear;
+        own.qpart = p->qpart;
         own.bpre = p->bpre;
         own.bpre_cap = p->bpre_cap;
     }
@@ -436,18 +442,20 @@ int plan_eval(useries_plan_t p, int64_t n, const float* xyz, const float* q, flo
     const float* ky = (const float*)p->ky;
     const float* kz = (const float*)p->kz;
     if (W.bpre && bin_local_ok(ni, ncol) && (int64_t)nq * (ncol + 1) <= W.bpre_cap) {
-        USERIES_STEP(0, st, launch_bin_local(hp.bin, xyz, q, W.coord, W.slots, W.bpre, st));
+        USERIES_STEP(0, st, launch_bin_local(hp.bin, xyz, q, W.coord, W.slots, W.bpre, W.qpart,
+                                             st));
         USERIES_STEP(5, st, launch_colbuild(ni, ncol, hp.bin.nc[0], hp.grid[2], npb, W.bpre,
                                             W.coord, W.slots, W.perm, W.sorted, W.cl_info,
-                                            W.cl_col, W.cl_z, p->zbin, q, p->qstats, st));
+                                            W.cl_col, W.cl_z, p->zbin, W.qpart, p->qstats, st));
     } else {
-        USERIES_STEP(1, st, launch_encode(hp.bin, xyz, q, W.coord, p->col_count, st));
+        USERIES_STEP(1, st, launch_encode(hp.bin, xyz, q, W.coord, p->col_count, W.qpart,
+                                          nq, st));
         if (!scan_fused(ni, ncol))
             USERIES_STEP(2, st, launch_scan(ncol, p->col_count, p->col_start, p->clus_start,
-                                            p->col_fill, ni, q, p->qstats, st));
+                                            p->col_fill, W.qpart, nq, p->qstats, st));
         USERIES_STEP(3, st, launch_scatter(hp.bin, W.coord, W.sorted, p->col_count,
-                                           p->col_start, p->clus_start, p->col_fill, W.slots, q,
-                                           p->qstats, st));
+                                           p->col_start, p->clus_start, p->col_fill, W.slots,
+                                           W.qpart, nq, p->qstats, st));
         USERIES_STEP(4, st, launch_colsort(ncol, hp.bin.nc[0], p->col_start, p->clus_start,
                                            W.slots, W.coord, W.perm, W.sorted, W.cl_info,
                                            W.cl_col, W.cl_z, hp.grid[2], p->zbin, p->col_count,

@@ -44,39 +44,12 @@ namespace useries {
 // column), then added to the global counters once per (block, column).
 constexpr int kHistCols = 4096;
 
-// Charge sums sum q and sum q^2 in FP64, in one fixed order whichever
-// binning sequence runs: thread t < 256 adds q[t], q[t + 256], ... in turn,
-// then the four wavefront sums (DPP) are added in order.  Every thread of
-// the block calls it (it holds a barrier); threads from 256 on only wait.
-__device__ __forceinline__ void qstats_direct(int n, const float* __restrict__ q,
-                                              double* __restrict__ qstats) {
-    __shared__ double qw[2][4];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    if (t < 256) {
-        double qa = 0.0, qb = 0.0;
-        for (int i = t; i < n; i += 256) {
-            const double v = (double)q[i];
-            qa += v;
-            qb += v * v;   // exact: a product of two floats
-        }
-        qa = wave_sum_d(qa);
-        qb = wave_sum_d(qb);
-        if (lane == 0) {
-            qw[0][wv] = qa;
-            qw[1][wv] = qb;
-        }
-    }
-    __syncthreads();
-    if (t == 0) {
-        qstats[0] = ((qw[0][0] + qw[0][1]) + qw[0][2]) + qw[0][3];
-        qstats[1] = ((qw[1][0] + qw[1][1]) + qw[1][2]) + qw[1][3];
-    }
-}
-
 __device__ __forceinline__ void encode_body(const BinArgs& a, int bid, const float* __restrict__ xyz,
                                             const float* __restrict__ q,
                                             uint4* __restrict__ coord,
-                                            int* __restrict__ col_count) {
+                                            int* __restrict__ col_count,
+                                            double* __restrict__ qpart) {
+    __shared__ double red[2][4];
     __shared__ int hist[kHistCols];
     const int ncol = a.nc[0] * a.nc[1];
     const bool local = ncol <= kHistCols;
@@ -84,6 +57,7 @@ __device__ __forceinline__ void encode_body(const BinArgs& a, int bid, const flo
         for (int k = threadIdx.x; k < ncol; k += 256) hist[k] = 0;
     __syncthreads();
     const int i = bid * 256 + threadIdx.x;
+    double qs = 0.0, q2 = 0.0;
     if (i < a.n) {
         uint32_t u[3];
 #pragma unroll
@@ -93,38 +67,54 @@ __device__ __forceinline__ void encode_body(const BinArgs& a, int bid, const flo
         coord[i] = make_uint4(u[0], u[1], u[2], __float_as_uint(qi));
         if (local) atomicAdd(&hist[c], 1);
         else atomicAdd(&col_count[c], 1);
+        qs = qi;
+        q2 = (double)qi * (double)qi;
     }
     __syncthreads();
     if (local)
         for (int k = threadIdx.x; k < ncol; k += 256)
             if (hist[k] > 0) atomicAdd(&col_count[k], hist[k]);
+    // charge sums: wavefront sums, then the 4 wavefront sums in order
+    qs = wave_sum_d(qs);
+    q2 = wave_sum_d(q2);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wv] = qs;
+        red[1][wv] = q2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        qpart[2 * bid] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+        qpart[2 * bid + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    }
 }
 
 __global__ void __launch_bounds__(256) k_encode(BinArgs a, const float* __restrict__ xyz,
                                                 const float* __restrict__ q,
                                                 uint4* __restrict__ coord,
-                                                int* __restrict__ col_count) {
-    encode_body(a, blockIdx.x, xyz, q, coord, col_count);
+                                                int* __restrict__ col_count,
+                                                double* __restrict__ qpart) {
+    encode_body(a, blockIdx.x, xyz, q, coord, col_count, qpart);
 }
 
 __global__ void __launch_bounds__(256) k_encode_batch(const BatchTable* __restrict__ tab,
                                                       const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_ENCODE, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        encode_body(d.bin, item, d.xyz, d.q, d.coord, d.col_count);
+        encode_body(d.bin, item, d.xyz, d.q, d.coord, d.col_count, d.qpart);
     });
 }
 
 // One block of 1024 threads: exclusive scans of the column counts and of the
 // cluster counts ceil(count / 8) (each thread owns a contiguous chunk;
 // wavefront scans by DPP lane moves, then a scan of the 16 wavefront totals), zero
-// the fill counters, and form the charge sums (qstats_direct).  The
+// the fill counters, and reduce the charge partials in a fixed order.  The
 // column counts are cleared once read, ready for the next evaluation (they
 // start at zero when the workspace is allocated).
 __device__ __forceinline__ void scan_body(int ncol, int* __restrict__ count,
                                           int* __restrict__ start, int* __restrict__ cstart,
-                                          int* __restrict__ fill, int n,
-                                          const float* __restrict__ q,
+                                          int* __restrict__ fill,
+                                          const double* __restrict__ qpart, int nqpart,
                                           double* __restrict__ qstats) {
     __shared__ int wsum[2][16];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -165,22 +155,34 @@ __device__ __forceinline__ void scan_body(int ncol, int* __restrict__ count,
         start[ncol] = run;
         cstart[ncol] = runc;
     }
-    qstats_direct(n, q, qstats);
+    if (wv == 1) {
+        double qa = 0.0, qb = 0.0;
+        for (int k = lane; k < nqpart; k += 64) {
+            qa += qpart[2 * k];
+            qb += qpart[2 * k + 1];
+        }
+        qa = wave_sum_d(qa);
+        qb = wave_sum_d(qb);
+        if (lane == 0) {
+            qstats[0] = qa;
+            qstats[1] = qb;
+        }
+    }
 }
 
 __global__ void __launch_bounds__(1024) k_scan(int ncol, int* __restrict__ count,
                                                int* __restrict__ start, int* __restrict__ cstart,
-                                               int* __restrict__ fill, int n,
-                                               const float* __restrict__ q,
+                                               int* __restrict__ fill,
+                                               const double* __restrict__ qpart, int nqpart,
                                                double* __restrict__ qstats) {
-    scan_body(ncol, count, start, cstart, fill, n, q, qstats);
+    scan_body(ncol, count, start, cstart, fill, qpart, nqpart, qstats);
 }
 
 __global__ void __launch_bounds__(1024) k_scan_batch(const BatchTable* __restrict__ tab,
                                                      const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_SCAN, [&](int i, int) {
         const BoxDesc& d = desc[tab->slot[i]];
-        scan_body(d.ncol, d.col_count, d.col_start, d.clus_start, d.col_fill, d.bin.n, d.q,
+        scan_body(d.ncol, d.col_count, d.col_start, d.clus_start, d.col_fill, d.qpart, d.nq,
                   d.qstats);
     });
 }
@@ -193,7 +195,7 @@ __global__ void __launch_bounds__(1024) k_scan_batch(const BatchTable* __restric
 // block first takes the exclusive prefix sums of the column counts (256
 // threads, a contiguous run of at most kHistCols / 256 columns each) as its
 // column starts; block 0 also writes them, the cluster starts and the charge
-// sums (qstats_direct), in place of the scan kernel.
+// sums, in place of the scan kernel.
 constexpr int kPrefixRun = kHistCols / 256;
 
 __device__ __forceinline__ void scatter_body(const BinArgs& a, int bid, bool fused,
@@ -202,7 +204,7 @@ __device__ __forceinline__ void scatter_body(const BinArgs& a, int bid, bool fus
                                              const int* __restrict__ count,
                                              int* __restrict__ start, int* __restrict__ cstart,
                                              int* __restrict__ fill, int* __restrict__ slots,
-                                             const float* __restrict__ q,
+                                             const double* __restrict__ qpart, int nqpart,
                                              double* __restrict__ qstats) {
     __shared__ int hist[kHistCols];
     __shared__ int base[kHistCols];
@@ -254,6 +256,19 @@ __device__ __forceinline__ void scatter_body(const BinArgs& a, int bid, bool fus
             start[ncol] = run;
             cstart[ncol] = runc;
         }
+        if (bid == 0 && wv == 1) {
+            double qa = 0.0, qb = 0.0;
+            for (int k = lane; k < nqpart; k += 64) {
+                qa += qpart[2 * k];
+                qb += qpart[2 * k + 1];
+            }
+            qa = wave_sum_d(qa);
+            qb = wave_sum_d(qb);
+            if (lane == 0) {
+                qstats[0] = qa;
+                qstats[1] = qb;
+            }
+        }
     }
     __syncthreads();
     int r = 0;
@@ -268,7 +283,6 @@ __device__ __forceinline__ void scatter_body(const BinArgs& a, int bid, bool fus
         slots[slot] = i;
         sorted[slot] = rec;
     }
-    if (fused && bid == 0) qstats_direct(n, q, qstats);
 }
 
 __global__ void __launch_bounds__(256) k_scatter(BinArgs a, int fused,
@@ -277,10 +291,10 @@ __global__ void __launch_bounds__(256) k_scatter(BinArgs a, int fused,
                                                  const int* __restrict__ count,
                                                  int* __restrict__ start, int* __restrict__ cstart,
                                                  int* __restrict__ fill, int* __restrict__ slots,
-                                                 const float* __restrict__ q,
+                                                 const double* __restrict__ qpart, int nqpart,
                                                  double* __restrict__ qstats) {
-    scatter_body(a, blockIdx.x, fused != 0, coord, sorted, count, start, cstart, fill, slots, q,
-                 qstats);
+    scatter_body(a, blockIdx.x, fused != 0, coord, sorted, count, start, cstart, fill, slots,
+                 qpart, nqpart, qstats);
 }
 
 __global__ void __launch_bounds__(256) k_scatter_batch(const BatchTable* __restrict__ tab,
@@ -288,7 +302,7 @@ __global__ void __launch_bounds__(256) k_scatter_batch(const BatchTable* __restr
     batch_for(tab, BK_SCATTER, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
         scatter_body(d.bin, item, false, d.coord, d.sorted, d.col_count, d.col_start,
-                     d.clus_start, d.col_fill, d.slots, d.q, d.qstats);
+                     d.clus_start, d.col_fill, d.slots, d.qpart, d.nq, d.qstats);
     });
 }
 
@@ -465,14 +479,16 @@ bool bin_local_ok(int n, int ncol) {
 // Block b: the records (fixed-point position and charge bits) of charges
 // 256 b .. 256 b + 255, grouped by column into coord[256 b ...] with their
 // input indices in slots[...] (order within a column as the LDS atomics
-// leave it) and the block's exclusive column prefix in bpre[b][0 .. ncol]
-// (bpre[b][ncol]: its charge count).
+// leave it), the block's exclusive column prefix in bpre[b][0 .. ncol]
+// (bpre[b][ncol]: its charge count) and its charge sums in qpart.
 __device__ __forceinline__ void bin_local_body(const BinArgs& a, int b, const float* __restrict__ xyz,
                                                const float* __restrict__ q,
                                                uint4* __restrict__ coord,
-                                               int* __restrict__ slots, int* __restrict__ bpre) {
+                                               int* __restrict__ slots, int* __restrict__ bpre,
+                                               double* __restrict__ qpart) {
     __shared__ int hist[kHistCols];
     __shared__ int wsum[4];
+    __shared__ double red[2][4];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int ncol = a.nc[0] * a.nc[1];
     for (int k = t; k < ncol; k += 256) hist[k] = 0;
@@ -480,6 +496,7 @@ __device__ __forceinline__ void bin_local_body(const BinArgs& a, int b, const fl
     const int i = b * 256 + t;
     uint4 rec = make_uint4(0, 0, 0, 0);
     int c = 0, r = 0;
+    double qs = 0.0, q2 = 0.0;
     if (i < a.n) {
         uint32_t u[3];
 #pragma unroll
@@ -488,6 +505,8 @@ __device__ __forceinline__ void bin_local_body(const BinArgs& a, int b, const fl
         c = cell_coord(u[1], a.nc[1]) * a.nc[0] + cell_coord(u[0], a.nc[0]);
         rec = make_uint4(u[0], u[1], u[2], __float_as_uint(qi));
         r = atomicAdd(&hist[c], 1);   // rank within the block's charges of column c
+        qs = qi;
+        q2 = (double)qi * (double)qi;
     }
     __syncthreads();
     // exclusive prefix of the block's column counts: thread t owns the run of
@@ -522,6 +541,18 @@ __device__ __forceinline__ void bin_local_body(const BinArgs& a, int b, const fl
         coord[slot] = rec;
         slots[slot] = i;
     }
+    // charge sums: wavefront sums, then the 4 wavefront sums in order
+    qs = wave_sum_d(qs);
+    q2 = wave_sum_d(q2);
+    if (lane == 0) {
+        red[0][wv] = qs;
+        red[1][wv] = q2;
+    }
+    __syncthreads();
+    if (t == 0) {
+        qpart[2 * b] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+        qpart[2 * b + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    }
 }
 
 // Block c (column c): from P[b][c] and P[b][c + 1] of the nb bin_local blocks,
@@ -531,13 +562,33 @@ __device__ __forceinline__ void bin_local_body(const BinArgs& a, int b, const fl
 // segoff[b + 1]), sorted by (z, input index) -- up to 256 by counting ranks,
 // up to kSortCap by a bitonic sort in LDS, beyond by ranking from global
 // memory -- and written with the column's z-plane index and clusters.
+// reduce_q: this block also reduces the charge sums (qstats_reduce).
+__device__ __forceinline__ void qstats_reduce(int nb, const double* __restrict__ qpart,
+                                              double* __restrict__ qstats) {
+    const int lane = threadIdx.x & 63;
+    double qa = 0.0, qb = 0.0;
+    for (int k = lane; k < nb; k += 64) {
+        qa += qpart[2 * k];
+        qb += qpart[2 * k + 1];
+    }
+    qa = wave_sum_d(qa);
+    qb = wave_sum_d(qb);
+    if (lane == 0) {
+        qstats[0] = qa;
+        qstats[1] = qb;
+    }
+}
+
 __device__ __forceinline__ void colbuild_body(int col, int nb, int ncol, int ncx, int gz, int npb,
+                                              bool reduce_q,
                                               const int* __restrict__ bpre,
                                               const uint4* __restrict__ coord,
                                               const int* __restrict__ slots,
                                               int* __restrict__ perm, uint4* __restrict__ sorted,
                                               int2* __restrict__ cl_info, int* __restrict__ cl_col,
-                                              uint2* __restrict__ cl_z, int* __restrict__ zbin) {
+                                              uint2* __restrict__ cl_z, int* __restrict__ zbin,
+                                              const double* __restrict__ qpart,
+                                              double* __restrict__ qstats) {
     __shared__ int segoff[kLocalBlocks + 1];
     __shared__ int segbase[kLocalBlocks];      // slot of list position k: segbase[b] + k
     __shared__ unsigned long long key[kSortCap];
@@ -585,6 +636,7 @@ __device__ __forceinline__ void colbuild_body(int col, int nb, int ncol, int ncx
         }
     }
     if (t == 0) segoff[nb] = cnt;
+    if (reduce_q && wv == 1) qstats_reduce(nb, qpart, qstats);
 
     // cluster numbers: this column's from floor(lo / 8) + col, the next
     // column's from floor((lo + cnt) / 8) + col + 1 (the last column's run to
@@ -735,8 +787,9 @@ __global__ void __launch_bounds__(256) k_bin_local(BinArgs a, const float* __res
                                                    const float* __restrict__ q,
                                                    uint4* __restrict__ coord,
                                                    int* __restrict__ slots,
-                                                   int* __restrict__ bpre) {
-    bin_local_body(a, blockIdx.x, xyz, q, coord, slots, bpre);
+                                                   int* __restrict__ bpre,
+                                                   double* __restrict__ qpart) {
+    bin_local_body(a, blockIdx.x, xyz, q, coord, slots, bpre, qpart);
 }
 
 __global__ void __launch_bounds__(256) k_colbuild(int nb, int ncol, int ncx, int gz, int npb,
@@ -748,36 +801,33 @@ __global__ void __launch_bounds__(256) k_colbuild(int nb, int ncol, int ncx, int
                                                   int2* __restrict__ cl_info,
                                                   int* __restrict__ cl_col,
                                                   uint2* __restrict__ cl_z,
-                                                  int* __restrict__ zbin, int n,
-                                                  const float* __restrict__ q,
+                                                  int* __restrict__ zbin,
+                                                  const double* __restrict__ qpart,
                                                   double* __restrict__ qstats) {
-    // block ncol (one past the columns) forms the charge sums, beside the columns
+    // block ncol (one past the columns) reduces the charge sums, beside the columns
     if (blockIdx.x == ncol) {
-        qstats_direct(n, q, qstats);
+        if (threadIdx.x < 64) qstats_reduce(nb, qpart, qstats);
         return;
     }
-    colbuild_body(blockIdx.x, nb, ncol, ncx, gz, npb, bpre, coord, slots, perm, sorted, cl_info,
-                  cl_col, cl_z, zbin);
+    colbuild_body(blockIdx.x, nb, ncol, ncx, gz, npb, false, bpre, coord, slots, perm, sorted,
+                  cl_info, cl_col, cl_z, zbin, qpart, qstats);
 }
 
 __global__ void __launch_bounds__(256) k_bin_local_batch(const BatchTable* __restrict__ tab,
                                                          const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_BINLOCAL, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        bin_local_body(d.bin, item, d.xyz, d.q, d.coord, d.slots, d.bpre);
+        bin_local_body(d.bin, item, d.xyz, d.q, d.coord, d.slots, d.bpre, d.qpart);
     });
 }
 
 __global__ void __launch_bounds__(256) k_colbuild_batch(const BatchTable* __restrict__ tab,
                                                         const BoxDesc* __restrict__ desc) {
-    // items 0 .. ncol - 1: the columns; item ncol: the charge sums
     batch_for(tab, BK_COLBUILD, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        if (item == d.ncol)
-            qstats_direct(d.bin.n, d.q, d.qstats);
-        else
-            colbuild_body(item, d.nq, d.ncol, d.bin.nc[0], d.grid.g[2], d.npb, d.bpre, d.coord,
-                          d.slots, d.perm, d.sorted, d.cl_info, d.cl_col, d.cl_z, d.zbin);
+        colbuild_body(item, d.nq, d.ncol, d.bin.nc[0], d.grid.g[2], d.npb, item == 0, d.bpre,
+                      d.coord, d.slots, d.perm, d.sorted, d.cl_info, d.cl_col, d.cl_z, d.zbin,
+                      d.qpart, d.qstats);
     });
 }
 
@@ -794,35 +844,37 @@ hipError_t launch_colbuild_batch(const BatchTable* tab, const BoxDesc* desc, int
 }
 
 hipError_t launch_bin_local(const BinArgs& a, const float* xyz, const float* q, uint4* coord,
-                            int* slots, int* bpre, hipStream_t st) {
+                            int* slots, int* bpre, double* qpart, hipStream_t st) {
     const int nb = (a.n + 255) / 256;
     if (nb > 0)
-        hipLaunchKernelGGL(k_bin_local, dim3(nb), dim3(256), 0, st, a, xyz, q, coord, slots, bpre);
+        hipLaunchKernelGGL(k_bin_local, dim3(nb), dim3(256), 0, st, a, xyz, q, coord, slots, bpre,
+                           qpart);
     return hipGetLastError();
 }
 
 hipError_t launch_colbuild(int n, int ncol, int ncx, int gz, int npb, const int* bpre,
                            const uint4* coord, const int* slots, int* perm, uint4* sorted,
-                           int2* cl_info, int* cl_col, uint2* cl_z, int* zbin, const float* q,
-                           double* qstats, hipStream_t st) {
+                           int2* cl_info, int* cl_col, uint2* cl_z, int* zbin,
+                           const double* qpart, double* qstats, hipStream_t st) {
     const int nb = (n + 255) / 256;
     hipLaunchKernelGGL(k_colbuild, dim3(ncol + 1), dim3(256), 0, st, nb, ncol, ncx, gz, npb, bpre,
-                       coord, slots, perm, sorted, cl_info, cl_col, cl_z, zbin, n, q, qstats);
+                       coord, slots, perm, sorted, cl_info, cl_col, cl_z, zbin, qpart, qstats);
     return hipGetLastError();
 }
 
 hipError_t launch_encode(const BinArgs& a, const float* xyz, const float* q, uint4* coord,
-                         int* col_count, hipStream_t st) {
+                         int* col_count, double* qpart, int nqpart, hipStream_t st) {
     if (a.n > 0)
-        hipLaunchKernelGGL(k_encode, dim3((a.n + 255) / 256), dim3(256), 0, st, a, xyz, q, coord,
-                           col_count);
+        hipLaunchKernelGGL(k_encode, dim3(nqpart), dim3(256), 0, st, a, xyz, q, coord, col_count,
+                           qpart);
     return hipGetLastError();
 }
 
 hipError_t launch_scan(int ncol, int* col_count, int* col_start, int* clus_start,
-                       int* col_fill, int n, const float* q, double* qstats, hipStream_t st) {
+                       int* col_fill, const double* qpart, int nqpart, double* qstats,
+                       hipStream_t st) {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, ncol, col_count, col_start, clus_start,
-                       col_fill, n, q, qstats);
+                       col_fill, qpart, nqpart, qstats);
     return hipGetLastError();
 }
 
@@ -833,14 +885,15 @@ bool scan_fused(int n, int ncol) {
 
 hipError_t launch_scatter(const BinArgs& a, const uint4* coord, uint4* sorted, const int* col_count,
                           int* col_start, int* clus_start, int* col_fill, int* slots,
-                          const float* q, double* qstats, hipStream_t st) {
+                          const double* qpart, int nqpart, double* qstats, hipStream_t st) {
     const int n = a.n, ncol = a.nc[0] * a.nc[1];
     const int fused = scan_fused(n, ncol) ? 1 : 0;
     // with no charges the fused prefix still has to run once (all columns empty)
     const int nb = std::max(1, (n + 255) / 256);
     if (n > 0 || fused)
         hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, st, a, fused, coord, sorted,
-                           col_count, col_start, clus_start, col_fill, slots, q, qstats);
+                           col_count, col_start, clus_start, col_fill, slots, qpart, nqpart,
+                           qstats);
     return hipGetLastError();
 }
 

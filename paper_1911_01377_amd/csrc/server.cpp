@@ -89,7 +89,7 @@ private:
 // forces, energies: one copy); the slot's pinned staging mirrors that prefix.
 struct Layout {
     size_t q, mat[3], col_count, xyz, forces, energies, up_bytes, prefix, coord, sorted, perm,
-        slots, cl_info, cl_col, cl_z, fnear, pair_parts, far_parts, qstats, col_start,
+        slots, cl_info, cl_col, cl_z, fnear, qpart, pair_parts, far_parts, qstats, col_start,
         col_fill, clus_start, bpre, zbin, rho, tgrid, phi, total;
 };
 
@@ -121,6 +121,7 @@ Layout make_layout(const HostPlan& hp, int n, int n_evals) {
     L.cl_col = take(4 * clmax);
     L.cl_z = take(8 * clmax);
     L.fnear = take(16 * c);
+    L.qpart = take(16 * ((c + 255) / 256));
     L.pair_parts = take(8 * clmax);
     L.far_parts = take(8 * (size_t)far_parts(hp.conv));
     L.qstats = take(16);
@@ -351,6 +352,7 @@ struct useries_server_s {
         d.cl_info = (int2*)(base + L.cl_info);
         d.cl_z = (uint2*)(base + L.cl_z);
         d.fnear = (float4*)(base + L.fnear);
+        d.qpart = (double*)(base + L.qpart);
         d.pair_parts = (double*)(base + L.pair_parts);
         d.far_parts = (double*)(base + L.far_parts);
         d.qstats = (double*)(base + L.qstats);
@@ -741,7 +743,7 @@ int useries_submit(useries_server_t S, const useries_request* req, uint64_t* tic
     R->local = bin_local_ok(n, ncol);
     if (R->local) {
         R->items[BK_BINLOCAL] = nq;
-        R->items[BK_COLBUILD] = ncol + 1;   // the columns, then the charge sums
+        R->items[BK_COLBUILD] = ncol;
     } else {
         R->items[BK_ENCODE] = nq;
         R->items[BK_SCAN] = 1;

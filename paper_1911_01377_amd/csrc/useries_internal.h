@@ -225,7 +225,7 @@ struct BoxDesc {
     int2* cl_info;
     uint2* cl_z;
     float4* fnear;
-    double *pair_parts, *far_parts, *qstats;
+    double *qpart, *pair_parts, *far_parts, *qstats;
     int *col_count, *col_start, *col_fill, *clus_start;
     int* bpre;                 // two-launch binning's block prefixes (NULL: four launches)
     int* zbin;                 // [ncol][g_z + 1]: first charge of each grid z-plane per column
@@ -279,6 +279,7 @@ struct AtomWs {
     uint2* cl_z = nullptr;
     double* pair_parts = nullptr;
     float4* fnear = nullptr;
+    double* qpart = nullptr;
     int* bpre = nullptr;       // per-block column prefixes of two-launch binning
     int64_t bpre_cap = 0;      // ints available there (0: four-launch binning only)
 };
@@ -296,13 +297,11 @@ int plan_device(useries_plan_t p);
 
 // ------------------------------------------------------------ kernel launchers
 // All launchers enqueue on `st` and return hipGetLastError().
-// Every binning sequence forms the charge sums qstats = {sum q, sum q^2} from
-// q in one fixed order (so that every path gives the same bits): scan, or
-// scatter's block 0 when scan_fused, or colbuild's extra block.
 hipError_t launch_encode(const BinArgs& a, const float* xyz, const float* q, uint4* coord,
-                         int* col_count, hipStream_t st);
+                         int* col_count, double* qpart, int nqpart, hipStream_t st);
 hipError_t launch_scan(int ncol, int* col_count, int* col_start, int* clus_start,
-                       int* col_fill, int n, const float* q, double* qstats, hipStream_t st);
+                       int* col_fill, const double* qpart, int nqpart, double* qstats,
+                       hipStream_t st);
 // true when scatter takes the column offsets itself (no scan launch): the
 // counts fit in its LDS and every block can afford to read them
 bool scan_fused(int n, int ncol);
@@ -310,7 +309,7 @@ bool scan_fused(int n, int ncol);
 // column order (colsort then sorts each column in place)
 hipError_t launch_scatter(const BinArgs& a, const uint4* coord, uint4* sorted, const int* col_count,
                           int* col_start, int* clus_start, int* col_fill, int* slots,
-                          const float* q, double* qstats, hipStream_t st);
+                          const double* qpart, int nqpart, double* qstats, hipStream_t st);
 // also clears col_count and col_fill of the ncol columns
 // cl_col holds each cluster's column as cx | cy << 16 (ncx columns along x);
 // cluster numbers from the last cluster to npb get a count of 0
@@ -326,11 +325,11 @@ hipError_t launch_colsort(int ncol, int ncx, const int* col_start, const int* cl
 // charge) and every other number below npb has a count of 0.
 bool bin_local_ok(int n, int ncol);
 hipError_t launch_bin_local(const BinArgs& a, const float* xyz, const float* q, uint4* coord,
-                            int* slots, int* bpre, hipStream_t st);
+                            int* slots, int* bpre, double* qpart, hipStream_t st);
 hipError_t launch_colbuild(int n, int ncol, int ncx, int gz, int npb, const int* bpre,
                            const uint4* coord, const int* slots, int* perm, uint4* sorted,
-                           int2* cl_info, int* cl_col, uint2* cl_z, int* zbin, const float* q,
-                           double* qstats, hipStream_t st);
+                           int2* cl_info, int* cl_col, uint2* cl_z, int* zbin,
+                           const double* qpart, double* qstats, hipStream_t st);
 // one block per cluster number below nblocks (those with a count of 0 only
 // write a zero energy part)
 hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted,
