@@ -429,6 +429,22 @@ def test_repulsion_kernel_alpha12(precision, tol):
             alpha=12, precision=precision)
 
 
+@pytest.mark.parametrize("alpha", [6, 12])
+def test_power_kernels_in_a_non_cubic_cell(alpha):
+    """1/r^6 and 1/r^12 (App. A) in a 22 x 24 x 26 A cell: the three axes
+    have different fixed-point scales, so the pair kernel scales each
+    distance component to A with its own hi/lo scale pair (the cubic path
+    keeps them in units); random positive coefficients, both forms, against
+    the oracle."""
+    rng = np.random.default_rng(70 + alpha)
+    box = (22.0, 24.0, 26.0)
+    xyz = (rng.uniform(0, 1, (900, 3)) * np.array(box)).astype(np.float32)
+    c = rng.uniform(0.2, 1.5, 900).astype(np.float32)
+    for precision, tol in FORMS:
+        compare("noncubic900/r^-%d/%s" % (alpha, _form(precision)), xyz, c, box, 9.0, (24, 24, 27),
+                tol[0], tol[1], alpha=alpha, precision=precision)
+
+
 def test_repulsion_lattice_forces_vanish():
     """Identical coefficients on a simple-cubic lattice (64 sites, spacing
     2 A): the 1/r^12 forces vanish by symmetry and the energy matches the
