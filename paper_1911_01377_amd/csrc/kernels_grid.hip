@@ -12,9 +12,9 @@
 //   x-y columns that can hold a charge touching the brick, each contributing
 //   the charges of the brick's z-planes (per-column z-plane index); the block
 //   keeps those that touch it, stages their weights in LDS and accumulates the
-//   brick in registers, lane (y, z) owning one grid row of 8 points, each
-//   wavefront a share of the staged charges; the partial bricks are summed in
-//   a fixed order.  No atomics.
+//   brick in registers, a lane owning 2 x 2 x 2 of its points, each wavefront
+//   a share of the staged charges; the partial bricks are summed in a fixed
+//   order.  No atomics.
 // gather: one block per brick with the potential on the brick and its halo in
 //   LDS; each charge is evaluated by the block whose brick holds its stencil
 //   anchor, 8 or 16 lanes per charge.  One more block forms the energy total.
@@ -299,7 +299,7 @@ constexpr int kGatherThreads = 64 * kGatherWaves;
 constexpr int kGatherBatch = 8;           // halo loads issued together per thread
 constexpr int kGatherOwners = 8;          // owners per wavefront pass, at most
 
-__host__ __device__ inline int gather_brick(int P) { return P <= 5 ? 8 : 4; }
+__host__ __device__ constexpr int gather_brick(int P) { return P <= 5 ? 8 : 4; }
 
 // Dynamic LDS of a gather block for stencil half width P (byte offsets): the
 // halo of edge brick + 2P - 1 and the per-owner weights are sized by P.
@@ -363,8 +363,24 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
     // approximate reciprocals: (idx + 1/2) / E stays 1 / (2E) from an integer
     const float inv0 = __builtin_amdgcn_rcpf((float)E0), inv1 = __builtin_amdgcn_rcpf((float)E1);
     const int nh = E0 * E1 * E2;
-    // the loads of a pass are issued together, then stored
-    for (int base = tid; base < nh; base += kGatherThreads * kGatherBatch) {
+    // columns overlapping the brick's cells in x and y (at most one per
+    // thread): the charge range of the brick's z-planes in each, loaded first
+    // so that these loads are in flight with the halo's
+    static_assert(kGatherMaxPieces <= kGatherThreads, "one column per thread");
+    const int cxl = X0 * a.nc[0] / a.g[0], cxh = ((X0 + B0) * a.nc[0] + a.g[0] - 1) / a.g[0] - 1;
+    const int cyl = Y0 * a.nc[1] / a.g[1], cyh = ((Y0 + B1) * a.nc[1] + a.g[1] - 1) / a.g[1] - 1;
+    const int cxn = cxh - cxl + 1, np = cxn * (cyh - cyl + 1);
+    int zb = 0, ze = 0;
+    if (tid < np) {
+        const int col = (cyl + tid / cxn) * a.nc[0] + cxl + tid % cxn;
+        const int* zr = zbin + (size_t)col * (a.g[2] + 1);
+        zb = zr[Z0];
+        ze = zr[Z0 + B2];
+    }
+    // the loads of a pass are issued together, then stored; a compile-time
+    // stencil gives a fixed number of passes (unrolled, so the column loads
+    // above stay in flight with the first pass's)
+    auto halo_pass = [&](int base) {
         float v[kGatherBatch];
 #pragma unroll
         for (int u = 0; u < kGatherBatch; ++u) {
@@ -381,22 +397,23 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
             const int idx = base + kGatherThreads * u;
             if (idx < nh) sphi[idx] = v[u];
         }
+    };
+    constexpr int kPass = kGatherThreads * kGatherBatch;
+    if constexpr (PT > 0) {
+        constexpr int EM = gather_brick(PT) + 2 * PT - 1;   // edge of a whole brick's halo
+#pragma unroll
+        for (int ps = 0; ps < (EM * EM * EM + kPass - 1) / kPass; ++ps) halo_pass(tid + ps * kPass);
+    } else {
+        for (int base = tid; base < nh; base += kPass) halo_pass(base);
     }
     // stencil rows (ky, kz) of a charge and their offsets in the halo, once per block
     for (int r = tid; r < P2 * P2; r += kGatherThreads) {
         const int ky = r % P2, kz = r / P2;
         rowtab[r] = make_int2((kz * E1 + ky) * E0, ky | (kz << 16));
     }
-    // columns overlapping the brick's cells in x and y
-    const int cxl = X0 * a.nc[0] / a.g[0], cxh = ((X0 + B0) * a.nc[0] + a.g[0] - 1) / a.g[0] - 1;
-    const int cyl = Y0 * a.nc[1] / a.g[1], cyh = ((Y0 + B1) * a.nc[1] + a.g[1] - 1) / a.g[1] - 1;
-    const int cxn = cxh - cxl + 1, np = cxn * (cyh - cyl + 1);
-    for (int k = tid; k < np; k += kGatherThreads) {
-        const int col = (cyl + k / cxn) * a.nc[0] + cxl + k % cxn;
-        const int* zr = zbin + (size_t)col * (a.g[2] + 1);
-        const int b = zr[Z0];
-        pbeg[k] = b;
-        poff[k + 1] = zr[Z0 + B2] - b;
+    if (tid < np) {
+        pbeg[tid] = zb;
+        poff[tid + 1] = ze - zb;
     }
     __syncthreads();
     {
