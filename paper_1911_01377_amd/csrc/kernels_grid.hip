@@ -191,11 +191,20 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
             before += v < w ? wtot[v] : 0;
             nst += wtot[v];
         }
-        if (touch) {
-            // the 3 x 8 brick weights of the charge: zero, then the 2P stencil
-            // points of each axis at their brick positions (k - k0) mod g
-            const int slot = before + __popcll(m & ((1ull << lane) - 1ull));
-            float* row = sw[slot];
+        // the touching charges' records, compacted: record s in the first 16
+        // bytes of weight row s
+        if (touch) *reinterpret_cast<uint4*>(sw[before + lanes_below(m)]) = c;
+        __syncthreads();
+        if (tid < nst) {
+            // thread s: the 3 x 8 brick weights of staged charge s (row s is
+            // its own until the next barrier): zero, then the 2P stencil points
+            // of each axis at their brick positions (k - k0) mod g
+            float* row = sw[tid];
+            const uint4 cs = *reinterpret_cast<const uint4*>(row);
+            grid_coord(cs.x, a.g[0], &gi[0], &f[0]);
+            grid_coord(cs.y, a.g[1], &gi[1], &f[1]);
+            grid_coord(cs.z, a.g[2], &gi[2], &f[2]);
+            qj = __uint_as_float(cs.w);
 #pragma unroll
             for (int b = 0; b < 3 * kBrick; b += 4)
                 *reinterpret_cast<float4*>(row + b) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
