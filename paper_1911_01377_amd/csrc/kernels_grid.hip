@@ -12,9 +12,10 @@
 //   x-y columns that can hold a charge touching the brick, each contributing
 //   the charges of the brick's z-planes (per-column z-plane index); the block
 //   keeps those that touch it, stages their weights in LDS and accumulates the
-//   brick in registers, a lane owning 2 x 2 x 2 of its points, each wavefront
-//   a share of the staged charges; the partial bricks are summed in a fixed
-//   order.  No atomics.
+//   brick in registers by x halves, four wavefronts per half, a lane owning a
+//   4-point x row of it; each wavefront takes a share of the charges that
+//   touch its half, and the partial sums are added in a fixed order.  No
+//   atomics.
 // gather: one block per brick with the potential on the brick and its halo in
 //   LDS; each charge is evaluated by the block whose brick holds its stencil
 //   anchor, 8 or 16 lanes per charge.  One more block forms the energy total.
@@ -63,10 +64,13 @@ __device__ __forceinline__ void cell_window(int X0, int bn, int P, int g, int nc
 // [Z0 - P, Z0 + B2 + P - 2] (periodic), read from each column's z-plane index
 // as at most two contiguous charge ranges.  The block loads the candidates in
 // chunks of one per thread, keeps those whose stencil touches the brick
-// (compacted in thread order, so the order is deterministic), stages their
-// 3 x 8 weights in LDS, and wavefront w accumulates the staged charges w, w + W, ...
-// (W wavefronts) into its partial brick; the partial bricks are summed in a
-// fixed order at the end.
+// (compacted in thread order within three classes: those meeting only the x
+// half 0 (x 0..3), both halves, only half 1 -- so the order is deterministic
+// and each half's charges are one contiguous run), stages their 3 x 8 weights
+// in LDS, and wavefront 4 h + u accumulates every fourth of half h's charges
+// from the u-th into its partial half brick (a dense 4 x 8 x 8 product per
+// charge, one fewer half for the ~30% of charges that meet only one); the
+// four partials of each point are summed in a fixed order at the end.
 // PT > 0: the stencil half width as a compile-time constant; PT = 0 takes it
 // from a.P.
 template <int PT>
@@ -76,17 +80,18 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
                                             const double* __restrict__ qstats,
                                             float* __restrict__ rho) {
     __shared__ __align__(16) float sw[kSpreadChunk][3 * kBrick];   // rows of 96 B (16-byte stores)
-    static_assert(kSpreadWaves * kBrick * 64 <= kSpreadChunk * 3 * kBrick, "red fits in sw");
-    static_assert(kSpreadWaves == kBrick && kBrick == 8, "one wavefront per x plane; 8-wide rows");
-    // the wavefronts' partial bricks, summed after the last chunk (reuses sw)
-    float (*red)[kBrick][64] = reinterpret_cast<float (*)[kBrick][64]>(&sw[0][0]);
+    static_assert(kSpreadWaves == 8 && kBrick == 8, "four wavefronts per half brick; 8-wide rows");
+    // the wavefronts' partial half bricks, summed after the last chunk (reuses sw)
+    float (*red)[4][64] = reinterpret_cast<float (*)[4][64]>(&sw[0][0]);
     __shared__ int pbeg[2 * kMaxWindowCols];       // first charge of each column piece
     __shared__ int poff[2 * kMaxWindowCols + 1];   // prefix sums of the piece lengths
     __shared__ int wtot[kSpreadWaves];
+    __shared__ int wcat[3][kSpreadWaves];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    // lane's 2 x 2 x 2 points of the brick: x 2cx + dx, y 2cy + dy, z 2cz + dz;
-    // its partial sums acc[dx + 2 dy + 4 dz]
-    const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
+    // wavefronts 4 h .. 4 h + 3 accumulate the x half h of the brick
+    // (x 4 h .. 4 h + 3); lane (y, z) owns the four points of that row,
+    // partial sums acc[x - 4 h]
+    const int hx = w >> 2, ly = lane & 7, lz = lane >> 3;
     // the grid mean of the charge (removed at the end), loaded first
     const float mean = (float)(qstats[0] * a.inv_ngrid);
     const int nbx = (a.g[0] + kBrick - 1) / kBrick, nby = (a.g[1] + kBrick - 1) / kBrick;
@@ -145,9 +150,7 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
     const int X0s[3] = {X0, Y0, Z0};
     const int Bs[3] = {B0, B1, B2};
 
-    float acc[kBrick];
-#pragma unroll
-    for (int b = 0; b < kBrick; ++b) acc[b] = 0.0f;
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 
     // candidate t of the window (loads are issued one chunk ahead)
     auto fetch = [&](int t) {
@@ -166,6 +169,7 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
     for (int base = 0; base < total; base += kSpreadChunk) {
         const int t = base + tid;
         bool touch = false;
+        int cat = 0;
         int gi[3];
         float f[3];
         float qj = 0.0f;
@@ -177,23 +181,39 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
             grid_coord(c.z, a.g[2], &gi[2], &f[2]);
             qj = __uint_as_float(c.w);
             touch = true;
+            int d[3];   // last stencil point's brick position (first: d - 2P + 1)
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax)
-                touch = touch && wrap1(gi[ax] - (X0s[ax] - P), a.g[ax]) <= Bs[ax] + 2 * P - 2;
+            for (int ax = 0; ax < 3; ++ax) {
+                d[ax] = wrap1(gi[ax] - (X0s[ax] - P), a.g[ax]);
+                touch = touch && d[ax] <= Bs[ax] + 2 * P - 2;
+            }
+            // x halves met: 0 (x 0..3) only, both, 1 (x 4 .. B0 - 1) only
+            const bool h0 = d[0] - 2 * P + 1 <= 3, h1 = d[0] >= 4 && B0 > 4;
+            cat = h0 ? (h1 ? 1 : 0) : 2;
         }
-        // compaction in thread order
-        const uint64_t m = __ballot(touch);
-        if (lane == 0) wtot[w] = __popcll(m);
+        // compaction in thread order within each x-half class, the classes
+        // one after the other: half 0's charges are rows [0, n0 + n01), half
+        // 1's rows [n0, nst)
+        const uint64_t mc[3] = {__ballot(touch && cat == 0), __ballot(touch && cat == 1),
+                                __ballot(touch && cat == 2)};
+        if (lane < 3) wcat[lane][w] = __popcll(lane == 0 ? mc[0] : lane == 1 ? mc[1] : mc[2]);
         __syncthreads();
-        int before = 0, nst = 0;
+        int ncat[3] = {0, 0, 0}, bcat[3] = {0, 0, 0};
 #pragma unroll
-        for (int v = 0; v < kSpreadWaves; ++v) {
-            before += v < w ? wtot[v] : 0;
-            nst += wtot[v];
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int v = 0; v < kSpreadWaves; ++v) {
+                bcat[k] += v < w ? wcat[k][v] : 0;
+                ncat[k] += wcat[k][v];
+            }
+        const int nst = ncat[0] + ncat[1] + ncat[2];
+        // the touching charges' records: record s in the first 16 bytes of
+        // weight row s
+        if (touch) {
+            const int cb = cat == 0 ? 0 : cat == 1 ? ncat[0] : ncat[0] + ncat[1];
+            const uint64_t mm = cat == 0 ? mc[0] : cat == 1 ? mc[1] : mc[2];
+            *reinterpret_cast<uint4*>(sw[cb + bcat[cat] + lanes_below(mm)]) = c;
         }
-        // the touching charges' records, compacted: record s in the first 16
-        // bytes of weight row s
-        if (touch) *reinterpret_cast<uint4*>(sw[before + lanes_below(m)]) = c;
         __syncthreads();
         if (tid < nst) {
             // thread s: the 3 x 8 brick weights of staged charge s (row s is
@@ -228,47 +248,56 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
             }
         }
         __syncthreads();
-        // the staged charges of this wavefront, two at a time with their LDS
-        // reads issued together; per charge three 8-byte reads (the lane's two
-        // weights of each axis), four y z products and eight FMAs, in staged
-        // order
-        auto add = [&](const float2 X, const float2 Y, const float2 Z) {
-            const float yz[4] = {Y.x * Z.x, Y.y * Z.x, Y.x * Z.y, Y.y * Z.y};
-#pragma unroll
-            for (int k = 0; k < 8; ++k) acc[k] = fmaf(k & 1 ? X.y : X.x, yz[k >> 1], acc[k]);
-        };
-        auto wts = [&](int sidx, float2& X, float2& Y, float2& Z) {
+        // the staged charges of this wavefront's x half, every fourth one, in
+        // staged order, two at a time with their LDS reads issued together;
+        // per charge the half's four x weights (one 16-byte read, the same
+        // address on every lane), the lane's y and z weights, one y z product
+        // and four FMAs
+        auto wts = [&](int sidx, float4& X, float& Y, float& Z) {
             const float* row = sw[sidx];
-            X = *reinterpret_cast<const float2*>(row + 2 * cx);
-            Y = *reinterpret_cast<const float2*>(row + kBrick + 2 * cy);
-            Z = *reinterpret_cast<const float2*>(row + 2 * kBrick + 2 * cz);
+            X = *reinterpret_cast<const float4*>(row + 4 * hx);
+            Y = row[kBrick + ly];
+            Z = row[2 * kBrick + lz];
         };
-        int sidx = w;
-        for (; sidx + kSpreadWaves < nst; sidx += 2 * kSpreadWaves) {
-            float2 X0w, Y0w, Z0w, X1w, Y1w, Z1w;
+        auto add = [&](const float4 X, const float Y, const float Z) {
+            const float yz = Y * Z;
+            acc[0] = fmaf(X.x, yz, acc[0]);
+            acc[1] = fmaf(X.y, yz, acc[1]);
+            acc[2] = fmaf(X.z, yz, acc[2]);
+            acc[3] = fmaf(X.w, yz, acc[3]);
+        };
+        // (uniform per wavefront: loop control in scalar registers)
+        const int hend = __builtin_amdgcn_readfirstlane(hx == 0 ? ncat[0] + ncat[1] : nst);
+        int sidx = __builtin_amdgcn_readfirstlane((hx == 0 ? 0 : ncat[0]) + (w & 3));
+        for (; sidx + 4 < hend; sidx += 8) {
+            float4 X0w, X1w;
+            float Y0w, Z0w, Y1w, Z1w;
             wts(sidx, X0w, Y0w, Z0w);
-            wts(sidx + kSpreadWaves, X1w, Y1w, Z1w);
+            wts(sidx + 4, X1w, Y1w, Z1w);
             add(X0w, Y0w, Z0w);
             add(X1w, Y1w, Z1w);
         }
-        if (sidx < nst) {
-            float2 Xw, Yw, Zw;
+        if (sidx < hend) {
+            float4 Xw;
+            float Yw, Zw;
             wts(sidx, Xw, Yw, Zw);
             add(Xw, Yw, Zw);
         }
         __syncthreads();
     }
 
-    // fixed-order sum of the wavefronts' partial bricks: all partials to LDS,
-    // then wavefront w sums partial w of every lane over them in wavefront
-    // order
+    // fixed-order sum of the four partials of each point (those of its half's
+    // wavefronts, in wavefront order): all partials to LDS, then thread
+    // (x, y, z) = (tid % 8, tid / 8 % 8, tid / 64) adds those of its point,
+    // lane (y, z)'s partial x % 4 of wavefronts 4 (x / 4) + u
 #pragma unroll
-    for (int k = 0; k < kBrick; ++k) red[w][k][lane] = acc[k];
+    for (int k = 0; k < 4; ++k) red[w][k][lane] = acc[k];
     __syncthreads();
-    float v = red[0][w][lane];
+    const int px = tid & 7, py = (tid >> 3) & 7, pz = tid >> 6;
+    const int h = px >> 2, k = px & 3, l = py + 8 * pz;
+    float v = red[4 * h][k][l];
 #pragma unroll
-    for (int u = 1; u < kSpreadWaves; ++u) v += red[u][w][lane];
-    const int px = 2 * cx + (w & 1), py = 2 * cy + ((w >> 1) & 1), pz = 2 * cz + (w >> 2);
+    for (int u = 1; u < 4; ++u) v += red[4 * h + u][k][l];
     if (px < B0 && py < B1 && pz < B2)
         rho[((size_t)(Z0 + pz) * a.g[1] + (Y0 + py)) * a.g[0] + X0 + px] = v - mean;
 }
