@@ -216,14 +216,21 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     const int ia = lane >> 3, ja = lane & 7;
     const int ncx = a.nc[0], ncy = a.nc[1], gz = a.gz;
     // the cluster's records, loaded together (those of a cluster number
-    // with no charges are not used)
+    // with no charges are not used); the empty asm takes all three, so that
+    // none of the loads is moved past the test below and waited for alone
     const int2 ii = cl_info[I];
     const int C = cl_col[I];                  // cx | cy << 16
     const uint2 zI = cl_z[I];
+    asm volatile("" ::"s"(ii.x), "s"(ii.y), "s"(C), "s"(zI.x), "s"(zI.y));
     if (ii.y == 0) {
         if (tid == 0) epart[I] = 0.0;
         return;
     }
+    // the i-charges and the cluster's first charge, in flight with the
+    // stencil columns' loads below
+    const bool ivalid = ia < ii.y;
+    const uint4 ci = ivalid ? sorted[ii.x + ia] : make_uint4(0, 0, 0, 0);   // q = 0 if invalid
+    const uint4 c0 = sorted[ii.x];
     const int cx = C & 0xffff, cy = C >> 16;
     const bool fullx = 2 * a.R[0] + 1 >= ncx, fully = 2 * a.R[1] + 1 >= ncy;
     const int nxs = fullx ? ncx : 2 * a.R[0] + 1, nys = fully ? ncy : 2 * a.R[1] + 1;
@@ -350,8 +357,6 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         }
     };
 
-    const bool ivalid = ia < ii.y;
-    const uint4 ci = ivalid ? sorted[ii.x + ia] : make_uint4(0, 0, 0, 0);   // q = 0 if invalid
     const float qi = __uint_as_float(ci.w);
     const float sx = a.scale[0], sy = a.scale[1], sz = a.scale[2];
     // cubic cells: distance components stay in fixed-point units u = L / 2^32
@@ -386,7 +391,6 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     // put it r_c or more from the box meets no i-charge within r_c and is
     // dropped before the pair steps (the margin covers the FP32 rounding of
     // the test: the pair set is unchanged)
-    const uint4 c0 = sorted[ii.x];
     int bl[3], bh[3];
     bl[0] = bh[0] = ivalid ? (int)(ci.x - c0.x) : 0;
     bl[1] = bh[1] = ivalid ? (int)(ci.y - c0.y) : 0;
