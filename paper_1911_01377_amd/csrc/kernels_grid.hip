@@ -81,8 +81,11 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
                                             float* __restrict__ rho) {
     __shared__ __align__(16) float sw[kSpreadChunk][3 * kBrick];   // rows of 96 B (16-byte stores)
     static_assert(kSpreadWaves == 8 && kBrick == 8, "four wavefronts per half brick; 8-wide rows");
-    // the wavefronts' partial half bricks, summed after the last chunk (reuses sw)
-    float (*red)[4][64] = reinterpret_cast<float (*)[4][64]>(&sw[0][0]);
+    // the wavefronts' partial half bricks, summed after the last chunk (reuses
+    // sw; rows of 65 so that the 8 partials a thread group reads lie in
+    // different banks)
+    float (*red)[4][65] = reinterpret_cast<float (*)[4][65]>(&sw[0][0]);
+    static_assert(kSpreadWaves * 4 * 65 <= kSpreadChunk * 3 * kBrick, "red fits in sw");
     __shared__ int pbeg[2 * kMaxWindowCols];       // first charge of each column piece
     __shared__ int poff[2 * kMaxWindowCols + 1];   // prefix sums of the piece lengths
     __shared__ int wtot[kSpreadWaves];
