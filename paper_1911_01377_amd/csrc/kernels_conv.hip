@@ -295,7 +295,8 @@ __device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid, floa
                                                 float* __restrict__ phi,
                                                 const float* __restrict__ rho,
                                                 double* __restrict__ fpart,
-                                                const float* ps = nullptr) {
+                                                const float* ps = nullptr,
+                                                bool straight = true) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int li = l & 15, lk = l >> 4;
     const int g2 = a.g[2], p2 = a.gp[2], ld = p2 + 4;
@@ -310,15 +311,19 @@ __device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid, floa
     const f32x4 rv = (act && grp == 0) ? conv_z_rho(a, tz, li, lk, cb, rho)
                                        : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int t0 = 0; t0 < a.nterms; t0 += tc) {
+    // one chunk of terms; with a single chunk and a single staging pass (the
+    // usual case) and `straight`, no loop is emitted, so that the loads of
+    // rho, of the Kz fragments and of the columns are all in flight together
+    // (the batched kernel keeps the loops: the straight copy would cost it
+    // registers and a resident block per CU)
+    auto chunk = [&](int t0) {
         const int nt = (a.nterms - t0 < tc) ? a.nterms - t0 : tc;
         Frag32 cur, nxt;
         if (act && grp < nt) load_frag32(cur, kz + mz * (t0 + grp), p2, tz, li, lk);
         if (t0 > 0) __syncthreads();     // the previous chunk's columns are consumed
         // octets (t, column c, z' = 8 zb .. 8 zb + 7): 8 loads down the
         // column (each coalesced over the 16 columns), two 16-byte stores
-        const int no = nt * 16 * (p2 / 8);
-        for (int o = threadIdx.x; o < no; o += kConvThreads) {
+        auto stage = [&](int o) {
             const int c = o & 15, q8 = o >> 4;
             const int t = small_div(q8, iq8), zb = q8 - t * (p2 / 8);
             float v[8];
@@ -332,6 +337,12 @@ __device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid, floa
             float* d = smem + (t * 16 + c) * ld + 8 * zb;
             *reinterpret_cast<float4*>(d) = make_float4(v[0], v[1], v[2], v[3]);
             *reinterpret_cast<float4*>(d + 4) = make_float4(v[4], v[5], v[6], v[7]);
+        };
+        const int no = nt * 16 * (p2 / 8);
+        if (straight && no <= kConvThreads) {
+            if ((int)threadIdx.x < no) stage(threadIdx.x);
+        } else {
+            for (int o = threadIdx.x; o < no; o += kConvThreads) stage(o);
         }
         __syncthreads();
         if (act)
@@ -344,6 +355,11 @@ __device__ __forceinline__ void conv_z_f32_body(const ConvArgs& a, int bid, floa
                         acc = mfma_chunk(cur.v[j], *reinterpret_cast<const f32x4*>(br + 16 * j), acc);
                 cur = nxt;
             }
+    };
+    if (straight && a.nterms <= tc) {
+        chunk(0);
+    } else {
+        for (int t0 = 0; t0 < a.nterms; t0 += tc) chunk(t0);
     }
     if (G > 1) acc = conv_z_reduce(acc, smem, act, grp, G, tz, tz_n, l);
     if (!act || grp != 0) return;
@@ -487,7 +503,8 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
                                                  float* __restrict__ phi,
                                                  const float* __restrict__ rho,
                                                  double* __restrict__ fpart,
-                                                 const float* ps = nullptr) {
+                                                 const float* ps = nullptr,
+                                                 bool straight = true) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int li = l & 15, lk = l >> 4;
     const int g2 = a.g[2], p2 = a.gp[2], ld = p2 + 8;
@@ -504,7 +521,12 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
     const f32x4 rv = (act && grp == 0) ? conv_z_rho(a, tz, li, lk, c0, rho)
                                        : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int t0 = 0; t0 < a.nterms; t0 += tc) {
+    // one chunk of terms; with a single chunk and a single staging pass (the
+    // usual case) and `straight`, no loop is emitted, so that the loads of
+    // rho, of the Kz fragments and of the columns are all in flight together
+    // (the batched kernel keeps the loops: the straight copy would cost it
+    // registers and a resident block per CU)
+    auto chunk = [&](int t0) {
         const int nt = (a.nterms - t0 < tc) ? a.nterms - t0 : tc;
         Frag cur, nxt;
         if (act && grp < nt)
@@ -513,8 +535,7 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
         // octets (t, column c, z' = 8 zb .. 8 zb + 7): 8 loads down the
         // column (each coalesced over the 16 columns), one split, two
         // 16-byte stores
-        const int no = nt * 16 * (p2 / 8);
-        for (int o = threadIdx.x; o < no; o += kConvThreads) {
+        auto stage = [&](int o) {
             const int c = o & 15, q8 = o >> 4;
             const int t = small_div(q8, iq8), zb = q8 - t * (p2 / 8);
             float v[8];
@@ -529,6 +550,12 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
             split8(v, &h, &lo);
             *reinterpret_cast<u16x8*>(th + (t * 16 + c) * ld + 8 * zb) = h;
             *reinterpret_cast<u16x8*>(tl + (t * 16 + c) * ld + 8 * zb) = lo;
+        };
+        const int no = nt * 16 * (p2 / 8);
+        if (straight && no <= kConvThreads) {
+            if ((int)threadIdx.x < no) stage(threadIdx.x);
+        } else {
+            for (int o = threadIdx.x; o < no; o += kConvThreads) stage(o);
         }
         __syncthreads();
         if (act)
@@ -548,6 +575,11 @@ __device__ __forceinline__ void conv_z_bf16_body(const ConvArgs& a, int bid, flo
                 }
                 cur = nxt;
             }
+    };
+    if (straight && a.nterms <= tc) {
+        chunk(0);
+    } else {
+        for (int t0 = 0; t0 < a.nterms; t0 += tc) chunk(t0);
     }
     if (G > 1) acc = conv_z_reduce(acc, smem, act, grp, G, tz, tz_n, l);
     if (!act || grp != 0) return;
@@ -786,9 +818,10 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_z_batch(const BatchTable*
         if constexpr (BF16 != 0)
             conv_z_bf16_body(d.conv, item, dyn_lds, d.tgrid,
                              reinterpret_cast<const unsigned short*>(d.kz), d.phi, d.rho,
-                             d.far_parts);
+                             d.far_parts, nullptr, false);
         else
-            conv_z_f32_body(d.conv, item, dyn_lds, d.tgrid, d.kz, d.phi, d.rho, d.far_parts);
+            conv_z_f32_body(d.conv, item, dyn_lds, d.tgrid, d.kz, d.phi, d.rho, d.far_parts,
+                            nullptr, false);
     });
 }
 
