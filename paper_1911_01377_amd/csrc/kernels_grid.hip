@@ -69,8 +69,10 @@ __device__ __forceinline__ void cell_window(int X0, int bn, int P, int g, int nc
 // and each half's charges are one contiguous run), stages their 3 x 8 weights
 // in LDS, and wavefront 4 h + u accumulates every fourth of half h's charges
 // from the u-th into its partial half brick (a dense 4 x 8 x 8 product per
-// charge, one fewer half for the ~30% of charges that meet only one); the
-// four partials of each point are summed in a fixed order at the end.
+// charge; a charge whose stencil ends at brick position d meets both halves
+// only for 4 <= d <= 2P + 2, so at P = 3 about 60% of the charges are
+// accumulated by one half only); the four partials of each point are summed
+// in a fixed order at the end.
 // PT > 0: the stencil half width as a compile-time constant; PT = 0 takes it
 // from a.P.
 template <int PT>
