@@ -20,6 +20,12 @@ ARCH = "gfx950"
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + INCLUDE, "-I" + CSRC]
+# device code only: the first 16 dwords of each kernel's arguments are
+# preloaded into scalar registers when the wave starts (the kernels take their
+# block count and pointers first, their parameter structs last), so the first
+# memory accesses need no argument load (firmware without preloading runs the
+# compiler's fallback prologue, which loads them)
+DEVICE_FLAGS = ["-mllvm", "-amdgpu-kernarg-preload-count=16"]
 
 
 def sources():
@@ -29,7 +35,7 @@ def sources():
 
 def _compile(src):
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + (DEVICE_FLAGS if src.endswith(".hip") else []) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

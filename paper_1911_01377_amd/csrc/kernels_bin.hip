@@ -783,12 +783,12 @@ __device__ __forceinline__ void colbuild_body(int col, int nb, int ncol, int ncx
     }
 }
 
-__global__ void __launch_bounds__(256) k_bin_local(BinArgs a, const float* __restrict__ xyz,
+__global__ void __launch_bounds__(256) k_bin_local(const float* __restrict__ xyz,
                                                    const float* __restrict__ q,
                                                    uint4* __restrict__ coord,
                                                    int* __restrict__ slots,
                                                    int* __restrict__ bpre,
-                                                   double* __restrict__ qpart) {
+                                                   double* __restrict__ qpart, BinArgs a) {
     bin_local_body(a, blockIdx.x, xyz, q, coord, slots, bpre, qpart);
 }
 
@@ -847,8 +847,8 @@ hipError_t launch_bin_local(const BinArgs& a, const float* xyz, const float* q, 
                             int* slots, int* bpre, double* qpart, hipStream_t st) {
     const int nb = (a.n + 255) / 256;
     if (nb > 0)
-        hipLaunchKernelGGL(k_bin_local, dim3(nb), dim3(256), 0, st, a, xyz, q, coord, slots, bpre,
-                           qpart);
+        hipLaunchKernelGGL(k_bin_local, dim3(nb), dim3(256), 0, st, xyz, q, coord, slots, bpre,
+                           qpart, a);
     return hipGetLastError();
 }
 

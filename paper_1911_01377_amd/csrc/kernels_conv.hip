@@ -733,10 +733,11 @@ __device__ __forceinline__ const float* spec_z_part(const ConvArgs& a, int bid, 
 // ------------------------------------------------------------------ kernels
 
 // blockIdx.y == a.nterms (only with spectral terms): the plane's projection
-__global__ void __launch_bounds__(kConvThreads) k_conv_xy_f32(ConvArgs a, const float* __restrict__ rho,
+__global__ void __launch_bounds__(kConvThreads) k_conv_xy_f32(const float* __restrict__ rho,
                                                      const float* __restrict__ kx,
                                                      const float* __restrict__ ky,
-                                                     float* __restrict__ tgrid, SpecPtrs sp) {
+                                                     float* __restrict__ tgrid, ConvArgs a,
+                                                     SpecPtrs sp) {
     extern __shared__ float dyn_lds[];
     if ((int)blockIdx.y == a.nterms) {
         spec_fwd_plane(a, blockIdx.x, dyn_lds, rho, sp);
@@ -749,14 +750,14 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_xy_f32(ConvArgs a, const 
 // which share 128-byte lines of T, then run on one XCD and share its L2.
 // With spectral terms the dynamic LDS holds the dense staging and then the
 // spectral part (from float offset spec_off).
-__global__ void __launch_bounds__(kConvThreads) k_conv_z_f32(ConvArgs a, int nb,
+__global__ void __launch_bounds__(kConvThreads) k_conv_z_f32(int nb, int spec_off,
                                                              const float* __restrict__ tgrid,
                                                              const float* __restrict__ kz,
                                                              float* __restrict__ phi,
                                                              const float* __restrict__ rho,
                                                              double* __restrict__ fpart,
                                                              const float* __restrict__ g,
-                                                             SpecPtrs sp, int spec_off) {
+                                                             ConvArgs a, SpecPtrs sp) {
     extern __shared__ float dyn_lds[];
     const int item = xcd_item(blockIdx.x, nb);
     if (item >= nb) return;
@@ -764,10 +765,11 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_z_f32(ConvArgs a, int nb,
     conv_z_f32_body(a, item, dyn_lds, tgrid, kz, phi, rho, fpart, ps);
 }
 
-__global__ void __launch_bounds__(kConvThreads) k_conv_xy_bf16(ConvArgs a, const float* __restrict__ rho,
+__global__ void __launch_bounds__(kConvThreads) k_conv_xy_bf16(const float* __restrict__ rho,
                                                       const unsigned short* __restrict__ kx,
                                                       const unsigned short* __restrict__ ky,
-                                                      float* __restrict__ tgrid, SpecPtrs sp) {
+                                                      float* __restrict__ tgrid, ConvArgs a,
+                                                      SpecPtrs sp) {
     extern __shared__ float dyn_lds[];
     if ((int)blockIdx.y == a.nterms) {
         spec_fwd_plane(a, blockIdx.x, dyn_lds, rho, sp);
@@ -776,14 +778,14 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_xy_bf16(ConvArgs a, const
     conv_xy_bf16_body(a, blockIdx.x, blockIdx.y, dyn_lds, rho, kx, ky, tgrid);
 }
 
-__global__ void __launch_bounds__(kConvThreads) k_conv_z_bf16(ConvArgs a, int nb,
+__global__ void __launch_bounds__(kConvThreads) k_conv_z_bf16(int nb, int spec_off,
                                                               const float* __restrict__ tgrid,
                                                               const unsigned short* __restrict__ kz,
                                                               float* __restrict__ phi,
                                                               const float* __restrict__ rho,
                                                               double* __restrict__ fpart,
                                                               const float* __restrict__ g,
-                                                              SpecPtrs sp, int spec_off) {
+                                                              ConvArgs a, SpecPtrs sp) {
     extern __shared__ float dyn_lds[];
     const int item = xcd_item(blockIdx.x, nb);
     if (item >= nb) return;
@@ -863,11 +865,11 @@ hipError_t launch_conv_xy(const ConvArgs& a, const float* rho, const float* kx, 
     const size_t lds = conv_xy_lds_bytes(a);
     const dim3 grid(a.g[2], a.nterms + (a.spec ? 1 : 0));
     if (a.bf16x3)
-        hipLaunchKernelGGL(k_conv_xy_bf16, grid, dim3(kConvThreads), lds, st, a, rho,
+        hipLaunchKernelGGL(k_conv_xy_bf16, grid, dim3(kConvThreads), lds, st, rho,
                            reinterpret_cast<const unsigned short*>(kx),
-                           reinterpret_cast<const unsigned short*>(ky), tgrid, sp);
+                           reinterpret_cast<const unsigned short*>(ky), tgrid, a, sp);
     else
-        hipLaunchKernelGGL(k_conv_xy_f32, grid, dim3(kConvThreads), lds, st, a, rho, kx, ky, tgrid,
+        hipLaunchKernelGGL(k_conv_xy_f32, grid, dim3(kConvThreads), lds, st, rho, kx, ky, tgrid, a,
                            sp);
     return hipGetLastError();
 }
@@ -885,12 +887,12 @@ hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz,
     const int off = (int)(conv_z_dense_lds_bytes(a) / sizeof(float));
     if (a.bf16x3)
         hipLaunchKernelGGL(k_conv_z_bf16, dim3(xcd_blocks(nb)), dim3(kConvThreads),
-                           conv_z_lds_bytes(a), st, a, nb, tgrid,
-                           reinterpret_cast<const unsigned short*>(kz), phi, rho, fpart, g, sp,
-                           off);
+                           conv_z_lds_bytes(a), st, nb, off, tgrid,
+                           reinterpret_cast<const unsigned short*>(kz), phi, rho, fpart, g, a,
+                           sp);
     else
         hipLaunchKernelGGL(k_conv_z_f32, dim3(xcd_blocks(nb)), dim3(kConvThreads),
-                           conv_z_lds_bytes(a), st, a, nb, tgrid, kz, phi, rho, fpart, g, sp, off);
+                           conv_z_lds_bytes(a), st, nb, off, tgrid, kz, phi, rho, fpart, g, a, sp);
     return hipGetLastError();
 }
 

@@ -308,11 +308,11 @@ __device__ __forceinline__ void spread_body(const GridArgs& a, int bid,
 }
 
 template <int PT>
-__global__ void __launch_bounds__(64 * kSpreadWaves) k_spread(GridArgs a, int nb,
-                                                              const uint4* __restrict__ sorted,
+__global__ void __launch_bounds__(64 * kSpreadWaves) k_spread(int nb,
                                                               const int* __restrict__ zbin,
                                                               const double* __restrict__ qstats,
-                                                              float* __restrict__ rho) {
+                                                              const uint4* __restrict__ sorted,
+                                                              float* __restrict__ rho, GridArgs a) {
     const int item = xcd_item(blockIdx.x, nb);
     if (item < nb) spread_body<PT>(a, item, sorted, zbin, qstats, rho);
 }
@@ -578,18 +578,19 @@ __device__ __forceinline__ void gather_body(const GridArgs& a, int bid,
 // Block xcd_blocks(nb) (one past the bricks' blocks) forms the energy total:
 // it reads only what earlier launches wrote, so it runs beside the bricks.
 template <int PT>
-__global__ void __launch_bounds__(kGatherThreads) k_gather(GridArgs a, int nb,
-                                                const uint4* __restrict__ sorted,
-                                                const int* __restrict__ perm,
+__global__ void __launch_bounds__(kGatherThreads) k_gather(int nb,
                                                 const int* __restrict__ zbin,
                                                 const float* __restrict__ phi,
+                                                const uint4* __restrict__ sorted,
                                                 const float4* __restrict__ fnear,
-                                                float* __restrict__ forces, FinalArgs fa,
+                                                const int* __restrict__ perm,
+                                                float* __restrict__ forces,
                                                 const double* __restrict__ pair_parts,
                                                 const double* __restrict__ far_parts,
                                                 const double* __restrict__ qstats,
                                                 double* __restrict__ energy,
-                                                double* __restrict__ parts) {
+                                                double* __restrict__ parts, GridArgs a,
+                                                FinalArgs fa) {
     extern __shared__ char dyn[];
     if ((int)blockIdx.x == xcd_blocks(nb)) {
         energy_total<kGatherThreads>(fa, pair_parts, far_parts, qstats, energy, parts,
@@ -623,11 +624,11 @@ hipError_t launch_spread(const GridArgs& a, const uint4* sorted, const int* zbin
                    ((a.g[2] + kBrick - 1) / kBrick);
     const dim3 grid(xcd_blocks(nb)), block(64 * kSpreadWaves);
     if (a.P == 3)
-        hipLaunchKernelGGL(k_spread<3>, grid, block, 0, st, a, nb, sorted, zbin, qstats, rho);
+        hipLaunchKernelGGL(k_spread<3>, grid, block, 0, st, nb, zbin, qstats, sorted, rho, a);
     else if (a.P == 5)
-        hipLaunchKernelGGL(k_spread<5>, grid, block, 0, st, a, nb, sorted, zbin, qstats, rho);
+        hipLaunchKernelGGL(k_spread<5>, grid, block, 0, st, nb, zbin, qstats, sorted, rho, a);
     else
-        hipLaunchKernelGGL(k_spread<0>, grid, block, 0, st, a, nb, sorted, zbin, qstats, rho);
+        hipLaunchKernelGGL(k_spread<0>, grid, block, 0, st, nb, zbin, qstats, sorted, rho, a);
     return hipGetLastError();
 }
 
@@ -645,8 +646,8 @@ hipError_t launch_gather(const GridArgs& a, const uint4* sorted, const int* perm
     const size_t lds = gather_lds(a.P).total;
     // the default stencils of the two forms (P = 3, 5) have their own code
 #define USERIES_GATHER_LAUNCH(PT)                                                            \
-    hipLaunchKernelGGL(k_gather<PT>, grid, block, lds, st, a, nb, sorted, perm, zbin, phi,   \
-                       fnear, forces, fa, pair_parts, far_parts, qstats, energy, parts)
+    hipLaunchKernelGGL(k_gather<PT>, grid, block, lds, st, nb, zbin, phi, sorted, fnear,     \
+                       perm, forces, pair_parts, far_parts, qstats, energy, parts, a, fa)
     if (a.P == 3)
         USERIES_GATHER_LAUNCH(3);
     else if (a.P == 5)

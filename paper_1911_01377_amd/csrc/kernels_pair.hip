@@ -481,9 +481,10 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
 template <int DEG, bool EXACT, int ALPHA>
 __global__ void __launch_bounds__(64 * kPairWaves)
 __attribute__((amdgpu_waves_per_eu(EXACT ? 6 : 7)))
-k_pair(PairArgs a, int nb, const uint4* __restrict__ sorted, const int2* __restrict__ cl_info,
-       const int* __restrict__ cl_col, const uint2* __restrict__ cl_z,
-       const int* __restrict__ zbin, float4* __restrict__ fnear, double* __restrict__ epart) {
+k_pair(int nb, const int2* __restrict__ cl_info, const int* __restrict__ cl_col,
+       const uint2* __restrict__ cl_z, const int* __restrict__ zbin,
+       const uint4* __restrict__ sorted, float4* __restrict__ fnear, double* __restrict__ epart,
+       PairArgs a) {
     const int item = xcd_item(blockIdx.x, nb);
     if (item < nb)
         pair_body<DEG, EXACT, ALPHA, true>(a, item, sorted, cl_info, cl_col, cl_z, zbin, fnear, epart);
@@ -512,8 +513,8 @@ hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted,
     if (a.alpha != 1 && a.alpha != 6 && a.alpha != 12) return hipErrorInvalidValue;
     switch (a.deg) {
 #define USERIES_PAIR_LAUNCH(D, E, A)                                                          \
-    hipLaunchKernelGGL((k_pair<D, E, A>), grid, block, 0, st, a, nblocks, sorted, cl_info,    \
-                       cl_col, cl_z, zbin, fnear, epart)
+    hipLaunchKernelGGL((k_pair<D, E, A>), grid, block, 0, st, nblocks, cl_info, cl_col, cl_z, \
+                       zbin, sorted, fnear, epart, a)
 #define USERIES_PAIR_DEG(D)                                                                   \
     case D:                                                                                   \
         if (a.alpha == 6) {                                                                   \
