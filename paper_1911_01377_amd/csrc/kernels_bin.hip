@@ -89,11 +89,11 @@ __device__ __forceinline__ void encode_body(const BinArgs& a, int bid, const flo
     }
 }
 
-__global__ void __launch_bounds__(256) k_encode(BinArgs a, const float* __restrict__ xyz,
+__global__ void __launch_bounds__(256) k_encode(const float* __restrict__ xyz,
                                                 const float* __restrict__ q,
                                                 uint4* __restrict__ coord,
                                                 int* __restrict__ col_count,
-                                                double* __restrict__ qpart) {
+                                                double* __restrict__ qpart, BinArgs a) {
     encode_body(a, blockIdx.x, xyz, q, coord, col_count, qpart);
 }
 
@@ -285,14 +285,14 @@ __device__ __forceinline__ void scatter_body(const BinArgs& a, int bid, bool fus
     }
 }
 
-__global__ void __launch_bounds__(256) k_scatter(BinArgs a, int fused,
+__global__ void __launch_bounds__(256) k_scatter(int fused, int nqpart,
                                                  const uint4* __restrict__ coord,
-                                                 uint4* __restrict__ sorted,
                                                  const int* __restrict__ count,
+                                                 uint4* __restrict__ sorted,
                                                  int* __restrict__ start, int* __restrict__ cstart,
                                                  int* __restrict__ fill, int* __restrict__ slots,
-                                                 const double* __restrict__ qpart, int nqpart,
-                                                 double* __restrict__ qstats) {
+                                                 const double* __restrict__ qpart,
+                                                 double* __restrict__ qstats, BinArgs a) {
     scatter_body(a, blockIdx.x, fused != 0, coord, sorted, count, start, cstart, fill, slots,
                  qpart, nqpart, qstats);
 }
@@ -865,8 +865,8 @@ hipError_t launch_colbuild(int n, int ncol, int ncx, int gz, int npb, const int*
 hipError_t launch_encode(const BinArgs& a, const float* xyz, const float* q, uint4* coord,
                          int* col_count, double* qpart, int nqpart, hipStream_t st) {
     if (a.n > 0)
-        hipLaunchKernelGGL(k_encode, dim3(nqpart), dim3(256), 0, st, a, xyz, q, coord, col_count,
-                           qpart);
+        hipLaunchKernelGGL(k_encode, dim3(nqpart), dim3(256), 0, st, xyz, q, coord, col_count,
+                           qpart, a);
     return hipGetLastError();
 }
 
@@ -891,9 +891,8 @@ hipError_t launch_scatter(const BinArgs& a, const uint4* coord, uint4* sorted, c
     // with no charges the fused prefix still has to run once (all columns empty)
     const int nb = std::max(1, (n + 255) / 256);
     if (n > 0 || fused)
-        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, st, a, fused, coord, sorted,
-                           col_count, col_start, clus_start, col_fill, slots, qpart, nqpart,
-                           qstats);
+        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, st, fused, nqpart, coord, col_count,
+                           sorted, col_start, clus_start, col_fill, slots, qpart, qstats, a);
     return hipGetLastError();
 }
 

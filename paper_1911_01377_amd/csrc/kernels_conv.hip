@@ -639,8 +639,8 @@ __device__ __forceinline__ void spec_fwd_plane(const ConvArgs& a, int z, float* 
 // round of independent loads, 16 consecutive o per row of lanes), and the 16
 // slices are then summed in a fixed order.
 constexpr int kSpecCoreThreads = 256;
-__global__ void __launch_bounds__(kSpecCoreThreads) k_spec_core(ConvArgs a, SpecPtrs sp,
-                                                               float* __restrict__ g) {
+__global__ void __launch_bounds__(kSpecCoreThreads) k_spec_core(float* __restrict__ g, ConvArgs a,
+                                                               SpecPtrs sp) {
     __shared__ float red[16][17];
     const int R = a.rk[1] * a.rk[0], r2 = a.rk[2], g2 = a.g[2];
     const int j = threadIdx.x & 15, slice = threadIdx.x >> 4;
@@ -881,8 +881,8 @@ hipError_t launch_conv_z(const ConvArgs& a, const float* tgrid, const float* kz,
     float* g = a.spec ? sp.c + (size_t)a.g[2] * a.rk[1] * a.rk[0] : nullptr;
     if (a.spec) {
         const int n = a.rk[2] * a.rk[1] * a.rk[0];
-        hipLaunchKernelGGL(k_spec_core, dim3((n + 15) / 16), dim3(kSpecCoreThreads), 0, st, a, sp,
-                           g);
+        hipLaunchKernelGGL(k_spec_core, dim3((n + 15) / 16), dim3(kSpecCoreThreads), 0, st, g, a,
+                           sp);
     }
     const int off = (int)(conv_z_dense_lds_bytes(a) / sizeof(float));
     if (a.bf16x3)
