@@ -432,14 +432,21 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
         // keep the candidates near the box, compacted in candidate order,
         // padded with zero charges to whole steps of 8
         int kept = 0;
+        // candidates from this chunk's start (uniform: the masks below in scalar registers)
+        const int rem = __builtin_amdgcn_readfirstlane(total - c * kChunkCharges);
 #pragma unroll
         for (int u = 0; u < kPerLane; ++u) {
-            const int p = c * kChunkCharges + kPerLane * lane + u;
-            // both tests evaluated (no branch): a candidate past the end is
-            // the zero record fetch left, tested and dropped
-            const bool keep = (p < total) & near_box(pre[u]);
-            const uint64_t m = __ballot(keep);
-            if (keep) stage[w][kept + lanes_below(m)] = pre[u];
+            // candidate u of lane l (position 4 l + u in the chunk) exists for
+            // the first ceil((rem - u) / 4) lanes: a mask in scalar registers;
+            // a candidate past the end is the zero record fetch left, tested
+            // (no branch) and dropped by the mask.  The ballot of the single
+            // compare is the compare's own lane mask, and the store's branch
+            // takes the mask back as the lane condition
+            const int ru = rem - u;
+            const int nl = ru <= 0 ? 0 : min(64, (ru + kPerLane - 1) / kPerLane);
+            const uint64_t live = nl >= 64 ? ~0ull : ((1ull << nl) - 1ull);
+            const uint64_t m = __builtin_amdgcn_ballot_w64(near_box(pre[u])) & live;
+            if (__builtin_amdgcn_inverse_ballot_w64(m)) stage[w][kept + lanes_below(m)] = pre[u];
             kept += __popcll(m);
         }
         if (lane < ((kept + 7) & ~7) - kept) stage[w][kept + lane] = make_uint4(0, 0, 0, 0);
