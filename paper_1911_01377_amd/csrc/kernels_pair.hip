@@ -195,7 +195,9 @@ __device__ __forceinline__ void pair_steps(const Poly<DEG, EXACT>& P, const uint
     }
 }
 
-template <int DEG, bool EXACT, int ALPHA, bool PIPE>
+// CM: the cell shape, 1 cubic, 2 other, 0 decided per box at run time (the
+// batched kernel); a one-box kernel compiled for one shape holds one chunk loop
+template <int DEG, bool EXACT, int ALPHA, bool PIPE, int CM>
 __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4* __restrict__ sorted,
                                           const int2* __restrict__ cl_info,
                                           const int* __restrict__ cl_col,
@@ -363,7 +365,7 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     // (the scale folded into r_c^2, x = r^2 / r_c^2, for 1/r into the
     // polynomials, and into the factors applied at the end); otherwise each
     // component is scaled to A
-    const bool cubic = sx == sy && sx == sz;
+    const bool cubic = CM == 1 || (CM == 0 && sx == sy && sx == sz);
     const bool units = cubic && ALPHA == 1;
     const float isx = a.inv_scale;
     const float rc2w = cubic ? a.rc2 * isx * isx : a.rc2;
@@ -412,14 +414,25 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     const uint32_t cenx = c0.x + (uint32_t)((bl[0] + bh[0]) / 2);
     const uint32_t ceny = c0.y + (uint32_t)((bl[1] + bh[1]) / 2);
     const uint32_t cenz = c0.z + (uint32_t)((bl[2] + bh[2]) / 2);
-    const float hx = (float)((bh[0] - bl[0]) / 2 + 1) * sx;
-    const float hy = (float)((bh[1] - bl[1]) / 2 + 1) * sy;
-    const float hz = (float)((bh[2] - bl[2]) / 2 + 1) * sz;
-    const float rcm2 = a.rcm2;
+    // half extents in fixed-point units; for a kernel compiled for cubic cells
+    // the test runs in those units (the reach r_c + margin scaled to them, no
+    // per-candidate scaling), otherwise in A per axis
+    const float hxu = (float)((bh[0] - bl[0]) / 2 + 1), hyu = (float)((bh[1] - bl[1]) / 2 + 1),
+                hzu = (float)((bh[2] - bl[2]) / 2 + 1);
+    const float hx = CM == 1 ? hxu : hxu * sx, hy = CM == 1 ? hyu : hyu * sy,
+                hz = CM == 1 ? hzu : hzu * sz;
+    const float rcm2 = CM == 1 ? a.rcm2 * isx * isx : a.rcm2;
     auto near_box = [&](const uint4& cj) {
-        const float ex = fmaxf(0.0f, fabsf((float)(int)(cj.x - cenx) * sx) - hx);
-        const float ey = fmaxf(0.0f, fabsf((float)(int)(cj.y - ceny) * sy) - hy);
-        const float ez = fmaxf(0.0f, fabsf((float)(int)(cj.z - cenz) * sz) - hz);
+        float dx = (float)(int)(cj.x - cenx), dy = (float)(int)(cj.y - ceny),
+              dz = (float)(int)(cj.z - cenz);
+        if constexpr (CM != 1) {
+            dx *= sx;
+            dy *= sy;
+            dz *= sz;
+        }
+        const float ex = fmaxf(0.0f, fabsf(dx) - hx);
+        const float ey = fmaxf(0.0f, fabsf(dy) - hy);
+        const float ez = fmaxf(0.0f, fabsf(dz) - hz);
         return fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < rcm2;
     };
 
@@ -485,7 +498,7 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
 
 // Held to 72 registers without exact Gaussians (7 wavefronts per SIMD, no
 // spill), 80 with them.
-template <int DEG, bool EXACT, int ALPHA>
+template <int DEG, bool EXACT, int ALPHA, bool CUB>
 __global__ void __launch_bounds__(64 * kPairWaves)
 __attribute__((amdgpu_waves_per_eu(EXACT ? 6 : 7)))
 k_pair(int nb, const int2* __restrict__ cl_info, const int* __restrict__ cl_col,
@@ -494,7 +507,8 @@ k_pair(int nb, const int2* __restrict__ cl_info, const int* __restrict__ cl_col,
        PairArgs a) {
     const int item = xcd_item(blockIdx.x, nb);
     if (item < nb)
-        pair_body<DEG, EXACT, ALPHA, true>(a, item, sorted, cl_info, cl_col, cl_z, zbin, fnear, epart);
+        pair_body<DEG, EXACT, ALPHA, true, CUB ? 1 : 2>(a, item, sorted, cl_info, cl_col, cl_z, zbin,
+                                                      fnear, epart);
 }
 
 // Held to 80 registers (6 wavefronts per SIMD instead of 5; the variant with
@@ -506,7 +520,7 @@ k_pair_batch(const BatchTable* __restrict__ tab,
                                                    const BoxDesc* __restrict__ desc) {
     batch_for(tab, BK_PAIR, [&](int i, int item) {
         const BoxDesc& d = desc[tab->slot[i]];
-        pair_body<DEG, EXACT, 1, false>(d.pair, item, d.sorted, d.cl_info, d.cl_col, d.cl_z, d.zbin,
+        pair_body<DEG, EXACT, 1, false, 0>(d.pair, item, d.sorted, d.cl_info, d.cl_col, d.cl_z, d.zbin,
                                  d.fnear, d.pair_parts);
     });
 }
@@ -517,11 +531,17 @@ hipError_t launch_pair(const PairArgs& a, int nblocks, const uint4* sorted,
     if (nblocks <= 0) return hipSuccess;
     const dim3 grid(xcd_blocks(nblocks)), block(64 * kPairWaves);
     const bool exact = a.ne > 0;
+    // the kernel's test of a cubic cell, made here (the same FP32 comparison)
+    const bool cubic = a.scale[0] == a.scale[1] && a.scale[0] == a.scale[2];
     if (a.alpha != 1 && a.alpha != 6 && a.alpha != 12) return hipErrorInvalidValue;
     switch (a.deg) {
 #define USERIES_PAIR_LAUNCH(D, E, A)                                                          \
-    hipLaunchKernelGGL((k_pair<D, E, A>), grid, block, 0, st, nblocks, cl_info, cl_col, cl_z, \
-                       zbin, sorted, fnear, epart, a)
+    if (cubic)                                                                                \
+        hipLaunchKernelGGL((k_pair<D, E, A, true>), grid, block, 0, st, nblocks, cl_info,     \
+                           cl_col, cl_z, zbin, sorted, fnear, epart, a);                      \
+    else                                                                                      \
+        hipLaunchKernelGGL((k_pair<D, E, A, false>), grid, block, 0, st, nblocks, cl_info,    \
+                           cl_col, cl_z, zbin, sorted, fnear, epart, a)
 #define USERIES_PAIR_DEG(D)                                                                   \
     case D:                                                                                   \
         if (a.alpha == 6) {                                                                   \
