@@ -23,7 +23,9 @@
 // candidates within r_c of the i-cluster's bounding box (about 58% of them
 // in water), so the steps skip most pairs that cannot be in range.  The force on
 // charge a is summed over its 8 lanes by shuffles, then over the two
-// wavefronts in a fixed order.
+// wavefronts in a fixed order.  The one-box kernel is compiled separately for
+// cubic cells (where the box test and the pair steps stay in fixed-point
+// units) and for other cells; the batched kernel decides per box.
 //
 // Each ordered pair (i, j) is evaluated once, by i's block (no
 // Newton's-third-law sharing), so forces need no atomics and the result does
