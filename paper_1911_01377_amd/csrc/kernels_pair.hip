@@ -215,6 +215,7 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     __shared__ int wtot[kPairWaves][2];
     __shared__ float4 fother[8];
     __shared__ double eother;
+    __shared__ int ibox[6];                          // the i-cluster's box: centre, half extents
     static_assert(kMaxStencilCols <= 64 * kPairWaves, "one stencil column per thread");
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int ia = lane >> 3, ja = lane & 7;
@@ -306,6 +307,43 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
             roff[M + (n0 > 0)] = O + n0;
         }
     }
+    // bounding box of the i-cluster (fixed point, offsets from its first
+    // charge), as a centre and half extents.  Per axis the periodic distance
+    // of a candidate from any i-charge is at least its periodic distance from
+    // the centre minus the half extent, so a candidate whose such distances
+    // put it r_c or more from the box meets no i-charge within r_c and is
+    // dropped before the pair steps (the margin covers the FP32 rounding of
+    // the test: the pair set is unchanged).  Both wavefronts hold the same
+    // i-charges: wavefront 0 forms the box and leaves it in LDS for the
+    // barrier below
+    if (w == 0) {
+        int bl[3], bh[3];
+        bl[0] = bh[0] = ivalid ? (int)(ci.x - c0.x) : 0;
+        bl[1] = bh[1] = ivalid ? (int)(ci.y - c0.y) : 0;
+        bl[2] = bh[2] = ivalid ? (int)(ci.z - c0.z) : 0;
+        // extremes over the i-charges (lanes l, l ^ 8, l ^ 16, l ^ 32): the
+        // xor-8 partner by a DPP row rotation, the other two by permutes
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            bl[k] = min(bl[k], dpp_move<0x128>(bl[k]));
+            bh[k] = max(bh[k], dpp_move<0x128>(bh[k]));
+        }
+#pragma unroll
+        for (int off = 16; off < 64; off <<= 1)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                bl[k] = min(bl[k], __shfl_xor(bl[k], off, 64));
+                bh[k] = max(bh[k], __shfl_xor(bh[k], off, 64));
+            }
+        if (lane == 0) {
+            ibox[0] = (int)(c0.x + (uint32_t)((bl[0] + bh[0]) / 2));
+            ibox[1] = (int)(c0.y + (uint32_t)((bl[1] + bh[1]) / 2));
+            ibox[2] = (int)(c0.z + (uint32_t)((bl[2] + bh[2]) / 2));
+            ibox[3] = (bh[0] - bl[0]) / 2 + 1;
+            ibox[4] = (bh[1] - bl[1]) / 2 + 1;
+            ibox[5] = (bh[2] - bl[2]) / 2 + 1;
+        }
+    }
     int nr = 0, tot = 0;
 #pragma unroll
     for (int v = 0; v < kPairWaves; ++v) {
@@ -388,39 +426,12 @@ __device__ __forceinline__ void pair_body(const PairArgs& a, int I, const uint4*
     const float ctop = to_vgpr(cubic ? Pu.c[DEG] : P.c[DEG]);
     const float dtop = to_vgpr(cubic ? Pu.d[DEG] : P.d[DEG]);
 
-    // bounding box of the i-cluster (fixed point, offsets from its first
-    // charge), as a centre and half extents.  Per axis the periodic distance
-    // of a candidate from any i-charge is at least its periodic distance from
-    // the centre minus the half extent, so a candidate whose such distances
-    // put it r_c or more from the box meets no i-charge within r_c and is
-    // dropped before the pair steps (the margin covers the FP32 rounding of
-    // the test: the pair set is unchanged)
-    int bl[3], bh[3];
-    bl[0] = bh[0] = ivalid ? (int)(ci.x - c0.x) : 0;
-    bl[1] = bh[1] = ivalid ? (int)(ci.y - c0.y) : 0;
-    bl[2] = bh[2] = ivalid ? (int)(ci.z - c0.z) : 0;
-    // extremes over the i-charges (lanes l, l ^ 8, l ^ 16, l ^ 32): the xor-8
-    // partner by a DPP row rotation, the other two by permutes
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        bl[k] = min(bl[k], dpp_move<0x128>(bl[k]));
-        bh[k] = max(bh[k], dpp_move<0x128>(bh[k]));
-    }
-#pragma unroll
-    for (int off = 16; off < 64; off <<= 1)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            bl[k] = min(bl[k], __shfl_xor(bl[k], off, 64));
-            bh[k] = max(bh[k], __shfl_xor(bh[k], off, 64));
-        }
-    const uint32_t cenx = c0.x + (uint32_t)((bl[0] + bh[0]) / 2);
-    const uint32_t ceny = c0.y + (uint32_t)((bl[1] + bh[1]) / 2);
-    const uint32_t cenz = c0.z + (uint32_t)((bl[2] + bh[2]) / 2);
+    // the i-cluster's box (formed by wavefront 0 before the range barrier):
     // half extents in fixed-point units; for a kernel compiled for cubic cells
     // the test runs in those units (the reach r_c + margin scaled to them, no
     // per-candidate scaling), otherwise in A per axis
-    const float hxu = (float)((bh[0] - bl[0]) / 2 + 1), hyu = (float)((bh[1] - bl[1]) / 2 + 1),
-                hzu = (float)((bh[2] - bl[2]) / 2 + 1);
+    const uint32_t cenx = (uint32_t)ibox[0], ceny = (uint32_t)ibox[1], cenz = (uint32_t)ibox[2];
+    const float hxu = (float)ibox[3], hyu = (float)ibox[4], hzu = (float)ibox[5];
     const float hx = CM == 1 ? hxu : hxu * sx, hy = CM == 1 ? hyu : hyu * sy,
                 hz = CM == 1 ? hzu : hzu * sz;
     const float rcm2 = CM == 1 ? a.rcm2 * isx * isx : a.rcm2;
